@@ -1,0 +1,206 @@
+/*
+ * wd.h -- Wilson-Dirac hopping term and solvers on AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the 4-d hopping term of Eq. 3 of "QCD on the Cell
+ * Broadband Engine" (Sec. 5):
+ *
+ *   psi'_x = sum_{mu=1..4} { U_{x,mu} (1 + gamma_mu) psi_{x+mu}
+ *                           + U^dag_{x-mu,mu} (1 - gamma_mu) psi_{x-mu} }
+ *
+ * and the Wilson-Dirac operator in hopping form D_W = 1 - kappa * H, on a
+ * lattice that is periodic in x1..x3 and carries the factor t_bc (-1:
+ * antiperiodic) on hops across the time boundary x4 = L4-1 <-> 0.  gamma_mu
+ * are the chiral (DeGrand-Rossi) matrices; gamma_5 = diag(1, 1, -1, -1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * dims[4] = (L1, L2, L3, L4); every L_i even and >= 2 (WD_ERR_DIMS otherwise).
+ * Canonical site index idx = x1 + L1*(x2 + L2*(x3 + L3*x4)); parity =
+ * (x1+x2+x3+x4) mod 2; checkerboard index cb = idx >> 1; V = L1 L2 L3 L4,
+ * V_h = V / 2.
+ *
+ * Canonical ("canon") layouts, complex128 = two doubles (re, im):
+ *   spinor [V][4 spin][3 colour];   gauge [V][4 mu][3 row][3 col].
+ *
+ * Device field layout ("field"): structure of arrays on one checkerboard.
+ * A half field holds the V_h sites of one parity in wd_vh_pad(dims) slots;
+ * spin-colour component c = 3*spin + colour.
+ *   WD_F64 : 12 planes of double2  -- plane c holds component c
+ *   WD_F32 :  6 planes of float4   -- plane k holds components 2k, 2k+1
+ *   WD_F16 :  3 planes of 8 x half  (components 4k..4k+3, re/im interleaved),
+ *             then one plane of float: stored value = component / s_x with
+ *             s_x = the largest |real| of the site's 24 reals (0 -> all zero)
+ *   WD_BF16:  3 planes of 8 x bfloat16 (round to nearest even)
+ * Element (plane k, cb i) sits at k * wd_vh_pad(dims) + i.  A full field is
+ * the even half followed by the odd half.  With nrhs right-hand sides the
+ * right-hand side index is outermost.  wd_field_bytes() gives the size.
+ *
+ * Ownership: the caller allocates and owns every field (device memory) and
+ * every host array.  The library never frees or keeps a caller pointer past
+ * the call.  A gauge handle owns its compressed links and its solver
+ * workspace and releases them in wd_gauge_destroy.  A handle is not
+ * thread-safe.
+ *
+ * Errors: no exception or abort crosses this interface.  A negative status
+ * means the call did nothing (argument errors) or that output contents are
+ * undefined (WD_ERR_HIP).  wd_last_error() returns a message for the calling
+ * thread's last failure.
+ */
+#ifndef WD_H
+#define WD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WD_OK = 0,
+  WD_NOT_CONVERGED = 1, /* result written (best iterate), tolerance not met */
+  WD_ERR_ARG = -1,      /* null pointer, bad enum value, bad scalar        */
+  WD_ERR_DIMS = -2,     /* odd/small extent or dims not the handle's dims  */
+  WD_ERR_PREC = -3,     /* precision not supported by this entry point     */
+  WD_ERR_NONFINITE = -4,/* kappa/tol or an input norm is not finite        */
+  WD_ERR_OOM = -5,      /* device allocation failed                        */
+  WD_ERR_HIP = -6       /* a HIP runtime call failed                       */
+} wd_status;
+
+typedef enum { WD_F64 = 0, WD_F32 = 1, WD_F16 = 2, WD_BF16 = 3 } wd_prec;
+
+enum { WD_EVEN = 0, WD_ODD = 1, WD_FULL = 2 };
+
+/* flags of wd_dslash_ex */
+enum { WD_DAGGER = 1 };
+
+typedef struct wd_gauge wd_gauge;
+
+/* ---------------------------------------------------------------- setup -- */
+
+/* Upload a gauge field and build the compressed link arrays (Sec. 5: a link
+ * is an SU(3) matrix of 18 reals; only rows 0 and 1 are stored and row 2 is
+ * rebuilt as conj(row0 x row1) at use, which is exact for SU(3) links).
+ * U_host: host pointer, canonical gauge layout, V*4*9 complex128 values.
+ * t_bc: -1 (antiperiodic time) or +1 (periodic).  prec: precision of the
+ * fields that wd_dslash() takes for this handle.  hip_stream: hipStream_t
+ * on which wd_dslash and the pack routines run (NULL = default stream).
+ * Returns WD_ERR_DIMS for bad dims, WD_ERR_OOM if device memory runs out. */
+wd_status wd_gauge_create(const double *U_host, const int dims[4], int t_bc,
+                          wd_prec prec, void *hip_stream, wd_gauge **out);
+
+/* Release a handle (NULL is accepted). */
+wd_status wd_gauge_destroy(wd_gauge *g);
+
+/* Change the stream of a handle (hipStream_t, NULL = default stream). */
+wd_status wd_gauge_set_stream(wd_gauge *g, void *hip_stream);
+
+/* Slots per half field (V_h rounded up to a multiple of 256). */
+size_t wd_vh_pad(const int dims[4]);
+
+/* Bytes of a field: parity WD_EVEN/WD_ODD = half field, WD_FULL = both
+ * halves; times nrhs (>= 1).  Returns 0 on bad arguments. */
+size_t wd_field_bytes(const int dims[4], wd_prec prec, int nrhs, int parity);
+
+/* Canonical spinor (device, V*12 complex128) <-> device field of precision
+ * prec.  parity WD_EVEN/WD_ODD converts that checkerboard only (the field is
+ * a half field); WD_FULL converts both.  Unpack writes only the sites of the
+ * converted parities.  Asynchronous on the handle's stream. */
+wd_status wd_spinor_pack(const wd_gauge *g, const void *canon, void *field,
+                         int parity, wd_prec prec);
+wd_status wd_spinor_unpack(const wd_gauge *g, const void *field, void *canon,
+                           int parity, wd_prec prec);
+
+/* --------------------------------------------------------------- dslash -- */
+
+/* Eq. 3 restricted to one checkerboard, or the full D_W.
+ *   parity WD_EVEN/WD_ODD: psi_out (half field, that parity) =
+ *        kappa * H_{p,1-p} psi_in (half field, the other parity);
+ *        kappa = 1 gives Eq. 3 exactly on the sites of parity p.
+ *   parity WD_FULL: psi_out = psi_in - kappa * H psi_in = D_W psi_in (full
+ *        fields).  psi_in and psi_out must not overlap.
+ * Fields are in the precision given at wd_gauge_create; dims must equal the
+ * handle's dims.  Asynchronous on the handle's stream; only launch errors are
+ * reported. */
+wd_status wd_dslash(const wd_gauge *U, const void *psi_in, void *psi_out,
+                    double kappa, const int dims[4], int parity);
+
+/* As wd_dslash with an explicit field precision and flags.  WD_DAGGER
+ * applies H^dag, i.e. Eq. 3 with the projectors (1 +- gamma_mu) exchanged
+ * (H^dag = gamma_5 H gamma_5). */
+wd_status wd_dslash_ex(const wd_gauge *U, const void *psi_in, void *psi_out,
+                       double kappa, int parity, wd_prec prec, int flags);
+
+/* Multi right-hand-side form of the single-parity hop: nrhs half fields
+ * (right-hand side outermost) share each link load.  parity WD_EVEN/WD_ODD
+ * only; prec WD_F64/WD_F32/WD_F16/WD_BF16; 1 <= nrhs <= 64. */
+wd_status wd_dslash_mrhs(const wd_gauge *U, const void *psi_in, void *psi_out,
+                         double kappa, int parity, wd_prec prec, int nrhs);
+
+/* ---------------------------------------------------------------- BLAS -- */
+/* Level-1 operations on n consecutive half fields (n = nrhs*halves) in
+ * precision prec, Sec. 4's caxpy among them.  Reductions accumulate in FP64
+ * in a fixed order (bitwise reproducible).  Results of reductions are written
+ * to host memory; these calls synchronise the handle's stream. */
+wd_status wd_caxpy(const wd_gauge *g, double c_re, double c_im, const void *x,
+                   void *y, int nhalf, wd_prec prec); /* y = c x + y */
+wd_status wd_cdot(const wd_gauge *g, const void *x, const void *y, int nhalf,
+                  wd_prec prec, double out[2]);     /* <x,y> = sum conj(x) y */
+wd_status wd_norm2(const wd_gauge *g, const void *x, int nhalf, wd_prec prec,
+                   double *out);
+
+/* --------------------------------------------------------------- solve -- */
+
+enum { WD_SOLVER_CG = 0, WD_SOLVER_DEFECT_CG = 1, WD_SOLVER_FGCR = 2 };
+
+typedef struct wd_ptc wd_ptc;
+
+typedef struct {
+  size_t struct_size;    /* sizeof(wd_solve_params)                         */
+  int solver;            /* WD_SOLVER_*                                     */
+  wd_prec inner_prec;    /* defect correction: storage of inner vectors     */
+  double inner_tol;      /* defect correction: inner relative tolerance     */
+  int max_iter;          /* cap on (inner) CG iterations in total           */
+  int check_every;       /* host polls convergence every k iterations       */
+  int use_graph;         /* capture one CG iteration pair in a hipGraph     */
+  int fgcr_m;            /* FGCR restart length                             */
+  const wd_ptc *precond; /* FGCR right preconditioner (NULL = identity)     */
+} wd_solve_params;
+
+typedef struct {
+  int iters;             /* CG iterations (inner iterations for defect cg)  */
+  int outer_iters;       /* defect-correction / FGCR restarts               */
+  int dslash_calls;      /* single-parity hop applications                  */
+  double true_rel_resid; /* |b - D_W x| / |b| in FP64, recomputed on return */
+  double seconds;        /* wall time of the solve                          */
+  int fallback_used;     /* FGCR fell back to CG                            */
+  int status;            /* same value as returned                          */
+} wd_solve_info;
+
+/* Fill params with defaults (plain FP64 even-odd CG on the normal equations). */
+void wd_solve_params_default(wd_solve_params *p);
+
+/* Solve D_W x = b to |b - D_W x| / |b| <= tol (FP64 true residual).  b and x
+ * are full FP64 fields (device); x is output only (the initial guess is 0).
+ * p = NULL selects FP64 even-odd CGLS; see wd_solve_params for the mixed
+ * precision and FGCR forms.  Synchronous.  b = 0 gives x = 0 and WD_OK.
+ * WD_NOT_CONVERGED: x holds the last iterate, info is filled. */
+wd_status wd_solve(const wd_gauge *U, const void *b, void *x, double kappa,
+                   double tol, const wd_solve_params *p, wd_solve_info *info);
+
+/* Solve nrhs systems with the same operator together (multi-RHS dslash,
+ * independent CG scalars per system).  b, x: nrhs full FP64 fields, right-hand
+ * side outermost.  Defect correction with inner_prec storage, FP64 outer. */
+wd_status wd_solve_mrhs(const wd_gauge *U, const void *b, void *x, int nrhs,
+                        double kappa, double tol, const wd_solve_params *p,
+                        wd_solve_info *info);
+
+/* --------------------------------------------------------------- misc --- */
+
+const char *wd_status_string(int status);
+const char *wd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WD_H */

@@ -1,0 +1,44 @@
+"""Wilson-Dirac hopping term (Eq. 3 of arXiv:0710.2442) and solvers on MI355X.
+
+Thin Python binding of ``libwd.so`` (see ``include/wd.h``).  Functions carry
+the C names and only marshal arguments: fields are torch device tensors
+(uint8 buffers of ``wd_field_bytes`` bytes, or complex128 canonical arrays for
+pack/unpack), passed by pointer; every computation runs in the library's HIP
+kernels.  There is no fallback: if the library is missing, importing this
+package raises.
+"""
+from ._lib import (  # noqa: F401
+    LIB_PATH,
+    WD_BF16,
+    WD_DAGGER,
+    WD_EVEN,
+    WD_F16,
+    WD_F32,
+    WD_F64,
+    WD_FULL,
+    WD_ODD,
+    WD_SOLVER_CG,
+    WD_SOLVER_DEFECT_CG,
+    WD_SOLVER_FGCR,
+    PRECS,
+    WdError,
+    Gauge,
+    lib,
+    wd_caxpy,
+    wd_cdot,
+    wd_dslash,
+    wd_dslash_ex,
+    wd_dslash_mrhs,
+    wd_field_bytes,
+    wd_gauge_create,
+    wd_gauge_destroy,
+    wd_new_field,
+    wd_norm2,
+    wd_solve,
+    wd_solve_mrhs,
+    wd_solve_params_default,
+    wd_spinor_pack,
+    wd_spinor_unpack,
+    wd_status_string,
+    wd_vh_pad,
+)

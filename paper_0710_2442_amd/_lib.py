@@ -1,0 +1,267 @@
+"""ctypes declarations of libwd.so and argument marshalling.
+
+Only pointers, sizes and scalars cross into the library.  torch supplies
+device memory and the current stream; nothing here computes on field data.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libwd.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build the HIP library first "
+        "(python -c 'import __graft_entry__; __graft_entry__.build()')"
+    )
+
+lib = C.CDLL(LIB_PATH)
+
+WD_F64, WD_F32, WD_F16, WD_BF16 = 0, 1, 2, 3
+PRECS = {"f64": WD_F64, "f32": WD_F32, "f16": WD_F16, "bf16": WD_BF16}
+WD_EVEN, WD_ODD, WD_FULL = 0, 1, 2
+WD_DAGGER = 1
+WD_SOLVER_CG, WD_SOLVER_DEFECT_CG, WD_SOLVER_FGCR = 0, 1, 2
+
+_vp = C.c_void_p
+_int4 = C.c_int * 4
+
+
+class wd_solve_params(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_size_t),
+        ("solver", C.c_int),
+        ("inner_prec", C.c_int),
+        ("inner_tol", C.c_double),
+        ("max_iter", C.c_int),
+        ("check_every", C.c_int),
+        ("use_graph", C.c_int),
+        ("fgcr_m", C.c_int),
+        ("precond", C.c_void_p),
+    ]
+
+
+class wd_solve_info(C.Structure):
+    _fields_ = [
+        ("iters", C.c_int),
+        ("outer_iters", C.c_int),
+        ("dslash_calls", C.c_int),
+        ("true_rel_resid", C.c_double),
+        ("seconds", C.c_double),
+        ("fallback_used", C.c_int),
+        ("status", C.c_int),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _decl(name, restype, argtypes):
+    f = getattr(lib, name)
+    f.restype = restype
+    f.argtypes = argtypes
+    return f
+
+
+_decl("wd_gauge_create", C.c_int, [_vp, _int4, C.c_int, C.c_int, _vp, C.POINTER(_vp)])
+_decl("wd_gauge_destroy", C.c_int, [_vp])
+_decl("wd_gauge_set_stream", C.c_int, [_vp, _vp])
+_decl("wd_vh_pad", C.c_size_t, [_int4])
+_decl("wd_field_bytes", C.c_size_t, [_int4, C.c_int, C.c_int, C.c_int])
+_decl("wd_spinor_pack", C.c_int, [_vp, _vp, _vp, C.c_int, C.c_int])
+_decl("wd_spinor_unpack", C.c_int, [_vp, _vp, _vp, C.c_int, C.c_int])
+_decl("wd_dslash", C.c_int, [_vp, _vp, _vp, C.c_double, _int4, C.c_int])
+_decl("wd_dslash_ex", C.c_int, [_vp, _vp, _vp, C.c_double, C.c_int, C.c_int, C.c_int])
+_decl("wd_dslash_mrhs", C.c_int, [_vp, _vp, _vp, C.c_double, C.c_int, C.c_int, C.c_int])
+_decl("wd_caxpy", C.c_int, [_vp, C.c_double, C.c_double, _vp, _vp, C.c_int, C.c_int])
+_decl("wd_cdot", C.c_int, [_vp, _vp, _vp, C.c_int, C.c_int, C.POINTER(C.c_double)])
+_decl("wd_norm2", C.c_int, [_vp, _vp, C.c_int, C.c_int, C.POINTER(C.c_double)])
+_decl("wd_solve_params_default", None, [C.POINTER(wd_solve_params)])
+_decl("wd_solve", C.c_int, [_vp, _vp, _vp, C.c_double, C.c_double, C.POINTER(wd_solve_params),
+                             C.POINTER(wd_solve_info)])
+_decl("wd_solve_mrhs", C.c_int, [_vp, _vp, _vp, C.c_int, C.c_double, C.c_double,
+                                  C.POINTER(wd_solve_params), C.POINTER(wd_solve_info)])
+_decl("wd_status_string", C.c_char_p, [C.c_int])
+_decl("wd_last_error", C.c_char_p, [])
+
+
+class WdError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = lib.wd_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {lib.wd_status_string(status).decode()} ({status}): {msg}")
+
+
+def _check(rc, where, allow_not_converged=False):
+    if rc < 0 or (rc > 0 and not allow_not_converged):
+        raise WdError(rc, where)
+    return rc
+
+
+def _prec(p):
+    if isinstance(p, str):
+        return PRECS[p]
+    return int(p)
+
+
+def _dims(d):
+    return _int4(*[int(x) for x in d])
+
+
+def _ptr(t):
+    """Device (or host) address of a torch tensor or numpy array."""
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def wd_status_string(s):
+    return lib.wd_status_string(int(s)).decode()
+
+
+def wd_vh_pad(dims):
+    return int(lib.wd_vh_pad(_dims(dims)))
+
+
+def wd_field_bytes(dims, prec, nrhs=1, parity=WD_FULL):
+    n = int(lib.wd_field_bytes(_dims(dims), _prec(prec), int(nrhs), int(parity)))
+    if n == 0:
+        raise WdError(-1, "wd_field_bytes")
+    return n
+
+
+def wd_new_field(dims, prec, nrhs=1, parity=WD_FULL, device="cuda"):
+    """Allocate an (uninitialised) device field buffer of the documented size."""
+    import torch
+    return torch.empty(wd_field_bytes(dims, prec, nrhs, parity), dtype=torch.uint8, device=device)
+
+
+class Gauge:
+    """Owning wrapper of a wd_gauge handle."""
+
+    def __init__(self, U, dims, t_bc=-1, prec="f64"):
+        U = np.ascontiguousarray(U, dtype=np.complex128)
+        dims = tuple(int(d) for d in dims)
+        V = int(np.prod(dims))
+        if U.size != V * 36:
+            raise ValueError(f"gauge field has {U.size} complex entries, expected {V * 36}")
+        self.dims = dims
+        self.prec = _prec(prec)
+        self.t_bc = int(t_bc)
+        h = C.c_void_p()
+        rc = lib.wd_gauge_create(U.ctypes.data, _dims(dims), int(t_bc), self.prec, _stream(), C.byref(h))
+        _check(rc, "wd_gauge_create")
+        self.handle = h
+
+    def sync_stream(self):
+        lib.wd_gauge_set_stream(self.handle, _stream())
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.wd_gauge_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def wd_gauge_create(U, dims, t_bc=-1, prec="f64"):
+    return Gauge(U, dims, t_bc, prec)
+
+
+def wd_gauge_destroy(g):
+    g.close()
+
+
+def wd_spinor_pack(g, canon, field, parity=WD_FULL, prec=None):
+    g.sync_stream()
+    p = g.prec if prec is None else _prec(prec)
+    _check(lib.wd_spinor_pack(g.handle, _ptr(canon), _ptr(field), int(parity), p), "wd_spinor_pack")
+
+
+def wd_spinor_unpack(g, field, canon, parity=WD_FULL, prec=None):
+    g.sync_stream()
+    p = g.prec if prec is None else _prec(prec)
+    _check(lib.wd_spinor_unpack(g.handle, _ptr(field), _ptr(canon), int(parity), p), "wd_spinor_unpack")
+
+
+def wd_dslash(g, psi_in, psi_out, kappa, dims, parity):
+    g.sync_stream()
+    _check(lib.wd_dslash(g.handle, _ptr(psi_in), _ptr(psi_out), float(kappa), _dims(dims), int(parity)),
+           "wd_dslash")
+
+
+def wd_dslash_ex(g, psi_in, psi_out, kappa, parity, prec, flags=0):
+    g.sync_stream()
+    _check(lib.wd_dslash_ex(g.handle, _ptr(psi_in), _ptr(psi_out), float(kappa), int(parity), _prec(prec),
+                            int(flags)), "wd_dslash_ex")
+
+
+def wd_dslash_mrhs(g, psi_in, psi_out, kappa, parity, prec, nrhs):
+    g.sync_stream()
+    _check(lib.wd_dslash_mrhs(g.handle, _ptr(psi_in), _ptr(psi_out), float(kappa), int(parity), _prec(prec),
+                              int(nrhs)), "wd_dslash_mrhs")
+
+
+def wd_caxpy(g, c, x, y, nhalf, prec):
+    g.sync_stream()
+    c = complex(c)
+    _check(lib.wd_caxpy(g.handle, c.real, c.imag, _ptr(x), _ptr(y), int(nhalf), _prec(prec)), "wd_caxpy")
+
+
+def wd_cdot(g, x, y, nhalf, prec):
+    g.sync_stream()
+    out = (C.c_double * 2)()
+    _check(lib.wd_cdot(g.handle, _ptr(x), _ptr(y), int(nhalf), _prec(prec), out), "wd_cdot")
+    return complex(out[0], out[1])
+
+
+def wd_norm2(g, x, nhalf, prec):
+    g.sync_stream()
+    out = C.c_double()
+    _check(lib.wd_norm2(g.handle, _ptr(x), int(nhalf), _prec(prec), C.byref(out)), "wd_norm2")
+    return out.value
+
+
+def wd_solve_params_default(**kw):
+    p = wd_solve_params()
+    lib.wd_solve_params_default(C.byref(p))
+    for k, v in kw.items():
+        if k == "inner_prec":
+            v = _prec(v)
+        if k == "precond":
+            v = v.handle if hasattr(v, "handle") else v
+        setattr(p, k, v)
+    return p
+
+
+def wd_solve(g, b, x, kappa, tol, params=None):
+    """Solve D_W x = b (full FP64 fields).  Returns (status, info dict)."""
+    g.sync_stream()
+    info = wd_solve_info()
+    pp = C.byref(params) if params is not None else None
+    rc = lib.wd_solve(g.handle, _ptr(b), _ptr(x), float(kappa), float(tol), pp, C.byref(info))
+    _check(rc, "wd_solve", allow_not_converged=True)
+    return rc, info.as_dict()
+
+
+def wd_solve_mrhs(g, b, x, nrhs, kappa, tol, params):
+    g.sync_stream()
+    infos = (wd_solve_info * int(nrhs))()
+    rc = lib.wd_solve_mrhs(g.handle, _ptr(b), _ptr(x), int(nrhs), float(kappa), float(tol), C.byref(params),
+                           infos)
+    _check(rc, "wd_solve_mrhs", allow_not_converged=True)
+    return rc, [i.as_dict() for i in infos]

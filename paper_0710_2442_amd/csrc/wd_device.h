@@ -1,0 +1,405 @@
+// Device helpers for the Wilson-Dirac kernels (gfx950, wave64).
+//
+// Complex arithmetic, the storage formats of spinor fields, the 12-real link
+// compression, the spin projectors of Eq. 3 in the chiral basis and the
+// fixed-order block reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wd_internal.h"
+
+namespace wd {
+
+// ------------------------------------------------------------------ complex
+template <class T>
+struct cplx {
+  T re, im;
+};
+
+template <class T>
+__device__ __forceinline__ cplx<T> cmk(T r, T i) { return {r, i}; }
+template <class T>
+__device__ __forceinline__ cplx<T> operator+(cplx<T> a, cplx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <class T>
+__device__ __forceinline__ cplx<T> operator-(cplx<T> a, cplx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <class T>
+__device__ __forceinline__ cplx<T> operator-(cplx<T> a) { return {-a.re, -a.im}; }
+template <class T>
+__device__ __forceinline__ cplx<T> operator*(cplx<T> a, cplx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class T>
+__device__ __forceinline__ cplx<T> operator*(T s, cplx<T> a) { return {s * a.re, s * a.im}; }
+// i * a
+template <class T>
+__device__ __forceinline__ cplx<T> mul_i(cplx<T> a) { return {-a.im, a.re}; }
+template <class T>
+__device__ __forceinline__ cplx<T> conj(cplx<T> a) { return {a.re, -a.im}; }
+// conj(a) * b
+template <class T>
+__device__ __forceinline__ cplx<T> cjmul(cplx<T> a, cplx<T> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+// acc += a * b
+template <class T>
+__device__ __forceinline__ void cfma(cplx<T> &acc, cplx<T> a, cplx<T> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+}
+
+// ------------------------------------------------------- bfloat16 / half
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  // round to nearest, ties to even, on the upper 16 bits of the binary32 word
+  uint32_t u = __float_as_uint(f);
+  uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+__device__ __forceinline__ uint16_t f32_to_f16(float f) {
+  _Float16 h = (_Float16)f;
+  return __builtin_bit_cast(uint16_t, h);
+}
+__device__ __forceinline__ float f16_to_f32(uint16_t h) {
+  return (float)__builtin_bit_cast(_Float16, h);
+}
+
+// ---------------------------------------------------------- memory access
+// 16-byte vector types (clang ext vectors, so the nontemporal builtins apply)
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+
+// Streaming (read-once / write-once) accesses bypass cache retention so the
+// reused neighbour spinors keep the L2.
+template <class T>
+__device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
+template <class T>
+__device__ __forceinline__ void st_stream(T v, T *p) { __builtin_nontemporal_store(v, p); }
+
+// -------------------------------------------------------- spinor storage
+// Spinor: 12 complex components, c = 3*spin + colour.
+template <int P>
+struct Spinor;
+
+template <>
+struct Spinor<WD_F64> {
+  using real = double;
+  static constexpr size_t bytes_per_slot = 192;
+  __device__ static void load(const void *base, size_t vp, size_t i, cplx<double> (&s)[12]) {
+    const v2d *p = (const v2d *)base + i;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      v2d v = p[c * vp];
+      s[c] = {v.x, v.y};
+    }
+  }
+  __device__ static void store(void *base, size_t vp, size_t i, const cplx<double> (&s)[12]) {
+    v2d *p = (v2d *)base + i;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) st_stream(v2d{s[c].re, s[c].im}, p + c * vp);
+  }
+};
+
+template <>
+struct Spinor<WD_F32> {
+  using real = float;
+  static constexpr size_t bytes_per_slot = 96;
+  __device__ static void load(const void *base, size_t vp, size_t i, cplx<float> (&s)[12]) {
+    const v4f *p = (const v4f *)base + i;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      v4f v = p[k * vp];
+      s[2 * k] = {v.x, v.y};
+      s[2 * k + 1] = {v.z, v.w};
+    }
+  }
+  __device__ static void store(void *base, size_t vp, size_t i, const cplx<float> (&s)[12]) {
+    v4f *p = (v4f *)base + i;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      st_stream(v4f{s[2 * k].re, s[2 * k].im, s[2 * k + 1].re, s[2 * k + 1].im}, p + k * vp);
+  }
+};
+
+// 16-byte packet of eight 16-bit reals
+struct alignas(16) pk8 {
+  uint32_t w[4];
+};
+
+template <>
+struct Spinor<WD_F16> {
+  using real = float;
+  static constexpr size_t bytes_per_slot = 52;
+  __device__ static void load(const void *base, size_t vp, size_t i, cplx<float> (&s)[12]) {
+    const v4u *p = (const v4u *)base + i;
+    const float nrm = ((const float *)((const v4u *)base + 3 * vp))[i];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      v4u v = p[k * vp];
+      uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        s[4 * k + j] = {nrm * f16_to_f32((uint16_t)(w[j] & 0xffffu)),
+                        nrm * f16_to_f32((uint16_t)(w[j] >> 16))};
+      }
+    }
+  }
+  __device__ static void store(void *base, size_t vp, size_t i, const cplx<float> (&s)[12]) {
+    float m = 0.f;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(s[c].re), fabsf(s[c].im)));
+    const float inv = m > 0.f ? 1.0f / m : 0.f;
+    v4u *p = (v4u *)base + i;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      uint32_t w[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const cplx<float> z = s[4 * k + j];
+        w[j] = (uint32_t)f32_to_f16(z.re * inv) | ((uint32_t)f32_to_f16(z.im * inv) << 16);
+      }
+      st_stream(v4u{w[0], w[1], w[2], w[3]}, p + k * vp);
+    }
+    st_stream(m, ((float *)((v4u *)base + 3 * vp)) + i);
+  }
+};
+
+template <>
+struct Spinor<WD_BF16> {
+  using real = float;
+  static constexpr size_t bytes_per_slot = 48;
+  __device__ static void load(const void *base, size_t vp, size_t i, cplx<float> (&s)[12]) {
+    const v4u *p = (const v4u *)base + i;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      v4u v = p[k * vp];
+      uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        s[4 * k + j] = {bf16_to_f32((uint16_t)(w[j] & 0xffffu)), bf16_to_f32((uint16_t)(w[j] >> 16))};
+    }
+  }
+  __device__ static void store(void *base, size_t vp, size_t i, const cplx<float> (&s)[12]) {
+    v4u *p = (v4u *)base + i;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      uint32_t w[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const cplx<float> z = s[4 * k + j];
+        w[j] = (uint32_t)f32_to_bf16(z.re) | ((uint32_t)f32_to_bf16(z.im) << 16);
+      }
+      st_stream(v4u{w[0], w[1], w[2], w[3]}, p + k * vp);
+    }
+  }
+};
+
+// ------------------------------------------------------ compressed links
+// A hop link is stored as its rows 0 and 1 (6 complex = 12 reals); row 2 is
+// conj(row0 x row1).  Double: 6 planes of v2d; float: 3 planes of v4f.
+template <class R>
+struct Link;
+
+template <>
+struct Link<double> {
+  static constexpr int planes = 6;
+  __device__ static void load(const void *base, size_t vp, size_t i, cplx<double> (&u)[6]) {
+    const v2d *p = (const v2d *)base + i;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      v2d v = ld_stream(p + k * vp);
+      u[k] = {v.x, v.y};
+    }
+  }
+};
+template <>
+struct Link<float> {
+  static constexpr int planes = 3;
+  __device__ static void load(const void *base, size_t vp, size_t i, cplx<float> (&u)[6]) {
+    const v4f *p = (const v4f *)base + i;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      v4f v = ld_stream(p + k * vp);
+      u[2 * k] = {v.x, v.y};
+      u[2 * k + 1] = {v.z, v.w};
+    }
+  }
+};
+
+// Full 3x3 from the two stored rows a = u[0..2], b = u[3..5].
+template <class T>
+__device__ __forceinline__ void rebuild_row2(const cplx<T> (&u)[6], cplx<T> (&c)[3]) {
+  const cplx<T> a0 = u[0], a1 = u[1], a2 = u[2], b0 = u[3], b1 = u[4], b2 = u[5];
+  c[0] = conj(a1 * b2 - a2 * b1);
+  c[1] = conj(a2 * b0 - a0 * b2);
+  c[2] = conj(a0 * b1 - a1 * b0);
+}
+
+// y = M v for the 3x3 matrix with rows (u[0..2], u[3..5], r2[0..2])
+template <class T>
+__device__ __forceinline__ void su3_mul(const cplx<T> (&u)[6], const cplx<T> (&r2)[3],
+                                        const cplx<T> (&v)[3], cplx<T> (&y)[3]) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    cplx<T> acc = u[3 * a] * v[0];
+    cfma(acc, u[3 * a + 1], v[1]);
+    cfma(acc, u[3 * a + 2], v[2]);
+    y[a] = acc;
+  }
+  cplx<T> acc = r2[0] * v[0];
+  cfma(acc, r2[1], v[1]);
+  cfma(acc, r2[2], v[2]);
+  y[2] = acc;
+}
+
+// --------------------------------------------------------- spin projection
+// For direction MU (0..3 = x1..x4) and projector (1 + S gamma_MU), S = +-1,
+// in the chiral basis:
+//   rows 0,1 of (1 + S g) psi form the half spinor h = (h0, h1);
+//   rows 2,3 follow from h:
+//   MU=0: h = (p0 + S i p3, p1 + S i p2);  r2 = -S i h1, r3 = -S i h0
+//   MU=1: h = (p0 - S p3,   p1 + S p2);    r2 =  S h1,   r3 = -S h0
+//   MU=2: h = (p0 + S i p2, p1 - S i p3);  r2 = -S i h0, r3 =  S i h1
+//   MU=3: h = (p0 + S p2,   p1 + S p3);    r2 =  S h0,   r3 =  S h1
+// (derived from the explicit gamma matrices; checked against the dense form)
+template <int MU, int S, class T>
+__device__ __forceinline__ void project(const cplx<T> (&p)[12], cplx<T> (&h)[6]) {
+  const T s = (T)S;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const cplx<T> p0 = p[a], p1 = p[3 + a], p2 = p[6 + a], p3 = p[9 + a];
+    if constexpr (MU == 0) {
+      h[a] = p0 + s * mul_i(p3);
+      h[3 + a] = p1 + s * mul_i(p2);
+    } else if constexpr (MU == 1) {
+      h[a] = p0 - s * p3;
+      h[3 + a] = p1 + s * p2;
+    } else if constexpr (MU == 2) {
+      h[a] = p0 + s * mul_i(p2);
+      h[3 + a] = p1 - s * mul_i(p3);
+    } else {
+      h[a] = p0 + s * p2;
+      h[3 + a] = p1 + s * p3;
+    }
+  }
+}
+
+// acc += full spinor rebuilt from the transported half spinor (g0, g1)
+template <int MU, int S, class T>
+__device__ __forceinline__ void reconstruct_add(cplx<T> (&acc)[12], const cplx<T> (&g)[6]) {
+  const T s = (T)S;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const cplx<T> g0 = g[a], g1 = g[3 + a];
+    acc[a] = acc[a] + g0;
+    acc[3 + a] = acc[3 + a] + g1;
+    if constexpr (MU == 0) {
+      acc[6 + a] = acc[6 + a] - s * mul_i(g1);
+      acc[9 + a] = acc[9 + a] - s * mul_i(g0);
+    } else if constexpr (MU == 1) {
+      acc[6 + a] = acc[6 + a] + s * g1;
+      acc[9 + a] = acc[9 + a] - s * g0;
+    } else if constexpr (MU == 2) {
+      acc[6 + a] = acc[6 + a] - s * mul_i(g0);
+      acc[9 + a] = acc[9 + a] + s * mul_i(g1);
+    } else {
+      acc[6 + a] = acc[6 + a] + s * g0;
+      acc[9 + a] = acc[9 + a] + s * g1;
+    }
+  }
+}
+
+// ------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum of v over the block, valid in thread 0.  Fixed order.
+template <int BS>
+__device__ __forceinline__ double block_sum(double v) {
+  static_assert(BS % 64 == 0 && BS <= 1024, "block size");
+  __shared__ double red[BS / 64];
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < BS / 64; ++k) t += red[k];
+  }
+  __syncthreads();
+  return t;
+}
+
+template <int BS, int N>
+__device__ __forceinline__ void block_sum_n(double (&v)[N]) {
+  static_assert(BS % 64 == 0 && BS <= 1024, "block size");
+  __shared__ double red[N][BS / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double s = wave_sum(v[j]);
+    if (lane == 0) red[j][w] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < BS / 64; ++k) t += red[j][k];
+      v[j] = t;
+    }
+  }
+  __syncthreads();
+}
+
+// Grid-wide sum: every block stores its partial(s); the block that arrives
+// last adds all partials in index order (deterministic whichever block that
+// is), writes the totals and re-arms the counter.  Returns true in thread 0 of
+// the last block, with the totals in `tot`.
+template <int BS, int N>
+__device__ __forceinline__ bool grid_sum_last(double (&v)[N], double *partials, unsigned *counter,
+                                              unsigned nblocks, unsigned bid, double (&tot)[N]) {
+  block_sum_n<BS, N>(v);
+  __shared__ int is_last;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+      __hip_atomic_store(&partials[(size_t)j * nblocks + bid], v[j], __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    const unsigned ticket = atomicAdd(counter, 1u);
+    is_last = (ticket == nblocks - 1);
+  }
+  __syncthreads();
+  if (!is_last) return false;
+  __threadfence();
+  double acc[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double s = 0.0;
+    for (unsigned b = threadIdx.x; b < nblocks; b += BS)
+      s += __hip_atomic_load(&partials[(size_t)j * nblocks + b], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    acc[j] = s;
+  }
+  block_sum_n<BS, N>(acc);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) tot[j] = acc[j];
+    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return threadIdx.x == 0;
+}
+
+}  // namespace wd

@@ -1,0 +1,21 @@
+// Host-side solver entry points (called by the C-ABI layer).
+#pragma once
+
+#include "wd_internal.h"
+
+namespace wd {
+
+wd_status solve(wd_gauge *g, const void *b, void *x, double kappa, double tol, const wd_solve_params &prm,
+                wd_solve_info &info);
+wd_status solve_mrhs(wd_gauge *g, const void *b, void *x, int nrhs, double kappa, double tol,
+                     const wd_solve_params &prm, wd_solve_info *infos);
+wd_status solve_fgcr(wd_gauge *g, const void *b, void *x, double kappa, double tol, const wd_solve_params &prm,
+                     wd_solve_info &info, hipStream_t st);
+void workspace_free(wd_gauge *g);
+
+}  // namespace wd
+
+namespace wd {
+// release the PTC preconditioner state a handle may hold (ptc.hip)
+void ptc_release(wd_gauge *g);
+}  // namespace wd

@@ -1,0 +1,40 @@
+"""Helpers for the GPU tests: move canonical numpy fields through the library's
+pack/unpack and compare with the oracle.  Only marshalling, no arithmetic of
+the method."""
+import numpy as np
+import torch
+
+import paper_0710_2442_amd as wd
+
+DEV = "cuda:0"
+
+
+def to_field(g, psi, prec="f64", parity=wd.WD_FULL):
+    """Canonical complex128 numpy spinor -> device field (full or one parity)."""
+    canon = torch.from_numpy(np.ascontiguousarray(psi).reshape(-1)).to(DEV)
+    f = wd.wd_new_field(g.dims, prec, 1, parity)
+    wd.wd_spinor_pack(g, canon, f, parity, prec)
+    return f
+
+
+def from_field(g, f, prec="f64", parity=wd.WD_FULL):
+    """Device field -> canonical complex128 numpy spinor (sites of other parity = 0)."""
+    L1, L2, L3, L4 = g.dims
+    canon = torch.zeros(L1 * L2 * L3 * L4 * 12, dtype=torch.complex128, device=DEV)
+    wd.wd_spinor_unpack(g, f, canon, parity, prec)
+    torch.cuda.synchronize()
+    return canon.cpu().numpy().reshape(L4, L3, L2, L1, 4, 3)
+
+
+def half_view(f, g, prec, which):
+    """Tensor view of the even (0) or odd (1) half of a full field."""
+    hb = wd.wd_field_bytes(g.dims, prec, 1, wd.WD_EVEN)
+    return f[which * hb:(which + 1) * hb]
+
+
+def rel_err(got, want):
+    return float(np.linalg.norm(got - want) / np.linalg.norm(want))
+
+
+def round_c64(a):
+    return a.astype(np.complex64).astype(np.complex128)

@@ -1,0 +1,233 @@
+"""GPU parity of the single-parity hop, D_W, layouts and multi-RHS hop.
+
+Bars: FP64 relative difference <= 1e-13, FP32 <= 1e-6 (the FP32 path is fed
+the FP64 inputs rounded once to complex64 and the oracle uses the same
+rounded inputs).  FP16 (+ per-site scale) and BF16 storage: the oracle sees
+the same rounded inputs; the bar is set by the rounding of the stored output
+(FP16: 1e-3, about 4x the RMS rounding error of 2^-11-ulp components;
+BF16: 2^-8).
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_0710_2442_amd as wd
+import synthetic as syn
+from gpu_util import DEV, from_field, half_view, rel_err, round_c64, to_field
+from oracle import free_field, solvers, wilson
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [(8, 8, 8, 8), (6, 4, 6, 10), (2, 2, 2, 2), (4, 2, 2, 4), (2, 2, 2, 64)]
+BARS = {"f64": 1e-13, "f32": 1e-6, "f16": 1e-3, "bf16": 2.0 ** -8}
+
+
+def _inputs(dims, prec, seed=7):
+    U = syn.gauge_field(dims, 0.3, 1000 + seed)
+    psi = syn.gaussian_spinor(dims, 2000 + seed)
+    if prec == "f64":
+        return U, psi, U, psi
+    Ur = round_c64(U)
+    if prec == "f32":
+        pr = round_c64(psi)
+    else:
+        pr = solvers.round_storage(psi, prec).astype(np.complex128)
+    return U, psi, Ur, pr
+
+
+@pytest.mark.parametrize("dims", SMALL)
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16", "bf16"])
+@pytest.mark.parametrize("parity", [0, 1])
+def test_parity_hop_matches_oracle(dims, prec, parity):
+    print(f"case: hop dims={dims} prec={prec} parity={parity}", flush=True)
+    U, psi, Ur, pr = _inputs(dims, prec)
+    g = wd.Gauge(U, dims, -1, prec)
+    src = to_field(g, psi, prec, 1 - parity)
+    out = wd.wd_new_field(dims, prec, 1, parity)
+    wd.wd_dslash(g, src, out, 1.0, dims, parity)
+    got = from_field(g, out, prec, parity)
+    want = wilson.hop_parity(Ur, pr, parity)
+    assert rel_err(got, want) <= BARS[prec], rel_err(got, want)
+    g.close()
+
+
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (6, 4, 6, 10), (2, 2, 2, 2)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_full_dirac_and_dagger(dims, prec):
+    print(f"case: D_W dims={dims} prec={prec}", flush=True)
+    kappa = 0.12
+    U, psi, Ur, pr = _inputs(dims, prec, seed=9)
+    g = wd.Gauge(U, dims, -1, prec)
+    src = to_field(g, psi, prec)
+    out = wd.wd_new_field(dims, prec)
+    wd.wd_dslash(g, src, out, kappa, dims, wd.WD_FULL)
+    assert rel_err(from_field(g, out, prec), wilson.dirac(Ur, pr, kappa)) <= BARS[prec]
+    for parity in (0, 1):
+        o = wd.wd_new_field(dims, prec, 1, parity)
+        wd.wd_dslash_ex(g, half_view(src, g, prec, 1 - parity), o, 1.0, parity, prec, wd.WD_DAGGER)
+        want = wilson.hop_parity(Ur, pr, parity, dagger=True)
+        assert rel_err(from_field(g, o, prec, parity), want) <= BARS[prec]
+    g.close()
+
+
+def test_periodic_time_boundary():
+    dims = (4, 4, 2, 6)
+    U, psi, _, _ = _inputs(dims, "f64", seed=11)
+    g = wd.Gauge(U, dims, +1, "f64")
+    src = to_field(g, psi)
+    out = wd.wd_new_field(dims, "f64")
+    wd.wd_dslash(g, src, out, 0.13, dims, wd.WD_FULL)
+    assert rel_err(from_field(g, out), wilson.dirac(U, psi, 0.13, tbc=+1)) <= 1e-13
+    g.close()
+
+
+def test_pack_layout_is_documented_soa():
+    """Device bytes equal the layout written in wd.h, built here index by index."""
+    dims = (6, 4, 2, 4)
+    L1, L2, L3, L4 = dims
+    psi = syn.gaussian_spinor(dims, 5)
+    g = wd.Gauge(syn.gauge_field(dims, 0.3, 5), dims, -1, "f64")
+    vpad = wd.wd_vh_pad(dims)
+    f = to_field(g, psi, "f64")
+    dev = f.cpu().numpy().view(np.float64).reshape(2, 12, vpad, 2)
+    want = np.zeros((2, 12, vpad, 2))
+    for x4 in range(L4):
+        for x3 in range(L3):
+            for x2 in range(L2):
+                for x1 in range(L1):
+                    idx = x1 + L1 * (x2 + L2 * (x3 + L3 * x4))
+                    p = (x1 + x2 + x3 + x4) % 2
+                    for c in range(12):
+                        z = psi[x4, x3, x2, x1, c // 3, c % 3]
+                        want[p, c, idx >> 1] = (z.real, z.imag)
+    assert np.array_equal(dev, want)
+    # FP32: plane k holds components 2k, 2k+1
+    f32 = to_field(g, psi, "f32")
+    d32 = f32.cpu().numpy().view(np.float32).reshape(2, 6, vpad, 4)
+    w32 = want.astype(np.float32).reshape(2, 6, 2, vpad, 2).transpose(0, 1, 3, 2, 4).reshape(2, 6, vpad, 4)
+    assert np.array_equal(d32, w32)
+    # round trip is exact in FP64
+    assert np.array_equal(from_field(g, f), psi)
+    g.close()
+
+
+def test_bitwise_deterministic():
+    dims = (8, 8, 8, 8)
+    U, psi, _, _ = _inputs(dims, "f64", seed=13)
+    g = wd.Gauge(U, dims, -1, "f64")
+    src = to_field(g, psi)
+    a = wd.wd_new_field(dims, "f64")
+    b = wd.wd_new_field(dims, "f64")
+    wd.wd_dslash(g, src, a, 0.12, dims, wd.WD_FULL)
+    wd.wd_dslash(g, src, b, 0.12, dims, wd.WD_FULL)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    g.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("nrhs", [1, 5, 12])
+def test_mrhs_equals_single_rhs_bitwise(prec, nrhs):
+    dims = (6, 4, 6, 10)
+    U = syn.gauge_field(dims, 0.3, 21)
+    g = wd.Gauge(U, dims, -1, prec)
+    psis = syn.gaussian_spinor(dims, 22, nrhs=nrhs)
+    hb = wd.wd_field_bytes(dims, prec, 1, wd.WD_EVEN)
+    src = torch.cat([to_field(g, psis[r], prec, wd.WD_ODD) for r in range(nrhs)])
+    out = wd.wd_new_field(dims, prec, nrhs, wd.WD_EVEN)
+    wd.wd_dslash_mrhs(g, src, out, 0.7, wd.WD_EVEN, prec, nrhs)
+    for r in range(nrhs):
+        one = wd.wd_new_field(dims, prec, 1, wd.WD_EVEN)
+        wd.wd_dslash_ex(g, src[r * hb:(r + 1) * hb], one, 0.7, wd.WD_EVEN, prec)
+        torch.cuda.synchronize()
+        assert torch.equal(one, out[r * hb:(r + 1) * hb]), r
+    g.close()
+
+
+def test_blas_against_numpy():
+    dims = (6, 4, 6, 10)
+    g = wd.Gauge(syn.gauge_field(dims, 0.3, 31), dims, -1, "f64")
+    a = syn.gaussian_spinor(dims, 32)
+    b = syn.gaussian_spinor(dims, 33)
+    fa, fb = to_field(g, a), to_field(g, b)
+    n = wd.wd_norm2(g, fa, 2, "f64")
+    assert abs(n - np.vdot(a, a).real) <= 1e-13 * n
+    d = wd.wd_cdot(g, fa, fb, 2, "f64")
+    want = np.vdot(a, b)
+    assert abs(d - want) <= 1e-13 * abs(want) * 10
+    c = 0.3 - 1.7j
+    wd.wd_caxpy(g, c, fa, fb, 2, "f64")
+    assert rel_err(from_field(g, fb), c * a + b) <= 1e-15
+    # caxpy in FP32 storage
+    fa32, fb32 = to_field(g, a, "f32"), to_field(g, b, "f32")
+    wd.wd_caxpy(g, c, fa32, fb32, 2, "f32")
+    assert rel_err(from_field(g, fb32, "f32"), c * round_c64(a) + round_c64(b)) <= 1e-6
+    g.close()
+
+
+def test_argument_errors_do_not_launch():
+    dims = (4, 4, 4, 4)
+    g = wd.Gauge(syn.gauge_field(dims, 0.3, 41), dims, -1, "f64")
+    f = wd.wd_new_field(dims, "f64")
+    o = wd.wd_new_field(dims, "f64")
+    with pytest.raises(wd.WdError) as e:
+        wd.wd_dslash(g, f, o, 0.1, (4, 4, 4, 6), 0)
+    assert e.value.status == -2
+    with pytest.raises(wd.WdError):
+        wd.wd_dslash(g, f, o, float("nan"), dims, 0)
+    with pytest.raises(wd.WdError):
+        wd.wd_dslash(g, f, o, 0.1, dims, 3)
+    with pytest.raises(wd.WdError):
+        wd.wd_dslash(g, f, f, 0.1, dims, 0)
+    g.close()
+
+
+# ------------------------------------------------------------------ full size
+@pytest.fixture(scope="module")
+def big():
+    dims = (32, 32, 32, 64)
+    U = syn.gauge_field(dims, 0.3, 1002)
+    psi = syn.gaussian_spinor(dims, 2002)
+    return dims, U, psi
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_full_size_sampled_sites(big, prec):
+    """32^3x64 in the benchmark's launch configuration, checked at sampled sites."""
+    dims, U, psi = big
+    print(f"case: 32^3x64 sampled prec={prec}", flush=True)
+    g = wd.Gauge(U, dims, -1, prec)
+    rng = np.random.default_rng(3)
+    for parity in (0, 1):
+        src = to_field(g, psi, prec, 1 - parity)
+        out = wd.wd_new_field(dims, prec, 1, parity)
+        wd.wd_dslash(g, src, out, 1.0, dims, parity)
+        got = from_field(g, out, prec, parity)
+        sites = [(0, 0, 0, 0), (31, 31, 31, 63), (1, 0, 0, 63), (0, 31, 5, 0), (30, 2, 31, 1)]
+        sites += [tuple(int(rng.integers(0, L)) for L in dims) for _ in range(60)]
+        sites = [s for s in sites if sum(s) % 2 == parity]
+        Ur = U if prec == "f64" else round_c64(U)
+        pr = psi if prec == "f64" else round_c64(psi)
+        want = wilson.hop_sites(Ur, pr, sites)
+        g_s = np.stack([got[x4, x3, x2, x1] for (x1, x2, x3, x4) in sites])
+        assert rel_err(g_s, want) <= BARS[prec]
+        # sites of the other parity were not written
+        assert np.all(got[wilson.parity_field(dims) != parity] == 0)
+    g.close()
+
+
+def test_full_size_plane_wave():
+    """Unit links at 32^3x64: D_W e^{ipx}u = symbol(p) u e^{ipx} at every site."""
+    dims = (32, 32, 32, 64)
+    U = syn.unit_gauge(dims)
+    g = wd.Gauge(U, dims, -1, "f64")
+    p = [2 * np.pi * 3 / 32, 2 * np.pi * 30 / 32, 2 * np.pi * 1 / 32, 2 * np.pi * (7 + 0.5) / 64]
+    u = syn.gaussian_spinor((2, 2, 2, 2), 5)[0, 0, 0, 0]
+    psi = free_field.plane_wave(dims, p, u)
+    src = to_field(g, psi)
+    out = wd.wd_new_field(dims, "f64")
+    wd.wd_dslash(g, src, out, 0.124, dims, wd.WD_FULL)
+    got = from_field(g, out)
+    want = free_field.plane_wave(dims, p, free_field.symbol(p, 0.124) @ u)
+    assert rel_err(got, want) <= 1e-13
+    g.close()
