@@ -1,0 +1,274 @@
+#!/usr/bin/env python3
+"""Wilson-Dirac hop bandwidth and time-to-solution on one MI355X.
+
+Headline: algorithmic GB/s of the single-parity hop (Eq. 3 on one
+checkerboard, 12-real compressed links) on a 32^3x64 lattice with near-unit
+random SU(3) links (eps = 0.3) and Gaussian spinors, and its fraction of the
+8 TB/s HBM peak.  One step = the hop on the even sites followed by the hop on
+the odd sites (two launches, ping-pong: each output feeds the next input;
+kappa = 1/8 keeps the values O(1)).  Algorithmic bytes per output site: 8
+links x 12 reals + 24 input reals + 24 output reals = 144 reals (1152 B in
+FP64, 576 B in FP32).
+
+Also reported:
+* the FP32 hop with the same protocol;
+* time to a true FP64 residual of 1e-10 on 32^3x64, kappa = 0.124: plain FP64
+  even-odd CG on the normal equations vs FP64 defect correction with FP32
+  inner arithmetic and FP32 / FP16 / BF16 vector storage;
+* the CPU oracle (numpy FP64) timed on one single-parity application of the
+  same workload (cpu_baseline);
+* HBM traffic per launch from the committed rocprofv3 counter summary when it
+  was taken on the current kernel source.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-solve] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+DIMS = (32, 32, 32, 64)
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_SITE = {"f64": 144 * 8, "f32": 144 * 4}
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "dslash_hop_32x32x32x64_traffic.txt")
+KERNEL_SOURCES = ["paper_0710_2442_amd/csrc/dslash.hip", "paper_0710_2442_amd/csrc/wd_device.h"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(prec):
+    """HBM bytes per launch from the committed counter summary, if current."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None, "no counter summary"
+    vals = {}
+    with open(TRAFFIC_SUMMARY) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_hash():
+        return None, "kernel changed since counters were taken"
+    key = f"hbm_bytes_per_launch_{prec}"
+    if key not in vals:
+        return None, "no entry"
+    return float(vals[key]), "ok"
+
+
+def time_hop(wd, torch, g, psi, prec, steps, warmup):
+    """Ping-pong single-parity hops; returns (seconds per launch, launches, total ms)."""
+    from paper_0710_2442_amd.fields import canon_to_field, half
+
+    f = canon_to_field(g, psi, prec)
+    E, O = half(f, g, prec, 0), half(f, g, prec, 1)
+    kappa = 0.125
+
+    def step():
+        wd.wd_dslash_ex(g, O, E, kappa, wd.WD_EVEN, prec)
+        wd.wd_dslash_ex(g, E, O, kappa, wd.WD_ODD, prec)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(s)
+    for _ in range(steps):
+        step()
+    t1.record(s)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    return ms / 1e3 / (2 * steps), 2 * steps, ms
+
+
+def solve_leg(wd, torch, syn, log_every=True):
+    """Time to |b - D x|/|b| <= 1e-10 on 32^3x64, kappa = 0.124."""
+    from paper_0710_2442_amd.fields import canon_to_field
+
+    kappa, tol = 0.124, 1e-10
+    gseed, sseed = syn.CONFIG_SEEDS["mixed_32x32x32x64"]
+    U = syn.gauge_field(DIMS, 0.3, gseed)
+    b = syn.gaussian_spinor(DIMS, sseed)
+    g = wd.Gauge(U, DIMS, -1, "f64")
+    fb = canon_to_field(g, b, "f64")
+    x = wd.wd_new_field(DIMS, "f64")
+    out = {}
+    cases = [
+        ("fp64_cg", dict(solver=wd.WD_SOLVER_CG)),
+        ("defect_f32", dict(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec="f32", inner_tol=1e-4)),
+        ("defect_f16", dict(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec="f16", inner_tol=1e-2)),
+        ("defect_bf16", dict(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec="bf16", inner_tol=1e-2)),
+    ]
+    for name, kw in cases:
+        p = wd.wd_solve_params_default(**kw)
+        wd.wd_solve(g, fb, x, kappa, tol, p)  # warm-up (graph capture, workspace)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rc, info = wd.wd_solve(g, fb, x, kappa, tol, p)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        out[name] = {
+            "seconds": round(wall, 4),
+            "iters": info["iters"],
+            "outer_iters": info["outer_iters"],
+            "dslash_calls": info["dslash_calls"],
+            "true_rel_resid": info["true_rel_resid"],
+            "status": rc,
+        }
+        log(f"solve {name}: {wall:.3f} s, iters {info['iters']}, outer {info['outer_iters']}, "
+            f"resid {info['true_rel_resid']:.2e}")
+    base = out["fp64_cg"]["seconds"]
+    for name in out:
+        out[name]["speedup_vs_fp64_cg"] = round(base / out[name]["seconds"], 3)
+    g.close()
+    return out
+
+
+def cpu_leg(syn, U, psi):
+    """Oracle single-parity hop on the full 32^3x64 workload (one application)."""
+    import numpy as np
+
+    from oracle import wilson
+
+    t = time.perf_counter()
+    wilson.hop_parity(U, psi, 0)
+    dt = time.perf_counter() - t
+    vh = int(np.prod(DIMS)) // 2
+    return {
+        "value": round(vh * BYTES_PER_SITE["f64"] / dt / 1e9, 4),
+        "unit": "GB/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"one FP64 single-parity hop (numpy oracle) on the full 32^3x64 lattice, {dt:.1f} s",
+        "host_cpus": os.cpu_count(),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="use the default hop variant")
+    ap.add_argument("--variant", default=None, help="force the hop variant 'block,groups' (no tuning)")
+    ap.add_argument("--only", choices=["f64", "f32"], default=None, help="time one precision only")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_0710_2442_amd as wd
+    import synthetic as syn
+
+    torch.cuda.set_device(0)
+    gseed, sseed = syn.CONFIG_SEEDS["dslash_32x32x32x64"]
+    t = time.perf_counter()
+    U = syn.gauge_field(DIMS, 0.3, gseed)
+    psi = syn.gaussian_spinor(DIMS, sseed)
+    log(f"inputs generated in {time.perf_counter() - t:.1f} s")
+
+    vh = int(np.prod(DIMS)) // 2
+    results = {}
+    precs = [args.only] if args.only else ["f64", "f32"]
+    for prec in precs:
+        g = wd.Gauge(U, DIMS, -1, prec)
+        if args.variant:
+            vb, vg = (int(x) for x in args.variant.split(","))
+            wd.wd_set_dslash_variant(g, prec, vb, vg)
+        elif not args.no_tune:
+            tb, tg, tus = wd.wd_tune_dslash(g, prec)
+            log(f"tuned hop {prec}: block {tb}, XCD groups {tg} ({tus:.1f} us in the tuner)")
+        sec, n, ms = time_hop(wd, torch, g, psi, prec, args.steps, args.warmup)
+        gbs = vh * BYTES_PER_SITE[prec] / sec / 1e9
+        results[prec] = {"sec_per_launch": sec, "gbs": gbs, "ms_total": ms, "launches": n,
+                         "variant": list(wd.wd_get_dslash_variant(g, prec))}
+        log(f"hop {prec}: {sec * 1e6:.1f} us/launch, {gbs:.0f} GB/s algorithmic, "
+            f"{100 * gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s")
+        g.close()
+        torch.cuda.empty_cache()
+
+    if args.calib_copy:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    head = "f64" if "f64" in results else precs[0]
+    r = results[head]
+    traffic, why = read_traffic(head)
+    roof = {
+        "bound": "hbm",
+        "achieved": round(r["gbs"], 2),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(r["gbs"] / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "kernel": f"k_dslash<{head}> single-parity hop, 32^3x64, 1,048,576 output sites per launch",
+        "algorithmic_bytes_per_launch": vh * BYTES_PER_SITE[head],
+        "avg_launch_us": round(r["sec_per_launch"] * 1e6, 2),
+        "variant_block_groups": r["variant"],
+    }
+    if traffic is None:
+        roof["traffic_note"] = why
+    line = {
+        "metric": "dslash_hbm_GBps",
+        "value": round(r["gbs"], 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_total"] / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": head,
+        "data": "synthetic: random SU(3) links exp(i*0.3*H), Gaussian spinors, seeded",
+        "config": {
+            "workload": "single-parity Wilson hop (Eq. 3), 32^3x64, 12-real links, even+odd per step",
+            "lattice": "32x32x32x64",
+            "sites_per_launch": vh,
+            "parallelism": "single GPU",
+        },
+        "roofline": roof,
+    }
+    if "f32" in results and head != "f32":
+        line["f32"] = {"value": round(results["f32"]["gbs"], 2), "unit": "GB/s",
+                       "frac": round(results["f32"]["gbs"] / HBM_PEAK_GBS, 4),
+                       "avg_launch_us": round(results["f32"]["sec_per_launch"] * 1e6, 2)}
+    if not args.no_solve:
+        line["solve_32x32x32x64_kappa0124"] = solve_leg(wd, torch, syn)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_leg(syn, U, psi)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -194,6 +194,26 @@ wd_status wd_solve_mrhs(const wd_gauge *U, const void *b, void *x, int nrhs,
                         double kappa, double tol, const wd_solve_params *p,
                         wd_solve_info *info);
 
+/* --------------------------------------------------------------- tuning -- */
+
+/* Autotune the single-RHS hop of precision prec on this handle's lattice:
+ * block size (64..512 threads) and the number of XCD regions the blocks are
+ * grouped into (0 = linear order).  Every candidate's output is first compared
+ * byte for byte with the reference variant (256 threads, linear); matching
+ * candidates are timed with HIP events and the fastest is kept in the handle.
+ * cache_path (may be NULL): JSON-lines file keyed by (arch, kernel, precision,
+ * lattice); an existing entry is used without timing unless force != 0, and
+ * new results are appended.  Outputs (may be NULL): chosen block, groups and
+ * time per launch in microseconds (-1 if taken from the cache).  Synchronous. */
+wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path,
+                         int force, int *block, int *groups, double *us);
+
+/* Set / read the hop variant used for precision prec.  WD_ERR_ARG if the
+ * variant does not fit the lattice (see wd_tune_dslash). */
+wd_status wd_set_dslash_variant(wd_gauge *g, wd_prec prec, int block, int groups);
+wd_status wd_get_dslash_variant(const wd_gauge *g, wd_prec prec, int *block,
+                                int *groups);
+
 /* --------------------------------------------------------------- misc --- */
 
 const char *wd_status_string(int status);

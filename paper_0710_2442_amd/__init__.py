@@ -41,4 +41,7 @@ from ._lib import (  # noqa: F401
     wd_spinor_unpack,
     wd_status_string,
     wd_vh_pad,
+    wd_tune_dslash,
+    wd_set_dslash_variant,
+    wd_get_dslash_variant,
 )

@@ -100,6 +100,11 @@ wd_status wd_gauge_create(const double *U_host, const int dims[4], int t_bc, wd_
   g->tbc = t_bc;
   g->prec = prec;
   g->stream = (hipStream_t)hip_stream;
+  for (int p = 0; p < 4; ++p) {
+    // default hop variant: 256 threads, eight XCD regions when the lattice allows
+    g->hop_block[p] = 256;
+    g->hop_groups[p] = dslash_variant_ok(g->geom, 256, 8) ? 8 : 0;
+  }
   wd_status rc = WD_OK;
   void *canon = nullptr;
   const size_t V = (size_t)dims[0] * dims[1] * dims[2] * dims[3];

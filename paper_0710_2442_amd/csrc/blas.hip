@@ -64,7 +64,7 @@ __global__ __launch_bounds__(BLAS_BS) void k_norm2(KBlas k) {
     for (int c = 0; c < 12; ++c) acc += (double)a[c].re * a[c].re + (double)a[c].im * a[c].im;
   }
   double v[1] = {acc}, tot[1];
-  if (grid_sum_last<BLAS_BS, 1>(v, k.partials + (size_t)sys * k.nblk, k.counter + sys, k.nblk, blockIdx.x, tot))
+  if (grid_sum_last<1>(v, k.partials + (size_t)sys * k.nblk, k.counter + sys, k.nblk, blockIdx.x, tot))
     k.result[sys] = tot[0];
 }
 
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(BLAS_BS) void k_cdot(KBlas k) {
     }
   }
   double v[2] = {re, im}, tot[2];
-  if (grid_sum_last<BLAS_BS, 2>(v, k.partials + (size_t)sys * 2 * k.nblk, k.counter + sys, k.nblk, blockIdx.x,
+  if (grid_sum_last<2>(v, k.partials + (size_t)sys * 2 * k.nblk, k.counter + sys, k.nblk, blockIdx.x,
                                 tot)) {
     k.result[2 * sys] = tot[0];
     k.result[2 * sys + 1] = tot[1];
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(BLAS_BS) void k_cg_update(KBlas k) {
     }
   }
   double v[1] = {acc}, tot[1];
-  if (grid_sum_last<BLAS_BS, 1>(v, k.partials + (size_t)sys * k.nblk, k.counter + sys, k.nblk, blockIdx.x, tot)) {
+  if (grid_sum_last<1>(v, k.partials + (size_t)sys * k.nblk, k.counter + sys, k.nblk, blockIdx.x, tot)) {
     sc->ss = tot[0];
     sc->iters += 1;
     if (tot[0] <= sc->stop2) sc->done = 1;

@@ -30,7 +30,6 @@ struct KDslash {
   const char *X;
   const char *Y;
   const char *links;  // hop-link arrays of this output parity
-  size_t hop_stride;  // bytes between consecutive hops' link arrays
   double a;
   int parity;
   int norm_accumulate;
@@ -38,7 +37,25 @@ struct KDslash {
   const int *skip;
   double *partials;
   unsigned *counter;
+  // block -> tile mapping (see tile_of)
+  int groups;           // 0: linear; G > 0: G contiguous regions per time slice
+  int tiles_per_slice;  // tiles (blocks) per time slice of one parity
 };
+
+// Workgroups are dispatched round-robin over the XCDs (8 on MI355X), each
+// with its own L2.  With `groups` = G, block b goes to region b % G and the
+// blocks of one region walk its tiles slice by slice in time order, so a
+// region's neighbour spinors (x1..x3 inside the slice, x4 one slice away)
+// are fetched into one L2 and re-read from there.  Requires
+// tiles_per_slice % G == 0 and gridDim.x == tiles_per_slice * L4.
+__device__ __forceinline__ int tile_of(const KDslash &k) {
+  const int b = blockIdx.x;
+  if (k.groups == 0) return b;
+  const int G = k.groups;
+  const int per = k.tiles_per_slice / G;
+  const int x = b % G, q = b / G;
+  return (q / per) * k.tiles_per_slice + x * per + (q % per);
+}
 
 // Site coordinates of checkerboard index i on parity p.
 struct Coords {
@@ -74,7 +91,7 @@ __device__ __forceinline__ void neighbours(const Geom &g, const Coords &c, int i
 // One hop: acc += M (1 + S gamma_MU) psi_nb, M = the stored hop link.
 template <int P, int MU, int S>
 __device__ __forceinline__ void hop_term(cplx<RealOf<P>> (&acc)[12], const char *in, size_t vp, int nb,
-                                         const char *link, size_t i, RealOf<P> sign) {
+                                         const char *links, int d, size_t i, RealOf<P> sign) {
   using T = RealOf<P>;
   cplx<T> psi[12];
   Spinor<P>::load(in, vp, nb, psi);
@@ -85,7 +102,7 @@ __device__ __forceinline__ void hop_term(cplx<RealOf<P>> (&acc)[12], const char 
     for (int c = 0; c < 6; ++c) h[c] = sign * h[c];
   }
   cplx<T> u[6];
-  Link<T>::load(link, vp, i, u);
+  Link<T>::load(links, d, i, u);
   cplx<T> r2[3];
   rebuild_row2(u, r2);
   cplx<T> g[6];
@@ -117,25 +134,24 @@ __device__ __forceinline__ void hop_all(const KDslash &k, int i, cplx<RealOf<P>>
   constexpr int F = DAG ? -1 : 1;  // forward hop projector (1 + F gamma)
   constexpr int B = -F;            // backward hop projector (1 + B gamma)
   const char *L = k.links;
-  const size_t hs = k.hop_stride;
 #pragma unroll
   for (int c2 = 0; c2 < 12; ++c2) acc[c2] = {(T)0, (T)0};
-  hop_term<P, 0, F>(acc, k.in, vp, nb[0], L + 0 * hs, i, one);
-  hop_term<P, 1, F>(acc, k.in, vp, nb[1], L + 1 * hs, i, one);
-  hop_term<P, 2, F>(acc, k.in, vp, nb[2], L + 2 * hs, i, one);
-  hop_term<P, 3, F>(acc, k.in, vp, nb[3], L + 3 * hs, i, sf);
-  hop_term<P, 0, B>(acc, k.in, vp, nb[4], L + 4 * hs, i, one);
-  hop_term<P, 1, B>(acc, k.in, vp, nb[5], L + 5 * hs, i, one);
-  hop_term<P, 2, B>(acc, k.in, vp, nb[6], L + 6 * hs, i, one);
-  hop_term<P, 3, B>(acc, k.in, vp, nb[7], L + 7 * hs, i, sb);
+  hop_term<P, 0, F>(acc, k.in, vp, nb[0], L, 0, i, one);
+  hop_term<P, 1, F>(acc, k.in, vp, nb[1], L, 1, i, one);
+  hop_term<P, 2, F>(acc, k.in, vp, nb[2], L, 2, i, one);
+  hop_term<P, 3, F>(acc, k.in, vp, nb[3], L, 3, i, sf);
+  hop_term<P, 0, B>(acc, k.in, vp, nb[4], L, 4, i, one);
+  hop_term<P, 1, B>(acc, k.in, vp, nb[5], L, 5, i, one);
+  hop_term<P, 2, B>(acc, k.in, vp, nb[6], L, 6, i, one);
+  hop_term<P, 3, B>(acc, k.in, vp, nb[7], L, 7, i, sb);
 }
 
 // EPI: 0 -> out = a H in;  1 -> out = X + a H in;  2 -> out = X - Y + a H in
-template <int P, bool DAG, int EPI, bool NORM, int BS>
-__global__ __launch_bounds__(BS) void k_dslash(KDslash k) {
+template <int P, bool DAG, int EPI, bool NORM>
+__global__ __launch_bounds__(512) void k_dslash(KDslash k) {
   using T = RealOf<P>;
   if (k.skip && *k.skip) return;
-  const int i = blockIdx.x * BS + threadIdx.x;
+  const int i = tile_of(k) * (int)blockDim.x + (int)threadIdx.x;
   const size_t vp = (size_t)k.g.vpad;
   double nrm = 0.0;
   if (i < k.g.vh) {
@@ -177,7 +193,7 @@ __global__ __launch_bounds__(BS) void k_dslash(KDslash k) {
   }
   if constexpr (NORM) {
     double v[1] = {nrm}, tot[1];
-    if (grid_sum_last<BS, 1>(v, k.partials, k.counter, gridDim.x, blockIdx.x, tot)) {
+    if (grid_sum_last<1>(v, k.partials, k.counter, gridDim.x, blockIdx.x, tot)) {
       *k.norm_out = k.norm_accumulate ? (*k.norm_out + tot[0]) : tot[0];
     }
   }
@@ -289,39 +305,50 @@ static KDslash make_k(const wd_gauge *g, wd_prec prec, int parity) {
   k.g = g->geom;
   const bool dbl = (prec == WD_F64);
   const char *base = (const char *)(dbl ? g->links64 : g->links32);
-  k.hop_stride = link_hop_stride_bytes(g->geom, dbl);
-  k.links = base + (size_t)parity * 8 * k.hop_stride;
+  k.links = base + (size_t)parity * link_parity_bytes(g->geom, dbl);
   k.parity = parity;
   return k;
 }
 
 template <int P, bool DAG, int EPI, bool NORM>
-static void launch_t(const KDslash &k, hipStream_t st) {
-  constexpr int BS = 256;
-  const unsigned nb = (unsigned)((k.g.vpad + BS - 1) / BS);
-  hipLaunchKernelGGL((k_dslash<P, DAG, EPI, NORM, BS>), dim3(nb), dim3(BS), 0, st, k);
+static void launch_t(const KDslash &k, unsigned nblk, unsigned bs, hipStream_t st) {
+  hipLaunchKernelGGL((k_dslash<P, DAG, EPI, NORM>), dim3(nblk), dim3(bs), 0, st, k);
 }
 
 template <int P, bool DAG>
-static void launch_epi(const KDslash &k, int epi, bool norm, hipStream_t st) {
+static void launch_epi(const KDslash &k, int epi, bool norm, unsigned nblk, unsigned bs, hipStream_t st) {
   if (norm) {
-    if (epi == 0) launch_t<P, DAG, 0, true>(k, st);
-    else if (epi == 1) launch_t<P, DAG, 1, true>(k, st);
-    else launch_t<P, DAG, 2, true>(k, st);
+    if (epi == 0) launch_t<P, DAG, 0, true>(k, nblk, bs, st);
+    else if (epi == 1) launch_t<P, DAG, 1, true>(k, nblk, bs, st);
+    else launch_t<P, DAG, 2, true>(k, nblk, bs, st);
   } else {
-    if (epi == 0) launch_t<P, DAG, 0, false>(k, st);
-    else if (epi == 1) launch_t<P, DAG, 1, false>(k, st);
-    else launch_t<P, DAG, 2, false>(k, st);
+    if (epi == 0) launch_t<P, DAG, 0, false>(k, nblk, bs, st);
+    else if (epi == 1) launch_t<P, DAG, 1, false>(k, nblk, bs, st);
+    else launch_t<P, DAG, 2, false>(k, nblk, bs, st);
   }
 }
 
 template <int P>
-static void launch_prec(const KDslash &k, bool dag, int epi, bool norm, hipStream_t st) {
-  if (dag) launch_epi<P, true>(k, epi, norm, st);
-  else launch_epi<P, false>(k, epi, norm, st);
+static void launch_prec(const KDslash &k, bool dag, int epi, bool norm, unsigned nblk, unsigned bs, hipStream_t st) {
+  if (dag) launch_epi<P, true>(k, epi, norm, nblk, bs, st);
+  else launch_epi<P, false>(k, epi, norm, nblk, bs, st);
 }
 
-unsigned dslash_grid_blocks(const wd_gauge *g) { return (unsigned)((g->geom.vpad + 255) / 256); }
+// Largest grid of a single-RHS hop launch (smallest block size, 64).
+unsigned dslash_grid_blocks(const wd_gauge *g) { return (unsigned)((g->geom.vpad + 63) / 64); }
+
+// A variant (block size, region groups) is valid for a lattice when the
+// block size divides the slots and, for G > 0, the tiles of one time slice
+// split evenly into G regions.
+bool dslash_variant_ok(const Geom &G, int bs, int groups) {
+  if (bs != 64 && bs != 128 && bs != 256 && bs != 512) return false;
+  if (groups == 0) return true;
+  if (groups < 0 || groups > 64) return false;
+  const long slice = (long)G.vh / G.L[3];
+  if (G.vpad != G.vh || slice % bs != 0) return false;
+  const long tps = slice / bs;
+  return tps % groups == 0;
+}
 
 wd_status launch_dslash(const wd_gauge *g, wd_prec prec, const DslashArgs &a, hipStream_t st) {
   KDslash k = make_k(g, prec, a.parity);
@@ -339,11 +366,17 @@ wd_status launch_dslash(const wd_gauge *g, wd_prec prec, const DslashArgs &a, hi
   if (a.Y && !a.X) return set_error(WD_ERR_ARG, "dslash epilogue: Y given without X");
   const bool norm = a.norm_out != nullptr;
   if (norm && (!k.partials || !k.counter)) return set_error(WD_ERR_ARG, "dslash norm: no reduction buffer");
+  const int pi = (int)prec;
+  int bs = g->hop_block[pi], groups = g->hop_groups[pi];
+  if (!dslash_variant_ok(g->geom, bs, groups)) { bs = 256; groups = 0; }
+  k.groups = groups;
+  k.tiles_per_slice = groups ? (int)((long)g->geom.vh / g->geom.L[3] / bs) : 0;
+  const unsigned nblk = (unsigned)((g->geom.vpad + bs - 1) / bs);
   switch (prec) {
-    case WD_F64: launch_prec<WD_F64>(k, a.dagger, epi, norm, st); break;
-    case WD_F32: launch_prec<WD_F32>(k, a.dagger, epi, norm, st); break;
-    case WD_F16: launch_prec<WD_F16>(k, a.dagger, epi, norm, st); break;
-    case WD_BF16: launch_prec<WD_BF16>(k, a.dagger, epi, norm, st); break;
+    case WD_F64: launch_prec<WD_F64>(k, a.dagger, epi, norm, nblk, bs, st); break;
+    case WD_F32: launch_prec<WD_F32>(k, a.dagger, epi, norm, nblk, bs, st); break;
+    case WD_F16: launch_prec<WD_F16>(k, a.dagger, epi, norm, nblk, bs, st); break;
+    case WD_BF16: launch_prec<WD_BF16>(k, a.dagger, epi, norm, nblk, bs, st); break;
     default: return set_error(WD_ERR_PREC, "dslash: unknown precision %d", (int)prec);
   }
   return hip_check(hipGetLastError(), "dslash launch");

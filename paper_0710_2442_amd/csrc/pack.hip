@@ -78,14 +78,13 @@ struct KPackGauge {
   const double *U;  // [V][4][3][3] complex128
   char *l64;
   char *l32;
-  size_t hop64, hop32;  // bytes per hop array
+  size_t par64, par32;  // bytes per parity
 };
 
 __global__ __launch_bounds__(256) void k_pack_gauge(KPackGauge k) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   const int p = blockIdx.y;
   if (i >= k.g.vpad) return;
-  const size_t vp = (size_t)k.g.vpad;
   int x[4] = {0, 0, 0, 0};
   const bool real_site = i < k.g.vh;
   if (real_site) {
@@ -119,8 +118,8 @@ __global__ __launch_bounds__(256) void k_pack_gauge(KPackGauge k) {
           }
         }
     }
-    v2d *d64 = (v2d *)(k.l64 + ((size_t)p * 8 + d) * k.hop64) + i;
-    v4f *d32 = (v4f *)(k.l32 + ((size_t)p * 8 + d) * k.hop32) + i;
+    v2d *d64 = (v2d *)(k.l64 + (size_t)p * k.par64);
+    v4f *d32 = (v4f *)(k.l32 + (size_t)p * k.par32);
     // element order: (row 0: c0 c1 c2, row 1: c0 c1 c2)
     double e[6][2];
     for (int r = 0; r < 2; ++r)
@@ -128,9 +127,10 @@ __global__ __launch_bounds__(256) void k_pack_gauge(KPackGauge k) {
         e[r * 3 + c][0] = m[r][c][0];
         e[r * 3 + c][1] = m[r][c][1];
       }
-    for (int q = 0; q < 6; ++q) d64[q * vp] = v2d{e[q][0], e[q][1]};
+    for (int q = 0; q < 6; ++q) d64[link_packet<6>(d, q, i)] = v2d{e[q][0], e[q][1]};
     for (int q = 0; q < 3; ++q)
-      d32[q * vp] = v4f{(float)e[2 * q][0], (float)e[2 * q][1], (float)e[2 * q + 1][0], (float)e[2 * q + 1][1]};
+      d32[link_packet<3>(d, q, i)] =
+          v4f{(float)e[2 * q][0], (float)e[2 * q][1], (float)e[2 * q + 1][0], (float)e[2 * q + 1][1]};
   }
 }
 
@@ -183,8 +183,8 @@ wd_status launch_pack_gauge(const wd_gauge *g, const void *canon_dev, hipStream_
   k.U = (const double *)canon_dev;
   k.l64 = (char *)g->links64;
   k.l32 = (char *)g->links32;
-  k.hop64 = link_hop_stride_bytes(g->geom, true);
-  k.hop32 = link_hop_stride_bytes(g->geom, false);
+  k.par64 = link_parity_bytes(g->geom, true);
+  k.par32 = link_parity_bytes(g->geom, false);
   dim3 grid((unsigned)((g->geom.vpad + 255) / 256), 2);
   hipLaunchKernelGGL(k_pack_gauge, grid, dim3(256), 0, st, k);
   return hip_check(hipGetLastError(), "pack_gauge launch");

@@ -1,0 +1,188 @@
+// Autotuner for the single-RHS hop: block size and XCD-region grouping.
+//
+// Each candidate is first checked for parity -- its output must equal the
+// reference variant's (256 threads, linear order) byte for byte, which holds
+// because every site's arithmetic is the same in every variant -- and then
+// timed with HIP events.  The fastest valid candidate is stored in the handle
+// and, if a cache path is given, appended to a JSON-lines cache keyed by
+// (architecture, kernel, precision, lattice).
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "wd_internal.h"
+
+namespace wd {
+
+static std::string tune_key(const wd_gauge *g, wd_prec prec) {
+  hipDeviceProp_t prop;
+  char arch[64] = "unknown";
+  if (hipGetDeviceProperties(&prop, g->device) == hipSuccess) {
+    snprintf(arch, sizeof arch, "%s", prop.gcnArchName);
+    char *colon = strchr(arch, ':');
+    if (colon) *colon = 0;
+  }
+  char buf[160];
+  snprintf(buf, sizeof buf, "%s/hop/p%d/%dx%dx%dx%d", arch, (int)prec, g->dims[0], g->dims[1], g->dims[2],
+           g->dims[3]);
+  return buf;
+}
+
+static bool cache_lookup(const char *path, const std::string &key, int &bs, int &groups, double &us) {
+  FILE *f = fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (fgets(line, sizeof line, f)) {
+    char k[200];
+    int b, gr;
+    double t;
+    if (sscanf(line, " {\"key\": \"%199[^\"]\", \"block\": %d, \"groups\": %d, \"us\": %lf", k, &b, &gr, &t) == 4 &&
+        key == k) {
+      bs = b; groups = gr; us = t; found = true;  // last entry wins
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+static void cache_append(const char *path, const std::string &key, int bs, int groups, double us) {
+  FILE *f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "{\"key\": \"%s\", \"block\": %d, \"groups\": %d, \"us\": %.3f}\n", key.c_str(), bs, groups, us);
+  fclose(f);
+}
+
+}  // namespace wd
+
+using namespace wd;
+
+extern "C" {
+
+wd_status wd_set_dslash_variant(wd_gauge *g, wd_prec prec, int block, int groups) {
+  if (!g) return set_error(WD_ERR_ARG, "gauge handle is NULL");
+  if ((int)prec < 0 || (int)prec > 3) return set_error(WD_ERR_PREC, "prec = %d", (int)prec);
+  if (!dslash_variant_ok(g->geom, block, groups))
+    return set_error(WD_ERR_ARG, "variant (block %d, groups %d) does not fit this lattice", block, groups);
+  g->hop_block[prec] = block;
+  g->hop_groups[prec] = groups;
+  return WD_OK;
+}
+
+wd_status wd_get_dslash_variant(const wd_gauge *g, wd_prec prec, int *block, int *groups) {
+  if (!g || !block || !groups) return set_error(WD_ERR_ARG, "NULL argument");
+  if ((int)prec < 0 || (int)prec > 3) return set_error(WD_ERR_PREC, "prec = %d", (int)prec);
+  *block = g->hop_block[prec];
+  *groups = g->hop_groups[prec];
+  return WD_OK;
+}
+
+wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int force, int *out_block,
+                         int *out_groups, double *out_us) {
+  if (!g) return set_error(WD_ERR_ARG, "gauge handle is NULL");
+  if ((int)prec < 0 || (int)prec > 3) return set_error(WD_ERR_PREC, "prec = %d", (int)prec);
+  WD_HIP(hipSetDevice(g->device));
+  const std::string key = tune_key(g, prec);
+  int bs = 256, groups = 0;
+  double best_us = -1.0;
+  if (cache_path && !force && cache_lookup(cache_path, key, bs, groups, best_us) &&
+      dslash_variant_ok(g->geom, bs, groups)) {
+    g->hop_block[prec] = bs;
+    g->hop_groups[prec] = groups;
+  } else {
+    const Geom &G = g->geom;
+    const size_t hb = half_bytes(G, prec);
+    const size_t V = 2 * (size_t)G.vh;
+    hipStream_t st = g->own_stream;
+    void *in = nullptr, *ref = nullptr, *cand = nullptr, *canon = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    wd_status rc = WD_OK;
+    std::vector<unsigned char> h_ref(hb), h_cand(hb);
+    do {
+      if ((rc = hip_check(hipMalloc(&in, hb), "tune alloc")) != WD_OK) break;
+      if ((rc = hip_check(hipMalloc(&ref, hb), "tune alloc")) != WD_OK) break;
+      if ((rc = hip_check(hipMalloc(&cand, hb), "tune alloc")) != WD_OK) break;
+      if ((rc = hip_check(hipMalloc(&canon, V * 24 * sizeof(double)), "tune alloc")) != WD_OK) break;
+      {
+        // deterministic input: a simple integer hash mapped to [-1, 1)
+        std::vector<double> h(V * 24);
+        uint64_t s = 0x9E3779B97F4A7C15ull;
+        for (size_t n = 0; n < h.size(); ++n) {
+          s ^= s << 13; s ^= s >> 7; s ^= s << 17;
+          h[n] = (double)(s >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+        }
+        if ((rc = hip_check(hipMemcpy(canon, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice),
+                            "tune upload")) != WD_OK)
+          break;
+      }
+      if ((rc = launch_pack_spinor(g, canon, in, WD_ODD, prec, st)) != WD_OK) break;
+      if ((rc = hip_check(hipEventCreate(&e0), "event")) != WD_OK) break;
+      if ((rc = hip_check(hipEventCreate(&e1), "event")) != WD_OK) break;
+      const int save_b = g->hop_block[prec], save_g = g->hop_groups[prec];
+      DslashArgs a;
+      a.in = in; a.a = 1.0; a.parity = WD_EVEN;
+      // reference variant
+      g->hop_block[prec] = 256; g->hop_groups[prec] = 0;
+      a.out = ref;
+      if ((rc = launch_dslash(g, prec, a, st)) != WD_OK) break;
+      if ((rc = hip_check(hipMemcpyAsync(h_ref.data(), ref, hb, hipMemcpyDeviceToHost, st), "copy")) != WD_OK) break;
+      if ((rc = hip_check(hipStreamSynchronize(st), "sync")) != WD_OK) break;
+      const int blocks[] = {64, 128, 256, 512};
+      const int grps[] = {0, 2, 4, 8, 16, 32};
+      best_us = 1e30;
+      int nbest_b = 256, nbest_g = 0;
+      for (int b : blocks) {
+        for (int gr : grps) {
+          if (!dslash_variant_ok(G, b, gr)) continue;
+          g->hop_block[prec] = b; g->hop_groups[prec] = gr;
+          if ((rc = launch_pack_spinor(g, canon, in, WD_ODD, prec, st)) != WD_OK) break;
+          a.out = cand;
+          if ((rc = hip_check(hipMemsetAsync(cand, 0xff, hb, st), "memset")) != WD_OK) break;
+          if ((rc = launch_dslash(g, prec, a, st)) != WD_OK) break;
+          if ((rc = hip_check(hipMemcpyAsync(h_cand.data(), cand, hb, hipMemcpyDeviceToHost, st), "copy")) != WD_OK)
+            break;
+          if ((rc = hip_check(hipStreamSynchronize(st), "sync")) != WD_OK) break;
+          if (memcmp(h_ref.data(), h_cand.data(), hb) != 0) continue;  // parity first
+          // time the pattern of a solver: even and odd hops alternate, so the
+          // two parities' link arrays stream through the caches in turn
+          const int reps = 6;
+          DslashArgs b2 = a;
+          b2.in = cand; b2.out = in; b2.parity = WD_ODD;
+          auto pair = [&]() { (void)launch_dslash(g, prec, a, st); (void)launch_dslash(g, prec, b2, st); };
+          for (int w = 0; w < 2; ++w) pair();
+          (void)hipEventRecord(e0, st);
+          for (int r = 0; r < reps; ++r) pair();
+          (void)hipEventRecord(e1, st);
+          if ((rc = hip_check(hipEventSynchronize(e1), "tune timing")) != WD_OK) break;
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          const double us = 1e3 * ms / (2 * reps);
+          if (getenv("WD_TUNE_VERBOSE")) fprintf(stderr, "tune %s: block %d groups %d: %.2f us\n", key.c_str(), b, gr, us);
+          if (us < best_us) { best_us = us; nbest_b = b; nbest_g = gr; }
+        }
+        if (rc != WD_OK) break;
+      }
+      if (rc != WD_OK) { g->hop_block[prec] = save_b; g->hop_groups[prec] = save_g; break; }
+      g->hop_block[prec] = nbest_b;
+      g->hop_groups[prec] = nbest_g;
+      bs = nbest_b; groups = nbest_g;
+      if (cache_path) cache_append(cache_path, key, bs, groups, best_us);
+    } while (0);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (in) (void)hipFree(in);
+    if (ref) (void)hipFree(ref);
+    if (cand) (void)hipFree(cand);
+    if (canon) (void)hipFree(canon);
+    if (rc != WD_OK) return rc;
+  }
+  if (out_block) *out_block = bs;
+  if (out_groups) *out_groups = groups;
+  if (out_us) *out_us = best_us;
+  return WD_OK;
+}
+
+}  // extern "C"

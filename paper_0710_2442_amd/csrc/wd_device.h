@@ -202,30 +202,39 @@ struct Spinor<WD_BF16> {
 
 // ------------------------------------------------------ compressed links
 // A hop link is stored as its rows 0 and 1 (6 complex = 12 reals); row 2 is
-// conj(row0 x row1).  Double: 6 planes of v2d; float: 3 planes of v4f.
+// conj(row0 x row1).  double: 6 packets of v2d; float: 3 packets of v4f.
+//
+// Layout of one output parity's hop links (chunks of 64 sites = one wave):
+//   packet (hop d, k, site i) at ((i / 64) * 8 + d) * NP * 64 + k * 64 + i % 64
+// so a wave's 8 x NP link loads read one contiguous block of 8*NP KiB.
+template <int NP>
+__device__ __forceinline__ size_t link_packet(int d, int k, size_t i) {
+  return (((i >> 6) * 8 + (size_t)d) * NP + (size_t)k) * 64 + (i & 63);
+}
+
 template <class R>
 struct Link;
 
 template <>
 struct Link<double> {
-  static constexpr int planes = 6;
-  __device__ static void load(const void *base, size_t vp, size_t i, cplx<double> (&u)[6]) {
-    const v2d *p = (const v2d *)base + i;
+  static constexpr int NP = 6;
+  __device__ static void load(const void *base, int d, size_t i, cplx<double> (&u)[6]) {
+    const v2d *p = (const v2d *)base;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      v2d v = ld_stream(p + k * vp);
+      v2d v = ld_stream(p + link_packet<6>(d, k, i));
       u[k] = {v.x, v.y};
     }
   }
 };
 template <>
 struct Link<float> {
-  static constexpr int planes = 3;
-  __device__ static void load(const void *base, size_t vp, size_t i, cplx<float> (&u)[6]) {
-    const v4f *p = (const v4f *)base + i;
+  static constexpr int NP = 3;
+  __device__ static void load(const void *base, int d, size_t i, cplx<float> (&u)[6]) {
+    const v4f *p = (const v4f *)base;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      v4f v = ld_stream(p + k * vp);
+      v4f v = ld_stream(p + link_packet<3>(d, k, i));
       u[2 * k] = {v.x, v.y};
       u[2 * k + 1] = {v.z, v.w};
     }
@@ -322,29 +331,12 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sum of v over the block, valid in thread 0.  Fixed order.
-template <int BS>
-__device__ __forceinline__ double block_sum(double v) {
-  static_assert(BS % 64 == 0 && BS <= 1024, "block size");
-  __shared__ double red[BS / 64];
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) red[w] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < BS / 64; ++k) t += red[k];
-  }
-  __syncthreads();
-  return t;
-}
-
-template <int BS, int N>
+// Sums over the block (blockDim.x a multiple of 64, at most 1024), valid in
+// thread 0.  Fixed order: wave sums, then waves in index order.
+template <int N>
 __device__ __forceinline__ void block_sum_n(double (&v)[N]) {
-  static_assert(BS % 64 == 0 && BS <= 1024, "block size");
-  __shared__ double red[N][BS / 64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __shared__ double red[N][16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     double s = wave_sum(v[j]);
@@ -355,8 +347,7 @@ __device__ __forceinline__ void block_sum_n(double (&v)[N]) {
 #pragma unroll
     for (int j = 0; j < N; ++j) {
       double t = 0.0;
-#pragma unroll
-      for (int k = 0; k < BS / 64; ++k) t += red[j][k];
+      for (int k = 0; k < nw; ++k) t += red[j][k];
       v[j] = t;
     }
   }
@@ -367,10 +358,10 @@ __device__ __forceinline__ void block_sum_n(double (&v)[N]) {
 // last adds all partials in index order (deterministic whichever block that
 // is), writes the totals and re-arms the counter.  Returns true in thread 0 of
 // the last block, with the totals in `tot`.
-template <int BS, int N>
+template <int N>
 __device__ __forceinline__ bool grid_sum_last(double (&v)[N], double *partials, unsigned *counter,
                                               unsigned nblocks, unsigned bid, double (&tot)[N]) {
-  block_sum_n<BS, N>(v);
+  block_sum_n<N>(v);
   __shared__ int is_last;
   if (threadIdx.x == 0) {
 #pragma unroll
@@ -388,12 +379,12 @@ __device__ __forceinline__ bool grid_sum_last(double (&v)[N], double *partials, 
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     double s = 0.0;
-    for (unsigned b = threadIdx.x; b < nblocks; b += BS)
+    for (unsigned b = threadIdx.x; b < nblocks; b += blockDim.x)
       s += __hip_atomic_load(&partials[(size_t)j * nblocks + b], __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
     acc[j] = s;
   }
-  block_sum_n<BS, N>(acc);
+  block_sum_n<N>(acc);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int j = 0; j < N; ++j) tot[j] = acc[j];

@@ -50,10 +50,11 @@ inline size_t half_bytes(const Geom &g, wd_prec p) { return slot_bytes(p) * (siz
 // Hop-link arrays: for output parity p and hop d (0..3 forward along x1..x4,
 // 4..7 backward), the 3x3 matrix that multiplies the projected neighbour
 // (U_{x,mu} forward, U^dag_{x-mu,mu} backward) stored at the output site's
-// checkerboard index as rows 0,1.  double: [2][8][6 planes double2][vpad];
-// float: [2][8][3 planes float4][vpad].
-inline size_t link_bytes(const Geom &g, bool dbl) { return (size_t)2 * 8 * 6 * 16 * g.vpad / (dbl ? 1 : 2); }
-inline size_t link_hop_stride_bytes(const Geom &g, bool dbl) { return (size_t)6 * 16 * g.vpad / (dbl ? 1 : 2); }
+// checkerboard index as rows 0,1 -- 6 packets of 16 bytes (double) or 3
+// (float) per hop.  Per parity the packets are grouped by chunks of 64 sites
+// (see link_packet in wd_device.h); the two parities follow each other.
+inline size_t link_parity_bytes(const Geom &g, bool dbl) { return (size_t)8 * 6 * 16 * g.vpad / (dbl ? 1 : 2); }
+inline size_t link_bytes(const Geom &g, bool dbl) { return 2 * link_parity_bytes(g, dbl); }
 
 struct Workspace;  // solver vectors and scalars (solver.hip)
 
@@ -69,6 +70,8 @@ struct wd_gauge {
   hipStream_t own_stream;  // library stream for synchronous solves (default priority)
   void *links64;
   void *links32;
+  int hop_block[4];        // per precision: block size of the single-RHS hop
+  int hop_groups[4];       // per precision: XCD region groups (0 = linear order)
   double *scratch_red;     // reduction partials / scalars for the BLAS entry points
   unsigned *scratch_cnt;
   wd::Workspace *ws;
@@ -121,6 +124,7 @@ struct DslashArgs {
   RedBuf red{nullptr, nullptr};
 };
 unsigned dslash_grid_blocks(const wd_gauge *g);
+bool dslash_variant_ok(const Geom &G, int bs, int groups);
 // grid.x of the multi-RHS hop (16 sites per block)
 inline size_t mrhs_grid_blocks(const wd_gauge *g) { return ((size_t)g->geom.vpad + 15) / 16; }
 wd_status launch_dslash(const wd_gauge *g, wd_prec prec, const DslashArgs &args, hipStream_t st);

@@ -231,3 +231,32 @@ def test_full_size_plane_wave():
     want = free_field.plane_wave(dims, p, free_field.symbol(p, 0.124) @ u)
     assert rel_err(got, want) <= 1e-13
     g.close()
+
+
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (16, 16, 16, 16), (6, 4, 6, 10)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_every_hop_variant_is_bitwise_identical(dims, prec):
+    """Block size and XCD-region order change only the schedule, never a result bit."""
+    U, psi, _, _ = _inputs(dims, prec, seed=15)
+    g = wd.Gauge(U, dims, -1, prec)
+    src = to_field(g, psi, prec, wd.WD_ODD)
+    ref = wd.wd_new_field(dims, prec, 1, wd.WD_EVEN)
+    wd.wd_set_dslash_variant(g, prec, 256, 0)
+    wd.wd_dslash_ex(g, src, ref, 0.9, wd.WD_EVEN, prec)
+    n = 0
+    for bs in (64, 128, 256, 512):
+        for groups in (0, 2, 4, 8, 16):
+            try:
+                wd.wd_set_dslash_variant(g, prec, bs, groups)
+            except wd.WdError:
+                continue
+            out = wd.wd_new_field(dims, prec, 1, wd.WD_EVEN)
+            out.fill_(0xAB)
+            wd.wd_dslash_ex(g, src, out, 0.9, wd.WD_EVEN, prec)
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref), (bs, groups)
+            n += 1
+    assert n >= 4
+    b, gr, us = wd.wd_tune_dslash(g, prec)
+    assert wd.wd_get_dslash_variant(g, prec) == (b, gr) and us > 0
+    g.close()

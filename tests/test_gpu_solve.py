@@ -1,0 +1,135 @@
+"""GPU solves against the oracle.
+
+Many x are correct: a solve passes when the oracle's own D_W applied to the
+GPU solution gives |b - D x|/|b| <= 1e-10 (the FP64 true residual the library
+reports must agree with it), and when the solution agrees with the oracle's
+(or the exact free-field) solution within cond(D) * tol.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_0710_2442_amd as wd
+import synthetic as syn
+from gpu_util import from_field, rel_err, to_field
+from oracle import free_field, solvers, wilson
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _solve(dims, kappa, eps, seed, **kw):
+    U = syn.gauge_field(dims, eps, 1000 + seed)
+    b = syn.gaussian_spinor(dims, 2000 + seed)
+    g = wd.Gauge(U, dims, -1, "f64")
+    fb = to_field(g, b)
+    fx = wd.wd_new_field(dims, "f64")
+    p = wd.wd_solve_params_default(**kw)
+    rc, info = wd.wd_solve(g, fb, fx, kappa, TOL, p)
+    x = from_field(g, fx)
+    g.close()
+    return U, b, x, rc, info
+
+
+def test_fp64_cg_8x4_matches_oracle():
+    """Plain FP64 Wilson-Dirac on 8^4, kappa = 0.12: CG on D^dag D to 1e-10."""
+    dims, kappa = (8, 8, 8, 8), 0.12
+    U, b, x, rc, info = _solve(dims, kappa, 0.3, 1, solver=wd.WD_SOLVER_CG)
+    print("info", info, flush=True)
+    assert rc == 0
+    r_oracle = solvers.true_residual(U, b, x, kappa)
+    assert r_oracle <= TOL
+    assert abs(r_oracle - info["true_rel_resid"]) <= 1e-3 * TOL
+    xo, it_o, _ = solvers.solve_eo_cgls(U, b, kappa, 1e-12)
+    assert rel_err(x, xo) <= 1e-7  # cond(D) ~ 20 here
+    # the GPU iteration count matches the oracle's eo-CGLS to within a few
+    _, it_o10, _ = solvers.solve_eo_cgls(U, b, kappa, TOL)
+    assert abs(info["iters"] - it_o10) <= 3, (info["iters"], it_o10)
+
+
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_fp64_cg_graph_and_eager_agree(use_graph):
+    dims, kappa = (6, 4, 6, 10), 0.124
+    U, b, x, rc, info = _solve(dims, kappa, 0.3, 2, solver=wd.WD_SOLVER_CG, use_graph=use_graph,
+                               check_every=4)
+    assert rc == 0 and solvers.true_residual(U, b, x, kappa) <= TOL
+
+
+def test_graph_replays_bitwise_equal_to_eager():
+    dims, kappa = (6, 4, 6, 10), 0.124
+    outs = []
+    for ug in (0, 1, 1):
+        _, _, x, rc, info = _solve(dims, kappa, 0.3, 3, solver=wd.WD_SOLVER_CG, use_graph=ug, check_every=8)
+        outs.append((x, info["iters"]))
+    assert outs[0][1] == outs[1][1] == outs[2][1]
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[1][0], outs[2][0])
+
+
+@pytest.mark.parametrize("prec,inner_tol", [("f32", 1e-4), ("f16", 1e-2), ("bf16", 1e-2)])
+def test_defect_correction_reaches_fp64_residual(prec, inner_tol):
+    dims, kappa = (8, 8, 8, 8), 0.124
+    U, b, x, rc, info = _solve(dims, kappa, 0.3, 4, solver=wd.WD_SOLVER_DEFECT_CG, inner_prec=prec,
+                               inner_tol=inner_tol)
+    print(prec, info, flush=True)
+    assert rc == 0
+    r = solvers.true_residual(U, b, x, kappa)
+    assert r <= TOL
+    assert info["outer_iters"] >= 2
+    xo, _, _ = solvers.solve_eo_cgls(U, b, kappa, 1e-12)
+    assert rel_err(x, xo) <= 1e-6
+
+
+def test_zero_source_and_kappa_zero():
+    dims = (4, 4, 4, 4)
+    U = syn.gauge_field(dims, 0.3, 5)
+    g = wd.Gauge(U, dims, -1, "f64")
+    fb = to_field(g, np.zeros(syn.lattice_shape(dims) + (4, 3), complex))
+    fx = wd.wd_new_field(dims, "f64")
+    rc, info = wd.wd_solve(g, fb, fx, 0.12, TOL)
+    assert rc == 0 and np.all(from_field(g, fx) == 0)
+    b = syn.gaussian_spinor(dims, 6)
+    fb = to_field(g, b)
+    rc, info = wd.wd_solve(g, fb, fx, 0.0, TOL)
+    assert rc == 0 and rel_err(from_field(g, fx), b) < 1e-15
+    g.close()
+
+
+def test_nonfinite_source_is_rejected():
+    dims = (4, 4, 4, 4)
+    g = wd.Gauge(syn.gauge_field(dims, 0.3, 7), dims, -1, "f64")
+    b = syn.gaussian_spinor(dims, 8)
+    b[0, 0, 0, 0, 0, 0] = np.nan
+    fb = to_field(g, b)
+    fx = wd.wd_new_field(dims, "f64")
+    with pytest.raises(wd.WdError) as e:
+        wd.wd_solve(g, fb, fx, 0.12, TOL)
+    assert e.value.status == -4
+    g.close()
+
+
+def test_iteration_cap_reports_not_converged():
+    dims, kappa = (8, 8, 8, 8), 0.124
+    U, b, x, rc, info = _solve(dims, kappa, 0.3, 9, solver=wd.WD_SOLVER_CG, max_iter=5)
+    assert rc == 1 and info["iters"] <= 6
+    assert info["true_rel_resid"] > TOL
+    # x is still the reported iterate: its residual matches the oracle's
+    assert abs(solvers.true_residual(U, b, x, kappa) - info["true_rel_resid"]) <= 1e-8
+
+
+def test_free_field_solve_matches_fft_16x4():
+    dims, kappa = (16, 16, 16, 16), 0.124
+    U = syn.unit_gauge(dims)
+    b = syn.gaussian_spinor(dims, 10)
+    g = wd.Gauge(U, dims, -1, "f64")
+    fb = to_field(g, b)
+    fx = wd.wd_new_field(dims, "f64")
+    for kw in (dict(solver=wd.WD_SOLVER_CG),
+               dict(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec="f16", inner_tol=1e-2)):
+        rc, info = wd.wd_solve(g, fb, fx, kappa, TOL, wd.wd_solve_params_default(**kw))
+        x = from_field(g, fx)
+        xs = free_field.solve(b, kappa)
+        assert rc == 0
+        # cond(D) of the free operator on 16^4 at kappa = 0.124 is ~ 50
+        assert rel_err(x, xs) <= 50 * TOL * 10, rel_err(x, xs)
+    g.close()
