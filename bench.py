@@ -169,7 +169,7 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the default hop variant")
-    ap.add_argument("--variant", default=None, help="force the hop variant 'block,groups' (no tuning)")
+    ap.add_argument("--variant", default=None, help="force the hop variant 'block,groups,occ' (no tuning)")
     ap.add_argument("--only", choices=["f64", "f32"], default=None, help="time one precision only")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
@@ -199,11 +199,11 @@ def main():
     for prec in precs:
         g = wd.Gauge(U, DIMS, -1, prec)
         if args.variant:
-            vb, vg = (int(x) for x in args.variant.split(","))
-            wd.wd_set_dslash_variant(g, prec, vb, vg)
+            vb, vg, vo = (int(x) for x in args.variant.split(","))
+            wd.wd_set_dslash_variant(g, prec, vb, vg, vo)
         elif not args.no_tune:
-            tb, tg, tus = wd.wd_tune_dslash(g, prec)
-            log(f"tuned hop {prec}: block {tb}, XCD groups {tg} ({tus:.1f} us in the tuner)")
+            tb, tg, to, tus = wd.wd_tune_dslash(g, prec)
+            log(f"tuned hop {prec}: block {tb}, XCD groups {tg}, occ {to} ({tus:.1f} us in the tuner)")
         sec, n, ms = time_hop(wd, torch, g, psi, prec, args.steps, args.warmup)
         gbs = vh * BYTES_PER_SITE[prec] / sec / 1e9
         results[prec] = {"sec_per_launch": sec, "gbs": gbs, "ms_total": ms, "launches": n,
@@ -234,7 +234,7 @@ def main():
         "kernel": f"k_dslash<{head}> single-parity hop, 32^3x64, 1,048,576 output sites per launch",
         "algorithmic_bytes_per_launch": vh * BYTES_PER_SITE[head],
         "avg_launch_us": round(r["sec_per_launch"] * 1e6, 2),
-        "variant_block_groups": r["variant"],
+        "variant_block_groups_occ": r["variant"],
     }
     if traffic is None:
         roof["traffic_note"] = why

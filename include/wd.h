@@ -197,22 +197,27 @@ wd_status wd_solve_mrhs(const wd_gauge *U, const void *b, void *x, int nrhs,
 /* --------------------------------------------------------------- tuning -- */
 
 /* Autotune the single-RHS hop of precision prec on this handle's lattice:
- * block size (64..512 threads) and the number of XCD regions the blocks are
- * grouped into (0 = linear order).  Every candidate's output is first compared
- * byte for byte with the reference variant (256 threads, linear); matching
- * candidates are timed with HIP events and the fastest is kept in the handle.
+ * block size (64..512 threads), the number of XCD regions the blocks are
+ * grouped into (0 = linear order) and the register budget (occ 0: compiler's
+ * choice; occ 4: at least 4 waves per SIMD).  Every candidate's output is
+ * first compared byte for byte with the reference variant (256 threads,
+ * linear, occ 0); matching candidates are timed with HIP events on
+ * alternating even/odd hops and the fastest is kept in the handle.
  * cache_path (may be NULL): JSON-lines file keyed by (arch, kernel, precision,
  * lattice); an existing entry is used without timing unless force != 0, and
- * new results are appended.  Outputs (may be NULL): chosen block, groups and
- * time per launch in microseconds (-1 if taken from the cache).  Synchronous. */
+ * new results are appended.  Outputs (may be NULL): the chosen variant and
+ * its time per launch in microseconds (-1 if taken from the cache).
+ * Synchronous. */
 wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path,
-                         int force, int *block, int *groups, double *us);
+                         int force, int *block, int *groups, int *occ,
+                         double *us);
 
 /* Set / read the hop variant used for precision prec.  WD_ERR_ARG if the
  * variant does not fit the lattice (see wd_tune_dslash). */
-wd_status wd_set_dslash_variant(wd_gauge *g, wd_prec prec, int block, int groups);
+wd_status wd_set_dslash_variant(wd_gauge *g, wd_prec prec, int block, int groups,
+                                int occ);
 wd_status wd_get_dslash_variant(const wd_gauge *g, wd_prec prec, int *block,
-                                int *groups);
+                                int *groups, int *occ);
 
 /* --------------------------------------------------------------- misc --- */
 

@@ -85,9 +85,9 @@ _decl("wd_solve", C.c_int, [_vp, _vp, _vp, C.c_double, C.c_double, C.POINTER(wd_
 _decl("wd_solve_mrhs", C.c_int, [_vp, _vp, _vp, C.c_int, C.c_double, C.c_double,
                                   C.POINTER(wd_solve_params), C.POINTER(wd_solve_info)])
 _decl("wd_tune_dslash", C.c_int, [_vp, C.c_int, C.c_char_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
-                                   C.POINTER(C.c_double)])
-_decl("wd_set_dslash_variant", C.c_int, [_vp, C.c_int, C.c_int, C.c_int])
-_decl("wd_get_dslash_variant", C.c_int, [_vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)])
+                                   C.POINTER(C.c_int), C.POINTER(C.c_double)])
+_decl("wd_set_dslash_variant", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int])
+_decl("wd_get_dslash_variant", C.c_int, [_vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)])
 _decl("wd_status_string", C.c_char_p, [C.c_int])
 _decl("wd_last_error", C.c_char_p, [])
 
@@ -272,20 +272,22 @@ def wd_solve_mrhs(g, b, x, nrhs, kappa, tol, params):
 
 
 def wd_tune_dslash(g, prec, cache_path=None, force=False):
-    """Autotune the hop variant; returns (block, groups, microseconds per launch)."""
+    """Autotune the hop variant; returns (block, groups, occ, microseconds per launch)."""
     g.sync_stream()
-    b, gr, us = C.c_int(), C.c_int(), C.c_double()
+    b, gr, oc, us = C.c_int(), C.c_int(), C.c_int(), C.c_double()
     cp = cache_path.encode() if cache_path else None
-    _check(lib.wd_tune_dslash(g.handle, _prec(prec), cp, int(force), C.byref(b), C.byref(gr), C.byref(us)),
-           "wd_tune_dslash")
-    return b.value, gr.value, us.value
+    _check(lib.wd_tune_dslash(g.handle, _prec(prec), cp, int(force), C.byref(b), C.byref(gr), C.byref(oc),
+                              C.byref(us)), "wd_tune_dslash")
+    return b.value, gr.value, oc.value, us.value
 
 
-def wd_set_dslash_variant(g, prec, block, groups):
-    _check(lib.wd_set_dslash_variant(g.handle, _prec(prec), int(block), int(groups)), "wd_set_dslash_variant")
+def wd_set_dslash_variant(g, prec, block, groups, occ=0):
+    _check(lib.wd_set_dslash_variant(g.handle, _prec(prec), int(block), int(groups), int(occ)),
+           "wd_set_dslash_variant")
 
 
 def wd_get_dslash_variant(g, prec):
-    b, gr = C.c_int(), C.c_int()
-    _check(lib.wd_get_dslash_variant(g.handle, _prec(prec), C.byref(b), C.byref(gr)), "wd_get_dslash_variant")
-    return b.value, gr.value
+    b, gr, oc = C.c_int(), C.c_int(), C.c_int()
+    _check(lib.wd_get_dslash_variant(g.handle, _prec(prec), C.byref(b), C.byref(gr), C.byref(oc)),
+           "wd_get_dslash_variant")
+    return b.value, gr.value, oc.value

@@ -104,6 +104,7 @@ wd_status wd_gauge_create(const double *U_host, const int dims[4], int t_bc, wd_
     // default hop variant: 256 threads, eight XCD regions when the lattice allows
     g->hop_block[p] = 256;
     g->hop_groups[p] = dslash_variant_ok(g->geom, 256, 8) ? 8 : 0;
+    g->hop_occ[p] = 0;
   }
   wd_status rc = WD_OK;
   void *canon = nullptr;

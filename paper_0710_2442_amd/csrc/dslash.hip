@@ -40,6 +40,7 @@ struct KDslash {
   // block -> tile mapping (see tile_of)
   int groups;           // 0: linear; G > 0: G contiguous regions per time slice
   int tiles_per_slice;  // tiles (blocks) per time slice of one parity
+  int occ;              // register-budget variant (0 or 4), host side only
 };
 
 // Workgroups are dispatched round-robin over the XCDs (8 on MI355X), each
@@ -147,8 +148,16 @@ __device__ __forceinline__ void hop_all(const KDslash &k, int i, cplx<RealOf<P>>
 }
 
 // EPI: 0 -> out = a H in;  1 -> out = X + a H in;  2 -> out = X - Y + a H in
+// OCC > 0 asks the compiler for at least OCC waves per SIMD (fewer registers,
+// possibly a few spills); OCC = 0 leaves the register budget to the compiler.
+#define WD_OCC_KERNEL(OCCV, ATTR)                                                   \
+  template <int P, bool DAG, int EPI, bool NORM>                                  \
+  __global__ __launch_bounds__(512) ATTR void k_dslash_o##OCCV(KDslash k) {     \
+    dslash_body<P, DAG, EPI, NORM>(k);                                            \
+  }
+
 template <int P, bool DAG, int EPI, bool NORM>
-__global__ __launch_bounds__(512) void k_dslash(KDslash k) {
+__device__ __forceinline__ void dslash_body(const KDslash &k) {
   using T = RealOf<P>;
   if (k.skip && *k.skip) return;
   const int i = tile_of(k) * (int)blockDim.x + (int)threadIdx.x;
@@ -198,6 +207,9 @@ __global__ __launch_bounds__(512) void k_dslash(KDslash k) {
     }
   }
 }
+
+WD_OCC_KERNEL(0, )
+WD_OCC_KERNEL(4, __attribute__((amdgpu_waves_per_eu(4))))
 
 // ---------------------------------------------------------------- mrhs
 // Lanes of a wave cover 16 sites x 4 right-hand sides (lane = site + 16*rhs),
@@ -312,7 +324,8 @@ static KDslash make_k(const wd_gauge *g, wd_prec prec, int parity) {
 
 template <int P, bool DAG, int EPI, bool NORM>
 static void launch_t(const KDslash &k, unsigned nblk, unsigned bs, hipStream_t st) {
-  hipLaunchKernelGGL((k_dslash<P, DAG, EPI, NORM>), dim3(nblk), dim3(bs), 0, st, k);
+  if (k.occ == 4) hipLaunchKernelGGL((k_dslash_o4<P, DAG, EPI, NORM>), dim3(nblk), dim3(bs), 0, st, k);
+  else hipLaunchKernelGGL((k_dslash_o0<P, DAG, EPI, NORM>), dim3(nblk), dim3(bs), 0, st, k);
 }
 
 template <int P, bool DAG>
@@ -370,6 +383,7 @@ wd_status launch_dslash(const wd_gauge *g, wd_prec prec, const DslashArgs &a, hi
   int bs = g->hop_block[pi], groups = g->hop_groups[pi];
   if (!dslash_variant_ok(g->geom, bs, groups)) { bs = 256; groups = 0; }
   k.groups = groups;
+  k.occ = g->hop_occ[pi];
   k.tiles_per_slice = groups ? (int)((long)g->geom.vh / g->geom.L[3] / bs) : 0;
   const unsigned nblk = (unsigned)((g->geom.vpad + bs - 1) / bs);
   switch (prec) {

@@ -31,28 +31,30 @@ static std::string tune_key(const wd_gauge *g, wd_prec prec) {
   return buf;
 }
 
-static bool cache_lookup(const char *path, const std::string &key, int &bs, int &groups, double &us) {
+static bool cache_lookup(const char *path, const std::string &key, int &bs, int &groups, int &occ, double &us) {
   FILE *f = fopen(path, "r");
   if (!f) return false;
   char line[512];
   bool found = false;
   while (fgets(line, sizeof line, f)) {
     char k[200];
-    int b, gr;
+    int b, gr, oc;
     double t;
-    if (sscanf(line, " {\"key\": \"%199[^\"]\", \"block\": %d, \"groups\": %d, \"us\": %lf", k, &b, &gr, &t) == 4 &&
+    if (sscanf(line, " {\"key\": \"%199[^\"]\", \"block\": %d, \"groups\": %d, \"occ\": %d, \"us\": %lf", k, &b,
+               &gr, &oc, &t) == 5 &&
         key == k) {
-      bs = b; groups = gr; us = t; found = true;  // last entry wins
+      bs = b; groups = gr; occ = oc; us = t; found = true;  // last entry wins
     }
   }
   fclose(f);
   return found;
 }
 
-static void cache_append(const char *path, const std::string &key, int bs, int groups, double us) {
+static void cache_append(const char *path, const std::string &key, int bs, int groups, int occ, double us) {
   FILE *f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "{\"key\": \"%s\", \"block\": %d, \"groups\": %d, \"us\": %.3f}\n", key.c_str(), bs, groups, us);
+  fprintf(f, "{\"key\": \"%s\", \"block\": %d, \"groups\": %d, \"occ\": %d, \"us\": %.3f}\n", key.c_str(), bs,
+          groups, occ, us);
   fclose(f);
 }
 
@@ -62,36 +64,40 @@ using namespace wd;
 
 extern "C" {
 
-wd_status wd_set_dslash_variant(wd_gauge *g, wd_prec prec, int block, int groups) {
+wd_status wd_set_dslash_variant(wd_gauge *g, wd_prec prec, int block, int groups, int occ) {
   if (!g) return set_error(WD_ERR_ARG, "gauge handle is NULL");
   if ((int)prec < 0 || (int)prec > 3) return set_error(WD_ERR_PREC, "prec = %d", (int)prec);
   if (!dslash_variant_ok(g->geom, block, groups))
     return set_error(WD_ERR_ARG, "variant (block %d, groups %d) does not fit this lattice", block, groups);
+  if (occ != 0 && occ != 4) return set_error(WD_ERR_ARG, "occ = %d: must be 0 or 4", occ);
   g->hop_block[prec] = block;
   g->hop_groups[prec] = groups;
+  g->hop_occ[prec] = occ;
   return WD_OK;
 }
 
-wd_status wd_get_dslash_variant(const wd_gauge *g, wd_prec prec, int *block, int *groups) {
-  if (!g || !block || !groups) return set_error(WD_ERR_ARG, "NULL argument");
+wd_status wd_get_dslash_variant(const wd_gauge *g, wd_prec prec, int *block, int *groups, int *occ) {
+  if (!g || !block || !groups || !occ) return set_error(WD_ERR_ARG, "NULL argument");
   if ((int)prec < 0 || (int)prec > 3) return set_error(WD_ERR_PREC, "prec = %d", (int)prec);
   *block = g->hop_block[prec];
   *groups = g->hop_groups[prec];
+  *occ = g->hop_occ[prec];
   return WD_OK;
 }
 
 wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int force, int *out_block,
-                         int *out_groups, double *out_us) {
+                         int *out_groups, int *out_occ, double *out_us) {
   if (!g) return set_error(WD_ERR_ARG, "gauge handle is NULL");
   if ((int)prec < 0 || (int)prec > 3) return set_error(WD_ERR_PREC, "prec = %d", (int)prec);
   WD_HIP(hipSetDevice(g->device));
   const std::string key = tune_key(g, prec);
-  int bs = 256, groups = 0;
+  int bs = 256, groups = 0, occ = 0;
   double best_us = -1.0;
-  if (cache_path && !force && cache_lookup(cache_path, key, bs, groups, best_us) &&
-      dslash_variant_ok(g->geom, bs, groups)) {
+  if (cache_path && !force && cache_lookup(cache_path, key, bs, groups, occ, best_us) &&
+      dslash_variant_ok(g->geom, bs, groups) && (occ == 0 || occ == 4)) {
     g->hop_block[prec] = bs;
     g->hop_groups[prec] = groups;
+    g->hop_occ[prec] = occ;
   } else {
     const Geom &G = g->geom;
     const size_t hb = half_bytes(G, prec);
@@ -121,11 +127,11 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
       if ((rc = launch_pack_spinor(g, canon, in, WD_ODD, prec, st)) != WD_OK) break;
       if ((rc = hip_check(hipEventCreate(&e0), "event")) != WD_OK) break;
       if ((rc = hip_check(hipEventCreate(&e1), "event")) != WD_OK) break;
-      const int save_b = g->hop_block[prec], save_g = g->hop_groups[prec];
+      const int save_b = g->hop_block[prec], save_g = g->hop_groups[prec], save_o = g->hop_occ[prec];
       DslashArgs a;
       a.in = in; a.a = 1.0; a.parity = WD_EVEN;
       // reference variant
-      g->hop_block[prec] = 256; g->hop_groups[prec] = 0;
+      g->hop_block[prec] = 256; g->hop_groups[prec] = 0; g->hop_occ[prec] = 0;
       a.out = ref;
       if ((rc = launch_dslash(g, prec, a, st)) != WD_OK) break;
       if ((rc = hip_check(hipMemcpyAsync(h_ref.data(), ref, hb, hipMemcpyDeviceToHost, st), "copy")) != WD_OK) break;
@@ -133,11 +139,12 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
       const int blocks[] = {64, 128, 256, 512};
       const int grps[] = {0, 2, 4, 8, 16, 32};
       best_us = 1e30;
-      int nbest_b = 256, nbest_g = 0;
+      int nbest_b = 256, nbest_g = 0, nbest_o = 0;
+      for (int oc : {0, 4})
       for (int b : blocks) {
         for (int gr : grps) {
           if (!dslash_variant_ok(G, b, gr)) continue;
-          g->hop_block[prec] = b; g->hop_groups[prec] = gr;
+          g->hop_block[prec] = b; g->hop_groups[prec] = gr; g->hop_occ[prec] = oc;
           if ((rc = launch_pack_spinor(g, canon, in, WD_ODD, prec, st)) != WD_OK) break;
           a.out = cand;
           if ((rc = hip_check(hipMemsetAsync(cand, 0xff, hb, st), "memset")) != WD_OK) break;
@@ -160,16 +167,21 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
           float ms = 0.f;
           (void)hipEventElapsedTime(&ms, e0, e1);
           const double us = 1e3 * ms / (2 * reps);
-          if (getenv("WD_TUNE_VERBOSE")) fprintf(stderr, "tune %s: block %d groups %d: %.2f us\n", key.c_str(), b, gr, us);
-          if (us < best_us) { best_us = us; nbest_b = b; nbest_g = gr; }
+          if (getenv("WD_TUNE_VERBOSE"))
+            fprintf(stderr, "tune %s: block %d groups %d occ %d: %.2f us\n", key.c_str(), b, gr, oc, us);
+          if (us < best_us) { best_us = us; nbest_b = b; nbest_g = gr; nbest_o = oc; }
         }
         if (rc != WD_OK) break;
       }
-      if (rc != WD_OK) { g->hop_block[prec] = save_b; g->hop_groups[prec] = save_g; break; }
+      if (rc != WD_OK) {
+        g->hop_block[prec] = save_b; g->hop_groups[prec] = save_g; g->hop_occ[prec] = save_o;
+        break;
+      }
       g->hop_block[prec] = nbest_b;
       g->hop_groups[prec] = nbest_g;
-      bs = nbest_b; groups = nbest_g;
-      if (cache_path) cache_append(cache_path, key, bs, groups, best_us);
+      g->hop_occ[prec] = nbest_o;
+      bs = nbest_b; groups = nbest_g; occ = nbest_o;
+      if (cache_path) cache_append(cache_path, key, bs, groups, occ, best_us);
     } while (0);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -181,6 +193,7 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
   }
   if (out_block) *out_block = bs;
   if (out_groups) *out_groups = groups;
+  if (out_occ) *out_occ = occ;
   if (out_us) *out_us = best_us;
   return WD_OK;
 }

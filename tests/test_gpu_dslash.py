@@ -241,22 +241,21 @@ def test_every_hop_variant_is_bitwise_identical(dims, prec):
     g = wd.Gauge(U, dims, -1, prec)
     src = to_field(g, psi, prec, wd.WD_ODD)
     ref = wd.wd_new_field(dims, prec, 1, wd.WD_EVEN)
-    wd.wd_set_dslash_variant(g, prec, 256, 0)
+    wd.wd_set_dslash_variant(g, prec, 256, 0, 0)
     wd.wd_dslash_ex(g, src, ref, 0.9, wd.WD_EVEN, prec)
     n = 0
-    for bs in (64, 128, 256, 512):
-        for groups in (0, 2, 4, 8, 16):
+    for bs, groups, occ in [(b, gr, o) for b in (64, 128, 256, 512) for gr in (0, 2, 4, 8, 16) for o in (0, 4)]:
             try:
-                wd.wd_set_dslash_variant(g, prec, bs, groups)
+                wd.wd_set_dslash_variant(g, prec, bs, groups, occ)
             except wd.WdError:
                 continue
             out = wd.wd_new_field(dims, prec, 1, wd.WD_EVEN)
             out.fill_(0xAB)
             wd.wd_dslash_ex(g, src, out, 0.9, wd.WD_EVEN, prec)
             torch.cuda.synchronize()
-            assert torch.equal(out, ref), (bs, groups)
+            assert torch.equal(out, ref), (bs, groups, occ)
             n += 1
     assert n >= 4
-    b, gr, us = wd.wd_tune_dslash(g, prec)
-    assert wd.wd_get_dslash_variant(g, prec) == (b, gr) and us > 0
+    b, gr, oc, us = wd.wd_tune_dslash(g, prec)
+    assert wd.wd_get_dslash_variant(g, prec) == (b, gr, oc) and us > 0
     g.close()
