@@ -194,12 +194,45 @@ wd_status wd_solve_mrhs(const wd_gauge *U, const void *b, void *x, int nrhs,
                         double kappa, double tol, const wd_solve_params *p,
                         wd_solve_info *info);
 
+/* ------------------------------------------------- learned preconditioner -- */
+/* Gauge-covariant parallel-transport convolution network (not in the paper):
+ * two layers, 1 -> 2 -> 1 spinor channels,
+ *   y_{c'}(x) = sum_c sum_h W^{(h)}_{c'c} (T_h psi_c)(x),  h = 0..8,
+ * T_0 = 1, T_{+mu} psi(x) = U_{x,mu} psi(x+mu), T_{-mu} psi(x) =
+ * U^dag_{x-mu,mu} psi(x-mu) (h = 1..4: +x1..+x4, h = 5..8: -x1..-x4, with
+ * the time-boundary factor of Eq. 3); W^{(h)}_{c'c} is a complex 4x4 spin
+ * matrix.  No bias, no nonlinearity.
+ * Weights (host, 1152 floats): layer 1 [9][2][1][4][4] complex then layer 2
+ * [9][1][2][4][4] complex, each complex as (re, im), spin row major.
+ * Fields: FP32 full fields in the layout of wd.h.  act_prec (WD_BF16 or
+ * WD_F32) is the storage of the network input and hidden layer.  A network
+ * belongs to one gauge handle (its links and lattice) and runs on that
+ * handle's stream. */
+wd_status wd_ptc_create(const wd_gauge *g, const float *W_host, wd_prec act_prec,
+                        wd_ptc **out);
+wd_status wd_ptc_destroy(wd_ptc *n);
+/* replace the weights (resets the optimizer state) / read them back */
+wd_status wd_ptc_set_weights(wd_ptc *n, const float *W_host);
+wd_status wd_ptc_get_weights(const wd_ptc *n, float *W_host);
+/* out = N(in); asynchronous */
+wd_status wd_ptc_apply(const wd_ptc *n, const void *in, void *out);
+/* Loss L = (1/B) sum_b |N(r_b) - e_b|^2 over B pairs (r and e: B consecutive
+ * FP32 full fields each) and its gradient dL/dRe W + i dL/dIm W (1152 floats,
+ * host; may be NULL).  Synchronous. */
+wd_status wd_ptc_loss_grad(wd_ptc *n, const void *r, const void *e, int B,
+                           double *loss, float *grad_host);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the same loss; returns
+ * the loss before the step if loss != NULL (then synchronous). */
+wd_status wd_ptc_train_step(wd_ptc *n, const void *r, const void *e, int B,
+                            double lr, double *loss);
+
 /* --------------------------------------------------------------- tuning -- */
 
 /* Autotune the single-RHS hop of precision prec on this handle's lattice:
  * block size (64..512 threads), the number of XCD regions the blocks are
- * grouped into (0 = linear order) and the register budget (occ 0: compiler's
- * choice; occ 4: at least 4 waves per SIMD).  Every candidate's output is
+ * grouped into (0 = linear order), the register budget (occ 0: compiler's
+ * choice; occ 4: at least 4 waves per SIMD) and the output store policy
+ * (WD_TUNE_CACHED_STORE set in occ: cached stores).  Every candidate's output is
  * first compared byte for byte with the reference variant (256 threads,
  * linear, occ 0); matching candidates are timed with HIP events on
  * alternating even/odd hops and the fastest is kept in the handle.
@@ -212,8 +245,14 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path,
                          int force, int *block, int *groups, int *occ,
                          double *us);
 
-/* Set / read the hop variant used for precision prec.  WD_ERR_ARG if the
- * variant does not fit the lattice (see wd_tune_dslash). */
+/* Bit of the occ value: the hop writes its output with ordinary (cached)
+ * stores instead of streaming stores, so that a following kernel can read a
+ * freshly written field from the caches. */
+enum { WD_TUNE_CACHED_STORE = 256 };
+
+/* Set / read the hop variant used for precision prec.  occ: 0 or 4, or'ed
+ * with WD_TUNE_CACHED_STORE.  WD_ERR_ARG if the variant does not fit the
+ * lattice (see wd_tune_dslash). */
 wd_status wd_set_dslash_variant(wd_gauge *g, wd_prec prec, int block, int groups,
                                 int occ);
 wd_status wd_get_dslash_variant(const wd_gauge *g, wd_prec prec, int *block,

@@ -11,6 +11,7 @@ from ._lib import (  # noqa: F401
     LIB_PATH,
     WD_BF16,
     WD_DAGGER,
+    WD_TUNE_CACHED_STORE,
     WD_EVEN,
     WD_F16,
     WD_F32,
@@ -44,4 +45,13 @@ from ._lib import (  # noqa: F401
     wd_tune_dslash,
     wd_set_dslash_variant,
     wd_get_dslash_variant,
+    Ptc,
+    ptc_weights_to_flat,
+    ptc_flat_to_weights,
+    wd_ptc_create,
+    wd_ptc_set_weights,
+    wd_ptc_get_weights,
+    wd_ptc_apply,
+    wd_ptc_loss_grad,
+    wd_ptc_train_step,
 )

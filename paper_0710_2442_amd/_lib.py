@@ -24,6 +24,7 @@ WD_F64, WD_F32, WD_F16, WD_BF16 = 0, 1, 2, 3
 PRECS = {"f64": WD_F64, "f32": WD_F32, "f16": WD_F16, "bf16": WD_BF16}
 WD_EVEN, WD_ODD, WD_FULL = 0, 1, 2
 WD_DAGGER = 1
+WD_TUNE_CACHED_STORE = 256
 WD_SOLVER_CG, WD_SOLVER_DEFECT_CG, WD_SOLVER_FGCR = 0, 1, 2
 
 _vp = C.c_void_p
@@ -88,6 +89,13 @@ _decl("wd_tune_dslash", C.c_int, [_vp, C.c_int, C.c_char_p, C.c_int, C.POINTER(C
                                    C.POINTER(C.c_int), C.POINTER(C.c_double)])
 _decl("wd_set_dslash_variant", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int])
 _decl("wd_get_dslash_variant", C.c_int, [_vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)])
+_decl("wd_ptc_create", C.c_int, [_vp, C.POINTER(C.c_float), C.c_int, C.POINTER(_vp)])
+_decl("wd_ptc_destroy", C.c_int, [_vp])
+_decl("wd_ptc_set_weights", C.c_int, [_vp, C.POINTER(C.c_float)])
+_decl("wd_ptc_get_weights", C.c_int, [_vp, C.POINTER(C.c_float)])
+_decl("wd_ptc_apply", C.c_int, [_vp, _vp, _vp])
+_decl("wd_ptc_loss_grad", C.c_int, [_vp, _vp, _vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_float)])
+_decl("wd_ptc_train_step", C.c_int, [_vp, _vp, _vp, C.c_int, C.c_double, C.POINTER(C.c_double)])
 _decl("wd_status_string", C.c_char_p, [C.c_int])
 _decl("wd_last_error", C.c_char_p, [])
 
@@ -291,3 +299,80 @@ def wd_get_dslash_variant(g, prec):
     _check(lib.wd_get_dslash_variant(g.handle, _prec(prec), C.byref(b), C.byref(gr), C.byref(oc)),
            "wd_get_dslash_variant")
     return b.value, gr.value, oc.value
+
+
+def _fptr(a):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def ptc_weights_to_flat(W1, W2):
+    """Complex weight arrays (9,2,1,4,4) and (9,1,2,4,4) -> the 1152-float layout."""
+    w = np.concatenate([np.asarray(W1, np.complex64).ravel(), np.asarray(W2, np.complex64).ravel()])
+    return w.view(np.float32).copy()
+
+
+def ptc_flat_to_weights(flat):
+    c = np.asarray(flat, np.float32).view(np.complex64).astype(np.complex128)
+    return c[:288].reshape(9, 2, 1, 4, 4), c[288:].reshape(9, 1, 2, 4, 4)
+
+
+class Ptc:
+    """Owning wrapper of a wd_ptc network handle."""
+
+    def __init__(self, g, flat_weights, act_prec="bf16"):
+        self.g = g
+        a, p = _fptr(flat_weights)
+        if a.size != 1152:
+            raise ValueError("PTC weights: 1152 floats expected")
+        h = C.c_void_p()
+        _check(lib.wd_ptc_create(g.handle, p, _prec(act_prec), C.byref(h)), "wd_ptc_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.wd_ptc_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def wd_ptc_create(g, flat_weights, act_prec="bf16"):
+    return Ptc(g, flat_weights, act_prec)
+
+
+def wd_ptc_set_weights(n, flat):
+    a, p = _fptr(flat)
+    _check(lib.wd_ptc_set_weights(n.handle, p), "wd_ptc_set_weights")
+
+
+def wd_ptc_get_weights(n):
+    out = np.empty(1152, np.float32)
+    _check(lib.wd_ptc_get_weights(n.handle, out.ctypes.data_as(C.POINTER(C.c_float))), "wd_ptc_get_weights")
+    return out
+
+
+def wd_ptc_apply(n, x, y):
+    n.g.sync_stream()
+    _check(lib.wd_ptc_apply(n.handle, _ptr(x), _ptr(y)), "wd_ptc_apply")
+
+
+def wd_ptc_loss_grad(n, r, e, B):
+    n.g.sync_stream()
+    loss = C.c_double()
+    grad = np.empty(1152, np.float32)
+    _check(lib.wd_ptc_loss_grad(n.handle, _ptr(r), _ptr(e), int(B), C.byref(loss),
+                                grad.ctypes.data_as(C.POINTER(C.c_float))), "wd_ptc_loss_grad")
+    return loss.value, grad
+
+
+def wd_ptc_train_step(n, r, e, B, lr, want_loss=True):
+    n.g.sync_stream()
+    loss = C.c_double()
+    _check(lib.wd_ptc_train_step(n.handle, _ptr(r), _ptr(e), int(B), float(lr),
+                                 C.byref(loss) if want_loss else None), "wd_ptc_train_step")
+    return loss.value if want_loss else None

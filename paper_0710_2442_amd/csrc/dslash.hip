@@ -41,6 +41,7 @@ struct KDslash {
   int groups;           // 0: linear; G > 0: G contiguous regions per time slice
   int tiles_per_slice;  // tiles (blocks) per time slice of one parity
   int occ;              // register-budget variant (0 or 4), host side only
+  int nt_store;         // 1: streaming output stores; 0: cached stores
 };
 
 // Workgroups are dispatched round-robin over the XCDs (8 on MI355X), each
@@ -181,7 +182,8 @@ __device__ __forceinline__ void dslash_body(const KDslash &k) {
 #pragma unroll
       for (int c = 0; c < 12; ++c) acc[c] = acc[c] - y[c];
     }
-    Spinor<P>::store(k.out, vp, i, acc);
+    if (k.nt_store) Spinor<P>::template store<true>(k.out, vp, i, acc);
+    else Spinor<P>::template store<false>(k.out, vp, i, acc);
     if constexpr (NORM) {
       // norm of what was stored (after rounding to the storage format)
       cplx<T> st[12];
@@ -314,6 +316,7 @@ __global__ __launch_bounds__(256) void k_dslash_mrhs(KMrhs m) {
 // ------------------------------------------------------------ launchers
 static KDslash make_k(const wd_gauge *g, wd_prec prec, int parity) {
   KDslash k{};
+  k.nt_store = 1;
   k.g = g->geom;
   const bool dbl = (prec == WD_F64);
   const char *base = (const char *)(dbl ? g->links64 : g->links32);
@@ -384,6 +387,7 @@ wd_status launch_dslash(const wd_gauge *g, wd_prec prec, const DslashArgs &a, hi
   if (!dslash_variant_ok(g->geom, bs, groups)) { bs = 256; groups = 0; }
   k.groups = groups;
   k.occ = g->hop_occ[pi];
+  k.nt_store = g->hop_ntst[pi];
   k.tiles_per_slice = groups ? (int)((long)g->geom.vh / g->geom.L[3] / bs) : 0;
   const unsigned nblk = (unsigned)((g->geom.vpad + bs - 1) / bs);
   switch (prec) {

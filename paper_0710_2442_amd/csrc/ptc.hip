@@ -1,0 +1,573 @@
+// Gauge-covariant parallel-transport convolution (PTC) network: forward,
+// backward (input and weight gradients), loss and Adam, on gfx950.
+//
+// A layer maps C_in spinor fields to C_out fields:
+//   y_{c'}(x) = sum_c sum_h W^{(h)}_{c'c} (T_h psi_c)(x),
+// h = 0 (T_0 = 1), h = 1..4: T_{+mu} psi(x) = U_{x,mu} psi(x+mu),
+// h = 5..8: T_{-mu} psi(x) = U^dag_{x-mu,mu} psi(x-mu), with the time-boundary
+// factor of Eq. 3.  W^{(h)}_{c'c} is a complex 4x4 spin matrix, so every
+// layer commutes with gauge transformations.  T_h for h >= 1 is exactly the
+// transport of the hop kernel: the same hop-link arrays (U_{x,mu} and
+// U^dag_{x-mu,mu} stored at x) and the same neighbour indices, applied to the
+// full 4-spinor instead of a projected half spinor.
+//
+// Network: 1 -> 2 -> 1 channels, weights FP32 ([layer][h][c'][c][4][4] complex,
+// 288 + 288 = 576 complex numbers), activations stored in BF16 (or FP32),
+// arithmetic and gradients in FP32, reductions over sites in FP64 in a
+// fixed order.
+//
+// Backward: the input gradient of a layer is the same layer applied with the
+// adjoint weights W'^{(hbar)}_{c c'} = (W^{(h)}_{c'c})^dag, hbar the adjoint hop
+// (T_{+mu}^dag = T_{-mu}), so it is a gather with no atomics.  The weight
+// gradient G^{(h)}_{c'c}[s',s] = sum_x sum_a g_{c'}(x)[s',a] conj((T_h psi_c)(x)[s,a])
+// is reduced wave -> block (fixed order) -> FP64 block partials -> one
+// final fixed-order pass.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "wd_blas.h"
+#include "wd_device.h"
+#include "wd_ptc.h"
+#include "wd_solver.h"
+
+namespace wd {
+
+template <int P>
+using RealOf = typename Spinor<P>::real;
+
+constexpr int PTC_BS = 256;
+constexpr int PTC_NW = 1152;  // floats in all weights
+
+struct KPtc {
+  Geom g;
+  const char *links32;  // float hop links, parity 0 then parity 1
+  size_t link_par;      // bytes per parity of the link arrays
+  const char *in;       // C_in full fields (channel-major)
+  char *out;            // C_out full fields
+  size_t in_chan;       // bytes per input channel (full field)
+  size_t out_chan;
+  size_t in_half, out_half;  // bytes per half field
+  const float *W;       // this layer's weights [9][cout][cin][4][4] (re, im)
+  // weight gradient
+  const char *gy;       // C_out full fields, FP32 gradients
+  size_t gy_chan, gy_half;
+  double *partials;     // [nblocks][nparam floats]
+  int accumulate;       // add to existing partials
+};
+
+// Coordinates and neighbours of checkerboard site i on parity p (same
+// arithmetic as the hop kernel).
+struct PtcSite {
+  int nb[8];
+  float sf, sb;
+};
+
+__device__ __forceinline__ PtcSite ptc_site(const Geom &g, int i, int p) {
+  PtcSite s;
+  const int x1h = i % g.L1h;
+  const int rest = i / g.L1h;
+  const int x2 = rest % g.L[1];
+  const int r2 = rest / g.L[1];
+  const int x3 = r2 % g.L[2];
+  const int x4 = r2 / g.L[2];
+  const int x1 = 2 * x1h + ((p + x2 + x3 + x4) & 1);
+  const int xp1 = (x1 + 1 == g.L[0]) ? 0 : x1 + 1;
+  const int xm1 = (x1 == 0) ? g.L[0] - 1 : x1 - 1;
+  s.nb[0] = (xp1 >> 1) + g.L1h * rest;
+  s.nb[4] = (xm1 >> 1) + g.L1h * rest;
+  s.nb[1] = i + ((x2 == g.L[1] - 1) ? -(g.L[1] - 1) * g.s2 : g.s2);
+  s.nb[5] = i + ((x2 == 0) ? (g.L[1] - 1) * g.s2 : -g.s2);
+  s.nb[2] = i + ((x3 == g.L[2] - 1) ? -(g.L[2] - 1) * g.s3 : g.s3);
+  s.nb[6] = i + ((x3 == 0) ? (g.L[2] - 1) * g.s3 : -g.s3);
+  s.nb[3] = i + ((x4 == g.L[3] - 1) ? -(g.L[3] - 1) * g.s4 : g.s4);
+  s.nb[7] = i + ((x4 == 0) ? (g.L[3] - 1) * g.s4 : -g.s4);
+  s.sf = (x4 == g.L[3] - 1) ? g.tbc : 1.0f;
+  s.sb = (x4 == 0) ? g.tbc : 1.0f;
+  return s;
+}
+
+// v = T_h psi_c at site (p, i); psi channel base `chan` (full field).
+template <int PIN>
+__device__ __forceinline__ void transport(const KPtc &k, const PtcSite &s, int p, int i, int h, const char *chan,
+                                          cplx<float> (&v)[12]) {
+  const size_t vp = (size_t)k.g.vpad;
+  if (h == 0) {
+    cplx<RealOf<PIN>> t[12];
+    Spinor<PIN>::load(chan + (size_t)p * k.in_half, vp, i, t);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) v[c] = {(float)t[c].re, (float)t[c].im};
+    return;
+  }
+  const int d = h - 1;
+  cplx<RealOf<PIN>> t[12];
+  Spinor<PIN>::load(chan + (size_t)(1 - p) * k.in_half, vp, s.nb[d], t);
+  cplx<float> u[6], r2[3];
+  Link<float>::load(k.links32 + (size_t)p * k.link_par, d, i, u);
+  rebuild_row2(u, r2);
+  const float sg = (d == 3) ? s.sf : ((d == 7) ? s.sb : 1.0f);
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp) {
+    cplx<float> a[3] = {{(float)t[3 * sp].re, (float)t[3 * sp].im},
+                        {(float)t[3 * sp + 1].re, (float)t[3 * sp + 1].im},
+                        {(float)t[3 * sp + 2].re, (float)t[3 * sp + 2].im}};
+    cplx<float> y[3];
+    su3_mul(u, r2, a, y);
+    v[3 * sp] = sg * y[0];
+    v[3 * sp + 1] = sg * y[1];
+    v[3 * sp + 2] = sg * y[2];
+  }
+}
+
+// acc += W v  (W: 4x4 complex on spin, v: 4 spins x 3 colours)
+__device__ __forceinline__ void spin_mat_acc(const float *W, const cplx<float> (&v)[12], cplx<float> (&acc)[12]) {
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const cplx<float> w = {W[2 * (4 * sp + t)], W[2 * (4 * sp + t) + 1]};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) cfma(acc[3 * sp + a], w, v[3 * t + a]);
+    }
+  }
+}
+
+template <int PIN, int POUT, int CIN, int COUT>
+__global__ __launch_bounds__(PTC_BS) void k_ptc_layer(KPtc k) {
+  const int p = blockIdx.y;
+  const int i = blockIdx.x * PTC_BS + threadIdx.x;
+  if (i >= k.g.vpad) return;
+  const size_t vp = (size_t)k.g.vpad;
+  cplx<RealOf<POUT>> o[12];
+  if (i >= k.g.vh) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) o[c] = {0, 0};
+#pragma unroll
+    for (int co = 0; co < COUT; ++co) Spinor<POUT>::store(k.out + co * k.out_chan + (size_t)p * k.out_half, vp, i, o);
+    return;
+  }
+  const PtcSite s = ptc_site(k.g, i, p);
+  cplx<float> acc[COUT][12];
+#pragma unroll
+  for (int co = 0; co < COUT; ++co)
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[co][c] = {0.f, 0.f};
+  for (int h = 0; h < 9; ++h) {
+#pragma unroll
+    for (int ci = 0; ci < CIN; ++ci) {
+      cplx<float> v[12];
+      transport<PIN>(k, s, p, i, h, k.in + ci * k.in_chan, v);
+#pragma unroll
+      for (int co = 0; co < COUT; ++co) spin_mat_acc(k.W + 32 * ((h * COUT + co) * CIN + ci), v, acc[co]);
+    }
+  }
+#pragma unroll
+  for (int co = 0; co < COUT; ++co) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) o[c] = {(RealOf<POUT>)acc[co][c].re, (RealOf<POUT>)acc[co][c].im};
+    Spinor<POUT>::store(k.out + co * k.out_chan + (size_t)p * k.out_half, vp, i, o);
+  }
+}
+
+// Weight gradient of one layer: partials[block][f] (+)= block sum of the
+// per-site products; f indexes the layer's floats [h][c'][c][s'][s](re,im).
+template <int PIN, int CIN, int COUT>
+__global__ __launch_bounds__(PTC_BS) void k_ptc_wgrad(KPtc k) {
+  constexpr int NF = 9 * COUT * CIN * 32;
+  __shared__ float red[PTC_BS / 64][NF];
+  const int p = blockIdx.y;
+  const int i = blockIdx.x * PTC_BS + threadIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const bool live = i < k.g.vh;
+  const size_t vp = (size_t)k.g.vpad;
+  PtcSite s;
+  cplx<float> gy[COUT][12];
+  if (live) {
+    s = ptc_site(k.g, i, p);
+#pragma unroll
+    for (int co = 0; co < COUT; ++co)
+      Spinor<WD_F32>::load(k.gy + co * k.gy_chan + (size_t)p * k.gy_half, vp, i, gy[co]);
+  }
+  for (int h = 0; h < 9; ++h) {
+#pragma unroll
+    for (int ci = 0; ci < CIN; ++ci) {
+      cplx<float> v[12];
+      if (live) {
+        transport<PIN>(k, s, p, i, h, k.in + ci * k.in_chan, v);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) v[c] = {0.f, 0.f};
+      }
+#pragma unroll
+      for (int co = 0; co < COUT; ++co) {
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            cplx<float> acc = {0.f, 0.f};
+            if (live) {
+#pragma unroll
+              for (int a = 0; a < 3; ++a) {
+                // gy[s',a] * conj(v[s,a])
+                const cplx<float> g = gy[co][3 * sp + a], x = v[3 * t + a];
+                acc.re += g.re * x.re + g.im * x.im;
+                acc.im += g.im * x.re - g.re * x.im;
+              }
+            }
+            float re = acc.re, im = acc.im;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+              re += __shfl_xor(re, off, 64);
+              im += __shfl_xor(im, off, 64);
+            }
+            if (lane == 0) {
+              const int f = (((h * COUT + co) * CIN + ci) * 16 + 4 * sp + t) * 2;
+              red[w][f] = re;
+              red[w][f + 1] = im;
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const size_t blk = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+  for (int f = threadIdx.x; f < NF; f += PTC_BS) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < PTC_BS / 64; ++q) t += (double)red[q][f];
+    double *dst = k.partials + blk * NF + f;
+    *dst = k.accumulate ? (*dst + t) : t;
+  }
+}
+
+// grad[f] = sum over blocks of partials[b][f], in block order.
+__global__ __launch_bounds__(256) void k_ptc_reduce(const double *partials, int nblk, int nf, float *grad) {
+  const int f = blockIdx.x * 256 + threadIdx.x;
+  if (f >= nf) return;
+  double t = 0.0;
+  for (int b = 0; b < nblk; ++b) t += partials[(size_t)b * nf + f];
+  grad[f] = (float)t;
+}
+
+// Adjoint weights for the input gradient of a layer (cout x cin):
+// Wa[hbar][c][c'] = (W[h][c'][c])^dag.
+__global__ void k_ptc_adjoint(const float *W, float *Wa, int cout, int cin) {
+  const int n = threadIdx.x + blockIdx.x * blockDim.x;
+  const int tot = 9 * cout * cin;
+  if (n >= tot) return;
+  const int h = n / (cout * cin), co = (n / cin) % cout, ci = n % cin;
+  const int hb = (h == 0) ? 0 : (h <= 4 ? h + 4 : h - 4);
+  const float *src = W + 32 * ((h * cout + co) * cin + ci);
+  float *dst = Wa + 32 * ((hb * cin + ci) * cout + co);
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
+      dst[2 * (4 * a + b)] = src[2 * (4 * b + a)];
+      dst[2 * (4 * a + b) + 1] = -src[2 * (4 * b + a) + 1];
+    }
+}
+
+// Loss pieces: d = y - e (FP32 full fields); gy = scale * d; partial |d|^2.
+__global__ __launch_bounds__(256) void k_ptc_loss(const char *y, const char *e, char *gy, Geom g, float scale,
+                                                  double *partials, unsigned *counter, double *loss) {
+  const int p = blockIdx.y;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const size_t vp = (size_t)g.vpad;
+  const size_t hb = (size_t)96 * g.vpad;  // one FP32 half field
+  double acc = 0.0;
+  if (i < g.vpad) {
+    cplx<float> a[12], b[12];
+    if (i < g.vh) {
+      Spinor<WD_F32>::load(y + p * hb, vp, i, a);
+      Spinor<WD_F32>::load(e + p * hb, vp, i, b);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        a[c] = a[c] - b[c];
+        acc += (double)a[c].re * a[c].re + (double)a[c].im * a[c].im;
+        a[c] = scale * a[c];
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) a[c] = {0.f, 0.f};
+    }
+    Spinor<WD_F32>::store(gy + p * hb, vp, i, a);
+  }
+  double v[1] = {acc}, tot[1];
+  const unsigned nb = gridDim.x * gridDim.y, bid = blockIdx.y * gridDim.x + blockIdx.x;
+  if (grid_sum_last<1>(v, partials, counter, nb, bid, tot)) *loss += tot[0];
+}
+
+// Adam on the 1152 real parameters (real and imaginary parts separately).
+__global__ void k_adam(float *w, const float *g, float *m, float *v, int n, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const float gj = g[j];
+  const float mj = b1 * m[j] + (1.f - b1) * gj;
+  const float vj = b2 * v[j] + (1.f - b2) * gj * gj;
+  m[j] = mj;
+  v[j] = vj;
+  w[j] -= lr * (mj / c1) / (sqrtf(vj / c2) + eps);
+}
+
+}  // namespace wd
+
+// ============================================================ host side
+struct wd_ptc {
+  const wd_gauge *g;
+  float *W;        // device, 1152 floats: layer 1 (576) then layer 2 (576)
+  float *Wadj;     // device, adjoint weights of both layers
+  float *grad;     // device, 1152
+  float *m, *v;    // Adam state
+  int t;           // Adam steps taken
+  wd_prec act;     // activation storage (WD_BF16 or WD_F32)
+  void *x0, *y1, *y2, *gy2, *gy1;  // activations / gradients of one sample
+  double *partials;                // wgrad partials: layer 1 then layer 2, nblk x 576 each
+  double *scal;                    // [0] loss; [64..] reduction partials
+  unsigned *cnt;
+  int nblk;                        // blocks of a full-lattice launch (both parities)
+};
+
+namespace wd {
+
+static KPtc ptc_k(const wd_ptc *n) {
+  KPtc k{};
+  k.g = n->g->geom;
+  k.links32 = (const char *)n->g->links32;
+  k.link_par = link_parity_bytes(n->g->geom, false);
+  return k;
+}
+
+static dim3 ptc_grid(const Geom &G) { return dim3((unsigned)((G.vpad + PTC_BS - 1) / PTC_BS), 2); }
+
+template <int PIN, int POUT>
+static void launch_layer(const KPtc &k, int cin, int cout, hipStream_t st) {
+  const dim3 grid = ptc_grid(k.g);
+  if (cin == 1 && cout == 2) hipLaunchKernelGGL((k_ptc_layer<PIN, POUT, 1, 2>), grid, dim3(PTC_BS), 0, st, k);
+  else hipLaunchKernelGGL((k_ptc_layer<PIN, POUT, 2, 1>), grid, dim3(PTC_BS), 0, st, k);
+}
+
+static void dispatch_layer(const KPtc &k, wd_prec pin, wd_prec pout, int cin, int cout, hipStream_t st) {
+  if (pin == WD_BF16 && pout == WD_BF16) launch_layer<WD_BF16, WD_BF16>(k, cin, cout, st);
+  else if (pin == WD_BF16 && pout == WD_F32) launch_layer<WD_BF16, WD_F32>(k, cin, cout, st);
+  else if (pin == WD_F32 && pout == WD_BF16) launch_layer<WD_F32, WD_BF16>(k, cin, cout, st);
+  else launch_layer<WD_F32, WD_F32>(k, cin, cout, st);
+}
+
+// out (pout, cout channels) = layer(in (pin, cin channels)) with weights W.
+static wd_status ptc_layer(const wd_ptc *n, const float *W, const void *in, wd_prec pin, int cin, void *out,
+                           wd_prec pout, int cout, hipStream_t st) {
+  KPtc k = ptc_k(n);
+  k.in = (const char *)in;
+  k.out = (char *)out;
+  k.in_half = half_bytes(k.g, pin);
+  k.out_half = half_bytes(k.g, pout);
+  k.in_chan = 2 * k.in_half;
+  k.out_chan = 2 * k.out_half;
+  k.W = W;
+  dispatch_layer(k, pin, pout, cin, cout, st);
+  return hip_check(hipGetLastError(), "ptc layer");
+}
+
+// Weight-gradient partials of one layer (layer 0: 1 -> 2, layer 1: 2 -> 1).
+static wd_status ptc_wgrad(const wd_ptc *n, int layer, const void *in, wd_prec pin, const void *gy, int accumulate,
+                           hipStream_t st) {
+  KPtc k = ptc_k(n);
+  k.in = (const char *)in;
+  k.in_half = half_bytes(k.g, pin);
+  k.in_chan = 2 * k.in_half;
+  k.gy = (const char *)gy;
+  k.gy_half = half_bytes(k.g, WD_F32);
+  k.gy_chan = 2 * k.gy_half;
+  k.partials = n->partials + (size_t)layer * n->nblk * 576;
+  k.accumulate = accumulate;
+  const dim3 grid = ptc_grid(k.g);
+#define WD_WG(PIN)                                                                                 \
+  if (layer == 0) hipLaunchKernelGGL((k_ptc_wgrad<PIN, 1, 2>), grid, dim3(PTC_BS), 0, st, k); \
+  else hipLaunchKernelGGL((k_ptc_wgrad<PIN, 2, 1>), grid, dim3(PTC_BS), 0, st, k);
+  if (pin == WD_BF16) { WD_WG(WD_BF16) } else { WD_WG(WD_F32) }
+#undef WD_WG
+  return hip_check(hipGetLastError(), "ptc wgrad");
+}
+
+void ptc_release(wd_gauge *) {}
+
+// N(in): F32 full field -> F32 full field; input and hidden layer are stored
+// in the activation precision.
+wd_status ptc_apply(const wd_ptc *n, const void *in, void *out, hipStream_t st) {
+  const Geom &G = n->g->geom;
+  WD_TRY(blas_convert(G, WD_F32, vref(in, 2), n->act, vref(n->x0, 2), 1.0, nullptr, 1, st));
+  WD_TRY(ptc_layer(n, n->W, n->x0, n->act, 1, n->y1, n->act, 2, st));
+  WD_TRY(ptc_layer(n, n->W + 576, n->y1, n->act, 2, out, WD_F32, 1, st));
+  return WD_OK;
+}
+
+static wd_status ptc_alloc(wd_ptc *n) {
+  const Geom &G = n->g->geom;
+  const size_t fa = 2 * half_bytes(G, n->act), f32 = 2 * half_bytes(G, WD_F32);
+  n->nblk = (int)((G.vpad + PTC_BS - 1) / PTC_BS) * 2;
+  WD_HIP(hipMalloc(&n->W, PTC_NW * sizeof(float)));
+  WD_HIP(hipMalloc(&n->Wadj, PTC_NW * sizeof(float)));
+  WD_HIP(hipMalloc(&n->grad, PTC_NW * sizeof(float)));
+  WD_HIP(hipMalloc(&n->m, PTC_NW * sizeof(float)));
+  WD_HIP(hipMalloc(&n->v, PTC_NW * sizeof(float)));
+  WD_HIP(hipMemset(n->m, 0, PTC_NW * sizeof(float)));
+  WD_HIP(hipMemset(n->v, 0, PTC_NW * sizeof(float)));
+  WD_HIP(hipMalloc(&n->x0, fa));
+  WD_HIP(hipMalloc(&n->y1, 2 * fa));
+  WD_HIP(hipMalloc(&n->y2, f32));
+  WD_HIP(hipMalloc(&n->gy2, f32));
+  WD_HIP(hipMalloc(&n->gy1, 2 * f32));
+  WD_HIP(hipMalloc(&n->partials, (size_t)2 * n->nblk * 576 * sizeof(double)));
+  WD_HIP(hipMalloc(&n->scal, (size_t)(n->nblk + 64) * sizeof(double)));
+  WD_HIP(hipMalloc(&n->cnt, 256));
+  WD_HIP(hipMemset(n->cnt, 0, 256));
+  return WD_OK;
+}
+
+static void ptc_free(wd_ptc *n) {
+  void *ps[] = {n->W, n->Wadj, n->grad, n->m, n->v, n->x0, n->y1, n->y2, n->gy2, n->gy1, n->partials, n->scal, n->cnt};
+  for (void *p : ps)
+    if (p) (void)hipFree(p);
+  delete n;
+}
+
+// Loss and gradients of a batch of B normalised pairs (r_b, e_b), F32 full
+// fields, B of each, consecutive.  n->grad receives dL/dRe W + i dL/dIm W of
+// L = (1/B) sum_b |N(r_b) - e_b|^2; n->scal[0] receives L * B.
+static wd_status ptc_loss_grad(wd_ptc *n, const void *r, const void *e, int B, hipStream_t st) {
+  const Geom &G = n->g->geom;
+  const size_t f32 = 2 * half_bytes(G, WD_F32);
+  WD_HIP(hipMemsetAsync(n->scal, 0, sizeof(double), st));
+  hipLaunchKernelGGL(k_ptc_adjoint, dim3(1), dim3(64), 0, st, (const float *)n->W, n->Wadj, 2, 1);
+  hipLaunchKernelGGL(k_ptc_adjoint, dim3(1), dim3(64), 0, st, (const float *)(n->W + 576), n->Wadj + 576, 1, 2);
+  WD_HIP(hipGetLastError());
+  for (int b = 0; b < B; ++b) {
+    const char *rb = (const char *)r + (size_t)b * f32;
+    const char *eb = (const char *)e + (size_t)b * f32;
+    WD_TRY(blas_convert(G, WD_F32, vref(rb, 2), n->act, vref(n->x0, 2), 1.0, nullptr, 1, st));
+    WD_TRY(ptc_layer(n, n->W, n->x0, n->act, 1, n->y1, n->act, 2, st));
+    WD_TRY(ptc_layer(n, n->W + 576, n->y1, n->act, 2, n->y2, WD_F32, 1, st));
+    hipLaunchKernelGGL(k_ptc_loss, ptc_grid(G), dim3(256), 0, st, (const char *)n->y2, eb, (char *)n->gy2, G,
+                       2.0f / (float)B, n->scal + 64, n->cnt, n->scal);
+    WD_HIP(hipGetLastError());
+    WD_TRY(ptc_wgrad(n, 1, n->y1, n->act, n->gy2, b > 0, st));
+    // input gradient of layer 2 (adjoint weights: 1 -> 2 channels)
+    WD_TRY(ptc_layer(n, n->Wadj + 576, n->gy2, WD_F32, 1, n->gy1, WD_F32, 2, st));
+    WD_TRY(ptc_wgrad(n, 0, n->x0, n->act, n->gy1, b > 0, st));
+  }
+  hipLaunchKernelGGL(k_ptc_reduce, dim3((576 + 255) / 256), dim3(256), 0, st, (const double *)n->partials, n->nblk,
+                     576, n->grad);
+  hipLaunchKernelGGL(k_ptc_reduce, dim3((576 + 255) / 256), dim3(256), 0, st,
+                     (const double *)(n->partials + (size_t)n->nblk * 576), n->nblk, 576, n->grad + 576);
+  return hip_check(hipGetLastError(), "ptc loss/grad");
+}
+
+static wd_status check_pair_args(const wd_ptc *n, const void *r, const void *e, int B) {
+  if (!n) return set_error(WD_ERR_ARG, "ptc handle is NULL");
+  if (!r || !e) return set_error(WD_ERR_ARG, "ptc: NULL field pointer");
+  if (B < 1 || B > 4096) return set_error(WD_ERR_ARG, "ptc: batch size %d", B);
+  return hip_check(hipSetDevice(n->g->device), "hipSetDevice");
+}
+
+}  // namespace wd
+
+using namespace wd;
+
+extern "C" {
+
+wd_status wd_ptc_create(const wd_gauge *g, const float *W_host, wd_prec act_prec, wd_ptc **out) {
+  if (!out) return set_error(WD_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!g || !W_host) return set_error(WD_ERR_ARG, "ptc_create: NULL argument");
+  if (act_prec != WD_F32 && act_prec != WD_BF16) return set_error(WD_ERR_PREC, "ptc activations: FP32 or BF16");
+  for (int j = 0; j < PTC_NW; ++j)
+    if (!isfinite(W_host[j])) return set_error(WD_ERR_NONFINITE, "ptc_create: weight %d is not finite", j);
+  WD_HIP(hipSetDevice(g->device));
+  wd_ptc *n = new (std::nothrow) wd_ptc();
+  if (!n) return set_error(WD_ERR_OOM, "host allocation failed");
+  memset(n, 0, sizeof(*n));
+  n->g = g;
+  n->act = act_prec;
+  wd_status rc = ptc_alloc(n);
+  if (rc == WD_OK) rc = hip_check(hipMemcpy(n->W, W_host, PTC_NW * sizeof(float), hipMemcpyHostToDevice), "weights");
+  if (rc != WD_OK) {
+    ptc_free(n);
+    return rc;
+  }
+  *out = n;
+  return WD_OK;
+}
+
+wd_status wd_ptc_destroy(wd_ptc *n) {
+  if (!n) return WD_OK;
+  (void)hipSetDevice(n->g->device);
+  (void)hipDeviceSynchronize();
+  ptc_free(n);
+  return WD_OK;
+}
+
+wd_status wd_ptc_set_weights(wd_ptc *n, const float *W_host) {
+  if (!n || !W_host) return set_error(WD_ERR_ARG, "NULL argument");
+  WD_HIP(hipSetDevice(n->g->device));
+  WD_HIP(hipMemcpy(n->W, W_host, PTC_NW * sizeof(float), hipMemcpyHostToDevice));
+  WD_HIP(hipMemset(n->m, 0, PTC_NW * sizeof(float)));
+  WD_HIP(hipMemset(n->v, 0, PTC_NW * sizeof(float)));
+  n->t = 0;
+  return WD_OK;
+}
+
+wd_status wd_ptc_get_weights(const wd_ptc *n, float *W_host) {
+  if (!n || !W_host) return set_error(WD_ERR_ARG, "NULL argument");
+  WD_HIP(hipSetDevice(n->g->device));
+  WD_HIP(hipStreamSynchronize(n->g->stream));
+  WD_HIP(hipMemcpy(W_host, n->W, PTC_NW * sizeof(float), hipMemcpyDeviceToHost));
+  return WD_OK;
+}
+
+wd_status wd_ptc_apply(const wd_ptc *n, const void *in, void *out) {
+  if (!n || !in || !out) return set_error(WD_ERR_ARG, "NULL argument");
+  if (in == out) return set_error(WD_ERR_ARG, "ptc_apply: in and out must differ");
+  WD_HIP(hipSetDevice(n->g->device));
+  return ptc_apply(n, in, out, n->g->stream);
+}
+
+wd_status wd_ptc_loss_grad(wd_ptc *n, const void *r, const void *e, int B, double *loss, float *grad_host) {
+  WD_TRY(check_pair_args(n, r, e, B));
+  hipStream_t st = n->g->stream;
+  WD_TRY(ptc_loss_grad(n, r, e, B, st));
+  double l = 0;
+  WD_HIP(hipMemcpyAsync(&l, n->scal, sizeof(double), hipMemcpyDeviceToHost, st));
+  if (grad_host) WD_HIP(hipMemcpyAsync(grad_host, n->grad, PTC_NW * sizeof(float), hipMemcpyDeviceToHost, st));
+  WD_HIP(hipStreamSynchronize(st));
+  if (loss) *loss = l / B;
+  return WD_OK;
+}
+
+wd_status wd_ptc_train_step(wd_ptc *n, const void *r, const void *e, int B, double lr, double *loss) {
+  WD_TRY(check_pair_args(n, r, e, B));
+  if (!(lr > 0.0) || !isfinite(lr)) return set_error(WD_ERR_ARG, "ptc_train_step: lr must be > 0");
+  hipStream_t st = n->g->stream;
+  WD_TRY(ptc_loss_grad(n, r, e, B, st));
+  n->t += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - powf(b1, (float)n->t), c2 = 1.f - powf(b2, (float)n->t);
+  hipLaunchKernelGGL(k_adam, dim3((PTC_NW + 255) / 256), dim3(256), 0, st, n->W, (const float *)n->grad, n->m, n->v,
+                     PTC_NW, (float)lr, b1, b2, 1e-8f, c1, c2);
+  WD_HIP(hipGetLastError());
+  if (loss) {
+    double l = 0;
+    WD_HIP(hipMemcpyAsync(&l, n->scal, sizeof(double), hipMemcpyDeviceToHost, st));
+    WD_HIP(hipStreamSynchronize(st));
+    *loss = l / B;
+  }
+  return WD_OK;
+}
+
+}  // extern "C"
+
+namespace wd {
+const wd_gauge *ptc_gauge(const wd_ptc *n) { return n->g; }
+}  // namespace wd

@@ -255,7 +255,7 @@ static wd_status true_residual64(const wd_gauge *g, const void *b, const void *x
 }
 
 // ------------------------------------------------------------ FP64 eo-CGLS
-static wd_status solve_cg64(wd_gauge *g, const void *b, void *x, double kappa, double tol,
+wd_status solve_cg64(wd_gauge *g, const void *b, void *x, double kappa, double tol,
                             const wd_solve_params &prm, wd_solve_info &info, hipStream_t st) {
   const Geom &G = g->geom;
   const size_t hb = half_bytes(G, WD_F64);

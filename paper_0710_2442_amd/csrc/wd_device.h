@@ -81,6 +81,13 @@ template <class T>
 __device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
 template <class T>
 __device__ __forceinline__ void st_stream(T v, T *p) { __builtin_nontemporal_store(v, p); }
+// NT: streaming store (no retention); otherwise an ordinary store, which can
+// leave a freshly written field in the caches for the next kernel to read.
+template <bool NT, class T>
+__device__ __forceinline__ void st_policy(T v, T *p) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
 
 // -------------------------------------------------------- spinor storage
 // Spinor: 12 complex components, c = 3*spin + colour.
@@ -99,10 +106,11 @@ struct Spinor<WD_F64> {
       s[c] = {v.x, v.y};
     }
   }
+  template <bool NT = true>
   __device__ static void store(void *base, size_t vp, size_t i, const cplx<double> (&s)[12]) {
     v2d *p = (v2d *)base + i;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) st_stream(v2d{s[c].re, s[c].im}, p + c * vp);
+    for (int c = 0; c < 12; ++c) st_policy<NT>(v2d{s[c].re, s[c].im}, p + c * vp);
   }
 };
 
@@ -119,11 +127,12 @@ struct Spinor<WD_F32> {
       s[2 * k + 1] = {v.z, v.w};
     }
   }
+  template <bool NT = true>
   __device__ static void store(void *base, size_t vp, size_t i, const cplx<float> (&s)[12]) {
     v4f *p = (v4f *)base + i;
 #pragma unroll
     for (int k = 0; k < 6; ++k)
-      st_stream(v4f{s[2 * k].re, s[2 * k].im, s[2 * k + 1].re, s[2 * k + 1].im}, p + k * vp);
+      st_policy<NT>(v4f{s[2 * k].re, s[2 * k].im, s[2 * k + 1].re, s[2 * k + 1].im}, p + k * vp);
   }
 };
 
@@ -150,6 +159,7 @@ struct Spinor<WD_F16> {
       }
     }
   }
+  template <bool NT = true>
   __device__ static void store(void *base, size_t vp, size_t i, const cplx<float> (&s)[12]) {
     float m = 0.f;
 #pragma unroll
@@ -164,9 +174,9 @@ struct Spinor<WD_F16> {
         const cplx<float> z = s[4 * k + j];
         w[j] = (uint32_t)f32_to_f16(z.re * inv) | ((uint32_t)f32_to_f16(z.im * inv) << 16);
       }
-      st_stream(v4u{w[0], w[1], w[2], w[3]}, p + k * vp);
+      st_policy<NT>(v4u{w[0], w[1], w[2], w[3]}, p + k * vp);
     }
-    st_stream(m, ((float *)((v4u *)base + 3 * vp)) + i);
+    st_policy<NT>(m, ((float *)((v4u *)base + 3 * vp)) + i);
   }
 };
 
@@ -185,6 +195,7 @@ struct Spinor<WD_BF16> {
         s[4 * k + j] = {bf16_to_f32((uint16_t)(w[j] & 0xffffu)), bf16_to_f32((uint16_t)(w[j] >> 16))};
     }
   }
+  template <bool NT = true>
   __device__ static void store(void *base, size_t vp, size_t i, const cplx<float> (&s)[12]) {
     v4u *p = (v4u *)base + i;
 #pragma unroll
@@ -195,7 +206,7 @@ struct Spinor<WD_BF16> {
         const cplx<float> z = s[4 * k + j];
         w[j] = (uint32_t)f32_to_bf16(z.re) | ((uint32_t)f32_to_bf16(z.im) << 16);
       }
-      st_stream(v4u{w[0], w[1], w[2], w[3]}, p + k * vp);
+      st_policy<NT>(v4u{w[0], w[1], w[2], w[3]}, p + k * vp);
     }
   }
 };
