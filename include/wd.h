@@ -258,6 +258,19 @@ wd_status wd_set_dslash_variant(wd_gauge *g, wd_prec prec, int block, int groups
 wd_status wd_get_dslash_variant(const wd_gauge *g, wd_prec prec, int *block,
                                 int *groups, int *occ);
 
+/* Solve one system on each of n lattices (uneven sizes allowed) together:
+ * every kernel of the solve is one persistent launch over a work list of
+ * (lattice, tile) items, with per-lattice descriptors, lattice-segmented
+ * reductions and per-lattice convergence masks; one pair of CG iterations is
+ * captured in a hipGraph (params->use_graph) and replayed.  gs[l], b[l], x[l]
+ * and kappa[l] as for wd_solve (FP64 full fields of lattice l); infos[l]
+ * receives that lattice's results.  params->solver must be
+ * WD_SOLVER_DEFECT_CG (FP64 outer, FP32 arithmetic inner with inner_prec
+ * storage).  All handles must live on the same device.  Synchronous. */
+wd_status wd_solve_batch(const wd_gauge *const *gs, int n, const void *const *b,
+                         void *const *x, const double *kappa, double tol,
+                         const wd_solve_params *params, wd_solve_info *infos);
+
 /* --------------------------------------------------------------- misc --- */
 
 const char *wd_status_string(int status);

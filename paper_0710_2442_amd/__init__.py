@@ -37,6 +37,7 @@ from ._lib import (  # noqa: F401
     wd_norm2,
     wd_solve,
     wd_solve_mrhs,
+    wd_solve_batch,
     wd_solve_params_default,
     wd_spinor_pack,
     wd_spinor_unpack,

@@ -85,6 +85,8 @@ _decl("wd_solve", C.c_int, [_vp, _vp, _vp, C.c_double, C.c_double, C.POINTER(wd_
                              C.POINTER(wd_solve_info)])
 _decl("wd_solve_mrhs", C.c_int, [_vp, _vp, _vp, C.c_int, C.c_double, C.c_double,
                                   C.POINTER(wd_solve_params), C.POINTER(wd_solve_info)])
+_decl("wd_solve_batch", C.c_int, [C.POINTER(_vp), C.c_int, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(C.c_double),
+                                   C.c_double, C.POINTER(wd_solve_params), C.POINTER(wd_solve_info)])
 _decl("wd_tune_dslash", C.c_int, [_vp, C.c_int, C.c_char_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                    C.POINTER(C.c_int), C.POINTER(C.c_double)])
 _decl("wd_set_dslash_variant", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int])
@@ -376,3 +378,18 @@ def wd_ptc_train_step(n, r, e, B, lr, want_loss=True):
     _check(lib.wd_ptc_train_step(n.handle, _ptr(r), _ptr(e), int(B), float(lr),
                                  C.byref(loss) if want_loss else None), "wd_ptc_train_step")
     return loss.value if want_loss else None
+
+
+def wd_solve_batch(gauges, bs, xs, kappas, tol, params):
+    """Solve D_W[l] x[l] = b[l] for every lattice l together (persistent launches)."""
+    n = len(gauges)
+    for g in gauges:
+        g.sync_stream()
+    hs = (_vp * n)(*[g.handle for g in gauges])
+    pb = (_vp * n)(*[_ptr(b) for b in bs])
+    px = (_vp * n)(*[_ptr(x) for x in xs])
+    ks = (C.c_double * n)(*[float(k) for k in kappas])
+    infos = (wd_solve_info * n)()
+    rc = lib.wd_solve_batch(hs, n, pb, px, ks, float(tol), C.byref(params), infos)
+    _check(rc, "wd_solve_batch", allow_not_converged=True)
+    return rc, [i.as_dict() for i in infos]

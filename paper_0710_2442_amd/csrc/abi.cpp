@@ -344,4 +344,20 @@ wd_status wd_solve_mrhs(const wd_gauge *U, const void *b, void *x, int nrhs, dou
   return rc;
 }
 
+wd_status wd_solve_batch(const wd_gauge *const *gs, int n, const void *const *b, void *const *x, const double *kappa,
+                         double tol, const wd_solve_params *p, wd_solve_info *infos) {
+  if (!gs || !b || !x || !kappa || !infos) return set_error(WD_ERR_ARG, "solve_batch: NULL argument");
+  if (n < 1 || n > 4096) return set_error(WD_ERR_ARG, "solve_batch: n = %d", n);
+  wd_solve_params prm;
+  for (int l = 0; l < n; ++l) {
+    WD_TRY(solve_args(gs[l], b[l], x[l], kappa[l], tol, p, prm));
+    if (gs[l]->device != gs[0]->device) return set_error(WD_ERR_ARG, "solve_batch: handles on different devices");
+  }
+  if (prm.solver != WD_SOLVER_DEFECT_CG) return set_error(WD_ERR_ARG, "solve_batch: only defect-correction CG");
+  wd_status rc = solve_batch(gs, n, b, x, kappa, tol, prm, infos);
+  if (rc < 0)
+    for (int l = 0; l < n; ++l) infos[l].status = rc;
+  return rc;
+}
+
 }  // extern "C"

@@ -16,137 +16,9 @@
 // once) + 24 output reals.
 #include <algorithm>
 
-#include "wd_device.h"
+#include "wd_hop.h"
 
 namespace wd {
-
-template <int P>
-using RealOf = typename Spinor<P>::real;
-
-struct KDslash {
-  Geom g;
-  const char *in;
-  char *out;
-  const char *X;
-  const char *Y;
-  const char *links;  // hop-link arrays of this output parity
-  double a;
-  int parity;
-  int norm_accumulate;
-  double *norm_out;
-  const int *skip;
-  double *partials;
-  unsigned *counter;
-  // block -> tile mapping (see tile_of)
-  int groups;           // 0: linear; G > 0: G contiguous regions per time slice
-  int tiles_per_slice;  // tiles (blocks) per time slice of one parity
-  int occ;              // register-budget variant (0 or 4), host side only
-  int nt_store;         // 1: streaming output stores; 0: cached stores
-};
-
-// Workgroups are dispatched round-robin over the XCDs (8 on MI355X), each
-// with its own L2.  With `groups` = G, block b goes to region b % G and the
-// blocks of one region walk its tiles slice by slice in time order, so a
-// region's neighbour spinors (x1..x3 inside the slice, x4 one slice away)
-// are fetched into one L2 and re-read from there.  Requires
-// tiles_per_slice % G == 0 and gridDim.x == tiles_per_slice * L4.
-__device__ __forceinline__ int tile_of(const KDslash &k) {
-  const int b = blockIdx.x;
-  if (k.groups == 0) return b;
-  const int G = k.groups;
-  const int per = k.tiles_per_slice / G;
-  const int x = b % G, q = b / G;
-  return (q / per) * k.tiles_per_slice + x * per + (q % per);
-}
-
-// Site coordinates of checkerboard index i on parity p.
-struct Coords {
-  int x1, x2, x3, x4, rest;
-};
-__device__ __forceinline__ Coords coords_of(const Geom &g, int i, int parity) {
-  Coords c;
-  const int x1h = i % g.L1h;
-  c.rest = i / g.L1h;
-  c.x2 = c.rest % g.L[1];
-  const int r2 = c.rest / g.L[1];
-  c.x3 = r2 % g.L[2];
-  c.x4 = r2 / g.L[2];
-  c.x1 = 2 * x1h + ((parity + c.x2 + c.x3 + c.x4) & 1);
-  return c;
-}
-
-// Checkerboard indices of the 8 neighbours, in hop order
-// (x1+, x2+, x3+, x4+, x1-, x2-, x3-, x4-).
-__device__ __forceinline__ void neighbours(const Geom &g, const Coords &c, int i, int (&nb)[8]) {
-  const int xp1 = (c.x1 + 1 == g.L[0]) ? 0 : c.x1 + 1;
-  const int xm1 = (c.x1 == 0) ? g.L[0] - 1 : c.x1 - 1;
-  nb[0] = (xp1 >> 1) + g.L1h * c.rest;
-  nb[4] = (xm1 >> 1) + g.L1h * c.rest;
-  nb[1] = i + ((c.x2 == g.L[1] - 1) ? -(g.L[1] - 1) * g.s2 : g.s2);
-  nb[5] = i + ((c.x2 == 0) ? (g.L[1] - 1) * g.s2 : -g.s2);
-  nb[2] = i + ((c.x3 == g.L[2] - 1) ? -(g.L[2] - 1) * g.s3 : g.s3);
-  nb[6] = i + ((c.x3 == 0) ? (g.L[2] - 1) * g.s3 : -g.s3);
-  nb[3] = i + ((c.x4 == g.L[3] - 1) ? -(g.L[3] - 1) * g.s4 : g.s4);
-  nb[7] = i + ((c.x4 == 0) ? (g.L[3] - 1) * g.s4 : -g.s4);
-}
-
-// One hop: acc += M (1 + S gamma_MU) psi_nb, M = the stored hop link.
-template <int P, int MU, int S>
-__device__ __forceinline__ void hop_term(cplx<RealOf<P>> (&acc)[12], const char *in, size_t vp, int nb,
-                                         const char *links, int d, size_t i, RealOf<P> sign) {
-  using T = RealOf<P>;
-  cplx<T> psi[12];
-  Spinor<P>::load(in, vp, nb, psi);
-  cplx<T> h[6];
-  project<MU, S>(psi, h);
-  if constexpr (MU == 3) {
-#pragma unroll
-    for (int c = 0; c < 6; ++c) h[c] = sign * h[c];
-  }
-  cplx<T> u[6];
-  Link<T>::load(links, d, i, u);
-  cplx<T> r2[3];
-  rebuild_row2(u, r2);
-  cplx<T> g[6];
-  {
-    cplx<T> v[3] = {h[0], h[1], h[2]};
-    cplx<T> y[3];
-    su3_mul(u, r2, v, y);
-    g[0] = y[0]; g[1] = y[1]; g[2] = y[2];
-  }
-  {
-    cplx<T> v[3] = {h[3], h[4], h[5]};
-    cplx<T> y[3];
-    su3_mul(u, r2, v, y);
-    g[3] = y[0]; g[4] = y[1]; g[5] = y[2];
-  }
-  reconstruct_add<MU, S>(acc, g);
-}
-
-template <int P, bool DAG>
-__device__ __forceinline__ void hop_all(const KDslash &k, int i, cplx<RealOf<P>> (&acc)[12]) {
-  using T = RealOf<P>;
-  const Coords c = coords_of(k.g, i, k.parity);
-  int nb[8];
-  neighbours(k.g, c, i, nb);
-  const size_t vp = (size_t)k.g.vpad;
-  const T one = (T)1;
-  const T sf = (c.x4 == k.g.L[3] - 1) ? (T)k.g.tbc : one;
-  const T sb = (c.x4 == 0) ? (T)k.g.tbc : one;
-  constexpr int F = DAG ? -1 : 1;  // forward hop projector (1 + F gamma)
-  constexpr int B = -F;            // backward hop projector (1 + B gamma)
-  const char *L = k.links;
-#pragma unroll
-  for (int c2 = 0; c2 < 12; ++c2) acc[c2] = {(T)0, (T)0};
-  hop_term<P, 0, F>(acc, k.in, vp, nb[0], L, 0, i, one);
-  hop_term<P, 1, F>(acc, k.in, vp, nb[1], L, 1, i, one);
-  hop_term<P, 2, F>(acc, k.in, vp, nb[2], L, 2, i, one);
-  hop_term<P, 3, F>(acc, k.in, vp, nb[3], L, 3, i, sf);
-  hop_term<P, 0, B>(acc, k.in, vp, nb[4], L, 4, i, one);
-  hop_term<P, 1, B>(acc, k.in, vp, nb[5], L, 5, i, one);
-  hop_term<P, 2, B>(acc, k.in, vp, nb[6], L, 6, i, one);
-  hop_term<P, 3, B>(acc, k.in, vp, nb[7], L, 7, i, sb);
-}
 
 // EPI: 0 -> out = a H in;  1 -> out = X + a H in;  2 -> out = X - Y + a H in
 // OCC > 0 asks the compiler for at least OCC waves per SIMD (fewer registers,
@@ -159,49 +31,9 @@ __device__ __forceinline__ void hop_all(const KDslash &k, int i, cplx<RealOf<P>>
 
 template <int P, bool DAG, int EPI, bool NORM>
 __device__ __forceinline__ void dslash_body(const KDslash &k) {
-  using T = RealOf<P>;
   if (k.skip && *k.skip) return;
   const int i = tile_of(k) * (int)blockDim.x + (int)threadIdx.x;
-  const size_t vp = (size_t)k.g.vpad;
-  double nrm = 0.0;
-  if (i < k.g.vh) {
-    cplx<T> acc[12];
-    hop_all<P, DAG>(k, i, acc);
-    const T a = (T)k.a;
-#pragma unroll
-    for (int c = 0; c < 12; ++c) acc[c] = a * acc[c];
-    if constexpr (EPI >= 1) {
-      cplx<T> x[12];
-      Spinor<P>::load(k.X, vp, i, x);
-#pragma unroll
-      for (int c = 0; c < 12; ++c) acc[c] = acc[c] + x[c];
-    }
-    if constexpr (EPI == 2) {
-      cplx<T> y[12];
-      Spinor<P>::load(k.Y, vp, i, y);
-#pragma unroll
-      for (int c = 0; c < 12; ++c) acc[c] = acc[c] - y[c];
-    }
-    if (k.nt_store) Spinor<P>::template store<true>(k.out, vp, i, acc);
-    else Spinor<P>::template store<false>(k.out, vp, i, acc);
-    if constexpr (NORM) {
-      // norm of what was stored (after rounding to the storage format)
-      cplx<T> st[12];
-      if constexpr (P == WD_F64 || P == WD_F32) {
-#pragma unroll
-        for (int c = 0; c < 12; ++c) st[c] = acc[c];
-      } else {
-        Spinor<P>::load(k.out, vp, i, st);
-      }
-#pragma unroll
-      for (int c = 0; c < 12; ++c) nrm += (double)st[c].re * st[c].re + (double)st[c].im * st[c].im;
-    }
-  } else if (i < k.g.vpad) {
-    cplx<T> z[12];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) z[c] = {(T)0, (T)0};
-    Spinor<P>::store(k.out, vp, i, z);
-  }
+  const double nrm = dslash_site<P, DAG, EPI, NORM>(k, i);
   if constexpr (NORM) {
     double v[1] = {nrm}, tot[1];
     if (grid_sum_last<1>(v, k.partials, k.counter, gridDim.x, blockIdx.x, tot)) {

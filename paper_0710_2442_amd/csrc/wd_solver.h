@@ -12,6 +12,8 @@ wd_status solve_mrhs(wd_gauge *g, const void *b, void *x, int nrhs, double kappa
 wd_status solve_fgcr(wd_gauge *g, const void *b, void *x, double kappa, double tol, const wd_solve_params &prm,
                      wd_solve_info &info, hipStream_t st);
 void workspace_free(wd_gauge *g);
+wd_status solve_batch(const wd_gauge *const *gs, int n, const void *const *b, void *const *x, const double *kappa,
+                      double tol, const wd_solve_params &prm, wd_solve_info *infos);
 // FP64 even-odd CGLS on stream st (synchronises st)
 wd_status solve_cg64(wd_gauge *g, const void *b, void *x, double kappa, double tol, const wd_solve_params &prm,
                      wd_solve_info &info, hipStream_t st);

@@ -27,3 +27,18 @@ def pytest_collection_modifyitems(config, items):
     for it in items:
         if "gpu" in it.keywords:
             it.add_marker(skip)
+
+
+def pytest_sessionstart(session):
+    # name the HIP / HSA runtime files this process maps (GPU runs only), so a
+    # failure report shows which runtime the library and torch resolved to
+    try:
+        import torch
+        if not torch.cuda.is_available():
+            return
+        import paper_0710_2442_amd  # noqa: F401  (loads libwd.so)
+        with open("/proc/self/maps") as f:
+            libs = sorted({l.split()[-1] for l in f if ("amdhip" in l or "hsa-runtime" in l or "libwd" in l)})
+        print("\n[runtime libraries]", *libs, sep="\n  ", flush=True)
+    except Exception as e:  # pragma: no cover
+        print("[runtime libraries] unavailable:", e, flush=True)
