@@ -31,6 +31,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -141,6 +143,154 @@ def solve_leg(wd, torch, syn, log_every=True):
     return out
 
 
+
+def _defect(wd, prec, tol_inner=1e-3):
+    return wd.wd_solve_params_default(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec=prec, inner_tol=tol_inner)
+
+
+def mrhs_leg(wd, torch, syn):
+    """12 spin-colour point sources on 24^3x48 (kappa 0.124, eps 0.3), solved together."""
+    from paper_0710_2442_amd.fields import canon_to_field
+
+    dims, kappa, tol = (24, 24, 24, 48), 0.124, 1e-10
+    gseed, _ = syn.CONFIG_SEEDS["mrhs_24x24x24x48"]
+    U = syn.gauge_field(dims, 0.3, gseed)
+    g = wd.Gauge(U, dims, -1, "f64")
+    nb = wd.wd_field_bytes(dims, "f64")
+    B = torch.cat([canon_to_field(g, syn.point_source(dims, s, c), "f64") for s in range(4) for c in range(3)])
+    X = wd.wd_new_field(dims, "f64", 12)
+    out = {}
+
+    def timed(fn):
+        fn()  # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, r
+
+    sec, (rc, infos) = timed(lambda: wd.wd_solve_mrhs(g, B, X, 12, kappa, tol, _defect(wd, "f32")))
+    out["mrhs12_defect_f32"] = {"seconds": round(sec, 4), "max_resid": max(i["true_rel_resid"] for i in infos),
+                                "iters": max(i["iters"] for i in infos), "status": rc}
+
+    def seq(params):
+        res = []
+        for r in range(12):
+            res.append(wd.wd_solve(g, B[r * nb:(r + 1) * nb], X[r * nb:(r + 1) * nb], kappa, tol, params))
+        return res
+
+    sec, res = timed(lambda: seq(_defect(wd, "f32")))
+    out["sequential12_defect_f32"] = {"seconds": round(sec, 4),
+                                      "max_resid": max(i["true_rel_resid"] for _, i in res)}
+    sec, res = timed(lambda: seq(wd.wd_solve_params_default(solver=wd.WD_SOLVER_CG)))
+    out["sequential12_fp64_cg"] = {"seconds": round(sec, 4),
+                                   "max_resid": max(i["true_rel_resid"] for _, i in res)}
+    base = out["sequential12_fp64_cg"]["seconds"]
+    for k in out:
+        out[k]["speedup_vs_fp64_cg"] = round(base / out[k]["seconds"], 3)
+    # multi-RHS hop throughput (FP32, 12 RHS): 48 spinor reals + 96/12 link reals per site per RHS
+    vh = int(np.prod(dims)) // 2
+    src = wd.wd_new_field(dims, "f32", 12, wd.WD_ODD)
+    dst = wd.wd_new_field(dims, "f32", 12, wd.WD_EVEN)
+    src.zero_()
+    for _ in range(3):
+        wd.wd_dslash_mrhs(g, src, dst, 1.0, wd.WD_EVEN, "f32", 12)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        wd.wd_dslash_mrhs(g, src, dst, 1.0, wd.WD_EVEN, "f32", 12)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / 20
+    out["mrhs12_hop_f32"] = {"us_per_launch": round(us, 2),
+                             "algorithmic_GBps": round(vh * 12 * 56 * 4 / (us * 1e-6) / 1e9, 1),
+                             "site_rhs_per_s": round(vh * 12 / (us * 1e-6), 0)}
+    g.close()
+    return out
+
+
+def batch_leg(wd, torch, syn):
+    """Eight lattices of uneven size (689,408 sites) in one persistent batched solve."""
+    from paper_0710_2442_amd.fields import canon_to_field
+
+    kappa, tol = 0.124, 1e-10
+    gs, bs, xs = [], [], []
+    for dims, eps, seed in syn.batch_lattices():
+        g = wd.Gauge(syn.gauge_field(dims, eps, seed), dims, -1, "f64")
+        gs.append(g)
+        bs.append(canon_to_field(g, syn.gaussian_spinor(dims, seed + 1000), "f64"))
+        xs.append(wd.wd_new_field(dims, "f64"))
+    out = {}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, r
+
+    sec, (rc, infos) = timed(lambda: wd.wd_solve_batch(gs, bs, xs, [kappa] * 8, tol, _defect(wd, "f32")))
+    out["batch8_persistent_graph_f32"] = {"seconds": round(sec, 4), "status": rc,
+                                          "max_resid": max(i["true_rel_resid"] for i in infos)}
+    sec, res = timed(lambda: [wd.wd_solve(g, b, x, kappa, tol, _defect(wd, "f32")) for g, b, x in zip(gs, bs, xs)])
+    out["sequential8_defect_f32"] = {"seconds": round(sec, 4),
+                                     "max_resid": max(i["true_rel_resid"] for _, i in res)}
+    sec, res = timed(lambda: [wd.wd_solve(g, b, x, kappa, tol, wd.wd_solve_params_default(solver=wd.WD_SOLVER_CG))
+                              for g, b, x in zip(gs, bs, xs)])
+    out["sequential8_fp64_cg"] = {"seconds": round(sec, 4),
+                                  "max_resid": max(i["true_rel_resid"] for _, i in res)}
+    base = out["sequential8_fp64_cg"]["seconds"]
+    for k in out:
+        out[k]["speedup_vs_fp64_cg"] = round(base / out[k]["seconds"], 3)
+    for g in gs:
+        g.close()
+    return out
+
+
+def learned_leg(wd, torch, syn, steps):
+    """Train the PTC network on 16^4 (kappa 0.124, eps 0.3); test FGCR on 32^3x64."""
+    from paper_0710_2442_amd import learn
+    from paper_0710_2442_amd.fields import canon_to_field
+
+    kappa, tol = 0.124, 1e-10
+    gseed, sseed = syn.CONFIG_SEEDS["ptc_16x16x16x16"]
+    gtr = wd.Gauge(syn.gauge_field((16, 16, 16, 16), 0.3, gseed), (16, 16, 16, 16), -1, "f64")
+    W, hist = learn.train(gtr, kappa, steps=steps, batch=8, lr=2e-3, seed=sseed, act="bf16", log_every=100,
+                          log=log)
+    gtr.close()
+    out = {"training": {"steps": steps, "pairs": hist["pairs"], "sources": hist["sources"],
+                        "seconds": round(hist["seconds"], 2),
+                        "pair_generation_seconds": round(hist["pair_generation_seconds"], 2),
+                        "loss_first": hist["losses"][0][1], "loss_last": hist["losses"][-1][1]}}
+    gt = wd.Gauge(syn.gauge_field(DIMS, 0.3, gseed + 100), DIMS, -1, "f64")
+    fb = canon_to_field(gt, syn.gaussian_spinor(DIMS, sseed + 100), "f64")
+    fx = wd.wd_new_field(DIMS, "f64")
+    net = wd.Ptc(gt, W, "bf16")
+    cases = [("fgcr_trained_bf16", dict(solver=wd.WD_SOLVER_FGCR, fgcr_m=16, precond=net)),
+             ("fgcr_identity", dict(solver=wd.WD_SOLVER_FGCR, fgcr_m=16)),
+             ("fp64_cg", dict(solver=wd.WD_SOLVER_CG)),
+             ("defect_bf16", dict(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec="bf16", inner_tol=1e-2))]
+    for name, kw in cases:
+        p = wd.wd_solve_params_default(**kw)
+        wd.wd_solve(gt, fb, fx, kappa, tol, p)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rc, info = wd.wd_solve(gt, fb, fx, kappa, tol, p)
+        torch.cuda.synchronize()
+        out[name] = {"seconds": round(time.perf_counter() - t, 4), "iters": info["iters"],
+                     "dslash_calls": info["dslash_calls"], "true_rel_resid": info["true_rel_resid"],
+                     "fallback_used": info["fallback_used"], "status": rc}
+        log(f"learned leg {name}: {out[name]}")
+    base = out["fp64_cg"]["seconds"]
+    for k in cases:
+        out[k[0]]["speedup_vs_fp64_cg"] = round(base / out[k[0]]["seconds"], 3)
+    net.close()
+    gt.close()
+    return out
+
+
 def cpu_leg(syn, U, psi):
     """Oracle single-parity hop on the full 32^3x64 workload (one application)."""
     import numpy as np
@@ -168,6 +318,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mrhs", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-learn", action="store_true")
+    ap.add_argument("--learn-steps", type=int, default=400)
     ap.add_argument("--no-tune", action="store_true", help="use the default hop variant")
     ap.add_argument("--variant", default=None, help="force the hop variant 'block,groups,occ' (no tuning)")
     ap.add_argument("--only", choices=["f64", "f32"], default=None, help="time one precision only")
@@ -265,6 +419,12 @@ def main():
                        "avg_launch_us": round(results["f32"]["sec_per_launch"] * 1e6, 2)}
     if not args.no_solve:
         line["solve_32x32x32x64_kappa0124"] = solve_leg(wd, torch, syn)
+    if not args.no_mrhs:
+        line["mrhs_24x24x24x48_12_point_sources"] = mrhs_leg(wd, torch, syn)
+    if not args.no_batch:
+        line["batch_8_lattices_689408_sites"] = batch_leg(wd, torch, syn)
+    if not args.no_learn:
+        line["learned_ptc_fgcr_32x32x32x64"] = learned_leg(wd, torch, syn, args.learn_steps)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_leg(syn, U, psi)
     print(json.dumps(line), flush=True)

@@ -147,6 +147,10 @@ wd_status wd_cdot(const wd_gauge *g, const void *x, const void *y, int nhalf,
                   wd_prec prec, double out[2]);     /* <x,y> = sum conj(x) y */
 wd_status wd_norm2(const wd_gauge *g, const void *x, int nhalf, wd_prec prec,
                    double *out);
+/* out (pout) = scale * in (pin) over nhalf half fields; padding slots are
+ * zeroed.  In place only for equal precisions.  Asynchronous. */
+wd_status wd_convert(const wd_gauge *g, const void *in, wd_prec pin, void *out,
+                     wd_prec pout, int nhalf, double scale);
 
 /* --------------------------------------------------------------- solve -- */
 

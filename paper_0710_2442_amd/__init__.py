@@ -26,6 +26,7 @@ from ._lib import (  # noqa: F401
     Gauge,
     lib,
     wd_caxpy,
+    wd_convert,
     wd_cdot,
     wd_dslash,
     wd_dslash_ex,

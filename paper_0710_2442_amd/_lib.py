@@ -80,6 +80,7 @@ _decl("wd_dslash_mrhs", C.c_int, [_vp, _vp, _vp, C.c_double, C.c_int, C.c_int, C
 _decl("wd_caxpy", C.c_int, [_vp, C.c_double, C.c_double, _vp, _vp, C.c_int, C.c_int])
 _decl("wd_cdot", C.c_int, [_vp, _vp, _vp, C.c_int, C.c_int, C.POINTER(C.c_double)])
 _decl("wd_norm2", C.c_int, [_vp, _vp, C.c_int, C.c_int, C.POINTER(C.c_double)])
+_decl("wd_convert", C.c_int, [_vp, _vp, C.c_int, _vp, C.c_int, C.c_int, C.c_double])
 _decl("wd_solve_params_default", None, [C.POINTER(wd_solve_params)])
 _decl("wd_solve", C.c_int, [_vp, _vp, _vp, C.c_double, C.c_double, C.POINTER(wd_solve_params),
                              C.POINTER(wd_solve_info)])
@@ -248,6 +249,12 @@ def wd_norm2(g, x, nhalf, prec):
     out = C.c_double()
     _check(lib.wd_norm2(g.handle, _ptr(x), int(nhalf), _prec(prec), C.byref(out)), "wd_norm2")
     return out.value
+
+
+def wd_convert(g, x, pin, y, pout, nhalf, scale=1.0):
+    g.sync_stream()
+    _check(lib.wd_convert(g.handle, _ptr(x), _prec(pin), _ptr(y), _prec(pout), int(nhalf), float(scale)),
+           "wd_convert")
 
 
 def wd_solve_params_default(**kw):

@@ -274,6 +274,16 @@ wd_status wd_norm2(const wd_gauge *g, const void *x, int nhalf, wd_prec prec, do
   return WD_OK;
 }
 
+wd_status wd_convert(const wd_gauge *g, const void *in, wd_prec pin, void *out, wd_prec pout, int nhalf,
+                     double scale) {
+  WD_TRY(blas_args(g, in, nhalf, pin));
+  if (!out) return set_error(WD_ERR_ARG, "convert: out is NULL");
+  if (!prec_ok(pout)) return set_error(WD_ERR_PREC, "convert: prec = %d", (int)pout);
+  if (!isfinite(scale)) return set_error(WD_ERR_NONFINITE, "convert: scale is not finite");
+  if (in == out && pin != pout) return set_error(WD_ERR_ARG, "convert: in place needs equal precisions");
+  return blas_convert(g->geom, pin, vref(in, nhalf), pout, vref(out, nhalf), scale, nullptr, 1, g->stream);
+}
+
 // ---------------------------------------------------------------- solve
 void wd_solve_params_default(wd_solve_params *p) {
   if (!p) return;

@@ -1,0 +1,130 @@
+"""Training driver of the learned preconditioner (orchestration only).
+
+Pairs (r, e) come from the solver itself: for a Gaussian source b the
+solution x* is computed with FP64 CG (to 1e-8, ample for a training
+target); CG stopped after k iterations (k in `ks`) gives x_k,
+e_k = x* - x_k and r_k = b - D x_k = D e_k.  Each pair is normalised by
+|r_k|.  The default uses k = 0 only (x_0 = 0: r = b, e = x*): residuals of
+later CG iterates are dominated by the low modes, and a network trained on
+them raised FGCR's iteration count (8^4, kappa 0.124: 88 with N = 1, 215-731
+with such pairs, 35 with k = 0 pairs).  Every step of this runs in the
+library's kernels (solves, hop, caxpy, conversion); this module only
+sequences the calls and draws the seeded sources.
+
+Training: Adam on L = mean |N(r) - e|^2 over mini-batches streamed from the
+generator (pairs are not stored beyond a small pool).
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import _lib as L
+from .fields import canon_to_field
+
+
+class PairGenerator:
+    """Streams normalised (r, e) pairs, FP32 full fields, on one lattice."""
+
+    def __init__(self, g, kappa, seed, ks=(0,), target_tol=1e-8):
+        import torch
+
+        self.torch = torch
+        self.g = g
+        self.kappa = float(kappa)
+        self.rng = np.random.Generator(np.random.PCG64(int(seed)))
+        self.ks = tuple(int(k) for k in ks)
+        self.target_tol = float(target_tol)
+        self.dims = g.dims
+        self.f64 = L.wd_field_bytes(self.dims, "f64")
+        self.f32 = L.wd_field_bytes(self.dims, "f32")
+        self.pool_r, self.pool_e = [], []
+        self.sources = 0
+        self.solve_seconds = 0.0
+        self._xs = L.wd_new_field(self.dims, "f64")
+        self._xk = L.wd_new_field(self.dims, "f64")
+        self._dx = L.wd_new_field(self.dims, "f64")
+
+    def _source(self):
+        L1, L2, L3, L4 = self.dims
+        z = self.rng.standard_normal((L4, L3, L2, L1, 4, 3, 2))
+        return canon_to_field(self.g, z[..., 0] + 1j * z[..., 1], "f64")
+
+    def _refill(self):
+        t = time.perf_counter()
+        fb = self._source()
+        self.sources += 1
+        exact = L.wd_solve_params_default(solver=L.WD_SOLVER_CG)
+        L.wd_solve(self.g, fb, self._xs, self.kappa, self.target_tol, exact)
+        for k in self.ks:
+            if k == 0:  # x_0 = 0: r = b, e = x*
+                L.wd_convert(self.g, fb, "f64", self._xk, "f64", 2, 0.0)
+            else:
+                L.wd_solve(self.g, fb, self._xk, self.kappa, 1e-14,
+                           L.wd_solve_params_default(solver=L.WD_SOLVER_CG, max_iter=k))
+            # r = b - D x_k  ;  e = x* - x_k
+            L.wd_dslash(self.g, self._xk, self._dx, self.kappa, self.dims, L.WD_FULL)
+            r = fb.clone()
+            L.wd_caxpy(self.g, -1.0, self._dx, r, 2, "f64")
+            e = self._xs.clone()
+            L.wd_caxpy(self.g, -1.0, self._xk, e, 2, "f64")
+            nr = np.sqrt(L.wd_norm2(self.g, r, 2, "f64"))
+            r32 = L.wd_new_field(self.dims, "f32")
+            e32 = L.wd_new_field(self.dims, "f32")
+            L.wd_convert(self.g, r, "f64", r32, "f32", 2, 1.0 / nr)
+            L.wd_convert(self.g, e, "f64", e32, "f32", 2, 1.0 / nr)
+            self.pool_r.append(r32)
+            self.pool_e.append(e32)
+        self.torch.cuda.synchronize()
+        self.solve_seconds += time.perf_counter() - t
+
+    def batch(self, B):
+        """B pairs as two tensors of B consecutive FP32 full fields."""
+        while len(self.pool_r) < B:
+            self._refill()
+        order = self.rng.permutation(len(self.pool_r))[:B]
+        r = self.torch.cat([self.pool_r[i] for i in order])
+        e = self.torch.cat([self.pool_e[i] for i in order])
+        keep = [i for i in range(len(self.pool_r)) if i not in set(order.tolist())]
+        self.pool_r = [self.pool_r[i] for i in keep]
+        self.pool_e = [self.pool_e[i] for i in keep]
+        return r, e
+
+
+def init_weights(seed, scale=1e-2):
+    """Near-identity start: W^(0) = I/sqrt(2) in both layers, other hops N(0, scale^2)."""
+    rng = np.random.Generator(np.random.PCG64(int(seed)))
+    z1 = rng.standard_normal((9, 2, 1, 4, 4, 2))
+    z2 = rng.standard_normal((9, 1, 2, 4, 4, 2))
+    W1 = scale * (z1[..., 0] + 1j * z1[..., 1]) / np.sqrt(2)
+    W2 = scale * (z2[..., 0] + 1j * z2[..., 1]) / np.sqrt(2)
+    for W in (W1, W2):
+        for co in range(W.shape[1]):
+            for c in range(W.shape[2]):
+                W[0, co, c] = np.eye(4) / np.sqrt(2)
+    return L.ptc_weights_to_flat(W1, W2)
+
+
+def train(g, kappa, steps=300, batch=8, lr=2e-3, seed=5, act="bf16", log_every=50, log=None, ks=(0,)):
+    """Train a PTC network on lattice g.  Returns (flat weights, history dict)."""
+    gen = PairGenerator(g, kappa, seed, ks)
+    net = L.Ptc(g, init_weights(seed + 1), act)
+    losses = []
+    t0 = time.perf_counter()
+    for s in range(steps):
+        r, e = gen.batch(batch)
+        want = (s % log_every == 0) or s == steps - 1
+        loss = L.wd_ptc_train_step(net, r, e, batch, lr * (0.1 if s > 0.8 * steps else 1.0), want_loss=want)
+        if want:
+            losses.append((s, loss))
+            if log:
+                log(f"ptc step {s}: loss {loss:.4f}")
+    import torch
+
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    W = L.wd_ptc_get_weights(net)
+    net.close()
+    return W, {"losses": losses, "pairs": steps * batch, "sources": gen.sources, "seconds": wall,
+               "pair_generation_seconds": gen.solve_seconds}
