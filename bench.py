@@ -40,6 +40,8 @@ DIMS = (32, 32, 32, 64)
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_SITE = {"f64": 144 * 8, "f32": 144 * 4}
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "dslash_hop_32x32x32x64_traffic.txt")
+# pre-tuned hop variants for MI355X (written by wd_tune_dslash; used without re-timing)
+TUNE_TABLE = os.path.join(ROOT, "paper_0710_2442_amd", "tuned", "mi355x_hop.jsonl")
 KERNEL_SOURCES = ["paper_0710_2442_amd/csrc/dslash.hip", "paper_0710_2442_amd/csrc/wd_device.h"]
 
 
@@ -55,7 +57,7 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(prec):
+def read_traffic(prec, variant):
     """HBM bytes per launch from the committed counter summary, if current."""
     if not os.path.exists(TRAFFIC_SUMMARY):
         return None, "no counter summary"
@@ -67,9 +69,9 @@ def read_traffic(prec):
                 vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != kernel_hash():
         return None, "kernel changed since counters were taken"
-    key = f"hbm_bytes_per_launch_{prec}"
+    key = f"hbm_bytes_per_launch_{prec}_{'_'.join(str(v) for v in variant)}"
     if key not in vals:
-        return None, "no entry"
+        return None, f"no counter entry for variant {variant}"
     return float(vals[key]), "ok"
 
 
@@ -160,6 +162,11 @@ def mrhs_leg(wd, torch, syn):
     B = torch.cat([canon_to_field(g, syn.point_source(dims, s, c), "f64") for s in range(4) for c in range(3)])
     X = wd.wd_new_field(dims, "f64", 12)
     out = {}
+    for prec in ("f32", "f64"):
+        tg, tus = wd.wd_tune_dslash_mrhs(g, prec, 12)
+        log(f"tuned mrhs hop {prec}: XCD groups {tg} ({tus:.1f} us)")
+    for prec in ("f32", "f64"):
+        wd.wd_tune_dslash(g, prec)
 
     def timed(fn):
         fn()  # warm-up
@@ -323,6 +330,8 @@ def main():
     ap.add_argument("--no-learn", action="store_true")
     ap.add_argument("--learn-steps", type=int, default=400)
     ap.add_argument("--no-tune", action="store_true", help="use the default hop variant")
+    ap.add_argument("--tune-table", default=TUNE_TABLE, help="JSON-lines tuning table (read, appended)")
+    ap.add_argument("--retune", action="store_true", help="time all variants even if the table has an entry")
     ap.add_argument("--variant", default=None, help="force the hop variant 'block,groups,occ' (no tuning)")
     ap.add_argument("--only", choices=["f64", "f32"], default=None, help="time one precision only")
     ap.add_argument("--calib-copy", action="store_true",
@@ -356,7 +365,7 @@ def main():
             vb, vg, vo = (int(x) for x in args.variant.split(","))
             wd.wd_set_dslash_variant(g, prec, vb, vg, vo)
         elif not args.no_tune:
-            tb, tg, to, tus = wd.wd_tune_dslash(g, prec)
+            tb, tg, to, tus = wd.wd_tune_dslash(g, prec, args.tune_table, force=args.retune)
             log(f"tuned hop {prec}: block {tb}, XCD groups {tg}, occ {to} ({tus:.1f} us in the tuner)")
         sec, n, ms = time_hop(wd, torch, g, psi, prec, args.steps, args.warmup)
         gbs = vh * BYTES_PER_SITE[prec] / sec / 1e9
@@ -377,7 +386,7 @@ def main():
 
     head = "f64" if "f64" in results else precs[0]
     r = results[head]
-    traffic, why = read_traffic(head)
+    traffic, why = read_traffic(head, r["variant"])
     roof = {
         "bound": "hbm",
         "achieved": round(r["gbs"], 2),

@@ -249,6 +249,13 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path,
                          int force, int *block, int *groups, int *occ,
                          double *us);
 
+/* Tune the multi-RHS hop for nrhs right-hand sides: the number of XCD
+ * regions its 16-site tiles are grouped into (candidates checked byte for
+ * byte against linear order, then timed).  Outputs may be NULL.
+ * Synchronous. */
+wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, int *groups,
+                              double *us);
+
 /* Bit of the occ value: the hop writes its output with ordinary (cached)
  * stores instead of streaming stores, so that a following kernel can read a
  * freshly written field from the caches. */

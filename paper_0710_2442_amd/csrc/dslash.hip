@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void k_dslash_mrhs(KMrhs m) {
   const int lane = threadIdx.x & 15;
   const int rl = threadIdx.x >> 4;             // rhs within the block
   const int rg = blockIdx.y * 16 + rl;         // global rhs
-  const int i = blockIdx.x * 16 + lane;
+  const int i = tile_of(m.k) * 16 + lane;
   const size_t vp = (size_t)m.k.g.vpad;
   const bool live = rg < m.nrhs && !(m.k.skip && m.k.skip[(size_t)rg * m.skip_stride]);
   double nrm = 0.0;
@@ -189,7 +189,7 @@ unsigned dslash_grid_blocks(const wd_gauge *g) { return (unsigned)((g->geom.vpad
 // block size divides the slots and, for G > 0, the tiles of one time slice
 // split evenly into G regions.
 bool dslash_variant_ok(const Geom &G, int bs, int groups) {
-  if (bs != 64 && bs != 128 && bs != 256 && bs != 512) return false;
+  if (bs != 16 && bs != 64 && bs != 128 && bs != 256 && bs != 512) return false;
   if (groups == 0) return true;
   if (groups < 0 || groups > 64) return false;
   const long slice = (long)G.vh / G.L[3];
@@ -269,6 +269,13 @@ wd_status launch_dslash_mrhs_ex(const wd_gauge *g, wd_prec prec, const MrhsArgs 
   const bool norm = a.norm_out != nullptr;
   if (norm && (!m.k.partials || !m.k.counter)) return set_error(WD_ERR_ARG, "dslash_mrhs norm: no reduction buffer");
   const int epi = a.Y ? 2 : (a.X ? 1 : 0);
+  {
+    const int pi = (int)prec;
+    int groups = g->mrhs_groups[pi];
+    if (!dslash_variant_ok(g->geom, 16, groups)) groups = 0;
+    m.k.groups = groups;
+    m.k.tiles_per_slice = groups ? (int)((long)g->geom.vh / g->geom.L[3] / 16) : 0;
+  }
   const int per_block = std::min(16, (a.nrhs + 3) / 4 * 4);
   dim3 grid((unsigned)mrhs_grid_blocks(g), (unsigned)((a.nrhs + 15) / 16));
   dim3 block((unsigned)(16 * per_block));

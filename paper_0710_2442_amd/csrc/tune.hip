@@ -67,7 +67,7 @@ extern "C" {
 wd_status wd_set_dslash_variant(wd_gauge *g, wd_prec prec, int block, int groups, int occ) {
   if (!g) return set_error(WD_ERR_ARG, "gauge handle is NULL");
   if ((int)prec < 0 || (int)prec > 3) return set_error(WD_ERR_PREC, "prec = %d", (int)prec);
-  if (!dslash_variant_ok(g->geom, block, groups))
+  if (block < 64 || !dslash_variant_ok(g->geom, block, groups))
     return set_error(WD_ERR_ARG, "variant (block %d, groups %d) does not fit this lattice", block, groups);
   const int o = occ & ~WD_TUNE_CACHED_STORE;
   if ((o != 0 && o != 4) || (occ & ~(WD_TUNE_CACHED_STORE | 4)))
@@ -202,6 +202,78 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
   if (out_block) *out_block = bs;
   if (out_groups) *out_groups = groups;
   if (out_occ) *out_occ = occ;
+  if (out_us) *out_us = best_us;
+  return WD_OK;
+}
+
+// Multi-RHS hop: tune the XCD region count (16-site tiles) for nrhs
+// right-hand sides; candidates checked byte for byte against linear order.
+wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, int *out_groups, double *out_us) {
+  if (!g) return set_error(WD_ERR_ARG, "gauge handle is NULL");
+  if ((int)prec < 0 || (int)prec > 3) return set_error(WD_ERR_PREC, "prec = %d", (int)prec);
+  if (nrhs < 1 || nrhs > 64) return set_error(WD_ERR_ARG, "nrhs = %d", nrhs);
+  WD_HIP(hipSetDevice(g->device));
+  const Geom &G = g->geom;
+  const size_t hb = half_bytes(G, prec) * (size_t)nrhs;
+  hipStream_t st = g->own_stream;
+  void *in = nullptr, *ref = nullptr, *cand = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  wd_status rc = WD_OK;
+  std::vector<unsigned char> h_ref(hb), h_cand(hb);
+  const int save = g->mrhs_groups[prec];
+  int best_g = 0;
+  double best_us = 1e30;
+  do {
+    if ((rc = hip_check(hipMalloc(&in, hb), "tune alloc")) != WD_OK) break;
+    if ((rc = hip_check(hipMalloc(&ref, hb), "tune alloc")) != WD_OK) break;
+    if ((rc = hip_check(hipMalloc(&cand, hb), "tune alloc")) != WD_OK) break;
+    {
+      std::vector<unsigned char> h(hb);
+      uint64_t s = 0x243F6A8885A308D3ull;
+      for (size_t n = 0; n < hb; ++n) {
+        s ^= s << 13; s ^= s >> 7; s ^= s << 17;
+        h[n] = (unsigned char)(s >> 56);
+      }
+      // keep every value a finite number in every precision: clear the exponent MSBs
+      if (prec == WD_F64) for (size_t n = 7; n < hb; n += 8) h[n] &= 0x3f;
+      else for (size_t n = 1; n < hb; n += 2) h[n] &= 0x3f;
+      if ((rc = hip_check(hipMemcpy(in, h.data(), hb, hipMemcpyHostToDevice), "upload")) != WD_OK) break;
+    }
+    if ((rc = hip_check(hipEventCreate(&e0), "event")) != WD_OK) break;
+    if ((rc = hip_check(hipEventCreate(&e1), "event")) != WD_OK) break;
+    g->mrhs_groups[prec] = 0;
+    if ((rc = launch_dslash_mrhs(g, prec, in, ref, 1.0, WD_EVEN, 0, nrhs, st)) != WD_OK) break;
+    if ((rc = hip_check(hipMemcpyAsync(h_ref.data(), ref, hb, hipMemcpyDeviceToHost, st), "copy")) != WD_OK) break;
+    if ((rc = hip_check(hipStreamSynchronize(st), "sync")) != WD_OK) break;
+    for (int gr : {0, 2, 4, 8, 16}) {
+      if (!dslash_variant_ok(G, 16, gr)) continue;
+      g->mrhs_groups[prec] = gr;
+      if ((rc = launch_dslash_mrhs(g, prec, in, cand, 1.0, WD_EVEN, 0, nrhs, st)) != WD_OK) break;
+      if ((rc = hip_check(hipMemcpyAsync(h_cand.data(), cand, hb, hipMemcpyDeviceToHost, st), "copy")) != WD_OK)
+        break;
+      if ((rc = hip_check(hipStreamSynchronize(st), "sync")) != WD_OK) break;
+      if (memcmp(h_ref.data(), h_cand.data(), hb) != 0) continue;
+      const int reps = 6;
+      for (int w = 0; w < 2; ++w) (void)launch_dslash_mrhs(g, prec, in, cand, 1.0, WD_EVEN, 0, nrhs, st);
+      (void)hipEventRecord(e0, st);
+      for (int r = 0; r < reps; ++r) (void)launch_dslash_mrhs(g, prec, in, cand, 1.0, WD_EVEN, 0, nrhs, st);
+      (void)hipEventRecord(e1, st);
+      if ((rc = hip_check(hipEventSynchronize(e1), "tune timing")) != WD_OK) break;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      const double us = 1e3 * ms / reps;
+      if (getenv("WD_TUNE_VERBOSE")) fprintf(stderr, "tune mrhs p%d nrhs %d: groups %d: %.2f us\n", (int)prec, nrhs, gr, us);
+      if (us < best_us) { best_us = us; best_g = gr; }
+    }
+  } while (0);
+  g->mrhs_groups[prec] = (rc == WD_OK) ? best_g : save;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (in) (void)hipFree(in);
+  if (ref) (void)hipFree(ref);
+  if (cand) (void)hipFree(cand);
+  if (rc != WD_OK) return rc;
+  if (out_groups) *out_groups = best_g;
   if (out_us) *out_us = best_us;
   return WD_OK;
 }

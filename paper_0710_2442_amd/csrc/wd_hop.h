@@ -36,14 +36,14 @@ struct KDslash {
 // region's neighbour spinors (x1..x3 inside the slice, x4 one slice away)
 // are fetched into one L2 and re-read from there.  Requires
 // tiles_per_slice % G == 0 and gridDim.x == tiles_per_slice * L4.
-__device__ __forceinline__ int tile_of(const KDslash &k) {
-  const int b = blockIdx.x;
+__device__ __forceinline__ int tile_of(const KDslash &k, int b) {
   if (k.groups == 0) return b;
   const int G = k.groups;
   const int per = k.tiles_per_slice / G;
   const int x = b % G, q = b / G;
   return (q / per) * k.tiles_per_slice + x * per + (q % per);
 }
+__device__ __forceinline__ int tile_of(const KDslash &k) { return tile_of(k, (int)blockIdx.x); }
 
 // Site coordinates of checkerboard index i on parity p.
 struct Coords {

@@ -128,13 +128,14 @@ def test_bitwise_deterministic():
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("nrhs", [1, 5, 12])
 def test_mrhs_equals_single_rhs_bitwise(prec, nrhs):
-    dims = (6, 4, 6, 10)
+    dims = (8, 8, 8, 16)
     U = syn.gauge_field(dims, 0.3, 21)
     g = wd.Gauge(U, dims, -1, prec)
     psis = syn.gaussian_spinor(dims, 22, nrhs=nrhs)
     hb = wd.wd_field_bytes(dims, prec, 1, wd.WD_EVEN)
     src = torch.cat([to_field(g, psis[r], prec, wd.WD_ODD) for r in range(nrhs)])
     out = wd.wd_new_field(dims, prec, nrhs, wd.WD_EVEN)
+    gr, us = wd.wd_tune_dslash_mrhs(g, prec, nrhs)  # any region count must give the same bits
     wd.wd_dslash_mrhs(g, src, out, 0.7, wd.WD_EVEN, prec, nrhs)
     for r in range(nrhs):
         one = wd.wd_new_field(dims, prec, 1, wd.WD_EVEN)
