@@ -401,6 +401,10 @@ def main():
     }
     if traffic is None:
         roof["traffic_note"] = why
+    from paper_0710_2442_amd import perf_model
+
+    ratio = traffic / roof["algorithmic_bytes_per_launch"] if traffic else None
+    roof["model_eq1_eq2"] = perf_model.report(vh, head, r["sec_per_launch"], ratio)
     line = {
         "metric": "dslash_hbm_GBps",
         "value": round(r["gbs"], 2),

@@ -235,8 +235,9 @@ wd_status wd_ptc_train_step(wd_ptc *n, const void *r, const void *e, int B,
 /* Autotune the single-RHS hop of precision prec on this handle's lattice:
  * block size (64..512 threads), the number of XCD regions the blocks are
  * grouped into (0 = linear order), the register budget (occ 0: compiler's
- * choice; occ 4: at least 4 waves per SIMD) and the output store policy
- * (WD_TUNE_CACHED_STORE set in occ: cached stores).  Every candidate's output is
+ * choice; occ 4: at least 4 waves per SIMD), the output store policy
+ * (WD_TUNE_CACHED_STORE set in occ: cached stores) and a cap on resident
+ * blocks per CU (dynamic LDS in KiB << WD_TUNE_LDS_SHIFT).  Every candidate's output is
  * first compared byte for byte with the reference variant (256 threads,
  * linear, occ 0); matching candidates are timed with HIP events on
  * alternating even/odd hops and the fastest is kept in the handle.
@@ -260,9 +261,12 @@ wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, int *groups,
  * stores instead of streaming stores, so that a following kernel can read a
  * freshly written field from the caches. */
 enum { WD_TUNE_CACHED_STORE = 256 };
+/* The dynamic LDS (KiB, 0..64) reserved per block, shifted into occ: it caps
+ * the blocks resident on a CU and so the sites in flight per XCD. */
+enum { WD_TUNE_LDS_SHIFT = 16 };
 
 /* Set / read the hop variant used for precision prec.  occ: 0 or 4, or'ed
- * with WD_TUNE_CACHED_STORE.  WD_ERR_ARG if the variant does not fit the
+ * with WD_TUNE_CACHED_STORE and (KiB of LDS << WD_TUNE_LDS_SHIFT).  WD_ERR_ARG if the variant does not fit the
  * lattice (see wd_tune_dslash). */
 wd_status wd_set_dslash_variant(wd_gauge *g, wd_prec prec, int block, int groups,
                                 int occ);

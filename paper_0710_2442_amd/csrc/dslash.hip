@@ -157,29 +157,34 @@ static KDslash make_k(const wd_gauge *g, wd_prec prec, int parity) {
   return k;
 }
 
+// `lds` bytes of dynamic LDS (unused by the kernel) cap the resident blocks
+// per CU (160 KiB of LDS per CU): fewer sites in flight per XCD means a
+// smaller set of neighbour spinors the L2 must hold for reuse.
 template <int P, bool DAG, int EPI, bool NORM>
-static void launch_t(const KDslash &k, unsigned nblk, unsigned bs, hipStream_t st) {
-  if (k.occ == 4) hipLaunchKernelGGL((k_dslash_o4<P, DAG, EPI, NORM>), dim3(nblk), dim3(bs), 0, st, k);
-  else hipLaunchKernelGGL((k_dslash_o0<P, DAG, EPI, NORM>), dim3(nblk), dim3(bs), 0, st, k);
+static void launch_t(const KDslash &k, unsigned nblk, unsigned bs, unsigned lds, hipStream_t st) {
+  if (k.occ == 4) hipLaunchKernelGGL((k_dslash_o4<P, DAG, EPI, NORM>), dim3(nblk), dim3(bs), lds, st, k);
+  else hipLaunchKernelGGL((k_dslash_o0<P, DAG, EPI, NORM>), dim3(nblk), dim3(bs), lds, st, k);
 }
 
 template <int P, bool DAG>
-static void launch_epi(const KDslash &k, int epi, bool norm, unsigned nblk, unsigned bs, hipStream_t st) {
+static void launch_epi(const KDslash &k, int epi, bool norm, unsigned nblk, unsigned bs, unsigned lds,
+                       hipStream_t st) {
   if (norm) {
-    if (epi == 0) launch_t<P, DAG, 0, true>(k, nblk, bs, st);
-    else if (epi == 1) launch_t<P, DAG, 1, true>(k, nblk, bs, st);
-    else launch_t<P, DAG, 2, true>(k, nblk, bs, st);
+    if (epi == 0) launch_t<P, DAG, 0, true>(k, nblk, bs, lds, st);
+    else if (epi == 1) launch_t<P, DAG, 1, true>(k, nblk, bs, lds, st);
+    else launch_t<P, DAG, 2, true>(k, nblk, bs, lds, st);
   } else {
-    if (epi == 0) launch_t<P, DAG, 0, false>(k, nblk, bs, st);
-    else if (epi == 1) launch_t<P, DAG, 1, false>(k, nblk, bs, st);
-    else launch_t<P, DAG, 2, false>(k, nblk, bs, st);
+    if (epi == 0) launch_t<P, DAG, 0, false>(k, nblk, bs, lds, st);
+    else if (epi == 1) launch_t<P, DAG, 1, false>(k, nblk, bs, lds, st);
+    else launch_t<P, DAG, 2, false>(k, nblk, bs, lds, st);
   }
 }
 
 template <int P>
-static void launch_prec(const KDslash &k, bool dag, int epi, bool norm, unsigned nblk, unsigned bs, hipStream_t st) {
-  if (dag) launch_epi<P, true>(k, epi, norm, nblk, bs, st);
-  else launch_epi<P, false>(k, epi, norm, nblk, bs, st);
+static void launch_prec(const KDslash &k, bool dag, int epi, bool norm, unsigned nblk, unsigned bs, unsigned lds,
+                        hipStream_t st) {
+  if (dag) launch_epi<P, true>(k, epi, norm, nblk, bs, lds, st);
+  else launch_epi<P, false>(k, epi, norm, nblk, bs, lds, st);
 }
 
 // Largest grid of a single-RHS hop launch (smallest block size, 64).
@@ -222,11 +227,12 @@ wd_status launch_dslash(const wd_gauge *g, wd_prec prec, const DslashArgs &a, hi
   k.nt_store = g->hop_ntst[pi];
   k.tiles_per_slice = groups ? (int)((long)g->geom.vh / g->geom.L[3] / bs) : 0;
   const unsigned nblk = (unsigned)((g->geom.vpad + bs - 1) / bs);
+  const unsigned lds = (unsigned)g->hop_lds[pi];
   switch (prec) {
-    case WD_F64: launch_prec<WD_F64>(k, a.dagger, epi, norm, nblk, bs, st); break;
-    case WD_F32: launch_prec<WD_F32>(k, a.dagger, epi, norm, nblk, bs, st); break;
-    case WD_F16: launch_prec<WD_F16>(k, a.dagger, epi, norm, nblk, bs, st); break;
-    case WD_BF16: launch_prec<WD_BF16>(k, a.dagger, epi, norm, nblk, bs, st); break;
+    case WD_F64: launch_prec<WD_F64>(k, a.dagger, epi, norm, nblk, bs, lds, st); break;
+    case WD_F32: launch_prec<WD_F32>(k, a.dagger, epi, norm, nblk, bs, lds, st); break;
+    case WD_F16: launch_prec<WD_F16>(k, a.dagger, epi, norm, nblk, bs, lds, st); break;
+    case WD_BF16: launch_prec<WD_BF16>(k, a.dagger, epi, norm, nblk, bs, lds, st); break;
     default: return set_error(WD_ERR_PREC, "dslash: unknown precision %d", (int)prec);
   }
   return hip_check(hipGetLastError(), "dslash launch");

@@ -58,6 +58,19 @@ static void cache_append(const char *path, const std::string &key, int bs, int g
   fclose(f);
 }
 
+// occ value: bits 0..7 register budget (0 or 4), WD_TUNE_CACHED_STORE, and
+// the dynamic LDS per block in KiB at WD_TUNE_LDS_SHIFT (0..64)
+static wd_status decode_occ(int occ, int &o, int &nts, int &lkb) {
+  o = occ & 0xff;
+  nts = (occ & WD_TUNE_CACHED_STORE) ? 0 : 1;
+  lkb = (occ >> WD_TUNE_LDS_SHIFT) & 0xff;
+  const int rest = occ & ~(0xff | WD_TUNE_CACHED_STORE | (0xff << WD_TUNE_LDS_SHIFT));
+  if ((o != 0 && o != 4) || rest || lkb > 64)
+    return set_error(WD_ERR_ARG, "occ = 0x%x: register budget 0 or 4, | WD_TUNE_CACHED_STORE, | KiB << %d (<= 64)",
+                     occ, WD_TUNE_LDS_SHIFT);
+  return WD_OK;
+}
+
 }  // namespace wd
 
 using namespace wd;
@@ -69,13 +82,13 @@ wd_status wd_set_dslash_variant(wd_gauge *g, wd_prec prec, int block, int groups
   if ((int)prec < 0 || (int)prec > 3) return set_error(WD_ERR_PREC, "prec = %d", (int)prec);
   if (block < 64 || !dslash_variant_ok(g->geom, block, groups))
     return set_error(WD_ERR_ARG, "variant (block %d, groups %d) does not fit this lattice", block, groups);
-  const int o = occ & ~WD_TUNE_CACHED_STORE;
-  if ((o != 0 && o != 4) || (occ & ~(WD_TUNE_CACHED_STORE | 4)))
-    return set_error(WD_ERR_ARG, "occ = %d: must be 0 or 4, optionally | WD_TUNE_CACHED_STORE", occ);
+  int o, nts, lkb;
+  WD_TRY(decode_occ(occ, o, nts, lkb));
   g->hop_block[prec] = block;
   g->hop_groups[prec] = groups;
   g->hop_occ[prec] = o;
-  g->hop_ntst[prec] = (occ & WD_TUNE_CACHED_STORE) ? 0 : 1;
+  g->hop_ntst[prec] = nts;
+  g->hop_lds[prec] = lkb * 1024;
   return WD_OK;
 }
 
@@ -84,7 +97,8 @@ wd_status wd_get_dslash_variant(const wd_gauge *g, wd_prec prec, int *block, int
   if ((int)prec < 0 || (int)prec > 3) return set_error(WD_ERR_PREC, "prec = %d", (int)prec);
   *block = g->hop_block[prec];
   *groups = g->hop_groups[prec];
-  *occ = g->hop_occ[prec] | (g->hop_ntst[prec] ? 0 : WD_TUNE_CACHED_STORE);
+  *occ = g->hop_occ[prec] | (g->hop_ntst[prec] ? 0 : WD_TUNE_CACHED_STORE) |
+         ((g->hop_lds[prec] / 1024) << WD_TUNE_LDS_SHIFT);
   return WD_OK;
 }
 
@@ -97,11 +111,7 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
   int bs = 256, groups = 0, occ = 0;
   double best_us = -1.0;
   if (cache_path && !force && cache_lookup(cache_path, key, bs, groups, occ, best_us) &&
-      dslash_variant_ok(g->geom, bs, groups) && ((occ & ~WD_TUNE_CACHED_STORE) == 0 || (occ & ~WD_TUNE_CACHED_STORE) == 4)) {
-    g->hop_block[prec] = bs;
-    g->hop_groups[prec] = groups;
-    g->hop_occ[prec] = occ & ~WD_TUNE_CACHED_STORE;
-    g->hop_ntst[prec] = (occ & WD_TUNE_CACHED_STORE) ? 0 : 1;
+      dslash_variant_ok(g->geom, bs, groups) && wd_set_dslash_variant(g, prec, bs, groups, occ) == WD_OK) {
   } else {
     const Geom &G = g->geom;
     const size_t hb = half_bytes(G, prec);
@@ -132,11 +142,12 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
       if ((rc = hip_check(hipEventCreate(&e0), "event")) != WD_OK) break;
       if ((rc = hip_check(hipEventCreate(&e1), "event")) != WD_OK) break;
       const int save_b = g->hop_block[prec], save_g = g->hop_groups[prec], save_o = g->hop_occ[prec];
-      const int save_n = g->hop_ntst[prec];
+      const int save_n = g->hop_ntst[prec], save_l = g->hop_lds[prec];
       DslashArgs a;
       a.in = in; a.a = 1.0; a.parity = WD_EVEN;
       // reference variant
       g->hop_block[prec] = 256; g->hop_groups[prec] = 0; g->hop_occ[prec] = 0; g->hop_ntst[prec] = 1;
+      g->hop_lds[prec] = 0;
       a.out = ref;
       if ((rc = launch_dslash(g, prec, a, st)) != WD_OK) break;
       if ((rc = hip_check(hipMemcpyAsync(h_ref.data(), ref, hb, hipMemcpyDeviceToHost, st), "copy")) != WD_OK) break;
@@ -144,13 +155,22 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
       const int blocks[] = {64, 128, 256, 512};
       const int grps[] = {0, 2, 4, 8, 16};
       best_us = 1e30;
-      int nbest_b = 256, nbest_g = 0, nbest_o = 0, nbest_n = 1;
+      int nbest_b = 256, nbest_g = 0, nbest_o = 0, nbest_n = 1, nbest_l = 0;
+      size_t lds_max = 65536;
+      {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, g->device) == hipSuccess) lds_max = prop.sharedMemPerBlock;
+      }
+      for (int lkb : {0, 24, 40, 60})
       for (int nts : {1, 0})
       for (int oc : {0, 4})
       for (int b : blocks) {
         for (int gr : grps) {
           if (!dslash_variant_ok(G, b, gr)) continue;
+          if (oc == 4 && lkb != 0) continue;  // both only lower occupancy; keep the grid small
+          if ((size_t)lkb * 1024 + 1024 > lds_max) continue;
           g->hop_block[prec] = b; g->hop_groups[prec] = gr; g->hop_occ[prec] = oc; g->hop_ntst[prec] = nts;
+          g->hop_lds[prec] = lkb * 1024;
           if ((rc = launch_pack_spinor(g, canon, in, WD_ODD, prec, st)) != WD_OK) break;
           a.out = cand;
           if ((rc = hip_check(hipMemsetAsync(cand, 0xff, hb, st), "memset")) != WD_OK) break;
@@ -174,21 +194,25 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
           (void)hipEventElapsedTime(&ms, e0, e1);
           const double us = 1e3 * ms / (2 * reps);
           if (getenv("WD_TUNE_VERBOSE"))
-            fprintf(stderr, "tune %s: block %d groups %d occ %d ntstore %d: %.2f us\n", key.c_str(), b, gr, oc, nts, us);
-          if (us < best_us) { best_us = us; nbest_b = b; nbest_g = gr; nbest_o = oc; nbest_n = nts; }
+            fprintf(stderr, "tune %s: block %d groups %d occ %d ntstore %d lds %dK: %.2f us\n", key.c_str(), b, gr, oc,
+                    nts, lkb, us);
+          if (us < best_us) { best_us = us; nbest_b = b; nbest_g = gr; nbest_o = oc; nbest_n = nts; nbest_l = lkb; }
         }
         if (rc != WD_OK) break;
       }
       if (rc != WD_OK) {
         g->hop_block[prec] = save_b; g->hop_groups[prec] = save_g; g->hop_occ[prec] = save_o;
         g->hop_ntst[prec] = save_n;
+        g->hop_lds[prec] = save_l;
         break;
       }
       g->hop_block[prec] = nbest_b;
       g->hop_groups[prec] = nbest_g;
       g->hop_occ[prec] = nbest_o;
       g->hop_ntst[prec] = nbest_n;
-      bs = nbest_b; groups = nbest_g; occ = nbest_o | (nbest_n ? 0 : WD_TUNE_CACHED_STORE);
+      g->hop_lds[prec] = nbest_l * 1024;
+      bs = nbest_b; groups = nbest_g;
+      occ = nbest_o | (nbest_n ? 0 : WD_TUNE_CACHED_STORE) | (nbest_l << WD_TUNE_LDS_SHIFT);
       if (cache_path) cache_append(cache_path, key, bs, groups, occ, best_us);
     } while (0);
     if (e0) (void)hipEventDestroy(e0);
