@@ -24,7 +24,13 @@
  *
  * Device field layout ("field"): structure of arrays on one checkerboard.
  * A half field holds the V_h sites of one parity in wd_vh_pad(dims) slots;
- * spin-colour component c = 3*spin + colour.
+ * spin-colour component c = 3*spin + colour, with the spin index in the
+ * basis where gamma_4 is diagonal: stored psi' = S psi, S = (1/sqrt 2) *
+ * [[1, 1], [1, -1]] in 2x2 spin blocks (so psi'_{0,1} = (psi_{0,1} +
+ * psi_{2,3}) / sqrt 2 and psi'_{2,3} = (psi_{0,1} - psi_{2,3}) / sqrt 2,
+ * computed as (a + b) * r, (a - b) * r with r = 1/sqrt 2 in double).  S is
+ * unitary, so norms and inner products of fields are the chiral-basis ones;
+ * wd_spinor_pack/unpack convert.
  *   WD_F64 : 12 planes of double2  -- plane c holds component c
  *   WD_F32 :  6 planes of float4   -- plane k holds components 2k, 2k+1
  *   WD_F16 :  3 planes of 8 x half  (components 4k..4k+3, re/im interleaved),

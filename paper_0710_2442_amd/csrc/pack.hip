@@ -30,6 +30,22 @@ __device__ __forceinline__ size_t canon_index(const Geom &g, int i, int parity) 
   return (size_t)x1 + (size_t)g.L[0] * rest;
 }
 
+// Chiral basis -> storage basis (and back: S is an involution):
+// spins (0,1) <- (psi_u + psi_l) / sqrt 2, spins (2,3) <- (psi_u - psi_l) / sqrt 2,
+// computed as (a + b) * r and (a - b) * r with r = 1/sqrt 2 rounded to double.
+__device__ __forceinline__ void to_storage_basis(const double *src, double (&o)[12][2]) {
+  const double r = 0.70710678118654752440;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const double a = src[2 * c + q], b = src[2 * (c + 6) + q];
+      o[c][q] = (a + b) * r;
+      o[c + 6][q] = (a - b) * r;
+    }
+  }
+}
+
 template <int P>
 __global__ __launch_bounds__(256) void k_pack_spinor(KPack k) {
   using T = RealOf<P>;
@@ -42,8 +58,10 @@ __global__ __launch_bounds__(256) void k_pack_spinor(KPack k) {
   if (i < k.g.vh) {
     const size_t idx = canon_index(k.g, i, parity);
     const double *src = k.canon + idx * 24;
+    double b[12][2];
+    to_storage_basis(src, b);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) s[c] = {(T)src[2 * c], (T)src[2 * c + 1]};
+    for (int c = 0; c < 12; ++c) s[c] = {(T)b[c][0], (T)b[c][1]};
   } else {
 #pragma unroll
     for (int c = 0; c < 12; ++c) s[c] = {(T)0, (T)0};
@@ -63,10 +81,18 @@ __global__ __launch_bounds__(256) void k_unpack_spinor(KPack k) {
   Spinor<P>::load(src, (size_t)k.g.vpad, i, s);
   const size_t idx = canon_index(k.g, i, parity);
   double *dst = k.canon_out + idx * 24;
+  double b[12][2];
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
-    dst[2 * c] = (double)s[c].re;
-    dst[2 * c + 1] = (double)s[c].im;
+    b[c][0] = (double)s[c].re;
+    b[c][1] = (double)s[c].im;
+  }
+  double o[12][2];
+  to_storage_basis(&b[0][0], o);  // S is its own inverse
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    dst[2 * c] = o[c][0];
+    dst[2 * c + 1] = o[c][1];
   }
 }
 

@@ -13,6 +13,8 @@
 //
 // Network: 1 -> 2 -> 1 channels, weights FP32 ([layer][h][c'][c][4][4] complex,
 // 288 + 288 = 576 complex numbers), activations stored in BF16 (or FP32),
+// spin matrices given in the chiral basis and rotated into the fields' storage
+// basis for the kernels (the optimiser works on the chiral-basis values),
 // arithmetic and gradients in FP32, reductions over sites in FP64 in a
 // fixed order.
 //
@@ -269,6 +271,40 @@ __global__ void k_ptc_adjoint(const float *W, float *Wa, int cout, int cin) {
     }
 }
 
+// out = S M S for n complex 4x4 spin matrices (chiral <-> storage basis;
+// S = (1/sqrt 2) [[1, 1], [1, -1]] in 2x2 blocks is real, symmetric, S^2 = 1).
+__global__ void k_ptc_rotate(const float *M, float *out, int n) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  const float r = 0.70710678118654752440f;
+  float S[4][4];
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) S[a][b] = ((a & 1) == (b & 1)) ? ((a >= 2 && b >= 2) ? -r : r) : 0.f;
+  const float *src = M + 32 * m;
+  float T[4][4][2];
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
+      float re = 0.f, im = 0.f;
+      for (int j = 0; j < 4; ++j) {
+        re += src[2 * (4 * a + j)] * S[j][b];
+        im += src[2 * (4 * a + j) + 1] * S[j][b];
+      }
+      T[a][b][0] = re;
+      T[a][b][1] = im;
+    }
+  float *dst = out + 32 * m;
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
+      float re = 0.f, im = 0.f;
+      for (int i = 0; i < 4; ++i) {
+        re += S[a][i] * T[i][b][0];
+        im += S[a][i] * T[i][b][1];
+      }
+      dst[2 * (4 * a + b)] = re;
+      dst[2 * (4 * a + b) + 1] = im;
+    }
+}
+
 // Loss pieces: d = y - e (FP32 full fields); gy = scale * d; partial |d|^2.
 __global__ __launch_bounds__(256) void k_ptc_loss(const char *y, const char *e, char *gy, Geom g, float scale,
                                                   double *partials, unsigned *counter, double *loss) {
@@ -317,7 +353,9 @@ __global__ void k_adam(float *w, const float *g, float *m, float *v, int n, floa
 // ============================================================ host side
 struct wd_ptc {
   const wd_gauge *g;
-  float *W;        // device, 1152 floats: layer 1 (576) then layer 2 (576)
+  float *Wc;       // device, the parameters: chiral-basis weights, 1152 floats
+  float *gradc;    // device, gradient with respect to Wc
+  float *W;        // device, the same weights in the storage spin basis (used by the kernels)
   float *Wadj;     // device, adjoint weights of both layers
   float *grad;     // device, 1152
   float *m, *v;    // Adam state
@@ -409,6 +447,8 @@ static wd_status ptc_alloc(wd_ptc *n) {
   const size_t fa = 2 * half_bytes(G, n->act), f32 = 2 * half_bytes(G, WD_F32);
   n->nblk = (int)((G.vpad + PTC_BS - 1) / PTC_BS) * 2;
   WD_HIP(hipMalloc(&n->W, PTC_NW * sizeof(float)));
+  WD_HIP(hipMalloc(&n->Wc, PTC_NW * sizeof(float)));
+  WD_HIP(hipMalloc(&n->gradc, PTC_NW * sizeof(float)));
   WD_HIP(hipMalloc(&n->Wadj, PTC_NW * sizeof(float)));
   WD_HIP(hipMalloc(&n->grad, PTC_NW * sizeof(float)));
   WD_HIP(hipMalloc(&n->m, PTC_NW * sizeof(float)));
@@ -428,7 +468,7 @@ static wd_status ptc_alloc(wd_ptc *n) {
 }
 
 static void ptc_free(wd_ptc *n) {
-  void *ps[] = {n->W, n->Wadj, n->grad, n->m, n->v, n->x0, n->y1, n->y2, n->gy2, n->gy1, n->partials, n->scal, n->cnt};
+  void *ps[] = {n->Wc, n->gradc, n->W, n->Wadj, n->grad, n->m, n->v, n->x0, n->y1, n->y2, n->gy2, n->gy1, n->partials, n->scal, n->cnt};
   for (void *p : ps)
     if (p) (void)hipFree(p);
   delete n;
@@ -462,7 +502,15 @@ static wd_status ptc_loss_grad(wd_ptc *n, const void *r, const void *e, int B, h
                      576, n->grad);
   hipLaunchKernelGGL(k_ptc_reduce, dim3((576 + 255) / 256), dim3(256), 0, st,
                      (const double *)(n->partials + (size_t)n->nblk * 576), n->nblk, 576, n->grad + 576);
+  // gradient with respect to the chiral-basis parameters (W = S Wc S, S orthogonal and symmetric)
+  hipLaunchKernelGGL(k_ptc_rotate, dim3(1), dim3(128), 0, st, (const float *)n->grad, n->gradc, PTC_NW / 32);
   return hip_check(hipGetLastError(), "ptc loss/grad");
+}
+
+// kernels' weights <- parameters (rotate every 4x4 block into the storage basis)
+static wd_status ptc_sync_weights(wd_ptc *n, hipStream_t st) {
+  hipLaunchKernelGGL(k_ptc_rotate, dim3(1), dim3(128), 0, st, (const float *)n->Wc, n->W, PTC_NW / 32);
+  return hip_check(hipGetLastError(), "ptc rotate");
 }
 
 static wd_status check_pair_args(const wd_ptc *n, const void *r, const void *e, int B) {
@@ -492,7 +540,9 @@ wd_status wd_ptc_create(const wd_gauge *g, const float *W_host, wd_prec act_prec
   n->g = g;
   n->act = act_prec;
   wd_status rc = ptc_alloc(n);
-  if (rc == WD_OK) rc = hip_check(hipMemcpy(n->W, W_host, PTC_NW * sizeof(float), hipMemcpyHostToDevice), "weights");
+  if (rc == WD_OK) rc = hip_check(hipMemcpy(n->Wc, W_host, PTC_NW * sizeof(float), hipMemcpyHostToDevice), "weights");
+  if (rc == WD_OK) rc = ptc_sync_weights(n, g->stream);
+  if (rc == WD_OK) rc = hip_check(hipStreamSynchronize(g->stream), "weights");
   if (rc != WD_OK) {
     ptc_free(n);
     return rc;
@@ -512,7 +562,10 @@ wd_status wd_ptc_destroy(wd_ptc *n) {
 wd_status wd_ptc_set_weights(wd_ptc *n, const float *W_host) {
   if (!n || !W_host) return set_error(WD_ERR_ARG, "NULL argument");
   WD_HIP(hipSetDevice(n->g->device));
-  WD_HIP(hipMemcpy(n->W, W_host, PTC_NW * sizeof(float), hipMemcpyHostToDevice));
+  WD_HIP(hipStreamSynchronize(n->g->stream));
+  WD_HIP(hipMemcpy(n->Wc, W_host, PTC_NW * sizeof(float), hipMemcpyHostToDevice));
+  WD_TRY(ptc_sync_weights(n, n->g->stream));
+  WD_HIP(hipStreamSynchronize(n->g->stream));
   WD_HIP(hipMemset(n->m, 0, PTC_NW * sizeof(float)));
   WD_HIP(hipMemset(n->v, 0, PTC_NW * sizeof(float)));
   n->t = 0;
@@ -523,7 +576,7 @@ wd_status wd_ptc_get_weights(const wd_ptc *n, float *W_host) {
   if (!n || !W_host) return set_error(WD_ERR_ARG, "NULL argument");
   WD_HIP(hipSetDevice(n->g->device));
   WD_HIP(hipStreamSynchronize(n->g->stream));
-  WD_HIP(hipMemcpy(W_host, n->W, PTC_NW * sizeof(float), hipMemcpyDeviceToHost));
+  WD_HIP(hipMemcpy(W_host, n->Wc, PTC_NW * sizeof(float), hipMemcpyDeviceToHost));
   return WD_OK;
 }
 
@@ -540,7 +593,7 @@ wd_status wd_ptc_loss_grad(wd_ptc *n, const void *r, const void *e, int B, doubl
   WD_TRY(ptc_loss_grad(n, r, e, B, st));
   double l = 0;
   WD_HIP(hipMemcpyAsync(&l, n->scal, sizeof(double), hipMemcpyDeviceToHost, st));
-  if (grad_host) WD_HIP(hipMemcpyAsync(grad_host, n->grad, PTC_NW * sizeof(float), hipMemcpyDeviceToHost, st));
+  if (grad_host) WD_HIP(hipMemcpyAsync(grad_host, n->gradc, PTC_NW * sizeof(float), hipMemcpyDeviceToHost, st));
   WD_HIP(hipStreamSynchronize(st));
   if (loss) *loss = l / B;
   return WD_OK;
@@ -554,9 +607,10 @@ wd_status wd_ptc_train_step(wd_ptc *n, const void *r, const void *e, int B, doub
   n->t += 1;
   const float b1 = 0.9f, b2 = 0.999f;
   const float c1 = 1.f - powf(b1, (float)n->t), c2 = 1.f - powf(b2, (float)n->t);
-  hipLaunchKernelGGL(k_adam, dim3((PTC_NW + 255) / 256), dim3(256), 0, st, n->W, (const float *)n->grad, n->m, n->v,
-                     PTC_NW, (float)lr, b1, b2, 1e-8f, c1, c2);
+  hipLaunchKernelGGL(k_adam, dim3((PTC_NW + 255) / 256), dim3(256), 0, st, n->Wc, (const float *)n->gradc, n->m,
+                     n->v, PTC_NW, (float)lr, b1, b2, 1e-8f, c1, c2);
   WD_HIP(hipGetLastError());
+  WD_TRY(ptc_sync_weights(n, st));
   if (loss) {
     double l = 0;
     WD_HIP(hipMemcpyAsync(&l, n->scal, sizeof(double), hipMemcpyDeviceToHost, st));

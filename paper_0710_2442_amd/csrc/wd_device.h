@@ -106,6 +106,16 @@ struct Spinor<WD_F64> {
       s[c] = {v.x, v.y};
     }
   }
+  // spins 0,1 (LOWER = false) or spins 2,3 (LOWER = true): components 6h .. 6h+5
+  template <bool LOWER>
+  __device__ static void load_half(const void *base, size_t vp, size_t i, cplx<double> (&s)[6]) {
+    const v2d *p = (const v2d *)base + i + (LOWER ? 6 : 0) * vp;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      v2d v = p[c * vp];
+      s[c] = {v.x, v.y};
+    }
+  }
   template <bool NT = true>
   __device__ static void store(void *base, size_t vp, size_t i, const cplx<double> (&s)[12]) {
     v2d *p = (v2d *)base + i;
@@ -122,6 +132,16 @@ struct Spinor<WD_F32> {
     const v4f *p = (const v4f *)base + i;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
+      v4f v = p[k * vp];
+      s[2 * k] = {v.x, v.y};
+      s[2 * k + 1] = {v.z, v.w};
+    }
+  }
+  template <bool LOWER>
+  __device__ static void load_half(const void *base, size_t vp, size_t i, cplx<float> (&s)[6]) {
+    const v4f *p = (const v4f *)base + i + (LOWER ? 3 : 0) * vp;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
       v4f v = p[k * vp];
       s[2 * k] = {v.x, v.y};
       s[2 * k + 1] = {v.z, v.w};
@@ -159,6 +179,18 @@ struct Spinor<WD_F16> {
       }
     }
   }
+  // components 6h .. 6h+5 live in packets (0, 1) or (1, 2)
+  template <bool LOWER>
+  __device__ static void load_half(const void *base, size_t vp, size_t i, cplx<float> (&s)[6]) {
+    const v4u *p = (const v4u *)base + i;
+    const float nrm = ((const float *)((const v4u *)base + 3 * vp))[i];
+    const v4u a = p[(LOWER ? 1 : 0) * vp], b = p[(LOWER ? 2 : 1) * vp];
+    const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    const int o = LOWER ? 2 : 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+      s[j] = {nrm * f16_to_f32((uint16_t)(w[o + j] & 0xffffu)), nrm * f16_to_f32((uint16_t)(w[o + j] >> 16))};
+  }
   template <bool NT = true>
   __device__ static void store(void *base, size_t vp, size_t i, const cplx<float> (&s)[12]) {
     float m = 0.f;
@@ -194,6 +226,16 @@ struct Spinor<WD_BF16> {
       for (int j = 0; j < 4; ++j)
         s[4 * k + j] = {bf16_to_f32((uint16_t)(w[j] & 0xffffu)), bf16_to_f32((uint16_t)(w[j] >> 16))};
     }
+  }
+  template <bool LOWER>
+  __device__ static void load_half(const void *base, size_t vp, size_t i, cplx<float> (&s)[6]) {
+    const v4u *p = (const v4u *)base + i;
+    const v4u a = p[(LOWER ? 1 : 0) * vp], b = p[(LOWER ? 2 : 1) * vp];
+    const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    const int o = LOWER ? 2 : 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+      s[j] = {bf16_to_f32((uint16_t)(w[o + j] & 0xffffu)), bf16_to_f32((uint16_t)(w[o + j] >> 16))};
   }
   template <bool NT = true>
   __device__ static void store(void *base, size_t vp, size_t i, const cplx<float> (&s)[12]) {
@@ -279,33 +321,35 @@ __device__ __forceinline__ void su3_mul(const cplx<T> (&u)[6], const cplx<T> (&r
 }
 
 // --------------------------------------------------------- spin projection
-// For direction MU (0..3 = x1..x4) and projector (1 + S gamma_MU), S = +-1,
-// in the chiral basis:
-//   rows 0,1 of (1 + S g) psi form the half spinor h = (h0, h1);
-//   rows 2,3 follow from h:
-//   MU=0: h = (p0 + S i p3, p1 + S i p2);  r2 = -S i h1, r3 = -S i h0
-//   MU=1: h = (p0 - S p3,   p1 + S p2);    r2 =  S h1,   r3 = -S h0
-//   MU=2: h = (p0 + S i p2, p1 - S i p3);  r2 = -S i h0, r3 =  S i h1
-//   MU=3: h = (p0 + S p2,   p1 + S p3);    r2 =  S h0,   r3 =  S h1
-// (derived from the explicit gamma matrices; checked against the dense form)
+// Fields are stored in the spin basis where gamma_4 is diagonal: psi' = S psi
+// with S = (1/sqrt 2) [[1, 1], [1, -1]] (2x2 spin blocks; real, orthogonal,
+// S = S^-1) applied to the chiral-basis spinor.  There gamma_4' =
+// diag(1, 1, -1, -1) and gamma_k' = [[0, -A_k], [A_k, 0]] with A_k the
+// upper-right block of the chiral gamma_k (A_1 = i s_x, A_2 = -i s_y,
+// A_3 = i s_z).  For the projector (1 + S gamma_MU), S = +-1:
+//   MU=0: h = (p0 - S i p3, p1 - S i p2);  lower rows = S i (g1, g0)
+//   MU=1: h = (p0 + S p3,   p1 - S p2);    lower rows = S (-g1, g0)
+//   MU=2: h = (p0 - S i p2, p1 + S i p3);  lower rows = S (i g0, -i g1)
+//   MU=3: S = +1: h = 2 (p0, p1), upper rows only;
+//         S = -1: h = 2 (p2, p3), lower rows only
+// where g = U h is the transported half spinor.  A time hop therefore reads
+// only half of the neighbour spinor.
 template <int MU, int S, class T>
 __device__ __forceinline__ void project(const cplx<T> (&p)[12], cplx<T> (&h)[6]) {
+  static_assert(MU < 3, "time hops use the half-spinor path");
   const T s = (T)S;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const cplx<T> p0 = p[a], p1 = p[3 + a], p2 = p[6 + a], p3 = p[9 + a];
     if constexpr (MU == 0) {
-      h[a] = p0 + s * mul_i(p3);
-      h[3 + a] = p1 + s * mul_i(p2);
+      h[a] = p0 - s * mul_i(p3);
+      h[3 + a] = p1 - s * mul_i(p2);
     } else if constexpr (MU == 1) {
-      h[a] = p0 - s * p3;
-      h[3 + a] = p1 + s * p2;
-    } else if constexpr (MU == 2) {
-      h[a] = p0 + s * mul_i(p2);
-      h[3 + a] = p1 - s * mul_i(p3);
+      h[a] = p0 + s * p3;
+      h[3 + a] = p1 - s * p2;
     } else {
-      h[a] = p0 + s * p2;
-      h[3 + a] = p1 + s * p3;
+      h[a] = p0 - s * mul_i(p2);
+      h[3 + a] = p1 + s * mul_i(p3);
     }
   }
 }
@@ -317,20 +361,27 @@ __device__ __forceinline__ void reconstruct_add(cplx<T> (&acc)[12], const cplx<T
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const cplx<T> g0 = g[a], g1 = g[3 + a];
-    acc[a] = acc[a] + g0;
-    acc[3 + a] = acc[3 + a] + g1;
-    if constexpr (MU == 0) {
-      acc[6 + a] = acc[6 + a] - s * mul_i(g1);
-      acc[9 + a] = acc[9 + a] - s * mul_i(g0);
-    } else if constexpr (MU == 1) {
-      acc[6 + a] = acc[6 + a] + s * g1;
-      acc[9 + a] = acc[9 + a] - s * g0;
-    } else if constexpr (MU == 2) {
-      acc[6 + a] = acc[6 + a] - s * mul_i(g0);
-      acc[9 + a] = acc[9 + a] + s * mul_i(g1);
+    if constexpr (MU == 3) {
+      if constexpr (S > 0) {
+        acc[a] = acc[a] + g0;
+        acc[3 + a] = acc[3 + a] + g1;
+      } else {
+        acc[6 + a] = acc[6 + a] + g0;
+        acc[9 + a] = acc[9 + a] + g1;
+      }
     } else {
-      acc[6 + a] = acc[6 + a] + s * g0;
-      acc[9 + a] = acc[9 + a] + s * g1;
+      acc[a] = acc[a] + g0;
+      acc[3 + a] = acc[3 + a] + g1;
+      if constexpr (MU == 0) {
+        acc[6 + a] = acc[6 + a] + s * mul_i(g1);
+        acc[9 + a] = acc[9 + a] + s * mul_i(g0);
+      } else if constexpr (MU == 1) {
+        acc[6 + a] = acc[6 + a] - s * g1;
+        acc[9 + a] = acc[9 + a] + s * g0;
+      } else {
+        acc[6 + a] = acc[6 + a] + s * mul_i(g0);
+        acc[9 + a] = acc[9 + a] - s * mul_i(g1);
+      }
     }
   }
 }

@@ -76,18 +76,23 @@ __device__ __forceinline__ void neighbours(const Geom &g, const Coords &c, int i
   nb[7] = i + ((c.x4 == 0) ? (g.L[3] - 1) * g.s4 : -g.s4);
 }
 
-// One hop: acc += M (1 + S gamma_MU) psi_nb, M = the stored hop link.
+// One hop: acc += M (1 + S gamma_MU) psi_nb, M = the stored hop link.  Time
+// hops (MU = 3) read only the half of the neighbour spinor that their
+// projector keeps (see the spin basis in wd_device.h).
 template <int P, int MU, int S>
 __device__ __forceinline__ void hop_term(cplx<RealOf<P>> (&acc)[12], const char *in, size_t vp, int nb,
                                          const char *links, int d, size_t i, RealOf<P> sign) {
   using T = RealOf<P>;
-  cplx<T> psi[12];
-  Spinor<P>::load(in, vp, nb, psi);
   cplx<T> h[6];
-  project<MU, S>(psi, h);
   if constexpr (MU == 3) {
+    Spinor<P>::template load_half<(S < 0)>(in, vp, nb, h);
+    const T f = (T)2 * sign;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) h[c] = sign * h[c];
+    for (int c = 0; c < 6; ++c) h[c] = f * h[c];
+  } else {
+    cplx<T> psi[12];
+    Spinor<P>::load(in, vp, nb, psi);
+    project<MU, S>(psi, h);
   }
   cplx<T> u[6];
   Link<T>::load(links, d, i, u);

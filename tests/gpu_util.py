@@ -38,3 +38,29 @@ def rel_err(got, want):
 
 def round_c64(a):
     return a.astype(np.complex64).astype(np.complex128)
+
+
+R = 0.70710678118654752440
+
+
+def to_storage_basis(psi):
+    """The library stores spin in the basis where gamma_4 is diagonal:
+    spins (0,1) <- (a + b) * r, spins (2,3) <- (a - b) * r, a = spins (0,1),
+    b = spins (2,3), r = 1/sqrt 2 (the map is its own inverse)."""
+    a = psi[..., 0:2, :]
+    b = psi[..., 2:4, :]
+    return np.concatenate([(a + b) * R, (a - b) * R], axis=-2)
+
+
+def storage_round(psi, prec):
+    """psi as the GPU sees it after storing it in `prec` (rounding happens in
+    the storage basis), returned in the chiral basis."""
+    from oracle import solvers
+    t = to_storage_basis(psi)
+    if prec == "f64":
+        r = t
+    elif prec == "f32":
+        r = t.astype(np.complex64).astype(np.complex128)
+    else:
+        r = solvers.round_storage(t, prec).astype(np.complex128)
+    return to_storage_basis(r)

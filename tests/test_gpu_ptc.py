@@ -14,7 +14,7 @@ import torch
 
 import paper_0710_2442_amd as wd
 import synthetic as syn
-from gpu_util import from_field, rel_err, round_c64, to_field
+from gpu_util import from_field, rel_err, round_c64, storage_round, to_field
 from oracle import ptc, solvers, wilson
 
 pytestmark = pytest.mark.gpu
@@ -33,7 +33,8 @@ def _weights(seed, scale=0.3):
 
 
 def _bf16(a):
-    return solvers.round_storage(a, "bf16").astype(np.complex128)
+    """bfloat16 storage of activations, which the library keeps in its storage spin basis."""
+    return storage_round(a, "bf16")
 
 
 @pytest.mark.parametrize("act", ["f32", "bf16"])
@@ -47,7 +48,7 @@ def test_forward_matches_oracle(act):
     fy = wd.wd_new_field(DIMS, "f32")
     wd.wd_ptc_apply(n, fr, fy)
     got = from_field(g, fy, "f32")
-    Ur, rr = round_c64(U), round_c64(r)
+    Ur, rr = round_c64(U), storage_round(r, "f32")
     if act == "f32":
         want = ptc.network(Ur, rr, W1, W2)
         assert rel_err(got, want) <= 1e-5
@@ -92,7 +93,8 @@ def test_loss_and_gradients_match_oracle():
     fe = torch.cat([to_field(g, es[b], "f32") for b in range(2)])
     loss, grad = wd.wd_ptc_loss_grad(n, fr, fe, 2)
     Ur = round_c64(U)
-    L, g1, g2 = ptc.loss_and_grads(Ur, W1, W2, [round_c64(x) for x in rs], [round_c64(x) for x in es])
+    L, g1, g2 = ptc.loss_and_grads(Ur, W1, W2, [storage_round(x, "f32") for x in rs],
+                                   [storage_round(x, "f32") for x in es])
     assert abs(loss - L) <= 1e-5 * L
     G1, G2 = wd.ptc_flat_to_weights(grad)
     want = np.concatenate([g1.ravel(), g2.ravel()])
@@ -120,7 +122,8 @@ def test_adam_steps_follow_oracle_and_reduce_loss():
     W_gpu = wd.wd_ptc_get_weights(n)
     # oracle: one Adam step from the same weights with the oracle's gradients
     Ur = round_c64(U)
-    L, g1, g2 = ptc.loss_and_grads(Ur, W1, W2, [round_c64(x) for x in rs], [round_c64(x) for x in es])
+    L, g1, g2 = ptc.loss_and_grads(Ur, W1, W2, [storage_round(x, "f32") for x in rs],
+                                   [storage_round(x, "f32") for x in es])
     gflat = np.concatenate([g1.ravel(), g2.ravel()])
     w = np.concatenate([W1.ravel(), W2.ravel()])
     w1, _, _ = ptc.adam_step(w, gflat, np.zeros((2, 576)), np.zeros((2, 576)), 1, lr=lr)
