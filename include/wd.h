@@ -22,24 +22,30 @@
  * Canonical ("canon") layouts, complex128 = two doubles (re, im):
  *   spinor [V][4 spin][3 colour];   gauge [V][4 mu][3 row][3 col].
  *
- * Device field layout ("field"): structure of arrays on one checkerboard.
- * A half field holds the V_h sites of one parity in wd_vh_pad(dims) slots;
- * spin-colour component c = 3*spin + colour, with the spin index in the
- * basis where gamma_4 is diagonal: stored psi' = S psi, S = (1/sqrt 2) *
- * [[1, 1], [1, -1]] in 2x2 spin blocks (so psi'_{0,1} = (psi_{0,1} +
- * psi_{2,3}) / sqrt 2 and psi'_{2,3} = (psi_{0,1} - psi_{2,3}) / sqrt 2,
- * computed as (a + b) * r, (a - b) * r with r = 1/sqrt 2 in double).  S is
- * unitary, so norms and inner products of fields are the chiral-basis ones;
- * wd_spinor_pack/unpack convert.
- *   WD_F64 : 12 planes of double2  -- plane c holds component c
- *   WD_F32 :  6 planes of float4   -- plane k holds components 2k, 2k+1
- *   WD_F16 :  3 planes of 8 x half  (components 4k..4k+3, re/im interleaved),
- *             then one plane of float: stored value = component / s_x with
- *             s_x = the largest |real| of the site's 24 reals (0 -> all zero)
- *   WD_BF16:  3 planes of 8 x bfloat16 (round to nearest even)
- * Element (plane k, cb i) sits at k * wd_vh_pad(dims) + i.  A full field is
- * the even half followed by the odd half.  With nrhs right-hand sides the
- * right-hand side index is outermost.  wd_field_bytes() gives the size.
+ * Device field layout ("field"): one checkerboard, chunked by 64 sites.
+ * A half field holds the V_h sites of one parity in wd_vh_pad(dims) slots
+ * (a multiple of 256; slots past V_h hold zeros).  Spin-colour component
+ * c = 3*spin + colour, with the spin index in the basis where gamma_4 is
+ * diagonal: stored psi' = S psi, S = (1/sqrt 2) * [[1, 1], [1, -1]] in 2x2
+ * spin blocks (so psi'_{0,1} = (psi_{0,1} + psi_{2,3}) / sqrt 2 and
+ * psi'_{2,3} = (psi_{0,1} - psi_{2,3}) / sqrt 2, computed as (a + b) * r,
+ * (a - b) * r with r = 1/sqrt 2 in double).  S is unitary, so norms and
+ * inner products of fields are the chiral-basis ones; wd_spinor_pack/unpack
+ * convert.  A site's components are cut into NP packets of 16 bytes:
+ *   WD_F64 : NP = 12 packets of double2    -- packet c holds component c
+ *   WD_F32 : NP =  6 packets of float4     -- packet k: components 2k, 2k+1
+ *   WD_F16 : NP =  3 packets of 8 x half   -- packet k: components 4k..4k+3,
+ *            re/im interleaved; stored value = component / s_x with s_x =
+ *            the largest |real| of the site's 24 reals (0 -> all zero)
+ *   WD_BF16: NP =  3 packets of 8 x bfloat16 (round to nearest even), as FP16
+ *            without the scale
+ * Packet k of checkerboard site i sits at packet index
+ *   (i / 64) * CHUNK + 64 * k + (i % 64),   CHUNK = 64 * NP,
+ * except that an FP16 chunk is followed by the 64 float scales s_x of its
+ * sites (CHUNK = 64 * 3 + 16 packets; scale of site i at float index
+ * 4 * ((i / 64) * CHUNK + 192) + i % 64).  A full field is the even half
+ * followed by the odd half.  With nrhs right-hand sides the right-hand
+ * side index is outermost.  wd_field_bytes() gives the size.
  *
  * Ownership: the caller allocates and owns every field (device memory) and
  * every host array.  The library never frees or keeps a caller pointer past

@@ -202,6 +202,18 @@ def wd_gauge_destroy(g):
     g.close()
 
 
+def wd_gauge_set_stream(g, stream=None):
+    """Bind the handle to a HIP stream (default: torch's current stream)."""
+    _check(lib.wd_gauge_set_stream(g.handle, _stream() if stream is None else C.c_void_p(stream)),
+           "wd_gauge_set_stream")
+
+
+def wd_last_error():
+    """Message of the calling thread's last failed library call."""
+    m = lib.wd_last_error()
+    return m.decode(errors="replace") if m else ""
+
+
 def wd_spinor_pack(g, canon, field, parity=WD_FULL, prec=None):
     g.sync_stream()
     p = g.prec if prec is None else _prec(prec)
@@ -353,6 +365,10 @@ class Ptc:
 
 def wd_ptc_create(g, flat_weights, act_prec="bf16"):
     return Ptc(g, flat_weights, act_prec)
+
+
+def wd_ptc_destroy(n):
+    n.close()
 
 
 def wd_ptc_set_weights(n, flat):

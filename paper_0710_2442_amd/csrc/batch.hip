@@ -145,7 +145,6 @@ __global__ __launch_bounds__(BT) void k_batch_elem(KBatch a) {
     CgScalars *sc = d.sc;
     if (a.use_mask && sc->done) continue;
     const int i = (t - d.tile0) * BT + (int)threadIdx.x;
-    const size_t vp = (size_t)d.g.vpad;
     double acc = 0.0;
     if constexpr (OP == OP_CGU) {
       // X(PA) += alpha P(PB); S(PB) -= alpha Q(PB); |S|^2
@@ -156,10 +155,10 @@ __global__ __launch_bounds__(BT) void k_batch_elem(KBatch a) {
         cplx<TA> x[12];
         cplx<TB> p[12], s[12], q[12];
         char *X = vec_ptr(d, Opnd{S_E, 0}, PA);
-        Spinor<PA>::load(X, vp, i, x);
-        Spinor<PB>::load(vec_ptr(d, Opnd{S_P, 0}, PB), vp, i, p);
-        Spinor<PB>::load(vec_ptr(d, Opnd{S_S, 0}, PB), vp, i, s);
-        Spinor<PB>::load(vec_ptr(d, Opnd{S_Q, 0}, PB), vp, i, q);
+        Spinor<PA>::load(X, i, x);
+        Spinor<PB>::load(vec_ptr(d, Opnd{S_P, 0}, PB), i, p);
+        Spinor<PB>::load(vec_ptr(d, Opnd{S_S, 0}, PB), i, s);
+        Spinor<PB>::load(vec_ptr(d, Opnd{S_Q, 0}, PB), i, q);
         const TA ax = (TA)alpha;
         const TB ab = (TB)alpha;
 #pragma unroll
@@ -169,10 +168,10 @@ __global__ __launch_bounds__(BT) void k_batch_elem(KBatch a) {
           s[c].re = fma(-ab, q[c].re, s[c].re);
           s[c].im = fma(-ab, q[c].im, s[c].im);
         }
-        Spinor<PA>::store(X, vp, i, x);
+        Spinor<PA>::store(X, i, x);
         char *S = vec_ptr(d, Opnd{S_S, 0}, PB);
-        Spinor<PB>::store(S, vp, i, s);
-        if constexpr (PB != WD_F32 && PB != WD_F64) Spinor<PB>::load(S, vp, i, s);
+        Spinor<PB>::store(S, i, s);
+        if constexpr (PB != WD_F32 && PB != WD_F64) Spinor<PB>::load(S, i, s);
 #pragma unroll
         for (int c = 0; c < 12; ++c) acc += (double)s[c].re * s[c].re + (double)s[c].im * s[c].im;
       }
@@ -185,14 +184,14 @@ __global__ __launch_bounds__(BT) void k_batch_elem(KBatch a) {
         const TB beta = (TB)(sc->rr[1 - a.j] / sc->rr[a.j]);
         cplx<TB> r[12], p[12];
         char *Pp = vec_ptr(d, Opnd{S_P, 0}, PB);
-        Spinor<PB>::load(vec_ptr(d, Opnd{S_R, 0}, PB), vp, i, r);
-        Spinor<PB>::load(Pp, vp, i, p);
+        Spinor<PB>::load(vec_ptr(d, Opnd{S_R, 0}, PB), i, r);
+        Spinor<PB>::load(Pp, i, p);
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
           p[c].re = fma(beta, p[c].re, r[c].re);
           p[c].im = fma(beta, p[c].im, r[c].im);
         }
-        Spinor<PB>::store(Pp, vp, i, p);
+        Spinor<PB>::store(Pp, i, p);
       }
     } else if constexpr (OP == OP_CONV) {
       // out(PB) = s * in(PA), s = scale (or scale / sqrt(rnorm2) if norm_field >= 0); pads zeroed
@@ -201,34 +200,34 @@ __global__ __launch_bounds__(BT) void k_batch_elem(KBatch a) {
       cplx<TB> o[12];
       if (i < d.g.vh) {
         cplx<TA> x[12];
-        Spinor<PA>::load(vec_ptr(d, Opnd{a.in.slot, a.in.half + h}, PA), vp, i, x);
+        Spinor<PA>::load(vec_ptr(d, Opnd{a.in.slot, a.in.half + h}, PA), i, x);
 #pragma unroll
         for (int c = 0; c < 12; ++c) o[c] = {(TB)(s * (double)x[c].re), (TB)(s * (double)x[c].im)};
       } else {
 #pragma unroll
         for (int c = 0; c < 12; ++c) o[c] = {(TB)0, (TB)0};
       }
-      if (i < d.g.vpad) Spinor<PB>::store(vec_ptr(d, Opnd{a.out.slot, a.out.half + h}, PB), vp, i, o);
+      if (i < d.g.vpad) Spinor<PB>::store(vec_ptr(d, Opnd{a.out.slot, a.out.half + h}, PB), i, o);
     } else if constexpr (OP == OP_ACC) {
       // X64(PB = F64) += sqrt(rnorm2) * E(PA)
       if (i < d.g.vh) {
         const double s = sqrt(sc->rnorm2);
         cplx<TA> e[12];
         cplx<double> x[12];
-        Spinor<PA>::load(vec_ptr(d, Opnd{a.in.slot, h}, PA), vp, i, e);
+        Spinor<PA>::load(vec_ptr(d, Opnd{a.in.slot, h}, PA), i, e);
         char *X = vec_ptr(d, Opnd{a.out.slot, h}, WD_F64);
-        Spinor<WD_F64>::load(X, vp, i, x);
+        Spinor<WD_F64>::load(X, i, x);
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
           x[c].re = fma(s, (double)e[c].re, x[c].re);
           x[c].im = fma(s, (double)e[c].im, x[c].im);
         }
-        Spinor<WD_F64>::store(X, vp, i, x);
+        Spinor<WD_F64>::store(X, i, x);
       }
     } else {  // OP_NORM of slot `in` over nhalf halves -> sc[norm_field]
       if (i < d.g.vh) {
         cplx<TA> x[12];
-        Spinor<PA>::load(vec_ptr(d, Opnd{a.in.slot, h}, PA), vp, i, x);
+        Spinor<PA>::load(vec_ptr(d, Opnd{a.in.slot, h}, PA), i, x);
 #pragma unroll
         for (int c = 0; c < 12; ++c) acc += (double)x[c].re * x[c].re + (double)x[c].im * x[c].im;
       }

@@ -59,7 +59,7 @@ __global__ __launch_bounds__(BLAS_BS) void k_norm2(KBlas k) {
     int h, i;
     site_of(k.v, f, h, i);
     cplx<T> a[12];
-    Spinor<P>::load(x + h * k.hx, k.v.vpad, i, a);
+    Spinor<P>::load(x + h * k.hx, i, a);
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc += (double)a[c].re * a[c].re + (double)a[c].im * a[c].im;
   }
@@ -80,8 +80,8 @@ __global__ __launch_bounds__(BLAS_BS) void k_cdot(KBlas k) {
     int h, i;
     site_of(k.v, f, h, i);
     cplx<T> a[12], b[12];
-    Spinor<P>::load(x + h * k.hx, k.v.vpad, i, a);
-    Spinor<P>::load(y + h * k.hy, k.v.vpad, i, b);
+    Spinor<P>::load(x + h * k.hx, i, a);
+    Spinor<P>::load(y + h * k.hy, i, b);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
       re += (double)a[c].re * b[c].re + (double)a[c].im * b[c].im;
@@ -108,11 +108,11 @@ __global__ __launch_bounds__(BLAS_BS) void k_caxpy(KBlas k) {
     int h, i;
     site_of(k.v, f, h, i);
     cplx<T> a[12], b[12];
-    Spinor<P>::load(k.x + sys * k.sx + h * k.hx, k.v.vpad, i, a);
-    Spinor<P>::load(k.y + sys * k.sy + h * k.hy, k.v.vpad, i, b);
+    Spinor<P>::load(k.x + sys * k.sx + h * k.hx, i, a);
+    Spinor<P>::load(k.y + sys * k.sy + h * k.hy, i, b);
 #pragma unroll
     for (int q = 0; q < 12; ++q) cfma(b[q], c, a[q]);
-    Spinor<P>::store(k.out + sys * k.so + h * k.ho, k.v.vpad, i, b);
+    Spinor<P>::store(k.out + sys * k.so + h * k.ho, i, b);
   }
 }
 
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(BLAS_BS) void k_convert(KBlas k) {
     cplx<TO> b[12];
     if (i < k.v.vh) {
       cplx<TI> a[12];
-      Spinor<PI>::load(k.x + sys * k.sx + h * k.hx, k.v.vpad, i, a);
+      Spinor<PI>::load(k.x + sys * k.sx + h * k.hx, i, a);
       if constexpr (PO == WD_F64) {
 #pragma unroll
         for (int q = 0; q < 12; ++q) b[q] = {(TO)(s * (double)a[q].re), (TO)(s * (double)a[q].im)};
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(BLAS_BS) void k_convert(KBlas k) {
 #pragma unroll
       for (int q = 0; q < 12; ++q) b[q] = {(TO)0, (TO)0};
     }
-    Spinor<PO>::store(k.out + sys * k.so + h * k.ho, k.v.vpad, i, b);
+    Spinor<PO>::store(k.out + sys * k.so + h * k.ho, i, b);
   }
 }
 
@@ -161,15 +161,15 @@ __global__ __launch_bounds__(BLAS_BS) void k_accum(KBlas k) {
     site_of(k.v, f, h, i);
     cplx<TE> e[12];
     cplx<double> x[12];
-    Spinor<PE>::load(k.x + sys * k.sx + h * k.hx, k.v.vpad, i, e);
+    Spinor<PE>::load(k.x + sys * k.sx + h * k.hx, i, e);
     char *o = k.out + sys * k.so + h * k.ho;
-    Spinor<WD_F64>::load(o, k.v.vpad, i, x);
+    Spinor<WD_F64>::load(o, i, x);
 #pragma unroll
     for (int q = 0; q < 12; ++q) {
       x[q].re = fma(s, (double)e[q].re, x[q].re);
       x[q].im = fma(s, (double)e[q].im, x[q].im);
     }
-    Spinor<WD_F64>::store(o, k.v.vpad, i, x);
+    Spinor<WD_F64>::store(o, i, x);
   }
 }
 
@@ -200,10 +200,10 @@ __global__ __launch_bounds__(BLAS_BS) void k_cg_update(KBlas k) {
     const char *Pp = k.y + sys * k.sy + h * k.hy;
     char *S = k.out + sys * k.so + h * k.ho;
     const char *Q = k.out2 + sys * k.so2 + h * k.ho2;
-    Spinor<PV>::load(Pp, k.v.vpad, i, p);
-    Spinor<PV>::load(Q, k.v.vpad, i, q);
-    Spinor<PV>::load(S, k.v.vpad, i, s);
-    Spinor<PX>::load(X, k.v.vpad, i, x);
+    Spinor<PV>::load(Pp, i, p);
+    Spinor<PV>::load(Q, i, q);
+    Spinor<PV>::load(S, i, s);
+    Spinor<PX>::load(X, i, x);
     const TV a = (TV)alpha;
     const TX ax = (TX)alpha;
 #pragma unroll
@@ -213,14 +213,14 @@ __global__ __launch_bounds__(BLAS_BS) void k_cg_update(KBlas k) {
       s[c].re = fma(-a, q[c].re, s[c].re);
       s[c].im = fma(-a, q[c].im, s[c].im);
     }
-    Spinor<PX>::store(X, k.v.vpad, i, x);
-    Spinor<PV>::store(S, k.v.vpad, i, s);
+    Spinor<PX>::store(X, i, x);
+    Spinor<PV>::store(S, i, s);
     if constexpr (PV == WD_F64 || PV == WD_F32) {
 #pragma unroll
       for (int c = 0; c < 12; ++c) acc += (double)s[c].re * s[c].re + (double)s[c].im * s[c].im;
     } else {  // norm of the stored (rounded) residual
       cplx<TV> r[12];
-      Spinor<PV>::load(S, k.v.vpad, i, r);
+      Spinor<PV>::load(S, i, r);
 #pragma unroll
       for (int c = 0; c < 12; ++c) acc += (double)r[c].re * r[c].re + (double)r[c].im * r[c].im;
     }
@@ -249,14 +249,14 @@ __global__ __launch_bounds__(BLAS_BS) void k_cg_pupdate(KBlas k) {
     site_of(k.v, f, h, i);
     cplx<TV> r[12], p[12];
     char *Pp = k.out + sys * k.so + h * k.ho;
-    Spinor<PV>::load(k.x + sys * k.sx + h * k.hx, k.v.vpad, i, r);
-    Spinor<PV>::load(Pp, k.v.vpad, i, p);
+    Spinor<PV>::load(k.x + sys * k.sx + h * k.hx, i, r);
+    Spinor<PV>::load(Pp, i, p);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
       p[c].re = fma(b, p[c].re, r[c].re);
       p[c].im = fma(b, p[c].im, r[c].im);
     }
-    Spinor<PV>::store(Pp, k.v.vpad, i, p);
+    Spinor<PV>::store(Pp, i, p);
   }
 }
 

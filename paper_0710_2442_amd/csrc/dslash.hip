@@ -66,7 +66,6 @@ __global__ __launch_bounds__(256) void k_dslash_mrhs(KMrhs m) {
   const int rl = threadIdx.x >> 4;             // rhs within the block
   const int rg = blockIdx.y * 16 + rl;         // global rhs
   const int i = tile_of(m.k) * 16 + lane;
-  const size_t vp = (size_t)m.k.g.vpad;
   const bool live = rg < m.nrhs && !(m.k.skip && m.k.skip[(size_t)rg * m.skip_stride]);
   double nrm = 0.0;
   if (live) {
@@ -82,24 +81,24 @@ __global__ __launch_bounds__(256) void k_dslash_mrhs(KMrhs m) {
       for (int c = 0; c < 12; ++c) acc[c] = a * acc[c];
       if constexpr (EPI >= 1) {
         cplx<T> x[12];
-        Spinor<P>::load(m.k.X + off, vp, i, x);
+        Spinor<P>::load(m.k.X + off, i, x);
 #pragma unroll
         for (int c = 0; c < 12; ++c) acc[c] = acc[c] + x[c];
       }
       if constexpr (EPI == 2) {
         cplx<T> y[12];
-        Spinor<P>::load(m.k.Y + off, vp, i, y);
+        Spinor<P>::load(m.k.Y + off, i, y);
 #pragma unroll
         for (int c = 0; c < 12; ++c) acc[c] = acc[c] - y[c];
       }
-      Spinor<P>::store(out, vp, i, acc);
+      Spinor<P>::store(out, i, acc);
       if constexpr (NORM) {
         cplx<T> st[12];
         if constexpr (P == WD_F64 || P == WD_F32) {
 #pragma unroll
           for (int c = 0; c < 12; ++c) st[c] = acc[c];
         } else {
-          Spinor<P>::load(out, vp, i, st);
+          Spinor<P>::load(out, i, st);
         }
 #pragma unroll
         for (int c = 0; c < 12; ++c) nrm += (double)st[c].re * st[c].re + (double)st[c].im * st[c].im;
@@ -108,7 +107,7 @@ __global__ __launch_bounds__(256) void k_dslash_mrhs(KMrhs m) {
       cplx<T> z[12];
 #pragma unroll
       for (int c = 0; c < 12; ++c) z[c] = {(T)0, (T)0};
-      Spinor<P>::store(out, vp, i, z);
+      Spinor<P>::store(out, i, z);
     }
   }
   if constexpr (NORM) {

@@ -66,7 +66,7 @@ __global__ __launch_bounds__(256) void k_pack_spinor(KPack k) {
 #pragma unroll
     for (int c = 0; c < 12; ++c) s[c] = {(T)0, (T)0};
   }
-  Spinor<P>::store(dst, (size_t)k.g.vpad, i, s);
+  Spinor<P>::store(dst, i, s);
 }
 
 template <int P>
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) void k_unpack_spinor(KPack k) {
   const int parity = k.parity0 + h;
   const char *src = k.field_in + (size_t)h * k.half_stride;
   cplx<T> s[12];
-  Spinor<P>::load(src, (size_t)k.g.vpad, i, s);
+  Spinor<P>::load(src, i, s);
   const size_t idx = canon_index(k.g, i, parity);
   double *dst = k.canon_out + idx * 24;
   double b[12][2];

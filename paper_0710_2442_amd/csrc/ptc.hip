@@ -95,17 +95,16 @@ __device__ __forceinline__ PtcSite ptc_site(const Geom &g, int i, int p) {
 template <int PIN>
 __device__ __forceinline__ void transport(const KPtc &k, const PtcSite &s, int p, int i, int h, const char *chan,
                                           cplx<float> (&v)[12]) {
-  const size_t vp = (size_t)k.g.vpad;
   if (h == 0) {
     cplx<RealOf<PIN>> t[12];
-    Spinor<PIN>::load(chan + (size_t)p * k.in_half, vp, i, t);
+    Spinor<PIN>::load(chan + (size_t)p * k.in_half, i, t);
 #pragma unroll
     for (int c = 0; c < 12; ++c) v[c] = {(float)t[c].re, (float)t[c].im};
     return;
   }
   const int d = h - 1;
   cplx<RealOf<PIN>> t[12];
-  Spinor<PIN>::load(chan + (size_t)(1 - p) * k.in_half, vp, s.nb[d], t);
+  Spinor<PIN>::load(chan + (size_t)(1 - p) * k.in_half, s.nb[d], t);
   cplx<float> u[6], r2[3];
   Link<float>::load(k.links32 + (size_t)p * k.link_par, d, i, u);
   rebuild_row2(u, r2);
@@ -141,13 +140,12 @@ __global__ __launch_bounds__(PTC_BS) void k_ptc_layer(KPtc k) {
   const int p = blockIdx.y;
   const int i = blockIdx.x * PTC_BS + threadIdx.x;
   if (i >= k.g.vpad) return;
-  const size_t vp = (size_t)k.g.vpad;
   cplx<RealOf<POUT>> o[12];
   if (i >= k.g.vh) {
 #pragma unroll
     for (int c = 0; c < 12; ++c) o[c] = {0, 0};
 #pragma unroll
-    for (int co = 0; co < COUT; ++co) Spinor<POUT>::store(k.out + co * k.out_chan + (size_t)p * k.out_half, vp, i, o);
+    for (int co = 0; co < COUT; ++co) Spinor<POUT>::store(k.out + co * k.out_chan + (size_t)p * k.out_half, i, o);
     return;
   }
   const PtcSite s = ptc_site(k.g, i, p);
@@ -169,7 +167,7 @@ __global__ __launch_bounds__(PTC_BS) void k_ptc_layer(KPtc k) {
   for (int co = 0; co < COUT; ++co) {
 #pragma unroll
     for (int c = 0; c < 12; ++c) o[c] = {(RealOf<POUT>)acc[co][c].re, (RealOf<POUT>)acc[co][c].im};
-    Spinor<POUT>::store(k.out + co * k.out_chan + (size_t)p * k.out_half, vp, i, o);
+    Spinor<POUT>::store(k.out + co * k.out_chan + (size_t)p * k.out_half, i, o);
   }
 }
 
@@ -183,14 +181,13 @@ __global__ __launch_bounds__(PTC_BS) void k_ptc_wgrad(KPtc k) {
   const int i = blockIdx.x * PTC_BS + threadIdx.x;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const bool live = i < k.g.vh;
-  const size_t vp = (size_t)k.g.vpad;
   PtcSite s;
   cplx<float> gy[COUT][12];
   if (live) {
     s = ptc_site(k.g, i, p);
 #pragma unroll
     for (int co = 0; co < COUT; ++co)
-      Spinor<WD_F32>::load(k.gy + co * k.gy_chan + (size_t)p * k.gy_half, vp, i, gy[co]);
+      Spinor<WD_F32>::load(k.gy + co * k.gy_chan + (size_t)p * k.gy_half, i, gy[co]);
   }
   for (int h = 0; h < 9; ++h) {
 #pragma unroll
@@ -310,14 +307,13 @@ __global__ __launch_bounds__(256) void k_ptc_loss(const char *y, const char *e, 
                                                   double *partials, unsigned *counter, double *loss) {
   const int p = blockIdx.y;
   const int i = blockIdx.x * 256 + threadIdx.x;
-  const size_t vp = (size_t)g.vpad;
   const size_t hb = (size_t)96 * g.vpad;  // one FP32 half field
   double acc = 0.0;
   if (i < g.vpad) {
     cplx<float> a[12], b[12];
     if (i < g.vh) {
-      Spinor<WD_F32>::load(y + p * hb, vp, i, a);
-      Spinor<WD_F32>::load(e + p * hb, vp, i, b);
+      Spinor<WD_F32>::load(y + p * hb, i, a);
+      Spinor<WD_F32>::load(e + p * hb, i, b);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         a[c] = a[c] - b[c];
@@ -328,7 +324,7 @@ __global__ __launch_bounds__(256) void k_ptc_loss(const char *y, const char *e, 
 #pragma unroll
       for (int c = 0; c < 12; ++c) a[c] = {0.f, 0.f};
     }
-    Spinor<WD_F32>::store(gy + p * hb, vp, i, a);
+    Spinor<WD_F32>::store(gy + p * hb, i, a);
   }
   double v[1] = {acc}, tot[1];
   const unsigned nb = gridDim.x * gridDim.y, bid = blockIdx.y * gridDim.x + blockIdx.x;

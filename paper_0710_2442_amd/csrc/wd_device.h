@@ -90,7 +90,17 @@ __device__ __forceinline__ void st_policy(T v, T *p) {
 }
 
 // -------------------------------------------------------- spinor storage
-// Spinor: 12 complex components, c = 3*spin + colour.
+// Spinor: 12 complex components, c = 3*spin + colour, in 16-byte packets.
+// Fields are chunked by 64 sites (one wave): packet k of checkerboard site i
+// sits at packet (i / 64) * CHUNK + 64 * k + i % 64, so the packets of a wave
+// of sites form one contiguous block and each packet load of a wave is one
+// 1 KiB run.  CHUNK = 64 * (packets per site), plus 16 packets of per-site
+// scales for FP16.
+template <int CHUNK>
+__device__ __forceinline__ size_t chunk_base(size_t i) {
+  return (i >> 6) * CHUNK + (i & 63);
+}
+
 template <int P>
 struct Spinor;
 
@@ -98,29 +108,30 @@ template <>
 struct Spinor<WD_F64> {
   using real = double;
   static constexpr size_t bytes_per_slot = 192;
-  __device__ static void load(const void *base, size_t vp, size_t i, cplx<double> (&s)[12]) {
-    const v2d *p = (const v2d *)base + i;
+  static constexpr int CHUNK = 12 * 64;
+  __device__ static void load(const void *base, size_t i, cplx<double> (&s)[12]) {
+    const v2d *p = (const v2d *)base + chunk_base<CHUNK>(i);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-      v2d v = p[c * vp];
+      v2d v = p[64 * c];
       s[c] = {v.x, v.y};
     }
   }
   // spins 0,1 (LOWER = false) or spins 2,3 (LOWER = true): components 6h .. 6h+5
   template <bool LOWER>
-  __device__ static void load_half(const void *base, size_t vp, size_t i, cplx<double> (&s)[6]) {
-    const v2d *p = (const v2d *)base + i + (LOWER ? 6 : 0) * vp;
+  __device__ static void load_half(const void *base, size_t i, cplx<double> (&s)[6]) {
+    const v2d *p = (const v2d *)base + chunk_base<CHUNK>(i) + (LOWER ? 6 * 64 : 0);
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      v2d v = p[c * vp];
+      v2d v = p[64 * c];
       s[c] = {v.x, v.y};
     }
   }
   template <bool NT = true>
-  __device__ static void store(void *base, size_t vp, size_t i, const cplx<double> (&s)[12]) {
-    v2d *p = (v2d *)base + i;
+  __device__ static void store(void *base, size_t i, const cplx<double> (&s)[12]) {
+    v2d *p = (v2d *)base + chunk_base<CHUNK>(i);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) st_policy<NT>(v2d{s[c].re, s[c].im}, p + c * vp);
+    for (int c = 0; c < 12; ++c) st_policy<NT>(v2d{s[c].re, s[c].im}, p + 64 * c);
   }
 };
 
@@ -128,31 +139,32 @@ template <>
 struct Spinor<WD_F32> {
   using real = float;
   static constexpr size_t bytes_per_slot = 96;
-  __device__ static void load(const void *base, size_t vp, size_t i, cplx<float> (&s)[12]) {
-    const v4f *p = (const v4f *)base + i;
+  static constexpr int CHUNK = 6 * 64;
+  __device__ static void load(const void *base, size_t i, cplx<float> (&s)[12]) {
+    const v4f *p = (const v4f *)base + chunk_base<CHUNK>(i);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      v4f v = p[k * vp];
+      v4f v = p[64 * k];
       s[2 * k] = {v.x, v.y};
       s[2 * k + 1] = {v.z, v.w};
     }
   }
   template <bool LOWER>
-  __device__ static void load_half(const void *base, size_t vp, size_t i, cplx<float> (&s)[6]) {
-    const v4f *p = (const v4f *)base + i + (LOWER ? 3 : 0) * vp;
+  __device__ static void load_half(const void *base, size_t i, cplx<float> (&s)[6]) {
+    const v4f *p = (const v4f *)base + chunk_base<CHUNK>(i) + (LOWER ? 3 * 64 : 0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      v4f v = p[k * vp];
+      v4f v = p[64 * k];
       s[2 * k] = {v.x, v.y};
       s[2 * k + 1] = {v.z, v.w};
     }
   }
   template <bool NT = true>
-  __device__ static void store(void *base, size_t vp, size_t i, const cplx<float> (&s)[12]) {
-    v4f *p = (v4f *)base + i;
+  __device__ static void store(void *base, size_t i, const cplx<float> (&s)[12]) {
+    v4f *p = (v4f *)base + chunk_base<CHUNK>(i);
 #pragma unroll
     for (int k = 0; k < 6; ++k)
-      st_policy<NT>(v4f{s[2 * k].re, s[2 * k].im, s[2 * k + 1].re, s[2 * k + 1].im}, p + k * vp);
+      st_policy<NT>(v4f{s[2 * k].re, s[2 * k].im, s[2 * k + 1].re, s[2 * k + 1].im}, p + 64 * k);
   }
 };
 
@@ -161,16 +173,21 @@ struct alignas(16) pk8 {
   uint32_t w[4];
 };
 
+// FP16: 3 packets of halves per site, then (per chunk) the 64 sites' scales.
 template <>
 struct Spinor<WD_F16> {
   using real = float;
   static constexpr size_t bytes_per_slot = 52;
-  __device__ static void load(const void *base, size_t vp, size_t i, cplx<float> (&s)[12]) {
-    const v4u *p = (const v4u *)base + i;
-    const float nrm = ((const float *)((const v4u *)base + 3 * vp))[i];
+  static constexpr int CHUNK = 3 * 64 + 16;
+  __device__ static float scale(const void *base, size_t i) {
+    return ((const float *)((const v4u *)base + (i >> 6) * CHUNK + 3 * 64))[i & 63];
+  }
+  __device__ static void load(const void *base, size_t i, cplx<float> (&s)[12]) {
+    const v4u *p = (const v4u *)base + chunk_base<CHUNK>(i);
+    const float nrm = scale(base, i);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      v4u v = p[k * vp];
+      v4u v = p[64 * k];
       uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -181,10 +198,10 @@ struct Spinor<WD_F16> {
   }
   // components 6h .. 6h+5 live in packets (0, 1) or (1, 2)
   template <bool LOWER>
-  __device__ static void load_half(const void *base, size_t vp, size_t i, cplx<float> (&s)[6]) {
-    const v4u *p = (const v4u *)base + i;
-    const float nrm = ((const float *)((const v4u *)base + 3 * vp))[i];
-    const v4u a = p[(LOWER ? 1 : 0) * vp], b = p[(LOWER ? 2 : 1) * vp];
+  __device__ static void load_half(const void *base, size_t i, cplx<float> (&s)[6]) {
+    const v4u *p = (const v4u *)base + chunk_base<CHUNK>(i);
+    const float nrm = scale(base, i);
+    const v4u a = p[(LOWER ? 1 : 0) * 64], b = p[(LOWER ? 2 : 1) * 64];
     const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
     const int o = LOWER ? 2 : 0;
 #pragma unroll
@@ -192,12 +209,12 @@ struct Spinor<WD_F16> {
       s[j] = {nrm * f16_to_f32((uint16_t)(w[o + j] & 0xffffu)), nrm * f16_to_f32((uint16_t)(w[o + j] >> 16))};
   }
   template <bool NT = true>
-  __device__ static void store(void *base, size_t vp, size_t i, const cplx<float> (&s)[12]) {
+  __device__ static void store(void *base, size_t i, const cplx<float> (&s)[12]) {
     float m = 0.f;
 #pragma unroll
     for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(s[c].re), fabsf(s[c].im)));
     const float inv = m > 0.f ? 1.0f / m : 0.f;
-    v4u *p = (v4u *)base + i;
+    v4u *p = (v4u *)base + chunk_base<CHUNK>(i);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       uint32_t w[4];
@@ -206,9 +223,9 @@ struct Spinor<WD_F16> {
         const cplx<float> z = s[4 * k + j];
         w[j] = (uint32_t)f32_to_f16(z.re * inv) | ((uint32_t)f32_to_f16(z.im * inv) << 16);
       }
-      st_policy<NT>(v4u{w[0], w[1], w[2], w[3]}, p + k * vp);
+      st_policy<NT>(v4u{w[0], w[1], w[2], w[3]}, p + 64 * k);
     }
-    st_policy<NT>(m, ((float *)((v4u *)base + 3 * vp)) + i);
+    st_policy<NT>(m, (float *)((v4u *)base + (i >> 6) * CHUNK + 3 * 64) + (i & 63));
   }
 };
 
@@ -216,11 +233,12 @@ template <>
 struct Spinor<WD_BF16> {
   using real = float;
   static constexpr size_t bytes_per_slot = 48;
-  __device__ static void load(const void *base, size_t vp, size_t i, cplx<float> (&s)[12]) {
-    const v4u *p = (const v4u *)base + i;
+  static constexpr int CHUNK = 3 * 64;
+  __device__ static void load(const void *base, size_t i, cplx<float> (&s)[12]) {
+    const v4u *p = (const v4u *)base + chunk_base<CHUNK>(i);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      v4u v = p[k * vp];
+      v4u v = p[64 * k];
       uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
       for (int j = 0; j < 4; ++j)
@@ -228,9 +246,9 @@ struct Spinor<WD_BF16> {
     }
   }
   template <bool LOWER>
-  __device__ static void load_half(const void *base, size_t vp, size_t i, cplx<float> (&s)[6]) {
-    const v4u *p = (const v4u *)base + i;
-    const v4u a = p[(LOWER ? 1 : 0) * vp], b = p[(LOWER ? 2 : 1) * vp];
+  __device__ static void load_half(const void *base, size_t i, cplx<float> (&s)[6]) {
+    const v4u *p = (const v4u *)base + chunk_base<CHUNK>(i);
+    const v4u a = p[(LOWER ? 1 : 0) * 64], b = p[(LOWER ? 2 : 1) * 64];
     const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
     const int o = LOWER ? 2 : 0;
 #pragma unroll
@@ -238,8 +256,8 @@ struct Spinor<WD_BF16> {
       s[j] = {bf16_to_f32((uint16_t)(w[o + j] & 0xffffu)), bf16_to_f32((uint16_t)(w[o + j] >> 16))};
   }
   template <bool NT = true>
-  __device__ static void store(void *base, size_t vp, size_t i, const cplx<float> (&s)[12]) {
-    v4u *p = (v4u *)base + i;
+  __device__ static void store(void *base, size_t i, const cplx<float> (&s)[12]) {
+    v4u *p = (v4u *)base + chunk_base<CHUNK>(i);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       uint32_t w[4];
@@ -248,7 +266,7 @@ struct Spinor<WD_BF16> {
         const cplx<float> z = s[4 * k + j];
         w[j] = (uint32_t)f32_to_bf16(z.re) | ((uint32_t)f32_to_bf16(z.im) << 16);
       }
-      st_policy<NT>(v4u{w[0], w[1], w[2], w[3]}, p + k * vp);
+      st_policy<NT>(v4u{w[0], w[1], w[2], w[3]}, p + 64 * k);
     }
   }
 };

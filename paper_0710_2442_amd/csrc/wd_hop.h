@@ -80,18 +80,18 @@ __device__ __forceinline__ void neighbours(const Geom &g, const Coords &c, int i
 // hops (MU = 3) read only the half of the neighbour spinor that their
 // projector keeps (see the spin basis in wd_device.h).
 template <int P, int MU, int S>
-__device__ __forceinline__ void hop_term(cplx<RealOf<P>> (&acc)[12], const char *in, size_t vp, int nb,
+__device__ __forceinline__ void hop_term(cplx<RealOf<P>> (&acc)[12], const char *in, int nb,
                                          const char *links, int d, size_t i, RealOf<P> sign) {
   using T = RealOf<P>;
   cplx<T> h[6];
   if constexpr (MU == 3) {
-    Spinor<P>::template load_half<(S < 0)>(in, vp, nb, h);
+    Spinor<P>::template load_half<(S < 0)>(in, nb, h);
     const T f = (T)2 * sign;
 #pragma unroll
     for (int c = 0; c < 6; ++c) h[c] = f * h[c];
   } else {
     cplx<T> psi[12];
-    Spinor<P>::load(in, vp, nb, psi);
+    Spinor<P>::load(in, nb, psi);
     project<MU, S>(psi, h);
   }
   cplx<T> u[6];
@@ -120,7 +120,6 @@ __device__ __forceinline__ void hop_all(const KDslash &k, int i, cplx<RealOf<P>>
   const Coords c = coords_of(k.g, i, k.parity);
   int nb[8];
   neighbours(k.g, c, i, nb);
-  const size_t vp = (size_t)k.g.vpad;
   const T one = (T)1;
   const T sf = (c.x4 == k.g.L[3] - 1) ? (T)k.g.tbc : one;
   const T sb = (c.x4 == 0) ? (T)k.g.tbc : one;
@@ -129,14 +128,14 @@ __device__ __forceinline__ void hop_all(const KDslash &k, int i, cplx<RealOf<P>>
   const char *L = k.links;
 #pragma unroll
   for (int c2 = 0; c2 < 12; ++c2) acc[c2] = {(T)0, (T)0};
-  hop_term<P, 0, F>(acc, k.in, vp, nb[0], L, 0, i, one);
-  hop_term<P, 1, F>(acc, k.in, vp, nb[1], L, 1, i, one);
-  hop_term<P, 2, F>(acc, k.in, vp, nb[2], L, 2, i, one);
-  hop_term<P, 3, F>(acc, k.in, vp, nb[3], L, 3, i, sf);
-  hop_term<P, 0, B>(acc, k.in, vp, nb[4], L, 4, i, one);
-  hop_term<P, 1, B>(acc, k.in, vp, nb[5], L, 5, i, one);
-  hop_term<P, 2, B>(acc, k.in, vp, nb[6], L, 6, i, one);
-  hop_term<P, 3, B>(acc, k.in, vp, nb[7], L, 7, i, sb);
+  hop_term<P, 0, F>(acc, k.in, nb[0], L, 0, i, one);
+  hop_term<P, 1, F>(acc, k.in, nb[1], L, 1, i, one);
+  hop_term<P, 2, F>(acc, k.in, nb[2], L, 2, i, one);
+  hop_term<P, 3, F>(acc, k.in, nb[3], L, 3, i, sf);
+  hop_term<P, 0, B>(acc, k.in, nb[4], L, 4, i, one);
+  hop_term<P, 1, B>(acc, k.in, nb[5], L, 5, i, one);
+  hop_term<P, 2, B>(acc, k.in, nb[6], L, 6, i, one);
+  hop_term<P, 3, B>(acc, k.in, nb[7], L, 7, i, sb);
 }
 
 // One output site i of the hop with the fused epilogue
@@ -146,7 +145,6 @@ __device__ __forceinline__ void hop_all(const KDslash &k, int i, cplx<RealOf<P>>
 template <int P, bool DAG, int EPI, bool NORM>
 __device__ __forceinline__ double dslash_site(const KDslash &k, int i) {
   using T = RealOf<P>;
-  const size_t vp = (size_t)k.g.vpad;
   double nrm = 0.0;
   if (i < k.g.vh) {
     cplx<T> acc[12];
@@ -156,18 +154,18 @@ __device__ __forceinline__ double dslash_site(const KDslash &k, int i) {
     for (int c = 0; c < 12; ++c) acc[c] = a * acc[c];
     if constexpr (EPI >= 1) {
       cplx<T> x[12];
-      Spinor<P>::load(k.X, vp, i, x);
+      Spinor<P>::load(k.X, i, x);
 #pragma unroll
       for (int c = 0; c < 12; ++c) acc[c] = acc[c] + x[c];
     }
     if constexpr (EPI == 2) {
       cplx<T> y[12];
-      Spinor<P>::load(k.Y, vp, i, y);
+      Spinor<P>::load(k.Y, i, y);
 #pragma unroll
       for (int c = 0; c < 12; ++c) acc[c] = acc[c] - y[c];
     }
-    if (k.nt_store) Spinor<P>::template store<true>(k.out, vp, i, acc);
-    else Spinor<P>::template store<false>(k.out, vp, i, acc);
+    if (k.nt_store) Spinor<P>::template store<true>(k.out, i, acc);
+    else Spinor<P>::template store<false>(k.out, i, acc);
     if constexpr (NORM) {
       // norm of what was stored (after rounding to the storage format)
       cplx<T> st[12];
@@ -175,7 +173,7 @@ __device__ __forceinline__ double dslash_site(const KDslash &k, int i) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) st[c] = acc[c];
       } else {
-        Spinor<P>::load(k.out, vp, i, st);
+        Spinor<P>::load(k.out, i, st);
       }
 #pragma unroll
       for (int c = 0; c < 12; ++c) nrm += (double)st[c].re * st[c].re + (double)st[c].im * st[c].im;
@@ -184,7 +182,7 @@ __device__ __forceinline__ double dslash_site(const KDslash &k, int i) {
     cplx<T> z[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) z[c] = {(T)0, (T)0};
-    Spinor<P>::store(k.out, vp, i, z);
+    Spinor<P>::store(k.out, i, z);
   }
   return nrm;
 }

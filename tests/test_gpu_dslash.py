@@ -79,16 +79,16 @@ def test_periodic_time_boundary():
 
 
 def test_pack_layout_is_documented_soa():
-    """Device bytes equal the layout written in wd.h, built here index by index."""
-    dims = (6, 4, 2, 4)
+    """Device bytes equal the layout written in wd.h, built here index by index:
+    packet k of checkerboard site i at packet (i // 64) * CHUNK + 64 k + i % 64."""
+    dims = (6, 4, 2, 4)  # V_h = 96: two chunks, the second one ragged
     L1, L2, L3, L4 = dims
     psi = syn.gaussian_spinor(dims, 5)
     g = wd.Gauge(syn.gauge_field(dims, 0.3, 5), dims, -1, "f64")
     vpad = wd.wd_vh_pad(dims)
-    f = to_field(g, psi, "f64")
-    dev = f.cpu().numpy().view(np.float64).reshape(2, 12, vpad, 2)
+    nc = vpad // 64
     stored = to_storage_basis(psi)
-    want = np.zeros((2, 12, vpad, 2))
+    planes = np.zeros((2, 12, vpad), dtype=np.complex128)  # [parity][component][cb]
     for x4 in range(L4):
         for x3 in range(L3):
             for x2 in range(L2):
@@ -96,14 +96,32 @@ def test_pack_layout_is_documented_soa():
                     idx = x1 + L1 * (x2 + L2 * (x3 + L3 * x4))
                     p = (x1 + x2 + x3 + x4) % 2
                     for c in range(12):
-                        z = stored[x4, x3, x2, x1, c // 3, c % 3]
-                        want[p, c, idx >> 1] = (z.real, z.imag)
-    assert np.array_equal(dev, want)
-    # FP32: plane k holds components 2k, 2k+1
+                        planes[p, c, idx >> 1] = stored[x4, x3, x2, x1, c // 3, c % 3]
+    chunked = planes.reshape(2, 12, nc, 64).transpose(0, 2, 1, 3)  # [parity][chunk][c][lane]
+    # FP64: packet c holds component c
+    f = to_field(g, psi, "f64")
+    dev = f.cpu().numpy().view(np.complex128).reshape(2, nc, 12, 64)
+    assert np.array_equal(dev, chunked)
+    # FP32: packet k holds components 2k, 2k+1
     f32 = to_field(g, psi, "f32")
-    d32 = f32.cpu().numpy().view(np.float32).reshape(2, 6, vpad, 4)
-    w32 = want.astype(np.float32).reshape(2, 6, 2, vpad, 2).transpose(0, 1, 3, 2, 4).reshape(2, 6, vpad, 4)
+    d32 = f32.cpu().numpy().view(np.complex64).reshape(2, nc, 6, 64, 2)
+    w32 = chunked.astype(np.complex64).reshape(2, nc, 6, 2, 64).transpose(0, 1, 2, 4, 3)
     assert np.array_equal(d32, w32)
+    # BF16: packet k holds components 4k .. 4k+3, (re, im) interleaved
+    fb = to_field(g, psi, "bf16")
+    raw = fb.cpu().numpy().view(np.uint16).reshape(2, nc, 3, 64, 4, 2).astype(np.uint32) << 16
+    vals = raw.view(np.float32)
+    db = (vals[..., 0] + 1j * vals[..., 1]).transpose(0, 1, 2, 4, 3).reshape(2, nc, 12, 64)
+    wb = solvers.round_storage(chunked, "bf16")
+    assert np.array_equal(db, wb)
+    # FP16: 3 packets of halves, then the chunk's 64 per-site scales
+    fh = to_field(g, psi, "f16").cpu().numpy().view(np.uint8).reshape(2, nc, 208 * 16)
+    halves = fh[:, :, :192 * 16].copy().view(np.float16).astype(np.float32).reshape(2, nc, 3, 64, 4, 2)
+    scales = fh[:, :, 192 * 16:].copy().view(np.float32).reshape(2, nc, 1, 64)
+    dh = (halves[..., 0] + 1j * halves[..., 1]).transpose(0, 1, 2, 4, 3).reshape(2, nc, 12, 64) * scales
+    amax = np.maximum(np.abs(chunked.real), np.abs(chunked.imag)).max(axis=2, keepdims=True)
+    assert np.allclose(scales, amax, rtol=1e-7, atol=0)
+    assert np.max(np.abs(dh - chunked)) <= 2.0 ** -11 * amax.max() * 1.01
     # the round trip applies the basis map twice: exact up to rounding
     assert rel_err(from_field(g, f), psi) <= 1e-15
     g.close()
