@@ -275,7 +275,10 @@ def learned_leg(wd, torch, syn, steps):
     fb = canon_to_field(gt, syn.gaussian_spinor(DIMS, sseed + 100), "f64")
     fx = wd.wd_new_field(DIMS, "f64")
     net = wd.Ptc(gt, W, "bf16")
-    cases = [("fgcr_trained_bf16", dict(solver=wd.WD_SOLVER_FGCR, fgcr_m=16, precond=net)),
+    cases = [("defect_fgcr_trained_bf16", dict(solver=wd.WD_SOLVER_DEFECT_FGCR, fgcr_m=4, inner_tol=1e-2,
+                                                precond=net)),
+             ("defect_fgcr_identity", dict(solver=wd.WD_SOLVER_DEFECT_FGCR, fgcr_m=4, inner_tol=1e-2)),
+             ("fgcr_trained_bf16", dict(solver=wd.WD_SOLVER_FGCR, fgcr_m=16, precond=net)),
              ("fgcr_identity", dict(solver=wd.WD_SOLVER_FGCR, fgcr_m=16)),
              ("fp64_cg", dict(solver=wd.WD_SOLVER_CG)),
              ("defect_bf16", dict(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec="bf16", inner_tol=1e-2))]

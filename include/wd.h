@@ -166,7 +166,20 @@ wd_status wd_convert(const wd_gauge *g, const void *in, wd_prec pin, void *out,
 
 /* --------------------------------------------------------------- solve -- */
 
-enum { WD_SOLVER_CG = 0, WD_SOLVER_DEFECT_CG = 1, WD_SOLVER_FGCR = 2 };
+/* WD_SOLVER_CG        : FP64 even-odd CGLS (CG on the normal equations).
+ * WD_SOLVER_DEFECT_CG : FP64 defect correction, inner even-odd CGLS in FP32
+ *                       arithmetic with inner_prec storage.
+ * WD_SOLVER_FGCR      : FP64 flexible GCR(fgcr_m) on the full D_W with
+ *                       precond as right preconditioner; modified
+ *                       Gram-Schmidt; falls back to FP64 CG when stalled.
+ * WD_SOLVER_DEFECT_FGCR: FP64 defect correction whose inner solver is an
+ *                       FP32 flexible GCR(fgcr_m <= 16, restarted) on the
+ *                       even-odd Schur operator with right preconditioner
+ *                       z = [precond (r_e, 0)]_e (identity if NULL);
+ *                       classical Gram-Schmidt in fused kernels, FP64
+ *                       reductions; inner_prec must be WD_F32; falls back to
+ *                       FP64 CG when stalled or non-finite. */
+enum { WD_SOLVER_CG = 0, WD_SOLVER_DEFECT_CG = 1, WD_SOLVER_FGCR = 2, WD_SOLVER_DEFECT_FGCR = 3 };
 
 typedef struct wd_ptc wd_ptc;
 
@@ -245,8 +258,10 @@ wd_status wd_ptc_train_step(wd_ptc *n, const void *r, const void *e, int B,
 /* --------------------------------------------------------------- tuning -- */
 
 /* Autotune the single-RHS hop of precision prec on this handle's lattice:
- * block size (64..512 threads), the number of XCD regions the blocks are
- * grouped into (0 = linear order), the register budget (occ 0: compiler's
+ * block size (64..512 threads), the block -> tile order (groups: 0 = linear;
+ * G > 0 = G regions of each time slice, dealt round-robin over the XCDs;
+ * -X = whole time slices dealt round-robin over X dispatch lanes, so with
+ * X = 8 every slice runs inside one XCD's L2), the register budget (occ 0: compiler's
  * choice; occ 4: at least 4 waves per SIMD), the output store policy
  * (WD_TUNE_CACHED_STORE set in occ: cached stores) and a cap on resident
  * blocks per CU (dynamic LDS in KiB << WD_TUNE_LDS_SHIFT).  Every candidate's output is
@@ -262,8 +277,8 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path,
                          int force, int *block, int *groups, int *occ,
                          double *us);
 
-/* Tune the multi-RHS hop for nrhs right-hand sides: the number of XCD
- * regions its 16-site tiles are grouped into (candidates checked byte for
+/* Tune the multi-RHS hop for nrhs right-hand sides: the block -> tile order
+ * of its 16-site tiles (groups as above; candidates checked byte for
  * byte against linear order, then timed).  Outputs may be NULL.
  * Synchronous. */
 wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, int *groups,

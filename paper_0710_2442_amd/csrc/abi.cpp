@@ -315,7 +315,7 @@ static wd_status solve_args(const wd_gauge *U, const void *b, void *x, double ka
     memcpy(&prm, p, p->struct_size);
     prm.struct_size = sizeof(prm);
   }
-  if (prm.solver < WD_SOLVER_CG || prm.solver > WD_SOLVER_FGCR)
+  if (prm.solver < WD_SOLVER_CG || prm.solver > WD_SOLVER_DEFECT_FGCR)
     return set_error(WD_ERR_ARG, "solve: solver = %d", prm.solver);
   if (prm.inner_prec == WD_F64 && prm.solver == WD_SOLVER_DEFECT_CG)
     return set_error(WD_ERR_PREC, "solve: defect correction needs a reduced inner precision");
@@ -324,6 +324,10 @@ static wd_status solve_args(const wd_gauge *U, const void *b, void *x, double ka
   if (prm.max_iter < 1) return set_error(WD_ERR_ARG, "solve: max_iter must be >= 1");
   if (prm.check_every < 1) prm.check_every = 1;
   if (prm.fgcr_m < 1 || prm.fgcr_m > 64) return set_error(WD_ERR_ARG, "solve: fgcr_m = %d", prm.fgcr_m);
+  if (prm.solver == WD_SOLVER_DEFECT_FGCR && prm.fgcr_m > 16)
+    return set_error(WD_ERR_ARG, "solve: the mixed FGCR keeps at most 16 directions (fgcr_m = %d)", prm.fgcr_m);
+  if (prm.solver == WD_SOLVER_DEFECT_FGCR && prm.inner_prec != WD_F32)
+    return set_error(WD_ERR_PREC, "solve: the mixed FGCR stores its inner vectors in FP32");
   return set_device(U);
 }
 

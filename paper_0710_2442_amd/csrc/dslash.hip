@@ -189,15 +189,17 @@ static void launch_prec(const KDslash &k, bool dag, int epi, bool norm, unsigned
 // Largest grid of a single-RHS hop launch (smallest block size, 64).
 unsigned dslash_grid_blocks(const wd_gauge *g) { return (unsigned)((g->geom.vpad + 63) / 64); }
 
-// A variant (block size, region groups) is valid for a lattice when the
-// block size divides the slots and, for G > 0, the tiles of one time slice
-// split evenly into G regions.
+// A variant (block size, tile order) is valid for a lattice when the block
+// size divides the slots and, for groups != 0, the blocks tile the time
+// slices exactly and either (G > 0) the tiles of one slice split evenly into
+// G regions or (-X < 0) the slices split evenly over X lanes.
 bool dslash_variant_ok(const Geom &G, int bs, int groups) {
   if (bs != 16 && bs != 64 && bs != 128 && bs != 256 && bs != 512) return false;
   if (groups == 0) return true;
-  if (groups < 0 || groups > 64) return false;
+  if (groups < -16 || groups > 64) return false;
   const long slice = (long)G.vh / G.L[3];
   if (G.vpad != G.vh || slice % bs != 0) return false;
+  if (groups < 0) return G.L[3] % (-groups) == 0;
   const long tps = slice / bs;
   return tps % groups == 0;
 }

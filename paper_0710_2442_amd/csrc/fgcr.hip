@@ -14,9 +14,11 @@
 
 #include <algorithm>
 #include <chrono>
+#include <utility>
 #include <vector>
 
 #include "wd_blas.h"
+#include "wd_device.h"
 #include "wd_ptc.h"
 #include "wd_solver.h"
 
@@ -224,6 +226,372 @@ wd_status solve_fgcr(wd_gauge *g, const void *b, void *x, double kappa, double t
     rn = sqrt(rr);
   }
   info.true_rel_resid = rn / bn;
+  return info.true_rel_resid <= tol ? WD_OK : WD_NOT_CONVERGED;
+}
+
+// ------------------------------------------------------------------------
+// Mixed precision: FP64 defect correction around an FP32 even-odd FGCR.
+//
+// Outer (FP64): r = b - D x;  rh = r / |r| (FP32);  Schur right-hand side
+// s = rh_e + kappa H_eo rh_o;  inner solve of Mhat e_e = s with
+// Mhat = 1 - kappa^2 H_eo H_oe to |s - Mhat e_e| <= inner_tol |s|;
+// e_o = rh_o + kappa H_oe e_e;  x += |r| e;  repeat until the FP64 true
+// residual meets tol.
+//
+// Inner (FP32 vectors, FP64 reductions), one direction per iteration:
+//   z_k = [N (r, 0)]_e   (the network restricted to the even sites; z = r
+//                         without a network)
+//   w_k = Mhat z_k
+//   c_j = <w_j, w_k> / |w_j|^2 (j < k, one fused pass: classical Gram-Schmidt
+//         against an unnormalised basis)
+//   w_k -= sum c_j w_j,  z_k -= sum c_j z_j,  sigma_k = |w_k|^2,
+//   rho = <w_k, r>       (one fused pass)
+//   alpha = rho / sigma_k,  e += alpha z_k,  r -= alpha w_k,  |r|^2 (one pass)
+// The basis is dropped after m directions (restart).  All coefficients stay
+// in device memory; the host reads |r|^2 once per iteration.
+
+namespace {
+
+constexpr int FG_MMAX = 16;
+constexpr int FG_BS = 256;
+constexpr unsigned FG_MAX_BLOCKS = 2048;
+
+struct KFg {
+  int vh;
+  unsigned nblk;
+  const char *W[FG_MMAX];  // basis w_j (FP32 half fields)
+  const char *Z[FG_MMAX];  // and z_j
+  char *wk, *zk;           // the new direction (updated in place)
+  char *r, *e;
+  double *dots;    // [2 FG_MMAX]: <w_j, w_k>
+  double *sig;     // [FG_MMAX]: |w_j|^2
+  double *rho;     // [2]: <w_k, r>
+  double *rr;      // |r|^2
+  int k;
+  double *partials;
+  unsigned *counter;
+};
+
+using F4 = Spinor<WD_F32>;
+
+// <a, b> = sum conj(a) b over one site, in FP64
+__device__ __forceinline__ void site_dot(const cplx<float> (&a)[12], const cplx<float> (&b)[12], double &re,
+                                         double &im) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    re += (double)a[c].re * b[c].re + (double)a[c].im * b[c].im;
+    im += (double)a[c].re * b[c].im - (double)a[c].im * b[c].re;
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(FG_BS) void k_fg_dots(KFg a) {
+  double acc[2 * K];
+#pragma unroll
+  for (int j = 0; j < 2 * K; ++j) acc[j] = 0.0;
+  for (long i = (long)blockIdx.x * FG_BS + threadIdx.x; i < a.vh; i += (long)a.nblk * FG_BS) {
+    cplx<float> w[12];
+    F4::load(a.wk, i, w);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      cplx<float> v[12];
+      F4::load(a.W[j], i, v);
+      site_dot(v, w, acc[2 * j], acc[2 * j + 1]);
+    }
+  }
+  double tot[2 * K];
+  if (grid_sum_last<2 * K>(acc, a.partials, a.counter, a.nblk, blockIdx.x, tot)) {
+#pragma unroll
+    for (int j = 0; j < 2 * K; ++j) a.dots[j] = tot[j];
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(FG_BS) void k_fg_orth(KFg a) {
+  cplx<float> c[K > 0 ? K : 1];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const double s = a.sig[j];
+    const double f = (s > 0.0) ? 1.0 / s : 0.0;
+    c[j] = {(float)(a.dots[2 * j] * f), (float)(a.dots[2 * j + 1] * f)};
+  }
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (long i = (long)blockIdx.x * FG_BS + threadIdx.x; i < a.vh; i += (long)a.nblk * FG_BS) {
+    cplx<float> w[12], z[12];
+    F4::load(a.wk, i, w);
+    if constexpr (K > 0) {
+      F4::load(a.zk, i, z);
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        cplx<float> v[12];
+        const cplx<float> m = {-c[j].re, -c[j].im};
+        F4::load(a.W[j], i, v);
+#pragma unroll
+        for (int q = 0; q < 12; ++q) cfma(w[q], m, v[q]);
+        F4::load(a.Z[j], i, v);
+#pragma unroll
+        for (int q = 0; q < 12; ++q) cfma(z[q], m, v[q]);
+      }
+      F4::store<false>(a.wk, i, w);
+      F4::store<false>(a.zk, i, z);
+    }
+    cplx<float> r[12];
+    F4::load(a.r, i, r);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) acc[0] += (double)w[q].re * w[q].re + (double)w[q].im * w[q].im;
+    site_dot(w, r, acc[1], acc[2]);
+  }
+  double tot[3];
+  if (grid_sum_last<3>(acc, a.partials, a.counter, a.nblk, blockIdx.x, tot)) {
+    a.sig[a.k] = tot[0];
+    a.rho[0] = tot[1];
+    a.rho[1] = tot[2];
+  }
+}
+
+__global__ __launch_bounds__(FG_BS) void k_fg_step(KFg a) {
+  const double s = a.sig[a.k];
+  const bool ok = s > 0.0 && s < 1e300;
+  const cplx<float> al = {ok ? (float)(a.rho[0] / s) : 0.f, ok ? (float)(a.rho[1] / s) : 0.f};
+  const cplx<float> ml = {-al.re, -al.im};
+  double acc[1] = {0.0};
+  for (long i = (long)blockIdx.x * FG_BS + threadIdx.x; i < a.vh; i += (long)a.nblk * FG_BS) {
+    cplx<float> z[12], w[12], e[12], r[12];
+    F4::load(a.zk, i, z);
+    F4::load(a.e, i, e);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) cfma(e[q], al, z[q]);
+    F4::store<false>(a.e, i, e);
+    F4::load(a.wk, i, w);
+    F4::load(a.r, i, r);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+      cfma(r[q], ml, w[q]);
+      acc[0] += (double)r[q].re * r[q].re + (double)r[q].im * r[q].im;
+    }
+    F4::store<false>(a.r, i, r);
+  }
+  double tot[1];
+  if (grid_sum_last<1>(acc, a.partials, a.counter, a.nblk, blockIdx.x, tot)) *a.rr = tot[0];
+}
+
+template <int K>
+void launch_dots_k(const KFg &a, hipStream_t st) {
+  hipLaunchKernelGGL((k_fg_dots<K>), dim3(a.nblk), dim3(FG_BS), 0, st, a);
+}
+template <int K>
+void launch_orth_k(const KFg &a, hipStream_t st) {
+  hipLaunchKernelGGL((k_fg_orth<K>), dim3(a.nblk), dim3(FG_BS), 0, st, a);
+}
+
+template <int... Ks>
+void launch_dots(const KFg &a, int k, hipStream_t st, std::integer_sequence<int, Ks...>) {
+  ((k == Ks + 1 ? launch_dots_k<Ks + 1>(a, st) : void()), ...);
+}
+template <int... Ks>
+void launch_orth(const KFg &a, int k, hipStream_t st, std::integer_sequence<int, Ks...>) {
+  ((k == Ks ? launch_orth_k<Ks>(a, st) : void()), ...);
+}
+
+// out = Mhat in = in - kappa^2 H_eo H_oe in   (FP32 even half fields; tmp: odd half)
+wd_status apply_mhat32(wd_gauge *g, const void *in, void *out, void *tmp, double kappa, hipStream_t st) {
+  DslashArgs a;
+  a.in = in;
+  a.out = tmp;
+  a.a = 1.0;
+  a.parity = 1;
+  WD_TRY(launch_dslash(g, WD_F32, a, st));
+  DslashArgs b;
+  b.in = tmp;
+  b.out = out;
+  b.X = in;
+  b.a = -kappa * kappa;
+  b.parity = 0;
+  return launch_dslash(g, WD_F32, b, st);
+}
+
+}  // namespace
+
+wd_status solve_fgcr_mixed(wd_gauge *g, const void *b, void *x, double kappa, double tol,
+                           const wd_solve_params &prm, wd_solve_info &info, hipStream_t st) {
+  const wd_ptc *N = prm.precond;
+  if (N && ptc_gauge(N) != g)
+    return set_error(WD_ERR_ARG, "FGCR: the preconditioner was created on another gauge handle");
+  const int m = std::min(prm.fgcr_m, FG_MMAX);
+  const Geom &G = g->geom;
+  const size_t h64 = half_bytes(G, WD_F64), h32 = half_bytes(G, WD_F32);
+  // r64, d64 (2 h64 each); rh, e (2 h32 each); R, T, Z[m], W[m] (h32 each)
+  Buf mem, red, pin;
+  const unsigned nblk = (unsigned)std::min<long>(std::max<long>(1, ((long)G.vh + FG_BS - 1) / FG_BS), FG_MAX_BLOCKS);
+  const size_t npart = std::max<size_t>((size_t)2 * FG_MMAX * nblk,
+                                        (size_t)2 * std::max<unsigned>(dslash_grid_blocks(g), BLAS_MAX_BLOCKS));
+  WD_HIP(hipMalloc(&mem.p, 4 * h64 + 4 * h32 + (2 + 2 * (size_t)m) * h32));
+  // device scalars: [0, 64) CgScalars + dots/sig/rho/rr; then partials; then the counter
+  const size_t scal_bytes = 1024;
+  WD_HIP(hipMalloc(&red.p, scal_bytes + npart * sizeof(double) + 256));
+  WD_HIP(hipMemsetAsync(red.p, 0, scal_bytes, st));
+  WD_HIP(hipMemsetAsync((char *)red.p + scal_bytes + npart * sizeof(double), 0, 256, st));
+  double *hres = nullptr;
+  WD_HIP(hipHostMalloc((void **)&hres, 64 * sizeof(double), hipHostMallocDefault));
+  struct HostFree {
+    double *p;
+    ~HostFree() { (void)hipHostFree(p); }
+  } hf{hres};
+  char *c0 = (char *)mem.p;
+  char *r64 = c0, *d64 = c0 + 2 * h64, *rh = c0 + 4 * h64, *e32 = rh + 2 * h32;
+  char *R = e32 + 2 * h32, *T = R + h32;
+  char *E = e32;  // inner solution = even half of e32
+  KFg a{};
+  a.vh = G.vh;
+  a.nblk = nblk;
+  for (int k = 0; k < m; ++k) {
+    a.Z[k] = T + (1 + (size_t)k) * h32;
+    a.W[k] = T + (1 + (size_t)m + k) * h32;
+  }
+  CgScalars *sc = (CgScalars *)red.p;
+  double *ds = (double *)((char *)red.p + 128);
+  a.dots = ds;
+  a.sig = ds + 2 * FG_MMAX;
+  a.rho = a.sig + FG_MMAX;
+  a.rr = a.rho + 2;
+  a.r = R;
+  a.e = E;
+  a.partials = (double *)((char *)red.p + scal_bytes);
+  a.counter = (unsigned *)((char *)red.p + scal_bytes + npart * sizeof(double));
+  RedBuf rb{a.partials, a.counter};
+  auto read = [&](const double *dev, int n, double *out) -> wd_status {
+    WD_HIP(hipMemcpyAsync(hres, dev, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    WD_HIP(hipStreamSynchronize(st));
+    for (int q = 0; q < n; ++q) out[q] = hres[q];
+    return WD_OK;
+  };
+
+  // |b|^2;  x = 0;  r = b
+  double bb;
+  WD_TRY(blas_norm2(G, WD_F64, vref(b, 2), 1, rb, a.rr, st));
+  WD_TRY(read(a.rr, 1, &bb));
+  if (!(bb < 1e300)) return set_error(WD_ERR_NONFINITE, "FGCR: |b|^2 is not finite");
+  WD_TRY(blas_convert(G, WD_F64, vref(b, 2), WD_F64, vref(x, 2), 0.0, nullptr, 1, st));
+  if (bb == 0.0) {
+    info.true_rel_resid = 0.0;
+    return WD_OK;
+  }
+  WD_TRY(blas_convert(G, WD_F64, vref(b, 2), WD_F64, vref(r64, 2), 1.0, nullptr, 1, st));
+  {
+    CgScalars h{};
+    h.rnorm2 = bb;
+    h.bb = bb;
+    WD_HIP(hipMemcpyAsync(sc, &h, sizeof h, hipMemcpyHostToDevice, st));
+    WD_HIP(hipStreamSynchronize(st));
+  }
+  double rn2 = bb, best_outer = 1e300;
+  int stalls = 0, it = 0, calls = 0;
+  bool converged = false, fallback = false;
+  const int stagnation = 30;
+  for (int outer = 0; outer < 100 && !fallback; ++outer) {
+    if (rn2 <= tol * tol * bb) {
+      converged = true;
+      break;
+    }
+    if (!(rn2 < 1e300) || it >= prm.max_iter) {
+      fallback = true;
+      break;
+    }
+    if (rn2 < 0.5 * best_outer) {
+      best_outer = rn2;
+      stalls = 0;
+    } else if (++stalls >= 3) {
+      fallback = true;
+      break;
+    }
+    // rh = r / |r|;  R = rh_e + kappa H_eo rh_o;  E = 0
+    WD_TRY(blas_convert(G, WD_F64, vref(r64, 2), WD_F32, vref(rh, 2), 1.0, sc, 1, st));
+    {
+      DslashArgs d;
+      d.in = rh + h32;
+      d.out = R;
+      d.X = rh;
+      d.a = kappa;
+      d.parity = 0;
+      WD_TRY(launch_dslash(g, WD_F32, d, st));
+      calls += 1;
+    }
+    WD_HIP(hipMemsetAsync(E, 0, h32, st));
+    double s2;
+    WD_TRY(blas_norm2(G, WD_F32, vref(R, 1), 1, rb, a.rr, st));
+    WD_TRY(read(a.rr, 1, &s2));
+    const double target = prm.inner_tol * prm.inner_tol * s2;
+    double rr = s2, best = s2;
+    int since = 0, k = 0;
+    while (rr > target && it < prm.max_iter) {
+      char *zk = (char *)a.Z[k], *wk = (char *)a.W[k];
+      if (N) WD_TRY(ptc_apply_even(N, R, zk, st));
+      else WD_TRY(blas_convert(G, WD_F32, vref(R, 1), WD_F32, vref(zk, 1), 1.0, nullptr, 1, st));
+      WD_TRY(apply_mhat32(g, zk, wk, T, kappa, st));
+      calls += 2;
+      a.wk = wk;
+      a.zk = zk;
+      a.k = k;
+      if (k > 0) launch_dots(a, k, st, std::make_integer_sequence<int, FG_MMAX - 1>{});
+      launch_orth(a, k, st, std::make_integer_sequence<int, FG_MMAX>{});
+      hipLaunchKernelGGL(k_fg_step, dim3(a.nblk), dim3(FG_BS), 0, st, a);
+      WD_TRY(hip_check(hipGetLastError(), "fgcr launch"));
+      WD_TRY(read(a.rr, 1, &rr));
+      ++it;
+      if (!(rr < 1e300)) {
+        fallback = true;
+        break;
+      }
+      if (rr < 0.98 * best) {
+        best = rr;
+        since = 0;
+      } else if (++since >= stagnation) {
+        fallback = true;
+        break;
+      }
+      k = (k + 1 == m) ? 0 : k + 1;
+    }
+    if (fallback) break;
+    // e_o = rh_o + kappa H_oe E;  x += |r| e;  r = b - D x
+    {
+      DslashArgs d;
+      d.in = E;
+      d.out = e32 + h32;
+      d.X = rh + h32;
+      d.a = kappa;
+      d.parity = 1;
+      WD_TRY(launch_dslash(g, WD_F32, d, st));
+    }
+    WD_TRY(blas_accum(G, WD_F32, vref(e32, 2), vref(x, 2), 1.0, sc, 1, st));
+    WD_TRY(true_residual64(g, b, x, r64, 1, 0, kappa, sc, rb, st));
+    calls += 3;
+    WD_TRY(read(&sc->rnorm2, 1, &rn2));
+    info.outer_iters += 1;
+  }
+  info.iters = it;
+  info.dslash_calls = calls;
+  if (!converged) {
+    // plain FP64 CG on the remaining residual: x <- x + D^{-1} r
+    if (!(rn2 < 1e300)) {  // restart from x = 0 if x itself went bad
+      WD_TRY(blas_convert(G, WD_F64, vref(b, 2), WD_F64, vref(x, 2), 0.0, nullptr, 1, st));
+      WD_TRY(blas_convert(G, WD_F64, vref(b, 2), WD_F64, vref(r64, 2), 1.0, nullptr, 1, st));
+      rn2 = bb;
+    }
+    wd_solve_params cg = prm;
+    cg.solver = WD_SOLVER_CG;
+    wd_solve_info ci;
+    memset(&ci, 0, sizeof ci);
+    const double tol_r = std::max(1e-15, tol * sqrt(bb / rn2));
+    wd_status rc = solve_cg64(g, r64, d64, kappa, 0.5 * tol_r, cg, ci, st);
+    if (rc < 0) return rc;
+    WD_TRY(blas_caxpy(G, WD_F64, 1.0, 0.0, vref(d64, 2), vref(x, 2), 1, st));
+    info.iters += ci.iters;
+    info.dslash_calls += ci.dslash_calls + 2;
+    info.fallback_used = 1;
+    WD_TRY(true_residual64(g, b, x, r64, 1, 0, kappa, sc, rb, st));
+    WD_TRY(read(&sc->rnorm2, 1, &rn2));
+  }
+  info.true_rel_resid = sqrt(rn2 / bb);
   return info.true_rel_resid <= tol ? WD_OK : WD_NOT_CONVERGED;
 }
 

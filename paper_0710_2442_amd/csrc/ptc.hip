@@ -135,7 +135,10 @@ __device__ __forceinline__ void spin_mat_acc(const float *W, const cplx<float> (
   }
 }
 
-template <int PIN, int POUT, int CIN, int COUT>
+// INPAR = -1: the input lives on both parities.  INPAR = q: the input is zero
+// off parity q, so a site of parity q takes only the h = 0 term and a site of
+// the other parity only the hops (h >= 1); the zero terms are not read.
+template <int PIN, int POUT, int CIN, int COUT, int INPAR = -1>
 __global__ __launch_bounds__(PTC_BS) void k_ptc_layer(KPtc k) {
   const int p = blockIdx.y;
   const int i = blockIdx.x * PTC_BS + threadIdx.x;
@@ -154,7 +157,9 @@ __global__ __launch_bounds__(PTC_BS) void k_ptc_layer(KPtc k) {
   for (int co = 0; co < COUT; ++co)
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[co][c] = {0.f, 0.f};
-  for (int h = 0; h < 9; ++h) {
+  const int h0 = (INPAR >= 0 && p != INPAR) ? 1 : 0;
+  const int h1 = (INPAR >= 0 && p == INPAR) ? 1 : 9;
+  for (int h = h0; h < h1; ++h) {
 #pragma unroll
     for (int ci = 0; ci < CIN; ++ci) {
       cplx<float> v[12];
@@ -427,6 +432,38 @@ static wd_status ptc_wgrad(const wd_ptc *n, int layer, const void *in, wd_prec p
 }
 
 void ptc_release(wd_gauge *) {}
+
+// Even-parity restriction of the network for the even-odd solver:
+// out_e = [N (in_e, 0)]_e, F32 half fields.  The input's odd half is never
+// read (layer 1 knows it is zero) and layer 2 computes even sites only.
+wd_status ptc_apply_even(const wd_ptc *n, const void *in_even, void *out_even, hipStream_t st) {
+  const Geom &G = n->g->geom;
+  WD_TRY(blas_convert(G, WD_F32, vref(in_even, 1), n->act, vref(n->x0, 1), 1.0, nullptr, 1, st));
+  KPtc k = ptc_k(n);
+  k.in = (const char *)n->x0;
+  k.out = (char *)n->y1;
+  k.in_half = half_bytes(G, n->act);
+  k.out_half = k.in_half;
+  k.in_chan = 2 * k.in_half;
+  k.out_chan = 2 * k.out_half;
+  k.W = n->W;
+  const dim3 grid = ptc_grid(G);
+  if (n->act == WD_BF16) hipLaunchKernelGGL((k_ptc_layer<WD_BF16, WD_BF16, 1, 2, 0>), grid, dim3(PTC_BS), 0, st, k);
+  else hipLaunchKernelGGL((k_ptc_layer<WD_F32, WD_F32, 1, 2, 0>), grid, dim3(PTC_BS), 0, st, k);
+  WD_TRY(hip_check(hipGetLastError(), "ptc layer"));
+  KPtc k2 = ptc_k(n);
+  k2.in = (const char *)n->y1;
+  k2.out = (char *)out_even;
+  k2.in_half = half_bytes(G, n->act);
+  k2.in_chan = 2 * k2.in_half;
+  k2.out_half = half_bytes(G, WD_F32);
+  k2.out_chan = 2 * k2.out_half;
+  k2.W = n->W + 576;
+  const dim3 grid_e(grid.x, 1);  // parity 0 only
+  if (n->act == WD_BF16) hipLaunchKernelGGL((k_ptc_layer<WD_BF16, WD_F32, 2, 1>), grid_e, dim3(PTC_BS), 0, st, k2);
+  else hipLaunchKernelGGL((k_ptc_layer<WD_F32, WD_F32, 2, 1>), grid_e, dim3(PTC_BS), 0, st, k2);
+  return hip_check(hipGetLastError(), "ptc layer");
+}
 
 // N(in): F32 full field -> F32 full field; input and hidden layer are stored
 // in the activation precision.

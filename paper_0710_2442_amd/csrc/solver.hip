@@ -217,8 +217,8 @@ static wd_status cgls_run(const wd_gauge *g, const CglsVecs &v, double kappa, co
 }
 
 // r = b - D x (FP64, full fields) for nsys systems, |r|^2 -> sc[y].rnorm2
-static wd_status true_residual64(const wd_gauge *g, const void *b, const void *x, void *r, int nsys,
-                                 size_t sys_stride, double kappa, CgScalars *sc, RedBuf red, hipStream_t st) {
+wd_status true_residual64(const wd_gauge *g, const void *b, const void *x, void *r, int nsys, size_t sys_stride,
+                          double kappa, CgScalars *sc, RedBuf red, hipStream_t st) {
   const size_t hb = half_bytes(g->geom, WD_F64);
   for (int par = 0; par < 2; ++par) {
     const int q = 1 - par;
@@ -478,6 +478,8 @@ wd_status solve(wd_gauge *g, const void *b, void *x, double kappa, double tol, c
     rc = solve_defect(g, b, x, 1, 0, kappa, tol, prm, &info, st);
   } else if (prm.solver == WD_SOLVER_FGCR) {
     rc = solve_fgcr(g, b, x, kappa, tol, prm, info, st);
+  } else if (prm.solver == WD_SOLVER_DEFECT_FGCR) {
+    rc = solve_fgcr_mixed(g, b, x, kappa, tol, prm, info, st);
   } else {
     return set_error(WD_ERR_ARG, "wd_solve: unknown solver %d", prm.solver);
   }

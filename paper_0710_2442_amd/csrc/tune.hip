@@ -153,7 +153,7 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
       if ((rc = hip_check(hipMemcpyAsync(h_ref.data(), ref, hb, hipMemcpyDeviceToHost, st), "copy")) != WD_OK) break;
       if ((rc = hip_check(hipStreamSynchronize(st), "sync")) != WD_OK) break;
       const int blocks[] = {64, 128, 256, 512};
-      const int grps[] = {0, 2, 4, 8, 16};
+      const int grps[] = {0, 2, 4, 8, 16, -8};
       best_us = 1e30;
       int nbest_b = 256, nbest_g = 0, nbest_o = 0, nbest_n = 1, nbest_l = 0;
       size_t lds_max = 65536;
@@ -269,7 +269,7 @@ wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, int *out_grou
     if ((rc = launch_dslash_mrhs(g, prec, in, ref, 1.0, WD_EVEN, 0, nrhs, st)) != WD_OK) break;
     if ((rc = hip_check(hipMemcpyAsync(h_ref.data(), ref, hb, hipMemcpyDeviceToHost, st), "copy")) != WD_OK) break;
     if ((rc = hip_check(hipStreamSynchronize(st), "sync")) != WD_OK) break;
-    for (int gr : {0, 2, 4, 8, 16}) {
+    for (int gr : {0, 2, 4, 8, 16, -8}) {
       if (!dslash_variant_ok(G, 16, gr)) continue;
       g->mrhs_groups[prec] = gr;
       if ((rc = launch_dslash_mrhs(g, prec, in, cand, 1.0, WD_EVEN, 0, nrhs, st)) != WD_OK) break;

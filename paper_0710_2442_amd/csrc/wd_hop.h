@@ -31,17 +31,28 @@ struct KDslash {
 };
 
 // Workgroups are dispatched round-robin over the XCDs (8 on MI355X), each
-// with its own L2.  With `groups` = G, block b goes to region b % G and the
+// with its own L2.  groups = G > 0: block b goes to region b % G and the
 // blocks of one region walk its tiles slice by slice in time order, so a
 // region's neighbour spinors (x1..x3 inside the slice, x4 one slice away)
 // are fetched into one L2 and re-read from there.  Requires
-// tiles_per_slice % G == 0 and gridDim.x == tiles_per_slice * L4.
+// tiles_per_slice % G == 0.  groups = -X: whole time slices are dealt
+// round-robin to X lanes (block b to lane b % X); with X = 8 one XCD computes
+// all tiles of a slice, so every spatial neighbour is re-read from its L2,
+// while the time hops, which read the two disjoint halves of a neighbour
+// slice's spinors, need no reuse at all.  Requires L4 % X == 0.  Both need
+// gridDim.x == tiles_per_slice * L4.
 __device__ __forceinline__ int tile_of(const KDslash &k, int b) {
   if (k.groups == 0) return b;
+  const int T = k.tiles_per_slice;
+  if (k.groups < 0) {
+    const int X = -k.groups;
+    const int x = b % X, q = b / X;
+    return ((q / T) * X + x) * T + (q % T);
+  }
   const int G = k.groups;
-  const int per = k.tiles_per_slice / G;
+  const int per = T / G;
   const int x = b % G, q = b / G;
-  return (q / per) * k.tiles_per_slice + x * per + (q % per);
+  return (q / per) * T + x * per + (q % per);
 }
 __device__ __forceinline__ int tile_of(const KDslash &k) { return tile_of(k, (int)blockIdx.x); }
 

@@ -24,15 +24,18 @@ def test_training_reduces_loss_and_fgcr_iterations():
     b = syn.gaussian_spinor(dims, 402)
     fb = to_field(g, b)
     res = {}
-    for name, net in (("identity", None), ("trained", wd.Ptc(g, W, "bf16"))):
-        fx = wd.wd_new_field(dims, "f64")
-        p = wd.wd_solve_params_default(solver=wd.WD_SOLVER_FGCR, fgcr_m=16, precond=net)
-        rc, info = wd.wd_solve(g, fb, fx, kappa, 1e-10, p)
-        assert rc == 0 and info["fallback_used"] == 0
-        assert solvers.true_residual(U, b, from_field(g, fx), kappa) <= 1e-10
-        res[name] = info["iters"]
-        if net is not None:
-            net.close()
+    for solver in (wd.WD_SOLVER_FGCR, wd.WD_SOLVER_DEFECT_FGCR):
+        for name, net in (("identity", None), ("trained", wd.Ptc(g, W, "bf16"))):
+            fx = wd.wd_new_field(dims, "f64")
+            p = wd.wd_solve_params_default(solver=solver, fgcr_m=16 if solver == wd.WD_SOLVER_FGCR else 8,
+                                           precond=net)
+            rc, info = wd.wd_solve(g, fb, fx, kappa, 1e-10, p)
+            assert rc == 0 and info["fallback_used"] == 0
+            assert solvers.true_residual(U, b, from_field(g, fx), kappa) <= 1e-10
+            res[(solver, name)] = info["iters"]
+            if net is not None:
+                net.close()
     print("fgcr iterations", res, flush=True)
-    assert res["trained"] < 0.8 * res["identity"]
+    for solver in (wd.WD_SOLVER_FGCR, wd.WD_SOLVER_DEFECT_FGCR):
+        assert res[(solver, "trained")] < 0.8 * res[(solver, "identity")]
     g.close()

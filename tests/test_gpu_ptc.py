@@ -141,14 +141,15 @@ def test_adam_steps_follow_oracle_and_reduce_loss():
 
 
 # ------------------------------------------------------------------ FGCR
-def _fgcr(dims, kappa, net_flat=None, act="bf16", m=12, seed=341):
+def _fgcr(dims, kappa, net_flat=None, act="bf16", m=12, seed=341, solver=None, **kw):
     U = syn.gauge_field(dims, 0.3, seed)
     b = syn.gaussian_spinor(dims, seed + 1)
     g = wd.Gauge(U, dims, -1, "f64")
     n = wd.Ptc(g, net_flat, act) if net_flat is not None else None
     fb = to_field(g, b)
     fx = wd.wd_new_field(dims, "f64")
-    p = wd.wd_solve_params_default(solver=wd.WD_SOLVER_FGCR, fgcr_m=m, precond=n)
+    p = wd.wd_solve_params_default(solver=wd.WD_SOLVER_FGCR if solver is None else solver, fgcr_m=m, precond=n,
+                                   **kw)
     rc, info = wd.wd_solve(g, fb, fx, kappa, 1e-10, p)
     x = from_field(g, fx)
     if n is not None:
@@ -200,5 +201,70 @@ def test_fgcr_falls_back_to_cg(bad):
         g.close()
     else:
         U, b, x, rc, info = _fgcr(dims, kappa, flat, "f32", seed=361)
+    assert rc == 0 and info["fallback_used"] == 1
+    assert solvers.true_residual(U, b, x, kappa) <= 1e-10
+
+
+# ------------------------------------------------- mixed-precision even-odd FGCR
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (6, 4, 6, 10)])
+@pytest.mark.parametrize("net", [None, "f32", "bf16"])
+def test_defect_fgcr_reaches_fp64_residual(dims, net):
+    """FP32 eo-FGCR inside FP64 defect correction: the oracle's own D_W must
+    see a true residual <= 1e-10, the reported residual must agree, and the
+    solution must agree with the oracle's FP64 eo-CGLS solution."""
+    kappa = 0.124
+    flat = None if net is None else wd.ptc_weights_to_flat(*ptc.init_weights(353))
+    U, b, x, rc, info = _fgcr(dims, kappa, flat, net or "bf16", m=8, solver=wd.WD_SOLVER_DEFECT_FGCR,
+                              inner_tol=1e-3)
+    assert rc == 0 and info["fallback_used"] == 0, info
+    r = solvers.true_residual(U, b, x, kappa)
+    assert r <= 1e-10
+    assert abs(r - info["true_rel_resid"]) <= 1e-3 * 1e-10 + 1e-15
+    assert info["outer_iters"] >= 2  # FP32 inner: at least one correction
+    xo, _, _ = solvers.solve_eo_cgls(U, b, kappa, 1e-12)
+    assert rel_err(x, xo) <= 1e-7
+
+
+@pytest.mark.parametrize("m", [1, 4, 16])
+def test_defect_fgcr_restart_lengths(m):
+    U, b, x, rc, info = _fgcr((8, 8, 8, 8), 0.124, None, m=m, solver=wd.WD_SOLVER_DEFECT_FGCR)
+    assert rc == 0 and info["fallback_used"] == 0
+    assert solvers.true_residual(U, b, x, 0.124) <= 1e-10
+
+
+def test_defect_fgcr_is_deterministic():
+    a = _fgcr((8, 8, 8, 8), 0.124, wd.ptc_weights_to_flat(*ptc.init_weights(354)), "bf16", m=8,
+              solver=wd.WD_SOLVER_DEFECT_FGCR)
+    b = _fgcr((8, 8, 8, 8), 0.124, wd.ptc_weights_to_flat(*ptc.init_weights(354)), "bf16", m=8,
+              solver=wd.WD_SOLVER_DEFECT_FGCR)
+    assert a[4]["iters"] == b[4]["iters"] and np.array_equal(a[2], b[2])
+
+
+def test_defect_fgcr_rejects_bad_parameters():
+    dims = (4, 4, 4, 4)
+    g = wd.Gauge(syn.gauge_field(dims, 0.3, 355), dims, -1, "f64")
+    fb = to_field(g, syn.gaussian_spinor(dims, 356))
+    fx = wd.wd_new_field(dims, "f64")
+    for kw in (dict(fgcr_m=17), dict(inner_prec="f16"), dict(inner_prec="bf16")):
+        p = wd.wd_solve_params_default(solver=wd.WD_SOLVER_DEFECT_FGCR, **kw)
+        with pytest.raises(wd.WdError):
+            wd.wd_solve(g, fb, fx, 0.124, 1e-10, p)
+    g.close()
+
+
+def test_defect_fgcr_falls_back_to_cg_on_overflow():
+    dims, kappa = (8, 8, 8, 8), 0.124
+    U = syn.gauge_field(dims, 0.3, 363)
+    b = syn.gaussian_spinor(dims, 364)
+    g = wd.Gauge(U, dims, -1, "f64")
+    n = wd.Ptc(g, np.zeros(1152, np.float32), "f32")
+    wd.wd_ptc_set_weights(n, np.full(1152, 3e38, np.float32))  # overflows to inf inside the network
+    fb = to_field(g, b)
+    fx = wd.wd_new_field(dims, "f64")
+    p = wd.wd_solve_params_default(solver=wd.WD_SOLVER_DEFECT_FGCR, precond=n)
+    rc, info = wd.wd_solve(g, fb, fx, kappa, 1e-10, p)
+    x = from_field(g, fx)
+    n.close()
+    g.close()
     assert rc == 0 and info["fallback_used"] == 1
     assert solvers.true_residual(U, b, x, kappa) <= 1e-10
