@@ -277,12 +277,14 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path,
                          int force, int *block, int *groups, int *occ,
                          double *us);
 
-/* Tune the multi-RHS hop for nrhs right-hand sides: the block -> tile order
- * of its 16-site tiles (groups as above; candidates checked byte for
- * byte against linear order, then timed).  Outputs may be NULL.
+/* Tune the multi-RHS hop for nrhs right-hand sides: its block size (FP32,
+ * FP16, BF16: 64, 128 or 256 sites, one lane per site looping over the RHS;
+ * FP64: fixed 16-site x RHS tiles) and block -> tile order (groups as above).
+ * Candidates are checked byte for byte against the linear variant, then
+ * timed; the fastest is kept in the handle.  Outputs may be NULL.
  * Synchronous. */
-wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, int *groups,
-                              double *us);
+wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, int *block,
+                              int *groups, double *us);
 
 /* Bit of the occ value: the hop writes its output with ordinary (cached)
  * stores instead of streaming stores, so that a following kernel can read a

@@ -144,6 +144,107 @@ __global__ __launch_bounds__(256) void k_dslash_mrhs(KMrhs m) {
   }
 }
 
+// Multi-RHS hop for FP32 arithmetic (FP32, FP16 and BF16 spinors): one lane
+// per output site loads its 8 hop links once into registers and then walks
+// the right-hand sides r0 .. r1-1 of its block's chunk, so every link byte is
+// read once per chunk (up to 16 RHS) and every spinor load of a wave is one
+// contiguous run.  Per-RHS skip flags, epilogue and FP64 norms as above.
+constexpr int MR_CHUNK = 16;
+
+template <int P, bool DAG, int EPI, bool NORM>
+__global__ __launch_bounds__(256) void k_dslash_mrhs_reg(KMrhs m) {
+  using T = RealOf<P>;
+  const KDslash &k = m.k;
+  const int i = tile_of(k) * (int)blockDim.x + (int)threadIdx.x;
+  const int r0 = blockIdx.y * MR_CHUNK;
+  const int r1 = min(m.nrhs, r0 + MR_CHUNK);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __shared__ double sred[MR_CHUNK][4];
+  const bool site = i < k.g.vh;
+  int nb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  cplx<T> u[8][6];
+  T sf = (T)1, sb = (T)1;
+  if (site) {
+    const Coords c = coords_of(k.g, i, k.parity);
+    neighbours(k.g, c, i, nb);
+    if (c.x4 == k.g.L[3] - 1) sf = (T)k.g.tbc;
+    if (c.x4 == 0) sb = (T)k.g.tbc;
+#pragma unroll
+    for (int d = 0; d < 8; ++d) Link<T>::load(k.links, d, i, u[d]);
+  }
+  const T a = (T)k.a;
+  for (int r = r0; r < r1; ++r) {
+    const bool live = !(k.skip && k.skip[(size_t)r * m.skip_stride]);
+    double nrm = 0.0;
+    if (live) {
+      const size_t off = (size_t)r * m.rhs_stride;
+      char *out = k.out + off;
+      if (site) {
+        cplx<T> acc[12];
+        hop_all_u<P, DAG>(k.in + off, nb, u, sf, sb, acc);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[c] = a * acc[c];
+        if constexpr (EPI >= 1) {
+          cplx<T> x[12];
+          Spinor<P>::load(k.X + off, i, x);
+#pragma unroll
+          for (int c = 0; c < 12; ++c) acc[c] = acc[c] + x[c];
+        }
+        if constexpr (EPI == 2) {
+          cplx<T> y[12];
+          Spinor<P>::load(k.Y + off, i, y);
+#pragma unroll
+          for (int c = 0; c < 12; ++c) acc[c] = acc[c] - y[c];
+        }
+        Spinor<P>::store(out, i, acc);
+        if constexpr (NORM) {
+          cplx<T> st[12];
+          if constexpr (P == WD_F32) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) st[c] = acc[c];
+          } else {
+            Spinor<P>::load(out, i, st);
+          }
+#pragma unroll
+          for (int c = 0; c < 12; ++c) nrm += (double)st[c].re * st[c].re + (double)st[c].im * st[c].im;
+        }
+      } else if (i < k.g.vpad) {
+        cplx<T> z[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) z[c] = {(T)0, (T)0};
+        Spinor<P>::store(out, i, z);
+      }
+    }
+    if constexpr (NORM) {
+      const double t = wave_sum(nrm);
+      if (lane == 0) sred[r - r0][w] = t;
+    }
+  }
+  if constexpr (NORM) {
+    __syncthreads();
+    double v[MR_CHUNK], tot[MR_CHUNK];
+    const int nw = (int)blockDim.x >> 6;
+#pragma unroll
+    for (int j = 0; j < MR_CHUNK; ++j) {
+      double s = 0.0;
+      if (threadIdx.x == 0 && j < r1 - r0)
+        for (int q = 0; q < nw; ++q) s += sred[j][q];
+      v[j] = s;
+    }
+    if (grid_sum_last<MR_CHUNK>(v, k.partials + (size_t)r0 * gridDim.x, k.counter + blockIdx.y, gridDim.x,
+                                blockIdx.x, tot)) {
+#pragma unroll
+      for (int j = 0; j < MR_CHUNK; ++j) {
+        const int r = r0 + j;
+        if (r < r1 && !(k.skip && k.skip[(size_t)r * m.skip_stride])) {
+          double *dst = k.norm_out + (size_t)r * m.norm_stride;
+          *dst = k.norm_accumulate ? (*dst + tot[j]) : tot[j];
+        }
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------ launchers
 static KDslash make_k(const wd_gauge *g, wd_prec prec, int parity) {
   KDslash k{};
@@ -241,7 +342,8 @@ wd_status launch_dslash(const wd_gauge *g, wd_prec prec, const DslashArgs &a, hi
 
 template <int P, bool DAG, int EPI, bool NORM>
 static void launch_mrhs_t(const KMrhs &m, dim3 grid, dim3 block, hipStream_t st) {
-  hipLaunchKernelGGL((k_dslash_mrhs<P, DAG, EPI, NORM>), grid, block, 0, st, m);
+  if constexpr (P == WD_F64) hipLaunchKernelGGL((k_dslash_mrhs<P, DAG, EPI, NORM>), grid, block, 0, st, m);
+  else hipLaunchKernelGGL((k_dslash_mrhs_reg<P, DAG, EPI, NORM>), grid, block, 0, st, m);
 }
 
 template <int P>
@@ -252,6 +354,17 @@ static void launch_mrhs_p(const KMrhs &m, bool dag, int epi, bool norm, dim3 gri
   WD_M(true, 0, false) WD_M(true, 1, false) WD_M(true, 2, false)
   WD_M(true, 0, true) WD_M(true, 1, true) WD_M(true, 2, true)
 #undef WD_M
+}
+
+// Block size of the multi-RHS hop: FP64 keeps 16 sites x RHS lanes, the
+// others one lane per site (tunable, 64..256).
+static int mrhs_block_of(const wd_gauge *g, wd_prec prec, int &groups) {
+  const int pi = (int)prec;
+  int bs = (prec == WD_F64) ? 16 : g->mrhs_block[pi];
+  if (prec != WD_F64 && bs != 64 && bs != 128 && bs != 256) bs = 128;
+  groups = g->mrhs_groups[pi];
+  if (!dslash_variant_ok(g->geom, bs, groups)) groups = 0;
+  return bs;
 }
 
 wd_status launch_dslash_mrhs_ex(const wd_gauge *g, wd_prec prec, const MrhsArgs &a, hipStream_t st) {
@@ -276,16 +389,19 @@ wd_status launch_dslash_mrhs_ex(const wd_gauge *g, wd_prec prec, const MrhsArgs 
   const bool norm = a.norm_out != nullptr;
   if (norm && (!m.k.partials || !m.k.counter)) return set_error(WD_ERR_ARG, "dslash_mrhs norm: no reduction buffer");
   const int epi = a.Y ? 2 : (a.X ? 1 : 0);
-  {
-    const int pi = (int)prec;
-    int groups = g->mrhs_groups[pi];
-    if (!dslash_variant_ok(g->geom, 16, groups)) groups = 0;
-    m.k.groups = groups;
-    m.k.tiles_per_slice = groups ? (int)((long)g->geom.vh / g->geom.L[3] / 16) : 0;
+  int groups;
+  const int bs = mrhs_block_of(g, prec, groups);
+  m.k.groups = groups;
+  m.k.tiles_per_slice = groups ? (int)((long)g->geom.vh / g->geom.L[3] / bs) : 0;
+  dim3 grid, block;
+  if (prec == WD_F64) {
+    const int per_block = std::min(16, (a.nrhs + 3) / 4 * 4);
+    grid = dim3((unsigned)mrhs_grid_blocks(g), (unsigned)((a.nrhs + 15) / 16));
+    block = dim3((unsigned)(16 * per_block));
+  } else {
+    grid = dim3((unsigned)((g->geom.vpad + bs - 1) / bs), (unsigned)((a.nrhs + MR_CHUNK - 1) / MR_CHUNK));
+    block = dim3((unsigned)bs);
   }
-  const int per_block = std::min(16, (a.nrhs + 3) / 4 * 4);
-  dim3 grid((unsigned)mrhs_grid_blocks(g), (unsigned)((a.nrhs + 15) / 16));
-  dim3 block((unsigned)(16 * per_block));
   switch (prec) {
     case WD_F64: launch_mrhs_p<WD_F64>(m, a.dagger, epi, norm, grid, block, st); break;
     case WD_F32: launch_mrhs_p<WD_F32>(m, a.dagger, epi, norm, grid, block, st); break;

@@ -26,9 +26,11 @@ template <class T>
 __device__ __forceinline__ cplx<T> operator-(cplx<T> a, cplx<T> b) { return {a.re - b.re, a.im - b.im}; }
 template <class T>
 __device__ __forceinline__ cplx<T> operator-(cplx<T> a) { return {-a.re, -a.im}; }
+// complex products with the fused multiply-adds written out (the code is
+// built without implicit contraction, so every kernel rounds alike)
 template <class T>
 __device__ __forceinline__ cplx<T> operator*(cplx<T> a, cplx<T> b) {
-  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+  return {fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
 }
 template <class T>
 __device__ __forceinline__ cplx<T> operator*(T s, cplx<T> a) { return {s * a.re, s * a.im}; }
@@ -40,7 +42,7 @@ __device__ __forceinline__ cplx<T> conj(cplx<T> a) { return {a.re, -a.im}; }
 // conj(a) * b
 template <class T>
 __device__ __forceinline__ cplx<T> cjmul(cplx<T> a, cplx<T> b) {
-  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+  return {fma(a.re, b.re, a.im * b.im), fma(a.re, b.im, -a.im * b.re)};
 }
 // acc += a * b
 template <class T>
@@ -316,9 +318,16 @@ struct Link<float> {
 template <class T>
 __device__ __forceinline__ void rebuild_row2(const cplx<T> (&u)[6], cplx<T> (&c)[3]) {
   const cplx<T> a0 = u[0], a1 = u[1], a2 = u[2], b0 = u[3], b1 = u[4], b2 = u[5];
-  c[0] = conj(a1 * b2 - a2 * b1);
-  c[1] = conj(a2 * b0 - a0 * b2);
-  c[2] = conj(a0 * b1 - a1 * b0);
+  // conj(x y - z w), as y x - (z w) with the second product accumulated by fma
+  auto det2 = [](cplx<T> x, cplx<T> y, cplx<T> z, cplx<T> w) {
+    cplx<T> t = z * w;
+    t = {-t.re, -t.im};
+    cfma(t, x, y);
+    return conj(t);
+  };
+  c[0] = det2(a1, b2, a2, b1);
+  c[1] = det2(a2, b0, a0, b2);
+  c[2] = det2(a0, b1, a1, b0);
 }
 
 // y = M v for the 3x3 matrix with rows (u[0..2], u[3..5], r2[0..2])

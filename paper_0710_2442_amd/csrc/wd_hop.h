@@ -87,12 +87,12 @@ __device__ __forceinline__ void neighbours(const Geom &g, const Coords &c, int i
   nb[7] = i + ((c.x4 == 0) ? (g.L[3] - 1) * g.s4 : -g.s4);
 }
 
-// One hop: acc += M (1 + S gamma_MU) psi_nb, M = the stored hop link.  Time
-// hops (MU = 3) read only the half of the neighbour spinor that their
-// projector keeps (see the spin basis in wd_device.h).
+// One hop: acc += M (1 + S gamma_MU) psi_nb, M = the hop link u (rows 0, 1;
+// row 2 rebuilt).  Time hops (MU = 3) read only the half of the neighbour
+// spinor that their projector keeps (see the spin basis in wd_device.h).
 template <int P, int MU, int S>
-__device__ __forceinline__ void hop_term(cplx<RealOf<P>> (&acc)[12], const char *in, int nb,
-                                         const char *links, int d, size_t i, RealOf<P> sign) {
+__device__ __forceinline__ void hop_term_u(cplx<RealOf<P>> (&acc)[12], const char *in, int nb,
+                                           const cplx<RealOf<P>> (&u)[6], RealOf<P> sign) {
   using T = RealOf<P>;
   cplx<T> h[6];
   if constexpr (MU == 3) {
@@ -105,8 +105,6 @@ __device__ __forceinline__ void hop_term(cplx<RealOf<P>> (&acc)[12], const char 
     Spinor<P>::load(in, nb, psi);
     project<MU, S>(psi, h);
   }
-  cplx<T> u[6];
-  Link<T>::load(links, d, i, u);
   cplx<T> r2[3];
   rebuild_row2(u, r2);
   cplx<T> g[6];
@@ -123,6 +121,36 @@ __device__ __forceinline__ void hop_term(cplx<RealOf<P>> (&acc)[12], const char 
     g[3] = y[0]; g[4] = y[1]; g[5] = y[2];
   }
   reconstruct_add<MU, S>(acc, g);
+}
+
+// The same hop with the link loaded from the hop-link array (direction d).
+template <int P, int MU, int S>
+__device__ __forceinline__ void hop_term(cplx<RealOf<P>> (&acc)[12], const char *in, int nb,
+                                         const char *links, int d, size_t i, RealOf<P> sign) {
+  cplx<RealOf<P>> u[6];
+  Link<RealOf<P>>::load(links, d, i, u);
+  hop_term_u<P, MU, S>(acc, in, nb, u, sign);
+}
+
+// The 8 hops of site i with its links already in registers: u[d] for hop
+// direction d (x1+, x2+, x3+, x4+, x1-, x2-, x3-, x4-).
+template <int P, bool DAG>
+__device__ __forceinline__ void hop_all_u(const char *in, const int (&nb)[8], const cplx<RealOf<P>> (&u)[8][6],
+                                          RealOf<P> sf, RealOf<P> sb, cplx<RealOf<P>> (&acc)[12]) {
+  using T = RealOf<P>;
+  const T one = (T)1;
+  constexpr int F = DAG ? -1 : 1;
+  constexpr int B = -F;
+#pragma unroll
+  for (int c2 = 0; c2 < 12; ++c2) acc[c2] = {(T)0, (T)0};
+  hop_term_u<P, 0, F>(acc, in, nb[0], u[0], one);
+  hop_term_u<P, 1, F>(acc, in, nb[1], u[1], one);
+  hop_term_u<P, 2, F>(acc, in, nb[2], u[2], one);
+  hop_term_u<P, 3, F>(acc, in, nb[3], u[3], sf);
+  hop_term_u<P, 0, B>(acc, in, nb[4], u[4], one);
+  hop_term_u<P, 1, B>(acc, in, nb[5], u[5], one);
+  hop_term_u<P, 2, B>(acc, in, nb[6], u[6], one);
+  hop_term_u<P, 3, B>(acc, in, nb[7], u[7], sb);
 }
 
 template <int P, bool DAG>

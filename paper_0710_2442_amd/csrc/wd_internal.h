@@ -74,7 +74,8 @@ struct wd_gauge {
   int hop_groups[4];       // per precision: XCD region groups (0 = linear order)
   int hop_occ[4];          // per precision: register-budget variant (0 or 4)
   int hop_ntst[4];         // per precision: 1 streaming output stores, 0 cached
-  int mrhs_groups[4];      // per precision: XCD region groups of the multi-RHS hop
+  int mrhs_groups[4];      // per precision: block -> tile order of the multi-RHS hop
+  int mrhs_block[4];       // per precision: sites per block of the FP32/16-bit multi-RHS hop
   int hop_lds[4];          // per precision: dynamic LDS bytes per block (caps blocks per CU)
   double *scratch_red;     // reduction partials / scalars for the BLAS entry points
   unsigned *scratch_cnt;

@@ -151,7 +151,7 @@ def test_mrhs_equals_single_rhs_bitwise(prec, nrhs):
     hb = wd.wd_field_bytes(dims, prec, 1, wd.WD_EVEN)
     src = torch.cat([to_field(g, psis[r], prec, wd.WD_ODD) for r in range(nrhs)])
     out = wd.wd_new_field(dims, prec, nrhs, wd.WD_EVEN)
-    gr, us = wd.wd_tune_dslash_mrhs(g, prec, nrhs)  # any region count must give the same bits
+    bs, gr, us = wd.wd_tune_dslash_mrhs(g, prec, nrhs)  # any variant must give the same bits
     wd.wd_dslash_mrhs(g, src, out, 0.7, wd.WD_EVEN, prec, nrhs)
     for r in range(nrhs):
         one = wd.wd_new_field(dims, prec, 1, wd.WD_EVEN)
