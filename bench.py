@@ -163,8 +163,8 @@ def mrhs_leg(wd, torch, syn):
     X = wd.wd_new_field(dims, "f64", 12)
     out = {}
     for prec in ("f32", "f64"):
-        tb, tg, tus = wd.wd_tune_dslash_mrhs(g, prec, 12)
-        log(f"tuned mrhs hop {prec}: block {tb}, groups {tg} ({tus:.1f} us)")
+        tb, tg, tr, tus = wd.wd_tune_dslash_mrhs(g, prec, 12)
+        log(f"tuned mrhs hop {prec}: block {tb}, groups {tg}, rhs per lane {tr} ({tus:.1f} us)")
     for prec in ("f32", "f64"):
         wd.wd_tune_dslash(g, prec)
 

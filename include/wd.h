@@ -260,8 +260,9 @@ wd_status wd_ptc_train_step(wd_ptc *n, const void *r, const void *e, int B,
 /* Autotune the single-RHS hop of precision prec on this handle's lattice:
  * block size (64..512 threads), the block -> tile order (groups: 0 = linear;
  * G > 0 = G regions of each time slice, dealt round-robin over the XCDs;
- * -X = whole time slices dealt round-robin over X dispatch lanes, so with
- * X = 8 every slice runs inside one XCD's L2), the register budget (occ 0: compiler's
+ * -X = X contiguous ranges of time slices, one per dispatch lane, each swept
+ * in time order, so with X = 8 every XCD's L2 sees whole neighbourhoods),
+ * the register budget (occ 0: compiler's
  * choice; occ 4: at least 4 waves per SIMD), the output store policy
  * (WD_TUNE_CACHED_STORE set in occ: cached stores) and a cap on resident
  * blocks per CU (dynamic LDS in KiB << WD_TUNE_LDS_SHIFT).  Every candidate's output is
@@ -277,14 +278,16 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path,
                          int force, int *block, int *groups, int *occ,
                          double *us);
 
-/* Tune the multi-RHS hop for nrhs right-hand sides: its block size (FP32,
- * FP16, BF16: 64, 128 or 256 sites, one lane per site looping over the RHS;
- * FP64: fixed 16-site x RHS tiles) and block -> tile order (groups as above).
- * Candidates are checked byte for byte against the linear variant, then
- * timed; the fastest is kept in the handle.  Outputs may be NULL.
+/* Tune the multi-RHS hop for nrhs right-hand sides.  FP32, FP16, BF16: one
+ * lane per site holds its 8 links in registers and loops over rpl
+ * right-hand sides (chunks of rpl RHS are dispatched one after the other);
+ * tuned: block size (64, 128, 256 sites), rpl (1..16) and block -> tile
+ * order (groups as above).  FP64: fixed 16-site x RHS tiles; tuned: tile
+ * order.  Candidates are checked byte for byte against the linear variant,
+ * then timed; the fastest is kept in the handle.  Outputs may be NULL.
  * Synchronous. */
 wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, int *block,
-                              int *groups, double *us);
+                              int *groups, int *rpl, double *us);
 
 /* Bit of the occ value: the hop writes its output with ordinary (cached)
  * stores instead of streaming stores, so that a following kernel can read a

@@ -91,7 +91,7 @@ _decl("wd_solve_batch", C.c_int, [C.POINTER(_vp), C.c_int, C.POINTER(_vp), C.POI
 _decl("wd_tune_dslash", C.c_int, [_vp, C.c_int, C.c_char_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                    C.POINTER(C.c_int), C.POINTER(C.c_double)])
 _decl("wd_tune_dslash_mrhs", C.c_int, [_vp, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
-                                       C.POINTER(C.c_double)])
+                                       C.POINTER(C.c_int), C.POINTER(C.c_double)])
 _decl("wd_set_dslash_variant", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int])
 _decl("wd_get_dslash_variant", C.c_int, [_vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)])
 _decl("wd_ptc_create", C.c_int, [_vp, C.POINTER(C.c_float), C.c_int, C.POINTER(_vp)])
@@ -421,9 +421,10 @@ def wd_solve_batch(gauges, bs, xs, kappas, tol, params):
 
 
 def wd_tune_dslash_mrhs(g, prec, nrhs):
-    """Tune the multi-RHS hop (block size, tile order); returns (block, groups, microseconds per launch)."""
+    """Tune the multi-RHS hop (block size, tile order, RHS per lane);
+    returns (block, groups, rpl, microseconds per launch)."""
     g.sync_stream()
-    bs, gr, us = C.c_int(), C.c_int(), C.c_double()
-    _check(lib.wd_tune_dslash_mrhs(g.handle, _prec(prec), int(nrhs), C.byref(bs), C.byref(gr), C.byref(us)),
-           "wd_tune_dslash_mrhs")
-    return bs.value, gr.value, us.value
+    bs, gr, rp, us = C.c_int(), C.c_int(), C.c_int(), C.c_double()
+    _check(lib.wd_tune_dslash_mrhs(g.handle, _prec(prec), int(nrhs), C.byref(bs), C.byref(gr), C.byref(rp),
+                                   C.byref(us)), "wd_tune_dslash_mrhs")
+    return bs.value, gr.value, rp.value, us.value

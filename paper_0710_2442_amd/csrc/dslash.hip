@@ -57,6 +57,7 @@ struct KMrhs {
   size_t rhs_stride;   // bytes between right-hand sides (all operands)
   int norm_stride;     // doubles between consecutive RHS norm slots
   int skip_stride;     // ints between consecutive RHS skip flags
+  int rpl;             // right-hand sides per lane (FP32-arithmetic kernel)
 };
 
 template <int P, bool DAG, int EPI, bool NORM>
@@ -146,18 +147,21 @@ __global__ __launch_bounds__(256) void k_dslash_mrhs(KMrhs m) {
 
 // Multi-RHS hop for FP32 arithmetic (FP32, FP16 and BF16 spinors): one lane
 // per output site loads its 8 hop links once into registers and then walks
-// the right-hand sides r0 .. r1-1 of its block's chunk, so every link byte is
-// read once per chunk (up to 16 RHS) and every spinor load of a wave is one
-// contiguous run.  Per-RHS skip flags, epilogue and FP64 norms as above.
-constexpr int MR_CHUNK = 16;
+// the m.rpl right-hand sides of its block's chunk (grid.y = chunk), so a link
+// is read once per chunk and every spinor load of a wave is one contiguous
+// run.  Chunks are dispatched one after the other (grid.x fastest), so the
+// blocks resident at one time share a chunk and their neighbour spinors stay
+// in L2; rpl trades that locality against link reuse and is tuned.  Per-RHS
+// skip flags, epilogue and FP64 norms as in the kernel above.
+constexpr int MR_CHUNK = 16;  // largest rpl
 
 template <int P, bool DAG, int EPI, bool NORM>
 __global__ __launch_bounds__(256) void k_dslash_mrhs_reg(KMrhs m) {
   using T = RealOf<P>;
   const KDslash &k = m.k;
   const int i = tile_of(k) * (int)blockDim.x + (int)threadIdx.x;
-  const int r0 = blockIdx.y * MR_CHUNK;
-  const int r1 = min(m.nrhs, r0 + MR_CHUNK);
+  const int r0 = blockIdx.y * m.rpl;
+  const int r1 = min(m.nrhs, r0 + m.rpl);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __shared__ double sred[MR_CHUNK][4];
   const bool site = i < k.g.vh;
@@ -221,27 +225,35 @@ __global__ __launch_bounds__(256) void k_dslash_mrhs_reg(KMrhs m) {
     }
   }
   if constexpr (NORM) {
+    // per-RHS partials at partials[r * gridDim.x + block]; the last block of
+    // the chunk sums each RHS's partials in block order
     __syncthreads();
-    double v[MR_CHUNK], tot[MR_CHUNK];
+    const unsigned nblk = gridDim.x;
     const int nw = (int)blockDim.x >> 6;
-#pragma unroll
-    for (int j = 0; j < MR_CHUNK; ++j) {
-      double s = 0.0;
-      if (threadIdx.x == 0 && j < r1 - r0)
-        for (int q = 0; q < nw; ++q) s += sred[j][q];
-      v[j] = s;
+    if (threadIdx.x == 0) {
+      for (int r = r0; r < r1; ++r) {
+        double s = 0.0;
+        for (int q = 0; q < nw; ++q) s += sred[r - r0][q];
+        __hip_atomic_store(&k.partials[(size_t)r * nblk + blockIdx.x], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      __threadfence();
     }
-    if (grid_sum_last<MR_CHUNK>(v, k.partials + (size_t)r0 * gridDim.x, k.counter + blockIdx.y, gridDim.x,
-                                blockIdx.x, tot)) {
-#pragma unroll
-      for (int j = 0; j < MR_CHUNK; ++j) {
-        const int r = r0 + j;
-        if (r < r1 && !(k.skip && k.skip[(size_t)r * m.skip_stride])) {
-          double *dst = k.norm_out + (size_t)r * m.norm_stride;
-          *dst = k.norm_accumulate ? (*dst + tot[j]) : tot[j];
-        }
+    __shared__ int is_last;
+    if (threadIdx.x == 0) is_last = (atomicAdd(k.counter + blockIdx.y, 1u) == nblk - 1);
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    for (int r = r0; r < r1; ++r) {
+      double v[1] = {0.0};
+      for (unsigned b = threadIdx.x; b < nblk; b += blockDim.x)
+        v[0] += __hip_atomic_load(&k.partials[(size_t)r * nblk + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      block_sum_n<1>(v);
+      if (threadIdx.x == 0 && !(k.skip && k.skip[(size_t)r * m.skip_stride])) {
+        double *dst = k.norm_out + (size_t)r * m.norm_stride;
+        *dst = k.norm_accumulate ? (*dst + v[0]) : v[0];
       }
     }
+    if (threadIdx.x == 0) __hip_atomic_store(k.counter + blockIdx.y, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -399,7 +411,8 @@ wd_status launch_dslash_mrhs_ex(const wd_gauge *g, wd_prec prec, const MrhsArgs 
     grid = dim3((unsigned)mrhs_grid_blocks(g), (unsigned)((a.nrhs + 15) / 16));
     block = dim3((unsigned)(16 * per_block));
   } else {
-    grid = dim3((unsigned)((g->geom.vpad + bs - 1) / bs), (unsigned)((a.nrhs + MR_CHUNK - 1) / MR_CHUNK));
+    m.rpl = std::max(1, std::min(MR_CHUNK, g->mrhs_rpl[(int)prec]));
+    grid = dim3((unsigned)((g->geom.vpad + bs - 1) / bs), (unsigned)((a.nrhs + m.rpl - 1) / m.rpl));
     block = dim3((unsigned)bs);
   }
   switch (prec) {

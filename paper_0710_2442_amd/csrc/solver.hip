@@ -47,8 +47,7 @@ static wd_status ws_reserve(wd_gauge *g, size_t vec_bytes, int nsys) {
   // largest grid.x of any reducing launch: single-RHS hop, level-1, multi-RHS hop
   const size_t nblk = std::max<size_t>(std::max<unsigned>(dslash_grid_blocks(g), BLAS_MAX_BLOCKS),
                                        mrhs_grid_blocks(g));
-  // (+16: the multi-RHS hop reduces RHS in chunks of 16 slots)
-  const size_t partial_need = nblk * 2 * ((size_t)nsys + 16);
+  const size_t partial_need = nblk * 2 * (size_t)nsys;
   if (w->base && w->bytes >= vec_bytes && w->nsys_cap >= nsys && w->partial_cap >= partial_need) return WD_OK;
   if (w->base) {
     WD_HIP(hipFree(w->base));

@@ -153,7 +153,7 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
       if ((rc = hip_check(hipMemcpyAsync(h_ref.data(), ref, hb, hipMemcpyDeviceToHost, st), "copy")) != WD_OK) break;
       if ((rc = hip_check(hipStreamSynchronize(st), "sync")) != WD_OK) break;
       const int blocks[] = {64, 128, 256, 512};
-      const int grps[] = {0, 2, 4, 8, 16, -8};
+      const int grps[] = {0, 2, 4, 8, 16, -8, -16};
       best_us = 1e30;
       int nbest_b = 256, nbest_g = 0, nbest_o = 0, nbest_n = 1, nbest_l = 0;
       size_t lds_max = 65536;
@@ -231,10 +231,10 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
 }
 
 // Multi-RHS hop: tune the block size (FP32 arithmetic: 64..256 sites; FP64:
-// fixed 16-site tiles) and the block -> tile order for nrhs right-hand
-// sides; candidates checked byte for byte against the linear 128-site (FP64:
-// 16-site) variant.
-wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, int *out_block, int *out_groups,
+// fixed 16-site tiles), the right-hand sides per lane (FP32 arithmetic) and
+// the block -> tile order for nrhs right-hand sides; candidates checked byte
+// for byte against the linear 128-site, 4-RHS (FP64: 16-site) variant.
+wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, int *out_block, int *out_groups, int *out_rpl,
                               double *out_us) {
   if (!g) return set_error(WD_ERR_ARG, "gauge handle is NULL");
   if ((int)prec < 0 || (int)prec > 3) return set_error(WD_ERR_PREC, "prec = %d", (int)prec);
@@ -247,9 +247,9 @@ wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, int *out_bloc
   hipEvent_t e0 = nullptr, e1 = nullptr;
   wd_status rc = WD_OK;
   std::vector<unsigned char> h_ref(hb), h_cand(hb);
-  const int save = g->mrhs_groups[prec], save_b = g->mrhs_block[prec];
+  const int save = g->mrhs_groups[prec], save_b = g->mrhs_block[prec], save_r = g->mrhs_rpl[prec];
   const int ref_b = (prec == WD_F64) ? 16 : 128;
-  int best_g = 0, best_b = ref_b;
+  int best_g = 0, best_b = ref_b, best_r = 4;
   double best_us = 1e30;
   do {
     if ((rc = hip_check(hipMalloc(&in, hb), "tune alloc")) != WD_OK) break;
@@ -271,17 +271,26 @@ wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, int *out_bloc
     if ((rc = hip_check(hipEventCreate(&e1), "event")) != WD_OK) break;
     g->mrhs_groups[prec] = 0;
     g->mrhs_block[prec] = ref_b;
+    g->mrhs_rpl[prec] = 4;
     if ((rc = launch_dslash_mrhs(g, prec, in, ref, 1.0, WD_EVEN, 0, nrhs, st)) != WD_OK) break;
     if ((rc = hip_check(hipMemcpyAsync(h_ref.data(), ref, hb, hipMemcpyDeviceToHost, st), "copy")) != WD_OK) break;
     if ((rc = hip_check(hipStreamSynchronize(st), "sync")) != WD_OK) break;
-    std::vector<int> blocks;
-    if (prec == WD_F64) blocks = {16};
-    else blocks = {64, 128, 256};
+    std::vector<int> blocks, rpls;
+    if (prec == WD_F64) {
+      blocks = {16};
+      rpls = {4};
+    } else {
+      blocks = {64, 128, 256};
+      for (int r : {1, 2, 3, 4, 6, 8, 12, 16})
+        if (r <= nrhs) rpls.push_back(r);
+    }
+    for (int rp : rpls)
     for (int bs : blocks)
-    for (int gr : {0, 2, 4, 8, 16, -8}) {
+    for (int gr : {0, 2, 4, 8, -8, -16}) {
       if (!dslash_variant_ok(G, bs, gr)) continue;
       g->mrhs_groups[prec] = gr;
       g->mrhs_block[prec] = bs;
+      g->mrhs_rpl[prec] = rp;
       if ((rc = hip_check(hipMemsetAsync(cand, 0xff, hb, st), "memset")) != WD_OK) break;
       if ((rc = launch_dslash_mrhs(g, prec, in, cand, 1.0, WD_EVEN, 0, nrhs, st)) != WD_OK) break;
       if ((rc = hip_check(hipMemcpyAsync(h_cand.data(), cand, hb, hipMemcpyDeviceToHost, st), "copy")) != WD_OK)
@@ -298,12 +307,14 @@ wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, int *out_bloc
       (void)hipEventElapsedTime(&ms, e0, e1);
       const double us = 1e3 * ms / reps;
       if (getenv("WD_TUNE_VERBOSE"))
-        fprintf(stderr, "tune mrhs p%d nrhs %d: block %d groups %d: %.2f us\n", (int)prec, nrhs, bs, gr, us);
-      if (us < best_us) { best_us = us; best_g = gr; best_b = bs; }
+        fprintf(stderr, "tune mrhs p%d nrhs %d: block %d groups %d rpl %d: %.2f us\n", (int)prec, nrhs, bs, gr, rp,
+                us);
+      if (us < best_us) { best_us = us; best_g = gr; best_b = bs; best_r = rp; }
     }
   } while (0);
   g->mrhs_groups[prec] = (rc == WD_OK) ? best_g : save;
   g->mrhs_block[prec] = (rc == WD_OK) ? best_b : save_b;
+  g->mrhs_rpl[prec] = (rc == WD_OK) ? best_r : save_r;
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (in) (void)hipFree(in);
@@ -311,6 +322,7 @@ wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, int *out_bloc
   if (cand) (void)hipFree(cand);
   if (rc != WD_OK) return rc;
   if (out_block) *out_block = best_b;
+  if (out_rpl) *out_rpl = best_r;
   if (out_groups) *out_groups = best_g;
   if (out_us) *out_us = best_us;
   return WD_OK;

@@ -35,11 +35,11 @@ struct KDslash {
 // blocks of one region walk its tiles slice by slice in time order, so a
 // region's neighbour spinors (x1..x3 inside the slice, x4 one slice away)
 // are fetched into one L2 and re-read from there.  Requires
-// tiles_per_slice % G == 0.  groups = -X: whole time slices are dealt
-// round-robin to X lanes (block b to lane b % X); with X = 8 one XCD computes
-// all tiles of a slice, so every spatial neighbour is re-read from its L2,
-// while the time hops, which read the two disjoint halves of a neighbour
-// slice's spinors, need no reuse at all.  Requires L4 % X == 0.  Both need
+// tiles_per_slice % G == 0.  groups = -X: the time slices are cut into X
+// contiguous ranges and block b walks range b % X in time order; with X = 8
+// each XCD sweeps its own block of slices, so the spatial neighbours (same
+// slice) and the time neighbours (the slices before and after) of a site are
+// all re-read from that XCD's L2.  Requires L4 % X == 0.  Both need
 // gridDim.x == tiles_per_slice * L4.
 __device__ __forceinline__ int tile_of(const KDslash &k, int b) {
   if (k.groups == 0) return b;
@@ -47,7 +47,8 @@ __device__ __forceinline__ int tile_of(const KDslash &k, int b) {
   if (k.groups < 0) {
     const int X = -k.groups;
     const int x = b % X, q = b / X;
-    return ((q / T) * X + x) * T + (q % T);
+    const int per = k.g.L[3] / X;  // slices per range
+    return (x * per + q / T) * T + (q % T);
   }
   const int G = k.groups;
   const int per = T / G;

@@ -76,6 +76,7 @@ struct wd_gauge {
   int hop_ntst[4];         // per precision: 1 streaming output stores, 0 cached
   int mrhs_groups[4];      // per precision: block -> tile order of the multi-RHS hop
   int mrhs_block[4];       // per precision: sites per block of the FP32/16-bit multi-RHS hop
+  int mrhs_rpl[4];         // per precision: right-hand sides per lane of that kernel
   int hop_lds[4];          // per precision: dynamic LDS bytes per block (caps blocks per CU)
   double *scratch_red;     // reduction partials / scalars for the BLAS entry points
   unsigned *scratch_cnt;

@@ -151,7 +151,7 @@ def test_mrhs_equals_single_rhs_bitwise(prec, nrhs):
     hb = wd.wd_field_bytes(dims, prec, 1, wd.WD_EVEN)
     src = torch.cat([to_field(g, psis[r], prec, wd.WD_ODD) for r in range(nrhs)])
     out = wd.wd_new_field(dims, prec, nrhs, wd.WD_EVEN)
-    bs, gr, us = wd.wd_tune_dslash_mrhs(g, prec, nrhs)  # any variant must give the same bits
+    bs, gr, rp, us = wd.wd_tune_dslash_mrhs(g, prec, nrhs)  # any variant must give the same bits
     wd.wd_dslash_mrhs(g, src, out, 0.7, wd.WD_EVEN, prec, nrhs)
     for r in range(nrhs):
         one = wd.wd_new_field(dims, prec, 1, wd.WD_EVEN)
@@ -261,7 +261,7 @@ def test_every_hop_variant_is_bitwise_identical(dims, prec):
     wd.wd_set_dslash_variant(g, prec, 256, 0, 0)
     wd.wd_dslash_ex(g, src, ref, 0.9, wd.WD_EVEN, prec)
     n = 0
-    for bs, groups, occ in [(b, gr, o) for b in (64, 128, 256, 512) for gr in (0, 2, 4, 8, 16, -2, -4, -8) for o in (0, 4, 256)]:
+    for bs, groups, occ in [(b, gr, o) for b in (64, 128, 256, 512) for gr in (0, 2, 4, 8, 16, -2, -4, -8, -16) for o in (0, 4, 256)]:
             try:
                 wd.wd_set_dslash_variant(g, prec, bs, groups, occ)
             except wd.WdError:
