@@ -42,7 +42,8 @@ BYTES_PER_SITE = {"f64": 144 * 8, "f32": 144 * 4}
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "dslash_hop_32x32x32x64_traffic.txt")
 # pre-tuned hop variants for MI355X (written by wd_tune_dslash; used without re-timing)
 TUNE_TABLE = os.path.join(ROOT, "paper_0710_2442_amd", "tuned", "mi355x_hop.jsonl")
-KERNEL_SOURCES = ["paper_0710_2442_amd/csrc/dslash.hip", "paper_0710_2442_amd/csrc/wd_device.h"]
+KERNEL_SOURCES = ["paper_0710_2442_amd/csrc/dslash.hip", "paper_0710_2442_amd/csrc/wd_hop.h",
+                  "paper_0710_2442_amd/csrc/wd_device.h", "paper_0710_2442_amd/build.py"]
 
 
 def log(*a):
