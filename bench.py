@@ -38,6 +38,7 @@ sys.path.insert(0, ROOT)
 
 DIMS = (32, 32, 32, 64)
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_FLOPS = 78.6e12  # MI355X dense FP64 vector
 BYTES_PER_SITE = {"f64": 144 * 8, "f32": 144 * 4}
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "dslash_hop_32x32x32x64_traffic.txt")
 # pre-tuned hop variants for MI355X (written by wd_tune_dslash; used without re-timing)
@@ -302,6 +303,62 @@ def learned_leg(wd, torch, syn, steps):
     return out
 
 
+def kernels_leg(wd, torch, syn, U, psi):
+    """Level-1 kernels (Sec. 4's caxpy), full D_W and the network at 32^3x64."""
+    import numpy as np
+
+    from paper_0710_2442_amd import learn
+    from paper_0710_2442_amd.fields import canon_to_field
+
+    V = int(np.prod(DIMS))
+    out = {}
+    g = wd.Gauge(U, DIMS, -1, "f64")
+    x = canon_to_field(g, psi, "f64")
+    y = x.clone()
+    z = wd.wd_new_field(DIMS, "f64")
+
+    def ev_time(fn, n=20):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / n
+
+    # caxpy y += c x on full FP64 fields: 3 x 192 B and 12 x 8 flop per site
+    t = ev_time(lambda: wd.wd_caxpy(g, 1e-3, x, y, 2, "f64"))
+    gbs = V * 576 / t / 1e9
+    out["caxpy_f64"] = {"us": round(t * 1e6, 2), "GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+                        "eps_fp": round(V * 96 / t / FP64_PEAK_FLOPS, 5),
+                        "eps_fp_hbm_bound": round(96 / 576 * HBM_PEAK_GBS * 1e9 / FP64_PEAK_FLOPS, 5)}
+    # |x|^2 with the result read back (one synchronisation per call)
+    for _ in range(3):
+        wd.wd_norm2(g, x, 2, "f64")
+    t0 = time.perf_counter()
+    for _ in range(20):
+        wd.wd_norm2(g, x, 2, "f64")
+    t = (time.perf_counter() - t0) / 20
+    out["norm2_f64_with_readback"] = {"us": round(t * 1e6, 2), "GBps": round(V * 192 / t / 1e9, 1)}
+    # full D_W = 1 - kappa H: two parity launches with the xpay epilogue
+    t = ev_time(lambda: wd.wd_dslash(g, x, z, 0.124, DIMS, wd.WD_FULL))
+    out["dirac_full_f64"] = {"us": round(t * 1e6, 2), "GBps": round(V * 1344 / t / 1e9, 1),
+                             "bytes_per_site": 1344}
+    # the PTC network (FP32 fields, BF16 activations), one application on the full lattice
+    net = wd.Ptc(g, learn.init_weights(1), "bf16")
+    r32 = wd.wd_new_field(DIMS, "f32")
+    wd.wd_convert(g, x, "f64", r32, "f32", 2, 1.0)
+    o32 = wd.wd_new_field(DIMS, "f32")
+    t = ev_time(lambda: wd.wd_ptc_apply(net, r32, o32))
+    out["ptc_apply_bf16"] = {"us": round(t * 1e6, 2), "sites": V}
+    net.close()
+    g.close()
+    return out
+
+
 def cpu_leg(syn, U, psi):
     """Oracle single-parity hop on the full 32^3x64 workload (one application)."""
     import numpy as np
@@ -332,6 +389,7 @@ def main():
     ap.add_argument("--no-mrhs", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-learn", action="store_true")
+    ap.add_argument("--no-kernels", action="store_true")
     ap.add_argument("--learn-steps", type=int, default=400)
     ap.add_argument("--no-tune", action="store_true", help="use the default hop variant")
     ap.add_argument("--tune-table", default=TUNE_TABLE, help="JSON-lines tuning table (read, appended)")
@@ -442,6 +500,8 @@ def main():
         line["batch_8_lattices_689408_sites"] = batch_leg(wd, torch, syn)
     if not args.no_learn:
         line["learned_ptc_fgcr_32x32x32x64"] = learned_leg(wd, torch, syn, args.learn_steps)
+    if not args.no_kernels:
+        line["kernels_32x32x32x64"] = kernels_leg(wd, torch, syn, U, psi)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_leg(syn, U, psi)
     print(json.dumps(line), flush=True)

@@ -1,8 +1,9 @@
 """Training driver of the learned preconditioner (orchestration only).
 
-Pairs (r, e) come from the solver itself: for a Gaussian source b the
-solution x* is computed with FP64 CG (to 1e-8, ample for a training
-target); CG stopped after k iterations (k in `ks`) gives x_k,
+Pairs (r, e) come from the solver itself: for Gaussian sources b the
+solutions x* are computed together by the multi-RHS defect-correction solver
+(`nsrc` sources per call, to 1e-8: ample for a training target); FP64 CG
+stopped after k iterations (k in `ks`) gives x_k,
 e_k = x* - x_k and r_k = b - D x_k = D e_k.  Each pair is normalised by
 |r_k|.  The default uses k = 0 only (x_0 = 0: r = b, e = x*): residuals of
 later CG iterates are dominated by the low modes, and a network trained on
@@ -27,7 +28,7 @@ from .fields import canon_to_field
 class PairGenerator:
     """Streams normalised (r, e) pairs, FP32 full fields, on one lattice."""
 
-    def __init__(self, g, kappa, seed, ks=(0,), target_tol=1e-8):
+    def __init__(self, g, kappa, seed, ks=(0,), target_tol=1e-8, nsrc=12):
         import torch
 
         self.torch = torch
@@ -36,13 +37,14 @@ class PairGenerator:
         self.rng = np.random.Generator(np.random.PCG64(int(seed)))
         self.ks = tuple(int(k) for k in ks)
         self.target_tol = float(target_tol)
+        self.nsrc = int(nsrc)
         self.dims = g.dims
         self.f64 = L.wd_field_bytes(self.dims, "f64")
         self.f32 = L.wd_field_bytes(self.dims, "f32")
         self.pool_r, self.pool_e = [], []
         self.sources = 0
         self.solve_seconds = 0.0
-        self._xs = L.wd_new_field(self.dims, "f64")
+        self._xs = L.wd_new_field(self.dims, "f64", self.nsrc)
         self._xk = L.wd_new_field(self.dims, "f64")
         self._dx = L.wd_new_field(self.dims, "f64")
 
@@ -51,31 +53,39 @@ class PairGenerator:
         z = self.rng.standard_normal((L4, L3, L2, L1, 4, 3, 2))
         return canon_to_field(self.g, z[..., 0] + 1j * z[..., 1], "f64")
 
+    def _push(self, r, e):
+        """Normalise the pair by |r| and keep it as two FP32 full fields."""
+        nr = np.sqrt(L.wd_norm2(self.g, r, 2, "f64"))
+        r32 = L.wd_new_field(self.dims, "f32")
+        e32 = L.wd_new_field(self.dims, "f32")
+        L.wd_convert(self.g, r, "f64", r32, "f32", 2, 1.0 / nr)
+        L.wd_convert(self.g, e, "f64", e32, "f32", 2, 1.0 / nr)
+        self.pool_r.append(r32)
+        self.pool_e.append(e32)
+
     def _refill(self):
         t = time.perf_counter()
-        fb = self._source()
-        self.sources += 1
-        exact = L.wd_solve_params_default(solver=L.WD_SOLVER_CG)
-        L.wd_solve(self.g, fb, self._xs, self.kappa, self.target_tol, exact)
-        for k in self.ks:
-            if k == 0:  # x_0 = 0: r = b, e = x*
-                L.wd_convert(self.g, fb, "f64", self._xk, "f64", 2, 0.0)
-            else:
+        n = self.nsrc
+        B = self.torch.cat([self._source() for _ in range(n)])
+        self.sources += n
+        prm = L.wd_solve_params_default(solver=L.WD_SOLVER_DEFECT_CG, inner_prec="f32", inner_tol=1e-3)
+        L.wd_solve_mrhs(self.g, B, self._xs, n, self.kappa, self.target_tol, prm)
+        f = self.f64
+        for y in range(n):
+            fb, xs = B[y * f:(y + 1) * f], self._xs[y * f:(y + 1) * f]
+            for k in self.ks:
+                if k == 0:  # x_0 = 0: r = b, e = x*
+                    self._push(fb, xs)
+                    continue
                 L.wd_solve(self.g, fb, self._xk, self.kappa, 1e-14,
                            L.wd_solve_params_default(solver=L.WD_SOLVER_CG, max_iter=k))
-            # r = b - D x_k  ;  e = x* - x_k
-            L.wd_dslash(self.g, self._xk, self._dx, self.kappa, self.dims, L.WD_FULL)
-            r = fb.clone()
-            L.wd_caxpy(self.g, -1.0, self._dx, r, 2, "f64")
-            e = self._xs.clone()
-            L.wd_caxpy(self.g, -1.0, self._xk, e, 2, "f64")
-            nr = np.sqrt(L.wd_norm2(self.g, r, 2, "f64"))
-            r32 = L.wd_new_field(self.dims, "f32")
-            e32 = L.wd_new_field(self.dims, "f32")
-            L.wd_convert(self.g, r, "f64", r32, "f32", 2, 1.0 / nr)
-            L.wd_convert(self.g, e, "f64", e32, "f32", 2, 1.0 / nr)
-            self.pool_r.append(r32)
-            self.pool_e.append(e32)
+                # r = b - D x_k  ;  e = x* - x_k
+                L.wd_dslash(self.g, self._xk, self._dx, self.kappa, self.dims, L.WD_FULL)
+                r = fb.clone()
+                L.wd_caxpy(self.g, -1.0, self._dx, r, 2, "f64")
+                e = xs.clone()
+                L.wd_caxpy(self.g, -1.0, self._xk, e, 2, "f64")
+                self._push(r, e)
         self.torch.cuda.synchronize()
         self.solve_seconds += time.perf_counter() - t
 
