@@ -298,6 +298,8 @@ def learned_leg(wd, torch, syn, steps):
     base = out["fp64_cg"]["seconds"]
     for k in cases:
         out[k[0]]["speedup_vs_fp64_cg"] = round(base / out[k[0]]["seconds"], 3)
+    saved = base - out["defect_fgcr_trained_bf16"]["seconds"]
+    out["training"]["solves_to_amortise_vs_fp64_cg"] = round(hist["seconds"] / saved, 1) if saved > 0 else None
     net.close()
     gt.close()
     return out
@@ -390,7 +392,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-learn", action="store_true")
     ap.add_argument("--no-kernels", action="store_true")
-    ap.add_argument("--learn-steps", type=int, default=400)
+    ap.add_argument("--learn-steps", type=int, default=1250, help="training steps of 8 pairs (1250: 10^4 pairs)")
     ap.add_argument("--no-tune", action="store_true", help="use the default hop variant")
     ap.add_argument("--tune-table", default=TUNE_TABLE, help="JSON-lines tuning table (read, appended)")
     ap.add_argument("--retune", action="store_true", help="time all variants even if the table has an entry")

@@ -164,6 +164,24 @@ wd_status wd_norm2(const wd_gauge *g, const void *x, int nhalf, wd_prec prec,
 wd_status wd_convert(const wd_gauge *g, const void *in, wd_prec pin, void *out,
                      wd_prec pout, int nhalf, double scale);
 
+/* Fill a field (parity WD_EVEN / WD_ODD: one half field; WD_FULL: both) with
+ * stored components whose real and imaginary parts are i.i.d. N(0,1),
+ * drawn on the device by the counter-based generator Philox4x64-10 (Salmon
+ * et al., SC 2011; multipliers 0xD2E7470EE14C6C93, 0xCA5A826395121157, key
+ * increments 0x9E3779B97F4A7C15, 0xBB67AE8584CAA73B).  For the site of
+ * parity q and checkerboard index i, and j = 0..5, the block with counter
+ * ((q V_h + i) 6 + j, stream, 0, 0) and key (seed, 0) gives four words
+ * x0..x3; stored component 2j = B(x0, x1) and 2j+1 = B(x2, x3), with the
+ * Box-Muller map B(a, b) = sqrt(-2 ln u) (cos 2 pi v + i sin 2 pi v),
+ * u = ((a >> 11) + 1) 2^-53, v = (b >> 11) 2^-53.  The values are those of
+ * the stored (storage-basis) components; since the basis map is orthogonal
+ * the chiral-basis field is i.i.d. Gaussian too.  prec: WD_F64 or WD_F32
+ * (rounded from double).  Padding slots get zeros.  Asynchronous on the
+ * handle's stream. */
+wd_status wd_gaussian_field(const wd_gauge *g, void *field, int parity,
+                            wd_prec prec, unsigned long long seed,
+                            unsigned long long stream);
+
 /* --------------------------------------------------------------- solve -- */
 
 /* WD_SOLVER_CG        : FP64 even-odd CGLS (CG on the normal equations).

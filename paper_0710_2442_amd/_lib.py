@@ -101,6 +101,7 @@ _decl("wd_ptc_get_weights", C.c_int, [_vp, C.POINTER(C.c_float)])
 _decl("wd_ptc_apply", C.c_int, [_vp, _vp, _vp])
 _decl("wd_ptc_loss_grad", C.c_int, [_vp, _vp, _vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_float)])
 _decl("wd_ptc_train_step", C.c_int, [_vp, _vp, _vp, C.c_int, C.c_double, C.POINTER(C.c_double)])
+_decl("wd_gaussian_field", C.c_int, [_vp, _vp, C.c_int, C.c_int, C.c_ulonglong, C.c_ulonglong])
 _decl("wd_status_string", C.c_char_p, [C.c_int])
 _decl("wd_last_error", C.c_char_p, [])
 
@@ -219,6 +220,13 @@ def wd_spinor_pack(g, canon, field, parity=WD_FULL, prec=None):
     g.sync_stream()
     p = g.prec if prec is None else _prec(prec)
     _check(lib.wd_spinor_pack(g.handle, _ptr(canon), _ptr(field), int(parity), p), "wd_spinor_pack")
+
+
+def wd_gaussian_field(g, field, parity, prec, seed, stream):
+    """Fill a field with i.i.d. N(0,1) stored components (Philox4x64-10 + Box-Muller, on the device)."""
+    g.sync_stream()
+    _check(lib.wd_gaussian_field(g.handle, _ptr(field), int(parity), _prec(prec), int(seed) & (2**64 - 1),
+                                 int(stream) & (2**64 - 1)), "wd_gaussian_field")
 
 
 def wd_spinor_unpack(g, field, canon, parity=WD_FULL, prec=None):

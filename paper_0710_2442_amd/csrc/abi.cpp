@@ -181,6 +181,16 @@ wd_status wd_spinor_unpack(const wd_gauge *g, const void *field, void *canon, in
   return launch_unpack_spinor(g, field, canon, parity, prec, g->stream);
 }
 
+wd_status wd_gaussian_field(const wd_gauge *g, void *field, int parity, wd_prec prec, unsigned long long seed,
+                            unsigned long long stream) {
+  WD_TRY(check_handle(g));
+  if (!field) return set_error(WD_ERR_ARG, "gaussian field: NULL pointer");
+  if (parity < 0 || parity > 2) return set_error(WD_ERR_ARG, "gaussian field: parity = %d", parity);
+  if (prec != WD_F64 && prec != WD_F32) return set_error(WD_ERR_PREC, "gaussian field: prec = %d", (int)prec);
+  WD_TRY(set_device(g));
+  return launch_gaussian(g, field, parity, prec, seed, stream, g->stream);
+}
+
 static wd_status dslash_common(const wd_gauge *U, const void *in, void *out, double kappa, int parity, wd_prec prec,
                                int flags) {
   WD_TRY(check_handle(U));

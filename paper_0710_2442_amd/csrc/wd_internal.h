@@ -162,6 +162,9 @@ wd_status launch_dslash_mrhs(const wd_gauge *g, wd_prec prec, const void *in, vo
                              int parity, int dagger, int nrhs, hipStream_t st);
 
 // pack / unpack between canonical complex128 (device) and a field
+// i.i.d. N(0,1) stored components from Philox4x64-10 (random.hip)
+wd_status launch_gaussian(const wd_gauge *g, void *field, int parity, wd_prec prec, uint64_t seed, uint64_t stream,
+                          hipStream_t st);
 wd_status launch_pack_spinor(const wd_gauge *g, const void *canon, void *field, int parity,
                              wd_prec prec, hipStream_t st);
 wd_status launch_unpack_spinor(const wd_gauge *g, const void *field, void *canon, int parity,

@@ -10,7 +10,8 @@ later CG iterates are dominated by the low modes, and a network trained on
 them raised FGCR's iteration count (8^4, kappa 0.124: 88 with N = 1, 215-731
 with such pairs, 35 with k = 0 pairs).  Every step of this runs in the
 library's kernels (solves, hop, caxpy, conversion); this module only
-sequences the calls and draws the seeded sources.
+sequences the calls; the Gaussian sources are drawn on the device by the
+library's counter-based generator (seed, source index).
 
 Training: Adam on L = mean |N(r) - e|^2 over mini-batches streamed from the
 generator (pairs are not stored beyond a small pool).
@@ -22,7 +23,6 @@ import time
 import numpy as np
 
 from . import _lib as L
-from .fields import canon_to_field
 
 
 class PairGenerator:
@@ -34,6 +34,7 @@ class PairGenerator:
         self.torch = torch
         self.g = g
         self.kappa = float(kappa)
+        self.seed = int(seed)
         self.rng = np.random.Generator(np.random.PCG64(int(seed)))
         self.ks = tuple(int(k) for k in ks)
         self.target_tol = float(target_tol)
@@ -49,9 +50,12 @@ class PairGenerator:
         self._dx = L.wd_new_field(self.dims, "f64")
 
     def _source(self):
-        L1, L2, L3, L4 = self.dims
-        z = self.rng.standard_normal((L4, L3, L2, L1, 4, 3, 2))
-        return canon_to_field(self.g, z[..., 0] + 1j * z[..., 1], "f64")
+        """A Gaussian source drawn on the device (counter-based generator:
+        stream = the source's running index, so every source differs)."""
+        f = L.wd_new_field(self.dims, "f64")
+        L.wd_gaussian_field(self.g, f, L.WD_FULL, "f64", self.seed, self.sources)
+        self.sources += 1
+        return f
 
     def _push(self, r, e):
         """Normalise the pair by |r| and keep it as two FP32 full fields."""
@@ -67,7 +71,6 @@ class PairGenerator:
         t = time.perf_counter()
         n = self.nsrc
         B = self.torch.cat([self._source() for _ in range(n)])
-        self.sources += n
         prm = L.wd_solve_params_default(solver=L.WD_SOLVER_DEFECT_CG, inner_prec="f32", inner_tol=1e-3)
         L.wd_solve_mrhs(self.g, B, self._xs, n, self.kappa, self.target_tol, prm)
         f = self.f64
