@@ -24,16 +24,16 @@ namespace wd {
 // OCC > 0 asks the compiler for at least OCC waves per SIMD (fewer registers,
 // possibly a few spills); OCC = 0 leaves the register budget to the compiler.
 #define WD_OCC_KERNEL(OCCV, ATTR)                                                   \
-  template <int P, bool DAG, int EPI, bool NORM>                                  \
+  template <int P, bool DAG, int EPI, bool NORM, bool PRE>                        \
   __global__ __launch_bounds__(512) ATTR void k_dslash_o##OCCV(KDslash k) {     \
-    dslash_body<P, DAG, EPI, NORM>(k);                                            \
+    dslash_body<P, DAG, EPI, NORM, PRE>(k);                                       \
   }
 
-template <int P, bool DAG, int EPI, bool NORM>
+template <int P, bool DAG, int EPI, bool NORM, bool PRE>
 __device__ __forceinline__ void dslash_body(const KDslash &k) {
   if (k.skip && *k.skip) return;
   const int i = tile_of(k) * (int)blockDim.x + (int)threadIdx.x;
-  const double nrm = dslash_site<P, DAG, EPI, NORM>(k, i);
+  const double nrm = dslash_site<P, DAG, EPI, NORM, PRE>(k, i);
   if constexpr (NORM) {
     double v[1] = {nrm}, tot[1];
     if (grid_sum_last<1>(v, k.partials, k.counter, gridDim.x, blockIdx.x, tot)) {
@@ -274,8 +274,15 @@ static KDslash make_k(const wd_gauge *g, wd_prec prec, int parity) {
 // smaller set of neighbour spinors the L2 must hold for reuse.
 template <int P, bool DAG, int EPI, bool NORM>
 static void launch_t(const KDslash &k, unsigned nblk, unsigned bs, unsigned lds, hipStream_t st) {
-  if (k.occ == 4) hipLaunchKernelGGL((k_dslash_o4<P, DAG, EPI, NORM>), dim3(nblk), dim3(bs), lds, st, k);
-  else hipLaunchKernelGGL((k_dslash_o0<P, DAG, EPI, NORM>), dim3(nblk), dim3(bs), lds, st, k);
+  if constexpr (P != WD_F64) {
+    if (k.preload) {
+      if (k.occ == 4) hipLaunchKernelGGL((k_dslash_o4<P, DAG, EPI, NORM, true>), dim3(nblk), dim3(bs), lds, st, k);
+      else hipLaunchKernelGGL((k_dslash_o0<P, DAG, EPI, NORM, true>), dim3(nblk), dim3(bs), lds, st, k);
+      return;
+    }
+  }
+  if (k.occ == 4) hipLaunchKernelGGL((k_dslash_o4<P, DAG, EPI, NORM, false>), dim3(nblk), dim3(bs), lds, st, k);
+  else hipLaunchKernelGGL((k_dslash_o0<P, DAG, EPI, NORM, false>), dim3(nblk), dim3(bs), lds, st, k);
 }
 
 template <int P, bool DAG>
@@ -339,6 +346,7 @@ wd_status launch_dslash(const wd_gauge *g, wd_prec prec, const DslashArgs &a, hi
   k.groups = groups;
   k.occ = g->hop_occ[pi];
   k.nt_store = g->hop_ntst[pi];
+  k.preload = (prec != WD_F64) ? g->hop_pre[pi] : 0;
   k.tiles_per_slice = groups ? (int)((long)g->geom.vh / g->geom.L[3] / bs) : 0;
   const unsigned nblk = (unsigned)((g->geom.vpad + bs - 1) / bs);
   const unsigned lds = (unsigned)g->hop_lds[pi];

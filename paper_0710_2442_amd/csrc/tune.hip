@@ -1,9 +1,11 @@
-// Autotuner for the single-RHS hop: block size and XCD-region grouping.
+// Autotuner for the single-RHS and multi-RHS hops (block size, block -> tile
+// order, register budget, store policy, resident-block cap, link preloading;
+// RHS per lane for the multi-RHS hop).
 //
 // Each candidate is first checked for parity -- its output must equal the
-// reference variant's (256 threads, linear order) byte for byte, which holds
-// because every site's arithmetic is the same in every variant -- and then
-// timed with HIP events.  The fastest valid candidate is stored in the handle
+// reference variant's byte for byte, which holds because every site's
+// arithmetic is the same in every variant (the comparison runs on the
+// device) -- and then timed with HIP events.  The fastest valid candidate is stored in the handle
 // and, if a cache path is given, appended to a JSON-lines cache keyed by
 // (architecture, kernel, precision, lattice).
 #include <stdio.h>
@@ -58,16 +60,48 @@ static void cache_append(const char *path, const std::string &key, int bs, int g
   fclose(f);
 }
 
-// occ value: bits 0..7 register budget (0 or 4), WD_TUNE_CACHED_STORE, and
-// the dynamic LDS per block in KiB at WD_TUNE_LDS_SHIFT (0..64)
-static wd_status decode_occ(int occ, int &o, int &nts, int &lkb) {
+// occ value: bits 0..7 register budget (0 or 4), WD_TUNE_CACHED_STORE,
+// WD_TUNE_PRELOAD_LINKS, and the dynamic LDS per block in KiB at
+// WD_TUNE_LDS_SHIFT (0..64)
+static wd_status decode_occ(int occ, int &o, int &nts, int &lkb, int &pre) {
   o = occ & 0xff;
   nts = (occ & WD_TUNE_CACHED_STORE) ? 0 : 1;
+  pre = (occ & WD_TUNE_PRELOAD_LINKS) ? 1 : 0;
   lkb = (occ >> WD_TUNE_LDS_SHIFT) & 0xff;
-  const int rest = occ & ~(0xff | WD_TUNE_CACHED_STORE | (0xff << WD_TUNE_LDS_SHIFT));
+  const int rest = occ & ~(0xff | WD_TUNE_CACHED_STORE | WD_TUNE_PRELOAD_LINKS | (0xff << WD_TUNE_LDS_SHIFT));
   if ((o != 0 && o != 4) || rest || lkb > 64)
-    return set_error(WD_ERR_ARG, "occ = 0x%x: register budget 0 or 4, | WD_TUNE_CACHED_STORE, | KiB << %d (<= 64)",
+    return set_error(WD_ERR_ARG,
+                     "occ = 0x%x: register budget 0 or 4, | WD_TUNE_CACHED_STORE, | WD_TUNE_PRELOAD_LINKS, "
+                     "| KiB << %d (<= 64)",
                      occ, WD_TUNE_LDS_SHIFT);
+  return WD_OK;
+}
+
+static int encode_occ(const wd_gauge *g, wd_prec prec) {
+  return g->hop_occ[prec] | (g->hop_ntst[prec] ? 0 : WD_TUNE_CACHED_STORE) |
+         (g->hop_pre[prec] ? WD_TUNE_PRELOAD_LINKS : 0) | ((g->hop_lds[prec] / 1024) << WD_TUNE_LDS_SHIFT);
+}
+
+// *differ = 1 if the n 16-byte words of a and b are not all equal (vector
+// stores only; the flag is cleared by the caller).
+__global__ __launch_bounds__(256) void k_differ(const uint4 *a, const uint4 *b, size_t n, int *differ) {
+  bool d = false;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const uint4 x = a[i], y = b[i];
+    d |= (x.x != y.x) | (x.y != y.y) | (x.z != y.z) | (x.w != y.w);
+  }
+  if (d) *differ = 1;
+}
+
+// true when the hb bytes at a and b are equal (synchronises st)
+static wd_status same_bytes(const void *a, const void *b, size_t hb, int *flag_dev, bool &same, hipStream_t st) {
+  WD_HIP(hipMemsetAsync(flag_dev, 0, sizeof(int), st));
+  hipLaunchKernelGGL(k_differ, dim3(1024), dim3(256), 0, st, (const uint4 *)a, (const uint4 *)b, hb / 16, flag_dev);
+  WD_HIP(hipGetLastError());
+  int h = 1;
+  WD_HIP(hipMemcpyAsync(&h, flag_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+  WD_HIP(hipStreamSynchronize(st));
+  same = (h == 0);
   return WD_OK;
 }
 
@@ -82,13 +116,15 @@ wd_status wd_set_dslash_variant(wd_gauge *g, wd_prec prec, int block, int groups
   if ((int)prec < 0 || (int)prec > 3) return set_error(WD_ERR_PREC, "prec = %d", (int)prec);
   if (block < 64 || !dslash_variant_ok(g->geom, block, groups))
     return set_error(WD_ERR_ARG, "variant (block %d, groups %d) does not fit this lattice", block, groups);
-  int o, nts, lkb;
-  WD_TRY(decode_occ(occ, o, nts, lkb));
+  int o, nts, lkb, pre;
+  WD_TRY(decode_occ(occ, o, nts, lkb, pre));
+  if (pre && prec == WD_F64) return set_error(WD_ERR_ARG, "link preloading is for FP32-arithmetic hops");
   g->hop_block[prec] = block;
   g->hop_groups[prec] = groups;
   g->hop_occ[prec] = o;
   g->hop_ntst[prec] = nts;
   g->hop_lds[prec] = lkb * 1024;
+  g->hop_pre[prec] = pre;
   return WD_OK;
 }
 
@@ -97,8 +133,7 @@ wd_status wd_get_dslash_variant(const wd_gauge *g, wd_prec prec, int *block, int
   if ((int)prec < 0 || (int)prec > 3) return set_error(WD_ERR_PREC, "prec = %d", (int)prec);
   *block = g->hop_block[prec];
   *groups = g->hop_groups[prec];
-  *occ = g->hop_occ[prec] | (g->hop_ntst[prec] ? 0 : WD_TUNE_CACHED_STORE) |
-         ((g->hop_lds[prec] / 1024) << WD_TUNE_LDS_SHIFT);
+  *occ = encode_occ(g, prec);
   return WD_OK;
 }
 
@@ -118,14 +153,15 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
     const size_t V = 2 * (size_t)G.vh;
     hipStream_t st = g->own_stream;
     void *in = nullptr, *ref = nullptr, *cand = nullptr, *canon = nullptr;
+    int *flag = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     wd_status rc = WD_OK;
-    std::vector<unsigned char> h_ref(hb), h_cand(hb);
     do {
       if ((rc = hip_check(hipMalloc(&in, hb), "tune alloc")) != WD_OK) break;
       if ((rc = hip_check(hipMalloc(&ref, hb), "tune alloc")) != WD_OK) break;
       if ((rc = hip_check(hipMalloc(&cand, hb), "tune alloc")) != WD_OK) break;
       if ((rc = hip_check(hipMalloc(&canon, V * 24 * sizeof(double)), "tune alloc")) != WD_OK) break;
+      if ((rc = hip_check(hipMalloc(&flag, 256), "tune alloc")) != WD_OK) break;
       {
         // deterministic input: a simple integer hash mapped to [-1, 1)
         std::vector<double> h(V * 24);
@@ -142,43 +178,43 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
       if ((rc = hip_check(hipEventCreate(&e0), "event")) != WD_OK) break;
       if ((rc = hip_check(hipEventCreate(&e1), "event")) != WD_OK) break;
       const int save_b = g->hop_block[prec], save_g = g->hop_groups[prec], save_o = g->hop_occ[prec];
-      const int save_n = g->hop_ntst[prec], save_l = g->hop_lds[prec];
+      const int save_n = g->hop_ntst[prec], save_l = g->hop_lds[prec], save_p = g->hop_pre[prec];
       DslashArgs a;
       a.in = in; a.a = 1.0; a.parity = WD_EVEN;
       // reference variant
       g->hop_block[prec] = 256; g->hop_groups[prec] = 0; g->hop_occ[prec] = 0; g->hop_ntst[prec] = 1;
-      g->hop_lds[prec] = 0;
+      g->hop_lds[prec] = 0; g->hop_pre[prec] = 0;
       a.out = ref;
       if ((rc = launch_dslash(g, prec, a, st)) != WD_OK) break;
-      if ((rc = hip_check(hipMemcpyAsync(h_ref.data(), ref, hb, hipMemcpyDeviceToHost, st), "copy")) != WD_OK) break;
-      if ((rc = hip_check(hipStreamSynchronize(st), "sync")) != WD_OK) break;
       const int blocks[] = {64, 128, 256, 512};
       const int grps[] = {0, 2, 4, 8, 16, -8, -16};
       best_us = 1e30;
-      int nbest_b = 256, nbest_g = 0, nbest_o = 0, nbest_n = 1, nbest_l = 0;
+      int nbest_b = 256, nbest_g = 0, nbest_o = 0, nbest_n = 1, nbest_l = 0, nbest_p = 0;
       size_t lds_max = 65536;
       {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, g->device) == hipSuccess) lds_max = prop.sharedMemPerBlock;
       }
+      for (int pre : {0, 1})
       for (int lkb : {0, 24, 40, 60})
       for (int nts : {1, 0})
       for (int oc : {0, 4})
       for (int b : blocks) {
         for (int gr : grps) {
           if (!dslash_variant_ok(G, b, gr)) continue;
+          if (pre && prec == WD_F64) continue;
           if (oc == 4 && lkb != 0) continue;  // both only lower occupancy; keep the grid small
           if ((size_t)lkb * 1024 + 1024 > lds_max) continue;
           g->hop_block[prec] = b; g->hop_groups[prec] = gr; g->hop_occ[prec] = oc; g->hop_ntst[prec] = nts;
           g->hop_lds[prec] = lkb * 1024;
+          g->hop_pre[prec] = pre;
           if ((rc = launch_pack_spinor(g, canon, in, WD_ODD, prec, st)) != WD_OK) break;
           a.out = cand;
           if ((rc = hip_check(hipMemsetAsync(cand, 0xff, hb, st), "memset")) != WD_OK) break;
           if ((rc = launch_dslash(g, prec, a, st)) != WD_OK) break;
-          if ((rc = hip_check(hipMemcpyAsync(h_cand.data(), cand, hb, hipMemcpyDeviceToHost, st), "copy")) != WD_OK)
-            break;
-          if ((rc = hip_check(hipStreamSynchronize(st), "sync")) != WD_OK) break;
-          if (memcmp(h_ref.data(), h_cand.data(), hb) != 0) continue;  // parity first
+          bool same = false;
+          if ((rc = same_bytes(ref, cand, hb, flag, same, st)) != WD_OK) break;
+          if (!same) continue;  // parity first
           // time the pattern of a solver: even and odd hops alternate, so the
           // two parities' link arrays stream through the caches in turn
           const int reps = 6;
@@ -194,9 +230,11 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
           (void)hipEventElapsedTime(&ms, e0, e1);
           const double us = 1e3 * ms / (2 * reps);
           if (getenv("WD_TUNE_VERBOSE"))
-            fprintf(stderr, "tune %s: block %d groups %d occ %d ntstore %d lds %dK: %.2f us\n", key.c_str(), b, gr, oc,
-                    nts, lkb, us);
-          if (us < best_us) { best_us = us; nbest_b = b; nbest_g = gr; nbest_o = oc; nbest_n = nts; nbest_l = lkb; }
+            fprintf(stderr, "tune %s: block %d groups %d occ %d ntstore %d lds %dK preload %d: %.2f us\n", key.c_str(),
+                    b, gr, oc, nts, lkb, pre, us);
+          if (us < best_us) {
+            best_us = us; nbest_b = b; nbest_g = gr; nbest_o = oc; nbest_n = nts; nbest_l = lkb; nbest_p = pre;
+          }
         }
         if (rc != WD_OK) break;
       }
@@ -204,6 +242,7 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
         g->hop_block[prec] = save_b; g->hop_groups[prec] = save_g; g->hop_occ[prec] = save_o;
         g->hop_ntst[prec] = save_n;
         g->hop_lds[prec] = save_l;
+        g->hop_pre[prec] = save_p;
         break;
       }
       g->hop_block[prec] = nbest_b;
@@ -211,8 +250,9 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
       g->hop_occ[prec] = nbest_o;
       g->hop_ntst[prec] = nbest_n;
       g->hop_lds[prec] = nbest_l * 1024;
+      g->hop_pre[prec] = nbest_p;
       bs = nbest_b; groups = nbest_g;
-      occ = nbest_o | (nbest_n ? 0 : WD_TUNE_CACHED_STORE) | (nbest_l << WD_TUNE_LDS_SHIFT);
+      occ = encode_occ(g, prec);
       if (cache_path) cache_append(cache_path, key, bs, groups, occ, best_us);
     } while (0);
     if (e0) (void)hipEventDestroy(e0);
@@ -221,6 +261,7 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
     if (ref) (void)hipFree(ref);
     if (cand) (void)hipFree(cand);
     if (canon) (void)hipFree(canon);
+    if (flag) (void)hipFree(flag);
     if (rc != WD_OK) return rc;
   }
   if (out_block) *out_block = bs;
@@ -246,7 +287,7 @@ wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, int *out_bloc
   void *in = nullptr, *ref = nullptr, *cand = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   wd_status rc = WD_OK;
-  std::vector<unsigned char> h_ref(hb), h_cand(hb);
+  int *flag = nullptr;
   const int save = g->mrhs_groups[prec], save_b = g->mrhs_block[prec], save_r = g->mrhs_rpl[prec];
   const int ref_b = (prec == WD_F64) ? 16 : 128;
   int best_g = 0, best_b = ref_b, best_r = 4;
@@ -255,6 +296,7 @@ wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, int *out_bloc
     if ((rc = hip_check(hipMalloc(&in, hb), "tune alloc")) != WD_OK) break;
     if ((rc = hip_check(hipMalloc(&ref, hb), "tune alloc")) != WD_OK) break;
     if ((rc = hip_check(hipMalloc(&cand, hb), "tune alloc")) != WD_OK) break;
+    if ((rc = hip_check(hipMalloc(&flag, 256), "tune alloc")) != WD_OK) break;
     {
       std::vector<unsigned char> h(hb);
       uint64_t s = 0x243F6A8885A308D3ull;
@@ -273,8 +315,6 @@ wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, int *out_bloc
     g->mrhs_block[prec] = ref_b;
     g->mrhs_rpl[prec] = 4;
     if ((rc = launch_dslash_mrhs(g, prec, in, ref, 1.0, WD_EVEN, 0, nrhs, st)) != WD_OK) break;
-    if ((rc = hip_check(hipMemcpyAsync(h_ref.data(), ref, hb, hipMemcpyDeviceToHost, st), "copy")) != WD_OK) break;
-    if ((rc = hip_check(hipStreamSynchronize(st), "sync")) != WD_OK) break;
     std::vector<int> blocks, rpls;
     if (prec == WD_F64) {
       blocks = {16};
@@ -293,10 +333,9 @@ wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, int *out_bloc
       g->mrhs_rpl[prec] = rp;
       if ((rc = hip_check(hipMemsetAsync(cand, 0xff, hb, st), "memset")) != WD_OK) break;
       if ((rc = launch_dslash_mrhs(g, prec, in, cand, 1.0, WD_EVEN, 0, nrhs, st)) != WD_OK) break;
-      if ((rc = hip_check(hipMemcpyAsync(h_cand.data(), cand, hb, hipMemcpyDeviceToHost, st), "copy")) != WD_OK)
-        break;
-      if ((rc = hip_check(hipStreamSynchronize(st), "sync")) != WD_OK) break;
-      if (memcmp(h_ref.data(), h_cand.data(), hb) != 0) continue;
+      bool same = false;
+      if ((rc = same_bytes(ref, cand, hb, flag, same, st)) != WD_OK) break;
+      if (!same) continue;
       const int reps = 6;
       for (int w = 0; w < 2; ++w) (void)launch_dslash_mrhs(g, prec, in, cand, 1.0, WD_EVEN, 0, nrhs, st);
       (void)hipEventRecord(e0, st);
@@ -320,6 +359,7 @@ wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, int *out_bloc
   if (in) (void)hipFree(in);
   if (ref) (void)hipFree(ref);
   if (cand) (void)hipFree(cand);
+  if (flag) (void)hipFree(flag);
   if (rc != WD_OK) return rc;
   if (out_block) *out_block = best_b;
   if (out_rpl) *out_rpl = best_r;

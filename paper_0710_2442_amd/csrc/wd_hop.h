@@ -28,6 +28,7 @@ struct KDslash {
   int tiles_per_slice;  // tiles (blocks) per time slice of one parity
   int occ;              // register-budget variant (0 or 4), host side only
   int nt_store;         // 1: streaming output stores; 0: cached stores
+  int preload;          // 1: load all 8 links before the first hop (FP32 arithmetic only), host side
 };
 
 // Workgroups are dispatched round-robin over the XCDs (8 on MI355X), each
@@ -178,17 +179,35 @@ __device__ __forceinline__ void hop_all(const KDslash &k, int i, cplx<RealOf<P>>
   hop_term<P, 3, B>(acc, k.in, nb[7], L, 7, i, sb);
 }
 
+// The 8 hops of site i with all 8 links loaded first: 48 (FP64) or 24
+// (FP32) independent 16-byte loads in flight per lane before any arithmetic,
+// at the cost of holding the links in registers.
+template <int P, bool DAG>
+__device__ __forceinline__ void hop_all_preload(const KDslash &k, int i, cplx<RealOf<P>> (&acc)[12]) {
+  using T = RealOf<P>;
+  const Coords c = coords_of(k.g, i, k.parity);
+  int nb[8];
+  neighbours(k.g, c, i, nb);
+  const T sf = (c.x4 == k.g.L[3] - 1) ? (T)k.g.tbc : (T)1;
+  const T sb = (c.x4 == 0) ? (T)k.g.tbc : (T)1;
+  cplx<T> u[8][6];
+#pragma unroll
+  for (int d = 0; d < 8; ++d) Link<T>::load(k.links, d, i, u[d]);
+  hop_all_u<P, DAG>(k.in, nb, u, sf, sb, acc);
+}
+
 // One output site i of the hop with the fused epilogue
 //   EPI 0: out = a H in;  1: out = X + a H in;  2: out = X - Y + a H in.
 // Padding slots (vh <= i < vpad) get zeros.  Returns |stored out|^2 (FP64)
-// when NORM, else 0.
-template <int P, bool DAG, int EPI, bool NORM>
+// when NORM, else 0.  PRE: links loaded up front (same arithmetic).
+template <int P, bool DAG, int EPI, bool NORM, bool PRE = false>
 __device__ __forceinline__ double dslash_site(const KDslash &k, int i) {
   using T = RealOf<P>;
   double nrm = 0.0;
   if (i < k.g.vh) {
     cplx<T> acc[12];
-    hop_all<P, DAG>(k, i, acc);
+    if constexpr (PRE) hop_all_preload<P, DAG>(k, i, acc);
+    else hop_all<P, DAG>(k, i, acc);
     const T a = (T)k.a;
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = a * acc[c];

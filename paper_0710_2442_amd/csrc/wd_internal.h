@@ -78,6 +78,7 @@ struct wd_gauge {
   int mrhs_block[4];       // per precision: sites per block of the FP32/16-bit multi-RHS hop
   int mrhs_rpl[4];         // per precision: right-hand sides per lane of that kernel
   int hop_lds[4];          // per precision: dynamic LDS bytes per block (caps blocks per CU)
+  int hop_pre[4];          // per precision: 1 = links loaded before the first hop (not FP64)
   double *scratch_red;     // reduction partials / scalars for the BLAS entry points
   unsigned *scratch_cnt;
   wd::Workspace *ws;
