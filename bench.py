@@ -361,6 +361,31 @@ def kernels_leg(wd, torch, syn, U, psi):
     return out
 
 
+def micro_leg(wd):
+    """Global -> LDS block copies vs size and misalignment, fitted to the form
+    of the paper's DMA model (Eq. 4): T = l0 + la * N_a + N_b * c, with N_b the
+    128-byte blocks touched and N_a = N_b for a source off a 128-byte boundary
+    (0 when aligned)."""
+    import numpy as np
+
+    rows = []
+    for nbytes in (128, 256, 512, 1024, 2048, 4096, 8192, 16384, 32768):
+        for off in (0, 4, 64, 128, 132):
+            cyc, _ = wd.wd_micro_lds_copy(nbytes, off, 64)
+            t = float(np.median(cyc[4:]))
+            nb = -(-((off % 128) + nbytes) // 128)
+            na = nb if off % 128 else 0
+            rows.append((nbytes, off, nb, na, t))
+    A = np.array([[1.0, r[3], r[2]] for r in rows])
+    y = np.array([r[4] for r in rows])
+    coef, *_ = np.linalg.lstsq(A, y, rcond=None)
+    fit = A @ coef
+    return {"lambda0_cycles": round(float(coef[0]), 1), "lambda_a_cycles_per_block": round(float(coef[1]), 2),
+            "cycles_per_128B_block": round(float(coef[2]), 2),
+            "max_rel_misfit": round(float(np.max(np.abs(fit - y) / y)), 3),
+            "samples": [{"bytes": r[0], "offset": r[1], "cycles": r[4]} for r in rows]}
+
+
 def cpu_leg(syn, U, psi):
     """Oracle single-parity hop on the full 32^3x64 workload (one application)."""
     import numpy as np
@@ -504,6 +529,7 @@ def main():
         line["learned_ptc_fgcr_32x32x32x64"] = learned_leg(wd, torch, syn, args.learn_steps)
     if not args.no_kernels:
         line["kernels_32x32x32x64"] = kernels_leg(wd, torch, syn, U, psi)
+        line["micro_lds_copy_eq4_fit"] = micro_leg(wd)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_leg(syn, U, psi)
     print(json.dumps(line), flush=True)

@@ -341,6 +341,22 @@ wd_status wd_solve_batch(const wd_gauge *const *gs, int n, const void *const *b,
                          void *const *x, const double *kappa, double tol,
                          const wd_solve_params *params, wd_solve_info *infos);
 
+/* ------------------------------------------------------ micro-benchmark -- */
+/* Global memory -> LDS block copy on device `device` (the analogue of the
+ * paper's DMA measurements, Sec. 6 / Eq. 4): one workgroup of 256 threads
+ * copies `bytes` bytes (16..32768, multiple of 16) starting `offset` bytes
+ * (0..252, multiple of 4) past a 256-byte boundary into LDS, `reps` times
+ * (1..1024), each from a fresh source block 1 MiB apart; 512 MB written
+ * elsewhere just before keep the sources out of the Infinity Cache.
+ * src_host: 1 MiB host pattern copied into every source block (NULL: zeros).
+ * Outputs (host arrays of reps entries): cycles[r] = shader-clock cycles of
+ * copy r between two barriers; sums[r] = sum mod 2^32 of the 32-bit words
+ * that LDS held after copy r (a check that the bytes arrived).
+ * Synchronous; allocates reps MiB + 512 MB of device memory for the call. */
+wd_status wd_micro_lds_copy(int device, int bytes, int offset, int reps,
+                            const void *src_host, unsigned long long *cycles,
+                            unsigned *sums);
+
 /* --------------------------------------------------------------- misc --- */
 
 const char *wd_status_string(int status);

@@ -103,6 +103,8 @@ _decl("wd_ptc_apply", C.c_int, [_vp, _vp, _vp])
 _decl("wd_ptc_loss_grad", C.c_int, [_vp, _vp, _vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_float)])
 _decl("wd_ptc_train_step", C.c_int, [_vp, _vp, _vp, C.c_int, C.c_double, C.POINTER(C.c_double)])
 _decl("wd_gaussian_field", C.c_int, [_vp, _vp, C.c_int, C.c_int, C.c_ulonglong, C.c_ulonglong])
+_decl("wd_micro_lds_copy", C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, _vp, C.POINTER(C.c_ulonglong),
+                                     C.POINTER(C.c_uint)])
 _decl("wd_status_string", C.c_char_p, [C.c_int])
 _decl("wd_last_error", C.c_char_p, [])
 
@@ -228,6 +230,21 @@ def wd_gaussian_field(g, field, parity, prec, seed, stream):
     g.sync_stream()
     _check(lib.wd_gaussian_field(g.handle, _ptr(field), int(parity), _prec(prec), int(seed) & (2**64 - 1),
                                  int(stream) & (2**64 - 1)), "wd_gaussian_field")
+
+
+def wd_micro_lds_copy(bytes_, offset, reps, pattern=None, device=0):
+    """Global -> LDS copy micro-benchmark; returns (cycles per copy, LDS checksums), numpy arrays."""
+    cyc = (C.c_ulonglong * int(reps))()
+    sums = (C.c_uint * int(reps))()
+    src = None
+    if pattern is not None:
+        src = np.ascontiguousarray(pattern, dtype=np.uint8)
+        if src.nbytes != 1 << 20:
+            raise ValueError("pattern must be 1 MiB")
+    _check(lib.wd_micro_lds_copy(int(device), int(bytes_), int(offset), int(reps),
+                                 None if src is None else src.ctypes.data_as(C.c_void_p), cyc, sums),
+           "wd_micro_lds_copy")
+    return np.array(cyc[:], dtype=np.uint64), np.array(sums[:], dtype=np.uint32)
 
 
 def wd_spinor_unpack(g, field, canon, parity=WD_FULL, prec=None):

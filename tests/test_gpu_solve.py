@@ -135,6 +135,34 @@ def test_free_field_solve_matches_fft_16x4():
     g.close()
 
 
+def test_free_field_solves_at_full_size_32x32x32x64():
+    """The solver workloads' lattice (32^3x64, kappa 0.124) with unit links,
+    where the exact D^{-1} b is the oracle's FFT solution: plain FP64 CG,
+    BF16-storage defect correction and the mixed even-odd FGCR must all land
+    within cond(D) * tol of it.  Free-field cond(D) here is ~134
+    (lambda_min(D^dag D) = 2.2e-4)."""
+    dims, kappa = (32, 32, 32, 64), 0.124
+    lo, hi = free_field.lambda_min_normal(dims, kappa)
+    cond = np.sqrt(hi / lo)
+    assert 130 < cond < 140
+    U = syn.unit_gauge(dims)
+    b = syn.gaussian_spinor(dims, 2003)
+    g = wd.Gauge(U, dims, -1, "f64")
+    del U
+    fb = to_field(g, b)
+    fx = wd.wd_new_field(dims, "f64")
+    xs = free_field.solve(b, kappa)
+    for kw in (dict(solver=wd.WD_SOLVER_CG),
+               dict(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec="bf16", inner_tol=1e-2),
+               dict(solver=wd.WD_SOLVER_DEFECT_FGCR, fgcr_m=4, inner_tol=1e-2)):
+        rc, info = wd.wd_solve(g, fb, fx, kappa, TOL, wd.wd_solve_params_default(**kw))
+        assert rc == 0 and info["true_rel_resid"] <= TOL, (kw, info)
+        err = rel_err(from_field(g, fx), xs)
+        print(kw["solver"], info["iters"], info["true_rel_resid"], err, flush=True)
+        assert err <= 2 * cond * TOL, (kw, err)
+    g.close()
+
+
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 def test_multi_rhs_point_sources(prec):
     """12 spin-colour point sources solved together (shared hop launches, own scalars)."""
