@@ -345,10 +345,15 @@ def kernels_leg(wd, torch, syn, U, psi):
         wd.wd_norm2(g, x, 2, "f64")
     t = (time.perf_counter() - t0) / 20
     out["norm2_f64_with_readback"] = {"us": round(t * 1e6, 2), "GBps": round(V * 192 / t / 1e9, 1)}
-    # full D_W = 1 - kappa H: two parity launches with the xpay epilogue
-    t = ev_time(lambda: wd.wd_dslash(g, x, z, 0.124, DIMS, wd.WD_FULL))
-    out["dirac_full_f64"] = {"us": round(t * 1e6, 2), "GBps": round(V * 1344 / t / 1e9, 1),
-                             "bytes_per_site": 1344}
+    # full D_W = 1 - kappa H in one launch: 4 x 12 link + 24 + 24 reals per site
+    t = ev_time(lambda: wd.wd_dslash_ex(g, x, z, 0.124, wd.WD_FULL, "f64", wd.WD_ONE_PASS))
+    out["dirac_full_f64_one_launch"] = {"us": round(t * 1e6, 2), "GBps": round(V * 768 / t / 1e9, 1),
+                                        "frac_hbm": round(V * 768 / t / 1e9 / HBM_PEAK_GBS, 4),
+                                        "bytes_per_site": 768}
+    # the same with two single-parity launches (each link read twice, xpay operand read)
+    t2 = ev_time(lambda: wd.wd_dslash(g, x, z, 0.124, DIMS, wd.WD_FULL))
+    out["dirac_full_f64_two_pass"] = {"us": round(t2 * 1e6, 2), "GBps": round(V * 1344 / t2 / 1e9, 1),
+                                      "bytes_per_site": 1344, "one_launch_speedup": round(t2 / t, 3)}
     # the PTC network (FP32 fields, BF16 activations), one application on the full lattice
     net = wd.Ptc(g, learn.init_weights(1), "bf16")
     r32 = wd.wd_new_field(DIMS, "f32")

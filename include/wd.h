@@ -82,8 +82,11 @@ typedef enum { WD_F64 = 0, WD_F32 = 1, WD_F16 = 2, WD_BF16 = 3 } wd_prec;
 
 enum { WD_EVEN = 0, WD_ODD = 1, WD_FULL = 2 };
 
-/* flags of wd_dslash_ex */
-enum { WD_DAGGER = 1 };
+/* flags of wd_dslash_ex.  WD_DAGGER: apply H^dag (D_W^dag).  WD_ONE_PASS
+ * (parity WD_FULL only): compute D_W in one full-lattice launch that takes
+ * each site's backward links from its neighbours' forward links (each link
+ * is needed once per application) instead of two single-parity launches. */
+enum { WD_DAGGER = 1, WD_ONE_PASS = 2 };
 
 typedef struct wd_gauge wd_gauge;
 

@@ -24,6 +24,7 @@ WD_F64, WD_F32, WD_F16, WD_BF16 = 0, 1, 2, 3
 PRECS = {"f64": WD_F64, "f32": WD_F32, "f16": WD_F16, "bf16": WD_BF16}
 WD_EVEN, WD_ODD, WD_FULL = 0, 1, 2
 WD_DAGGER = 1
+WD_ONE_PASS = 2
 WD_TUNE_CACHED_STORE = 256
 WD_TUNE_PRELOAD_LINKS = 512
 WD_SOLVER_CG, WD_SOLVER_DEFECT_CG, WD_SOLVER_FGCR, WD_SOLVER_DEFECT_FGCR = 0, 1, 2, 3

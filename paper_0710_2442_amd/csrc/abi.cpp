@@ -200,7 +200,7 @@ static wd_status dslash_common(const wd_gauge *U, const void *in, void *out, dou
   if (parity < 0 || parity > 2) return set_error(WD_ERR_ARG, "dslash: parity = %d", parity);
   if (!prec_ok(prec)) return set_error(WD_ERR_PREC, "dslash: prec = %d", (int)prec);
   if (!isfinite(kappa)) return set_error(WD_ERR_NONFINITE, "dslash: kappa is not finite");
-  if (flags & ~WD_DAGGER) return set_error(WD_ERR_ARG, "dslash: unknown flags 0x%x", flags);
+  if (flags & ~(WD_DAGGER | WD_ONE_PASS)) return set_error(WD_ERR_ARG, "dslash: unknown flags 0x%x", flags);
   WD_TRY(set_device(U));
   const int dag = (flags & WD_DAGGER) ? 1 : 0;
   if (parity != WD_FULL) {
@@ -213,6 +213,11 @@ static wd_status dslash_common(const wd_gauge *U, const void *in, void *out, dou
   const size_t ob = (const char *)out > (const char *)in ? (size_t)((const char *)out - (const char *)in)
                                                           : (size_t)((const char *)in - (const char *)out);
   if (ob < 2 * hb) return set_error(WD_ERR_ARG, "dslash: full fields overlap");
+  if (flags & WD_ONE_PASS) {
+    DiracArgs a;
+    a.in = in; a.out = out; a.X = in; a.a = -kappa; a.dagger = dag;
+    return launch_dirac(U, prec, a, U->stream);
+  }
   for (int p = 0; p < 2; ++p) {
     DslashArgs a;
     a.in = (const char *)in + (1 - p) * hb;

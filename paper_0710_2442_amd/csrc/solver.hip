@@ -220,11 +220,13 @@ static wd_status cgls_run(const wd_gauge *g, const CglsVecs &v, double kappa, co
 wd_status true_residual64(const wd_gauge *g, const void *b, const void *x, void *r, int nsys, size_t sys_stride,
                           double kappa, CgScalars *sc, RedBuf red, hipStream_t st) {
   const size_t hb = half_bytes(g->geom, WD_F64);
-  for (int par = 0; par < 2; ++par) {
-    const int q = 1 - par;
-    if (nsys == 1) {
+  if (nsys == 1) {
+    // two single-parity launches with the xpay and norm epilogues (the tuned
+    // hop; the one-launch kernel moves fewer bytes but re-reads its shared
+    // links from HBM at this size, see the full-lattice kernel)
+    for (int par = 0; par < 2; ++par) {
       DslashArgs a;
-      a.in = (const char *)x + q * hb;
+      a.in = (const char *)x + (1 - par) * hb;
       a.out = (char *)r + par * hb;
       a.X = (const char *)b + par * hb;
       a.Y = (const char *)x + par * hb;
@@ -234,22 +236,24 @@ wd_status true_residual64(const wd_gauge *g, const void *b, const void *x, void 
       a.norm_accumulate = par;
       a.red = red;
       WD_TRY(launch_dslash(g, WD_F64, a, st));
-    } else {
-      MrhsArgs m;
-      m.in = (const char *)x + q * hb;
-      m.out = (char *)r + par * hb;
-      m.X = (const char *)b + par * hb;
-      m.Y = (const char *)x + par * hb;
-      m.a = kappa;
-      m.parity = par;
-      m.nrhs = nsys;
-      m.rhs_stride = sys_stride;
-      m.norm_out = &sc->rnorm2;
-      m.norm_stride = sizeof(CgScalars) / sizeof(double);
-      m.norm_accumulate = par;
-      m.red = red;
-      WD_TRY(launch_dslash_mrhs_ex(g, WD_F64, m, st));
     }
+    return WD_OK;
+  }
+  for (int par = 0; par < 2; ++par) {
+    MrhsArgs m;
+    m.in = (const char *)x + (1 - par) * hb;
+    m.out = (char *)r + par * hb;
+    m.X = (const char *)b + par * hb;
+    m.Y = (const char *)x + par * hb;
+    m.a = kappa;
+    m.parity = par;
+    m.nrhs = nsys;
+    m.rhs_stride = sys_stride;
+    m.norm_out = &sc->rnorm2;
+    m.norm_stride = sizeof(CgScalars) / sizeof(double);
+    m.norm_accumulate = par;
+    m.red = red;
+    WD_TRY(launch_dslash_mrhs_ex(g, WD_F64, m, st));
   }
   return WD_OK;
 }

@@ -288,14 +288,18 @@ __device__ __forceinline__ size_t link_packet(int d, int k, size_t i) {
 template <class R>
 struct Link;
 
+// NT = true (default): streaming loads, for links read once per launch;
+// NT = false: ordinary loads, for links another site of the launch re-reads.
 template <>
 struct Link<double> {
   static constexpr int NP = 6;
+  template <bool NT = true>
   __device__ static void load(const void *base, int d, size_t i, cplx<double> (&u)[6]) {
     const v2d *p = (const v2d *)base;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      v2d v = ld_stream(p + link_packet<6>(d, k, i));
+      const v2d *a = p + link_packet<6>(d, k, i);
+      v2d v = NT ? ld_stream(a) : *a;
       u[k] = {v.x, v.y};
     }
   }
@@ -303,11 +307,13 @@ struct Link<double> {
 template <>
 struct Link<float> {
   static constexpr int NP = 3;
+  template <bool NT = true>
   __device__ static void load(const void *base, int d, size_t i, cplx<float> (&u)[6]) {
     const v4f *p = (const v4f *)base;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      v4f v = ld_stream(p + link_packet<3>(d, k, i));
+      const v4f *a = p + link_packet<3>(d, k, i);
+      v4f v = NT ? ld_stream(a) : *a;
       u[2 * k] = {v.x, v.y};
       u[2 * k + 1] = {v.z, v.w};
     }
@@ -345,6 +351,19 @@ __device__ __forceinline__ void su3_mul(const cplx<T> (&u)[6], const cplx<T> (&r
   cfma(acc, r2[1], v[1]);
   cfma(acc, r2[2], v[2]);
   y[2] = acc;
+}
+
+// y = M^dag v for the same M (columns of M conjugated)
+template <class T>
+__device__ __forceinline__ void su3_mul_dag(const cplx<T> (&u)[6], const cplx<T> (&r2)[3],
+                                            const cplx<T> (&v)[3], cplx<T> (&y)[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cplx<T> acc = cjmul(u[a], v[0]);
+    cfma(acc, conj(u[3 + a]), v[1]);
+    cfma(acc, conj(r2[a]), v[2]);
+    y[a] = acc;
+  }
 }
 
 // --------------------------------------------------------- spin projection

@@ -92,7 +92,9 @@ __device__ __forceinline__ void neighbours(const Geom &g, const Coords &c, int i
 // One hop: acc += M (1 + S gamma_MU) psi_nb, M = the hop link u (rows 0, 1;
 // row 2 rebuilt).  Time hops (MU = 3) read only the half of the neighbour
 // spinor that their projector keeps (see the spin basis in wd_device.h).
-template <int P, int MU, int S>
+// LDAG: multiply by u^dag instead of u (u holds the rows of the link that
+// the neighbour stores as its forward link).
+template <int P, int MU, int S, bool LDAG = false>
 __device__ __forceinline__ void hop_term_u(cplx<RealOf<P>> (&acc)[12], const char *in, int nb,
                                            const cplx<RealOf<P>> (&u)[6], RealOf<P> sign) {
   using T = RealOf<P>;
@@ -113,13 +115,15 @@ __device__ __forceinline__ void hop_term_u(cplx<RealOf<P>> (&acc)[12], const cha
   {
     cplx<T> v[3] = {h[0], h[1], h[2]};
     cplx<T> y[3];
-    su3_mul(u, r2, v, y);
+    if constexpr (LDAG) su3_mul_dag(u, r2, v, y);
+    else su3_mul(u, r2, v, y);
     g[0] = y[0]; g[1] = y[1]; g[2] = y[2];
   }
   {
     cplx<T> v[3] = {h[3], h[4], h[5]};
     cplx<T> y[3];
-    su3_mul(u, r2, v, y);
+    if constexpr (LDAG) su3_mul_dag(u, r2, v, y);
+    else su3_mul(u, r2, v, y);
     g[3] = y[0]; g[4] = y[1]; g[5] = y[2];
   }
   reconstruct_add<MU, S>(acc, g);

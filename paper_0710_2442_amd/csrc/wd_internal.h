@@ -130,6 +130,21 @@ struct DslashArgs {
   const int *skip = nullptr;   // device flag
   RedBuf red{nullptr, nullptr};
 };
+// Full-lattice D_W in one launch (dirac.hip): full fields in, out, X, Y;
+// out = a H in (+ X (- Y)), optional FP64 |out|^2 over both parities.
+struct DiracArgs {
+  const void *in = nullptr;
+  void *out = nullptr;
+  const void *X = nullptr;
+  const void *Y = nullptr;
+  double a = 1.0;
+  int dagger = 0;
+  double *norm_out = nullptr;
+  int norm_accumulate = 0;
+  RedBuf red{nullptr, nullptr};
+};
+unsigned dirac_grid_blocks(const wd_gauge *g);
+wd_status launch_dirac(const wd_gauge *g, wd_prec prec, const DiracArgs &args, hipStream_t st);
 unsigned dslash_grid_blocks(const wd_gauge *g);
 bool dslash_variant_ok(const Geom &G, int bs, int groups);
 // grid.x of the multi-RHS hop (16 sites per block)
