@@ -122,6 +122,38 @@ __device__ __forceinline__ void transport(const KPtc &k, const PtcSite &s, int p
   }
 }
 
+// t = the raw input spinor that hop h reads at site (p, i): the site itself
+// for h = 0, else its neighbour in direction h - 1 (other parity).
+template <int PIN>
+__device__ __forceinline__ void load_source(const KPtc &k, const PtcSite &s, int p, int i, int h, const char *chan,
+                                            cplx<float> (&v)[12]) {
+  cplx<RealOf<PIN>> t[12];
+  if (h == 0) Spinor<PIN>::load(chan + (size_t)p * k.in_half, i, t);
+  else Spinor<PIN>::load(chan + (size_t)(1 - p) * k.in_half, s.nb[h - 1], t);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) v[c] = {(float)t[c].re, (float)t[c].im};
+}
+
+// acc += sg U m on every spin of m, U = the hop link of direction d at (p, i)
+__device__ __forceinline__ void transport_add(const KPtc &k, const PtcSite &s, int p, int i, int d,
+                                              const cplx<float> (&m)[12], cplx<float> (&acc)[12]) {
+  cplx<float> u[6], r2[3];
+  Link<float>::load(k.links32 + (size_t)p * k.link_par, d, i, u);
+  rebuild_row2(u, r2);
+  const float sg = (d == 3) ? s.sf : ((d == 7) ? s.sb : 1.0f);
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp) {
+    cplx<float> a[3] = {m[3 * sp], m[3 * sp + 1], m[3 * sp + 2]};
+    cplx<float> y[3];
+    su3_mul(u, r2, a, y);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      acc[3 * sp + c].re = fmaf(sg, y[c].re, acc[3 * sp + c].re);
+      acc[3 * sp + c].im = fmaf(sg, y[c].im, acc[3 * sp + c].im);
+    }
+  }
+}
+
 // acc += W v  (W: 4x4 complex on spin, v: 4 spins x 3 colours)
 __device__ __forceinline__ void spin_mat_acc(const float *W, const cplx<float> (&v)[12], cplx<float> (&acc)[12]) {
 #pragma unroll
@@ -159,13 +191,35 @@ __global__ __launch_bounds__(PTC_BS) void k_ptc_layer(KPtc k) {
     for (int c = 0; c < 12; ++c) acc[co][c] = {0.f, 0.f};
   const int h0 = (INPAR >= 0 && p != INPAR) ? 1 : 0;
   const int h1 = (INPAR >= 0 && p == INPAR) ? 1 : 9;
-  for (int h = h0; h < h1; ++h) {
+  if constexpr (COUT == 1 && CIN > 1) {
+    // more inputs than outputs: mix the spins first (W and the link commute:
+    // one acts on spin, the other on colour), then transport once per hop
+    for (int h = h0; h < h1; ++h) {
+      cplx<float> m[12];
 #pragma unroll
-    for (int ci = 0; ci < CIN; ++ci) {
-      cplx<float> v[12];
-      transport<PIN>(k, s, p, i, h, k.in + ci * k.in_chan, v);
+      for (int c = 0; c < 12; ++c) m[c] = {0.f, 0.f};
 #pragma unroll
-      for (int co = 0; co < COUT; ++co) spin_mat_acc(k.W + 32 * ((h * COUT + co) * CIN + ci), v, acc[co]);
+      for (int ci = 0; ci < CIN; ++ci) {
+        cplx<float> v[12];
+        load_source<PIN>(k, s, p, i, h, k.in + ci * k.in_chan, v);
+        spin_mat_acc(k.W + 32 * (h * CIN + ci), v, m);
+      }
+      if (h == 0) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[0][c] = acc[0][c] + m[c];
+      } else {
+        transport_add(k, s, p, i, h - 1, m, acc[0]);
+      }
+    }
+  } else {
+    for (int h = h0; h < h1; ++h) {
+#pragma unroll
+      for (int ci = 0; ci < CIN; ++ci) {
+        cplx<float> v[12];
+        transport<PIN>(k, s, p, i, h, k.in + ci * k.in_chan, v);
+#pragma unroll
+        for (int co = 0; co < COUT; ++co) spin_mat_acc(k.W + 32 * ((h * COUT + co) * CIN + ci), v, acc[co]);
+      }
     }
   }
 #pragma unroll
