@@ -294,7 +294,8 @@ wd_status wd_ptc_train_step(wd_ptc *n, const void *r, const void *e, int B,
  * cache_path (may be NULL): JSON-lines file keyed by (arch, kernel, precision,
  * lattice); an existing entry is used without timing unless force != 0, and
  * new results are appended.  Outputs (may be NULL): the chosen variant and
- * its time per launch in microseconds (-1 if taken from the cache).
+ * its time per launch in microseconds (the stored time when the entry was taken
+ * from the cache).
  * Synchronous. */
 wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path,
                          int force, int *block, int *groups, int *occ,
@@ -359,6 +360,15 @@ wd_status wd_solve_batch(const wd_gauge *const *gs, int n, const void *const *b,
 wd_status wd_micro_lds_copy(int device, int bytes, int offset, int reps,
                             const void *src_host, unsigned long long *cycles,
                             unsigned *sums);
+
+/* Streaming probe on device `device`: a kernel reads nread (1..8) arrays of
+ * `bytes` bytes each (16-byte lanes, one element per thread) and, with
+ * write = 1, writes their sum to one more array; nontemporal = 1 uses
+ * streaming loads and stores.  *seconds = mean time of one pass over reps
+ * passes (HIP events, after 3 warm-up passes).  The measured ceilings feed
+ * the timing model (Eqs. 1-2).  Synchronous; allocates (nread + 1) * bytes. */
+wd_status wd_micro_stream(int device, int nread, int write, int nontemporal,
+                          size_t bytes, int reps, double *seconds);
 
 /* --------------------------------------------------------------- misc --- */
 

@@ -106,6 +106,8 @@ _decl("wd_ptc_train_step", C.c_int, [_vp, _vp, _vp, C.c_int, C.c_double, C.POINT
 _decl("wd_gaussian_field", C.c_int, [_vp, _vp, C.c_int, C.c_int, C.c_ulonglong, C.c_ulonglong])
 _decl("wd_micro_lds_copy", C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, _vp, C.POINTER(C.c_ulonglong),
                                      C.POINTER(C.c_uint)])
+_decl("wd_micro_stream", C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_size_t, C.c_int,
+                                   C.POINTER(C.c_double)])
 _decl("wd_status_string", C.c_char_p, [C.c_int])
 _decl("wd_last_error", C.c_char_p, [])
 
@@ -246,6 +248,14 @@ def wd_micro_lds_copy(bytes_, offset, reps, pattern=None, device=0):
                                  None if src is None else src.ctypes.data_as(C.c_void_p), cyc, sums),
            "wd_micro_lds_copy")
     return np.array(cyc[:], dtype=np.uint64), np.array(sums[:], dtype=np.uint32)
+
+
+def wd_micro_stream(nread, write, nontemporal, bytes_, reps=20, device=0):
+    """Streaming probe; returns seconds per pass."""
+    t = C.c_double()
+    _check(lib.wd_micro_stream(int(device), int(nread), int(write), int(nontemporal), int(bytes_), int(reps),
+                               C.byref(t)), "wd_micro_stream")
+    return t.value
 
 
 def wd_spinor_unpack(g, field, canon, parity=WD_FULL, prec=None):

@@ -96,6 +96,19 @@ __global__ __launch_bounds__(BLAS_BS) void k_cdot(KBlas k) {
   }
 }
 
+// ------------------------------------------------------------ finishing sums
+__global__ __launch_bounds__(256) void k_finish_sums(const double *partials, unsigned nblocks, double *out,
+                                                     int ostride, int accumulate, const int *skip, int sstride) {
+  const int j = blockIdx.x;
+  double v[1] = {0.0};
+  for (unsigned b = threadIdx.x; b < nblocks; b += 256) v[0] += partials[(size_t)j * nblocks + b];
+  block_sum_n<1>(v);
+  if (threadIdx.x == 0 && !(skip && skip[(size_t)j * sstride])) {
+    double *d = out + (size_t)j * ostride;
+    *d = accumulate ? (*d + v[0]) : v[0];
+  }
+}
+
 // ------------------------------------------------------------ elementwise
 // out = c * x + y  (out may alias y)
 template <int P>
@@ -404,6 +417,14 @@ wd_status blas_cg_pupdate(const Geom &g, wd_prec pv, const VecRef &r, const VecR
   dim3 grid(k.nblk, (unsigned)nsys);
   WD_DISPATCH_P(pv, k_cg_pupdate, grid, k, st);
   return hip_check(hipGetLastError(), "cg_pupdate launch");
+}
+
+wd_status launch_finish_sums(const double *partials, unsigned nblocks, int n, double *out, int ostride,
+                             int accumulate, const int *skip, int sstride, hipStream_t st) {
+  if (n < 1) return WD_OK;
+  hipLaunchKernelGGL(k_finish_sums, dim3((unsigned)n), dim3(256), 0, st, partials, nblocks, out, ostride, accumulate,
+                     skip, sstride);
+  return hip_check(hipGetLastError(), "finishing sums launch");
 }
 
 }  // namespace wd

@@ -124,9 +124,8 @@ __global__ __launch_bounds__(DR_BS) void k_dirac(KDirac k) {
     }
   }
   if constexpr (NORM) {
-    double v[1] = {nrm}, tot[1];
-    if (grid_sum_last<1>(v, k.partials, k.counter, gridDim.x, blockIdx.x, tot))
-      *k.norm_out = k.norm_accumulate ? (*k.norm_out + tot[0]) : tot[0];
+    double v[1] = {nrm};
+    block_sum_store<1>(v, k.partials, gridDim.x, blockIdx.x);
   }
 }
 
@@ -180,7 +179,9 @@ wd_status launch_dirac(const wd_gauge *g, wd_prec prec, const DiracArgs &a, hipS
     default: return set_error(WD_ERR_PREC, "dirac: unknown precision %d", (int)prec);
   }
 #undef WD_DP
-  return hip_check(hipGetLastError(), "dirac launch");
+  WD_TRY(hip_check(hipGetLastError(), "dirac launch"));
+  if (norm) return launch_finish_sums(k.partials, nblk, 1, k.norm_out, 1, k.norm_accumulate, nullptr, 1, st);
+  return WD_OK;
 }
 
 }  // namespace wd

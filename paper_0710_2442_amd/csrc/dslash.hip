@@ -35,10 +35,8 @@ __device__ __forceinline__ void dslash_body(const KDslash &k) {
   const int i = tile_of(k) * (int)blockDim.x + (int)threadIdx.x;
   const double nrm = dslash_site<P, DAG, EPI, NORM, PRE>(k, i);
   if constexpr (NORM) {
-    double v[1] = {nrm}, tot[1];
-    if (grid_sum_last<1>(v, k.partials, k.counter, gridDim.x, blockIdx.x, tot)) {
-      *k.norm_out = k.norm_accumulate ? (*k.norm_out + tot[0]) : tot[0];
-    }
+    double v[1] = {nrm};
+    block_sum_store<1>(v, k.partials, gridDim.x, blockIdx.x);
   }
 }
 
@@ -112,36 +110,11 @@ __global__ __launch_bounds__(256) void k_dslash_mrhs(KMrhs m) {
     }
   }
   if constexpr (NORM) {
-    // the 16 lanes of one RHS are contiguous in a wave: reduce within them
+    // the 16 lanes of one RHS are contiguous in a wave: reduce within them;
+    // the per-RHS block partials are summed by the finishing kernel
 #pragma unroll
     for (int off = 8; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
-    const unsigned nblk = gridDim.x;
-    if (lane == 0 && rg < m.nrhs)
-      __hip_atomic_store(&m.k.partials[(size_t)rg * nblk + blockIdx.x], nrm, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    __shared__ int is_last;
-    if (threadIdx.x == 0) {
-      __threadfence();
-      const unsigned ticket = atomicAdd(m.k.counter + blockIdx.y, 1u);
-      is_last = (ticket == nblk - 1);
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-    // last block of this RHS group: 16 lanes per RHS sum its partials in order
-    double s = 0.0;
-    if (rg < m.nrhs) {
-      for (unsigned b = lane; b < nblk; b += 16)
-        s += __hip_atomic_load(&m.k.partials[(size_t)rg * nblk + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-#pragma unroll
-    for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (lane == 0 && live) {
-      double *dst = m.k.norm_out + (size_t)rg * m.norm_stride;
-      *dst = m.k.norm_accumulate ? (*dst + s) : s;
-    }
-    if (threadIdx.x == 0) __hip_atomic_store(m.k.counter + blockIdx.y, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0 && rg < m.nrhs) m.k.partials[(size_t)rg * gridDim.x + blockIdx.x] = nrm;
   }
 }
 
@@ -225,35 +198,17 @@ __global__ __launch_bounds__(256) void k_dslash_mrhs_reg(KMrhs m) {
     }
   }
   if constexpr (NORM) {
-    // per-RHS partials at partials[r * gridDim.x + block]; the last block of
-    // the chunk sums each RHS's partials in block order
+    // per-RHS partials at partials[r * gridDim.x + block], summed by the
+    // finishing kernel
     __syncthreads();
-    const unsigned nblk = gridDim.x;
-    const int nw = (int)blockDim.x >> 6;
     if (threadIdx.x == 0) {
+      const int nw = (int)blockDim.x >> 6;
       for (int r = r0; r < r1; ++r) {
         double s = 0.0;
         for (int q = 0; q < nw; ++q) s += sred[r - r0][q];
-        __hip_atomic_store(&k.partials[(size_t)r * nblk + blockIdx.x], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      __threadfence();
-    }
-    __shared__ int is_last;
-    if (threadIdx.x == 0) is_last = (atomicAdd(k.counter + blockIdx.y, 1u) == nblk - 1);
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-    for (int r = r0; r < r1; ++r) {
-      double v[1] = {0.0};
-      for (unsigned b = threadIdx.x; b < nblk; b += blockDim.x)
-        v[0] += __hip_atomic_load(&k.partials[(size_t)r * nblk + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      block_sum_n<1>(v);
-      if (threadIdx.x == 0 && !(k.skip && k.skip[(size_t)r * m.skip_stride])) {
-        double *dst = k.norm_out + (size_t)r * m.norm_stride;
-        *dst = k.norm_accumulate ? (*dst + v[0]) : v[0];
+        k.partials[(size_t)r * gridDim.x + blockIdx.x] = s;
       }
     }
-    if (threadIdx.x == 0) __hip_atomic_store(k.counter + blockIdx.y, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -357,7 +312,9 @@ wd_status launch_dslash(const wd_gauge *g, wd_prec prec, const DslashArgs &a, hi
     case WD_BF16: launch_prec<WD_BF16>(k, a.dagger, epi, norm, nblk, bs, lds, st); break;
     default: return set_error(WD_ERR_PREC, "dslash: unknown precision %d", (int)prec);
   }
-  return hip_check(hipGetLastError(), "dslash launch");
+  WD_TRY(hip_check(hipGetLastError(), "dslash launch"));
+  if (norm) return launch_finish_sums(k.partials, nblk, 1, k.norm_out, 1, k.norm_accumulate, k.skip, 1, st);
+  return WD_OK;
 }
 
 template <int P, bool DAG, int EPI, bool NORM>
@@ -430,7 +387,11 @@ wd_status launch_dslash_mrhs_ex(const wd_gauge *g, wd_prec prec, const MrhsArgs 
     case WD_BF16: launch_mrhs_p<WD_BF16>(m, a.dagger, epi, norm, grid, block, st); break;
     default: return set_error(WD_ERR_PREC, "dslash_mrhs: unknown precision %d", (int)prec);
   }
-  return hip_check(hipGetLastError(), "dslash_mrhs launch");
+  WD_TRY(hip_check(hipGetLastError(), "dslash_mrhs launch"));
+  if (norm)
+    return launch_finish_sums(m.k.partials, grid.x, a.nrhs, m.k.norm_out, m.norm_stride, m.k.norm_accumulate, m.k.skip,
+                              m.skip_stride, st);
+  return WD_OK;
 }
 
 wd_status launch_dslash_mrhs(const wd_gauge *g, wd_prec prec, const void *in, void *out, double a, int parity,

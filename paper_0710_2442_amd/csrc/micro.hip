@@ -59,11 +59,91 @@ __global__ __launch_bounds__(MC_BS) void k_lds_copy(const char *src, int bytes, 
   }
 }
 
+// Streaming probe: R read streams (and W = 0/1 write stream) of 16-byte
+// lanes, non-temporal (NT) or cached, one element per thread.
+typedef double mv2d __attribute__((ext_vector_type(2)));
+
+template <int R, int W, int NT>
+__global__ __launch_bounds__(256) void k_stream(const mv2d *const *in, mv2d *out, long n) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  mv2d s = {0.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < R; ++r) s += NT ? __builtin_nontemporal_load(in[r] + i) : in[r][i];
+  if (W) {
+    if (NT) __builtin_nontemporal_store(s, out + i);
+    else out[i] = s;
+  } else if (s.x == 1234.5678) {
+    out[i] = s;  // never true for the zero-filled inputs; keeps the loads live
+  }
+}
+
+template <int R, int W, int NT>
+void launch_stream(const mv2d *const *in, mv2d *out, long n, hipStream_t st) {
+  hipLaunchKernelGGL((k_stream<R, W, NT>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out, n);
+}
+
 }  // namespace
 
 }  // namespace wd
 
 using namespace wd;
+
+extern "C" wd_status wd_micro_stream(int device, int nread, int write, int nontemporal, size_t bytes, int reps,
+                                     double *seconds) {
+  if (nread < 1 || nread > 8) return set_error(WD_ERR_ARG, "micro stream: nread = %d (1..8)", nread);
+  if (write != 0 && write != 1) return set_error(WD_ERR_ARG, "micro stream: write = %d", write);
+  if (bytes < 16 || bytes % 16 || bytes > ((size_t)4 << 30))
+    return set_error(WD_ERR_ARG, "micro stream: bytes = %zu (16 B .. 4 GiB, multiple of 16)", bytes);
+  if (reps < 1 || reps > 1000) return set_error(WD_ERR_ARG, "micro stream: reps = %d", reps);
+  if (!seconds) return set_error(WD_ERR_ARG, "micro stream: NULL output");
+  WD_HIP(hipSetDevice(device));
+  const long n = (long)(bytes / 16);
+  void *buf[9] = {nullptr};
+  mv2d **d_in = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  wd_status rc = WD_OK;
+  do {
+    for (int r = 0; r <= nread; ++r) {
+      if ((rc = hip_check(hipMalloc(&buf[r], bytes), "micro alloc")) != WD_OK) break;
+      if ((rc = hip_check(hipMemset(buf[r], 0, bytes), "micro fill")) != WD_OK) break;
+    }
+    if (rc != WD_OK) break;
+    if ((rc = hip_check(hipMalloc(&d_in, 8 * sizeof(mv2d *)), "micro alloc")) != WD_OK) break;
+    mv2d *h_in[8] = {nullptr};
+    for (int r = 0; r < nread; ++r) h_in[r] = (mv2d *)buf[r];
+    if ((rc = hip_check(hipMemcpy(d_in, h_in, sizeof h_in, hipMemcpyHostToDevice), "micro upload")) != WD_OK) break;
+    mv2d *out = (mv2d *)buf[nread];
+    auto run = [&]() {
+#define WD_ST(RR)                                                                              \
+  if (nread == RR) {                                                                           \
+    if (write && nontemporal) launch_stream<RR, 1, 1>(d_in, out, n, 0);                        \
+    else if (write) launch_stream<RR, 1, 0>(d_in, out, n, 0);                                  \
+    else if (nontemporal) launch_stream<RR, 0, 1>(d_in, out, n, 0);                            \
+    else launch_stream<RR, 0, 0>(d_in, out, n, 0);                                             \
+  }
+      WD_ST(1) WD_ST(2) WD_ST(3) WD_ST(4) WD_ST(5) WD_ST(6) WD_ST(7) WD_ST(8)
+#undef WD_ST
+    };
+    for (int w = 0; w < 3; ++w) run();
+    if ((rc = hip_check(hipEventCreate(&e0), "event")) != WD_OK) break;
+    if ((rc = hip_check(hipEventCreate(&e1), "event")) != WD_OK) break;
+    WD_HIP(hipEventRecord(e0, 0));
+    for (int r = 0; r < reps; ++r) run();
+    WD_HIP(hipEventRecord(e1, 0));
+    if ((rc = hip_check(hipEventSynchronize(e1), "micro timing")) != WD_OK) break;
+    float ms = 0.f;
+    WD_HIP(hipEventElapsedTime(&ms, e0, e1));
+    *seconds = 1e-3 * ms / reps;
+    rc = hip_check(hipGetLastError(), "micro launch");
+  } while (0);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  for (void *b : buf)
+    if (b) (void)hipFree(b);
+  if (d_in) (void)hipFree(d_in);
+  return rc;
+}
 
 extern "C" wd_status wd_micro_lds_copy(int device, int bytes, int offset, int reps, const void *src_host,
                                        unsigned long long *cycles, unsigned *sums) {

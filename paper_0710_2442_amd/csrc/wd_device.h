@@ -462,6 +462,20 @@ __device__ __forceinline__ void block_sum_n(double (&v)[N]) {
   __syncthreads();
 }
 
+// Block sums of v (fixed order) stored as this block's partials,
+// partials[j * nblocks + bid]; a finishing kernel (launch_finish_sums) adds
+// them up after the launch.  No atomics and no fences: the kernel boundary
+// makes the stores visible.  Used where a launch has many blocks, for which
+// the last-block scheme below serialises on its counter.
+template <int N>
+__device__ __forceinline__ void block_sum_store(double (&v)[N], double *partials, unsigned nblocks, unsigned bid) {
+  block_sum_n<N>(v);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) partials[(size_t)j * nblocks + bid] = v[j];
+  }
+}
+
 // Grid-wide sum: every block stores its partial(s); the block that arrives
 // last adds all partials in index order (deterministic whichever block that
 // is), writes the totals and re-arms the counter.  Returns true in thread 0 of

@@ -145,6 +145,11 @@ struct DiracArgs {
 };
 unsigned dirac_grid_blocks(const wd_gauge *g);
 wd_status launch_dirac(const wd_gauge *g, wd_prec prec, const DiracArgs &args, hipStream_t st);
+// out[j * ostride] = (accumulate ? out[j * ostride] : 0) + sum over b of
+// partials[j * nblocks + b], for j < n, in block order (one workgroup per j);
+// entries whose skip[j * sstride] is set are left alone (blas.hip).
+wd_status launch_finish_sums(const double *partials, unsigned nblocks, int n, double *out, int ostride,
+                             int accumulate, const int *skip, int sstride, hipStream_t st);
 unsigned dslash_grid_blocks(const wd_gauge *g);
 bool dslash_variant_ok(const Geom &G, int bs, int groups);
 // grid.x of the multi-RHS hop (16 sites per block)

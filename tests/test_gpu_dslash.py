@@ -7,6 +7,9 @@ the same rounded inputs; the bar is set by the rounding of the stored output
 (FP16: 1e-3, about 4x the RMS rounding error of 2^-11-ulp components;
 BF16: 2^-8).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -239,6 +242,14 @@ def test_full_size_sampled_sites(big, prec):
     dims, U, psi = big
     print(f"case: 32^3x64 sampled prec={prec}", flush=True)
     g = wd.Gauge(U, dims, -1, prec)
+    # the committed tuning table is what the benchmark loads: same variant here
+    table = os.path.join(os.path.dirname(wd.__file__), "tuned", "mi355x_hop.jsonl")
+    key = "gfx950/hop/p%d/32x32x32x64" % {"f64": 0, "f32": 1}[prec]
+    entries = [json.loads(line) for line in open(table) if line.strip()]
+    want = [e for e in entries if e["key"] == key][-1]
+    b, gr, oc, us = wd.wd_tune_dslash(g, prec, table)
+    assert (b, gr, oc) == (want["block"], want["groups"], want["occ"])
+    assert wd.wd_get_dslash_variant(g, prec) == (b, gr, oc)
     rng = np.random.default_rng(3)
     for parity in (0, 1):
         src = to_field(g, psi, prec, 1 - parity)
