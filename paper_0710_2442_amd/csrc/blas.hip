@@ -97,11 +97,13 @@ __global__ __launch_bounds__(BLAS_BS) void k_cdot(KBlas k) {
 }
 
 // ------------------------------------------------------------ finishing sums
-__global__ __launch_bounds__(256) void k_finish_sums(const double *partials, unsigned nblocks, double *out,
-                                                     int ostride, int accumulate, const int *skip, int sstride) {
+constexpr int FIN_BS = 1024;
+
+__global__ __launch_bounds__(FIN_BS) void k_finish_sums(const double *partials, unsigned nblocks, double *out,
+                                                        int ostride, int accumulate, const int *skip, int sstride) {
   const int j = blockIdx.x;
   double v[1] = {0.0};
-  for (unsigned b = threadIdx.x; b < nblocks; b += 256) v[0] += partials[(size_t)j * nblocks + b];
+  for (unsigned b = threadIdx.x; b < nblocks; b += FIN_BS) v[0] += partials[(size_t)j * nblocks + b];
   block_sum_n<1>(v);
   if (threadIdx.x == 0 && !(skip && skip[(size_t)j * sstride])) {
     double *d = out + (size_t)j * ostride;
@@ -238,11 +240,23 @@ __global__ __launch_bounds__(BLAS_BS) void k_cg_update(KBlas k) {
       for (int c = 0; c < 12; ++c) acc += (double)r[c].re * r[c].re + (double)r[c].im * r[c].im;
     }
   }
-  double v[1] = {acc}, tot[1];
-  if (grid_sum_last<1>(v, k.partials + (size_t)sys * k.nblk, k.counter + sys, k.nblk, blockIdx.x, tot)) {
-    sc->ss = tot[0];
+  double v[1] = {acc};
+  block_sum_store<1>(v, k.partials + (size_t)sys * k.nblk, k.nblk, blockIdx.x);
+}
+
+// Second stage of the CG update: ss = sum of the block partials (block
+// order), iteration count and convergence flags.  Systems that were done, or
+// broke down in the update, are left alone.
+__global__ __launch_bounds__(FIN_BS) void k_cg_update_finish(const double *partials, unsigned nblk, CgScalars *scs) {
+  CgScalars *sc = scs + blockIdx.x;
+  if (sc->done) return;
+  double v[1] = {0.0};
+  for (unsigned b = threadIdx.x; b < nblk; b += FIN_BS) v[0] += partials[(size_t)blockIdx.x * nblk + b];
+  block_sum_n<1>(v);
+  if (threadIdx.x == 0) {
+    sc->ss = v[0];
     sc->iters += 1;
-    if (tot[0] <= sc->stop2) sc->done = 1;
+    if (v[0] <= sc->stop2) sc->done = 1;
     else if (sc->iters >= sc->max_iters) sc->done = 3;
   }
 }
@@ -403,7 +417,10 @@ wd_status blas_cg_update(const Geom &g, wd_prec px, const VecRef &x, wd_prec pv,
   dim3 grid(k.nblk, (unsigned)nsys);
   if (px == WD_F64) launch_cgu<WD_F64>(pv, grid, k, st);
   else launch_cgu<WD_F32>(pv, grid, k, st);
-  return hip_check(hipGetLastError(), "cg_update launch");
+  WD_TRY(hip_check(hipGetLastError(), "cg_update launch"));
+  hipLaunchKernelGGL(k_cg_update_finish, dim3((unsigned)nsys), dim3(FIN_BS), 0, st, (const double *)k.partials, k.nblk,
+                     sc);
+  return hip_check(hipGetLastError(), "cg_update finish launch");
 }
 
 wd_status blas_cg_pupdate(const Geom &g, wd_prec pv, const VecRef &r, const VecRef &p, CgScalars *sc, int j,
@@ -422,8 +439,8 @@ wd_status blas_cg_pupdate(const Geom &g, wd_prec pv, const VecRef &r, const VecR
 wd_status launch_finish_sums(const double *partials, unsigned nblocks, int n, double *out, int ostride,
                              int accumulate, const int *skip, int sstride, hipStream_t st) {
   if (n < 1) return WD_OK;
-  hipLaunchKernelGGL(k_finish_sums, dim3((unsigned)n), dim3(256), 0, st, partials, nblocks, out, ostride, accumulate,
-                     skip, sstride);
+  hipLaunchKernelGGL(k_finish_sums, dim3((unsigned)n), dim3(FIN_BS), 0, st, partials, nblocks, out, ostride,
+                     accumulate, skip, sstride);
   return hip_check(hipGetLastError(), "finishing sums launch");
 }
 

@@ -299,11 +299,7 @@ __global__ __launch_bounds__(FG_BS) void k_fg_dots(KFg a) {
       site_dot(v, w, acc[2 * j], acc[2 * j + 1]);
     }
   }
-  double tot[2 * K];
-  if (grid_sum_last<2 * K>(acc, a.partials, a.counter, a.nblk, blockIdx.x, tot)) {
-#pragma unroll
-    for (int j = 0; j < 2 * K; ++j) a.dots[j] = tot[j];
-  }
+  block_sum_store<2 * K>(acc, a.partials, a.nblk, blockIdx.x);
 }
 
 template <int K>
@@ -341,12 +337,7 @@ __global__ __launch_bounds__(FG_BS) void k_fg_orth(KFg a) {
     for (int q = 0; q < 12; ++q) acc[0] += (double)w[q].re * w[q].re + (double)w[q].im * w[q].im;
     site_dot(w, r, acc[1], acc[2]);
   }
-  double tot[3];
-  if (grid_sum_last<3>(acc, a.partials, a.counter, a.nblk, blockIdx.x, tot)) {
-    a.sig[a.k] = tot[0];
-    a.rho[0] = tot[1];
-    a.rho[1] = tot[2];
-  }
+  block_sum_store<3>(acc, a.partials, a.nblk, blockIdx.x);
 }
 
 __global__ __launch_bounds__(FG_BS) void k_fg_step(KFg a) {
@@ -371,8 +362,22 @@ __global__ __launch_bounds__(FG_BS) void k_fg_step(KFg a) {
     }
     F4::store<false>(a.r, i, r);
   }
-  double tot[1];
-  if (grid_sum_last<1>(acc, a.partials, a.counter, a.nblk, blockIdx.x, tot)) *a.rr = tot[0];
+  block_sum_store<1>(acc, a.partials, a.nblk, blockIdx.x);
+}
+
+// Second stage of the three kernels above: value j = sum of the block
+// partials (block order) goes to dst[j] (dots, or rr), or for the
+// orthogonalisation to sig[k] (j = 0) and rho (j = 1, 2).
+constexpr int FG_FIN = 1024;
+__global__ __launch_bounds__(FG_FIN) void k_fg_finish(KFg a, int which) {
+  const int j = blockIdx.x;
+  double v[1] = {0.0};
+  for (unsigned b = threadIdx.x; b < a.nblk; b += FG_FIN) v[0] += a.partials[(size_t)j * a.nblk + b];
+  block_sum_n<1>(v);
+  if (threadIdx.x != 0) return;
+  if (which == 0) a.dots[j] = v[0];
+  else if (which == 1) (j == 0 ? a.sig[a.k] : a.rho[j - 1]) = v[0];
+  else *a.rr = v[0];
 }
 
 template <int K>
@@ -532,9 +537,14 @@ wd_status solve_fgcr_mixed(wd_gauge *g, const void *b, void *x, double kappa, do
       a.wk = wk;
       a.zk = zk;
       a.k = k;
-      if (k > 0) launch_dots(a, k, st, std::make_integer_sequence<int, FG_MMAX - 1>{});
+      if (k > 0) {
+        launch_dots(a, k, st, std::make_integer_sequence<int, FG_MMAX - 1>{});
+        hipLaunchKernelGGL(k_fg_finish, dim3(2 * k), dim3(FG_FIN), 0, st, a, 0);
+      }
       launch_orth(a, k, st, std::make_integer_sequence<int, FG_MMAX>{});
+      hipLaunchKernelGGL(k_fg_finish, dim3(3), dim3(FG_FIN), 0, st, a, 1);
       hipLaunchKernelGGL(k_fg_step, dim3(a.nblk), dim3(FG_BS), 0, st, a);
+      hipLaunchKernelGGL(k_fg_finish, dim3(1), dim3(FG_FIN), 0, st, a, 2);
       WD_TRY(hip_check(hipGetLastError(), "fgcr launch"));
       WD_TRY(read(a.rr, 1, &rr));
       ++it;
