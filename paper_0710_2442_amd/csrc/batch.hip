@@ -5,10 +5,10 @@
 // workgroups walks the list; each tile reads its lattice's descriptor
 // (geometry, links, vector pointers, kappa, CG scalars), so lattices of any
 // size share every launch.  Reductions are segmented by lattice: each tile
-// stores its block partial, and the tile that completes a lattice (per-lattice
-// arrival counter) sums that lattice's partials in tile order, so results do
-// not depend on scheduling.  A lattice whose CG has converged is masked: its
-// tiles are skipped.  One pair of CG iterations over the whole batch is
+// stores its block partial, and a finishing kernel (one workgroup per
+// lattice) sums that lattice's partials in tile order, so results do not
+// depend on scheduling and no block waits on a shared counter.  A lattice
+// whose CG has converged is masked: its tiles are skipped.  One pair of CG iterations over the whole batch is
 // captured in a hipGraph and replayed; the host polls the per-lattice flags
 // every few replays.  Outer loop: FP64 defect correction per lattice (true
 // residual, solution accumulation and norms in FP64; inner CG in FP32
@@ -65,41 +65,17 @@ struct KBatch {
   double scale;
   int use_mask;         // skip lattices whose CG is done
   double *partials;     // per work item
-  unsigned *counter;    // per lattice
 };
 
 __device__ __forceinline__ char *vec_ptr(const LatDesc &d, Opnd o, int P) {
   return d.vec[o.slot] + (size_t)o.half * dev_half_bytes(d.g.vpad, P);
 }
 
-// Segmented sum: partial of work item w of lattice l (nitems items per
-// lattice, stored at item indices listed by item_of(k) for k < nitems).
-template <class ItemOf>
-__device__ __forceinline__ void seg_sum(double v, int w, int l, int nitems, ItemOf item_of, double *partials,
-                                        unsigned *counter, double *dst, int accumulate) {
+// Block partial of work item w (summed per lattice by k_batch_finish).
+__device__ __forceinline__ void seg_store(double v, int w, double *partials) {
   double x[1] = {v};
   block_sum_n<1>(x);
-  __shared__ int last;
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(&partials[w], x[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    const unsigned ticket = atomicAdd(&counter[l], 1u);
-    last = (ticket == (unsigned)nitems - 1u);
-  }
-  __syncthreads();
-  if (last) {
-    __threadfence();
-    double s = 0.0;
-    for (int q = threadIdx.x; q < nitems; q += blockDim.x)
-      s += __hip_atomic_load(&partials[item_of(q)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    double y[1] = {s};
-    block_sum_n<1>(y);
-    if (threadIdx.x == 0) {
-      *dst = accumulate ? (*dst + y[0]) : y[0];
-      __hip_atomic_store(&counter[l], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
-  __syncthreads();
+  if (threadIdx.x == 0) partials[w] = x[0];
 }
 
 // ------------------------------------------------------------------ hop
@@ -121,11 +97,7 @@ __global__ __launch_bounds__(BT) void k_batch_hop(KBatch a) {
     k.nt_store = 1;
     const int i = (t - d.tile0) * BT + (int)threadIdx.x;
     const double nrm = dslash_site<P, DAG, EPI, NORM>(k, i);
-    if constexpr (NORM) {
-      const int t0 = d.tile0;
-      seg_sum(nrm, t, l, d.ntiles, [t0](int q) { return t0 + q; }, a.partials, a.counter,
-              (double *)d.sc + a.norm_field, a.norm_accumulate);
-    }
+    if constexpr (NORM) seg_store(nrm, t, a.partials);
   }
 }
 
@@ -175,10 +147,9 @@ __global__ __launch_bounds__(BT) void k_batch_elem(KBatch a) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) acc += (double)s[c].re * s[c].re + (double)s[c].im * s[c].im;
       }
-      // every tile of the lattice joins the sum (the arrival count must be
-      // complete); flags are decided afterwards by k_batch_flags
-      const int t0 = d.tile0;
-      seg_sum(acc, t, l, d.ntiles, [t0](int q) { return t0 + q; }, a.partials, a.counter, &sc->ss, 0);
+      // every tile of the lattice stores a partial; the sum and then the
+      // flags (k_batch_flags) follow in their own launches
+      seg_store(acc, t, a.partials);
     } else if constexpr (OP == OP_PUP) {
       if (i < d.g.vh) {
         const TB beta = (TB)(sc->rr[1 - a.j] / sc->rr[a.j]);
@@ -231,11 +202,29 @@ __global__ __launch_bounds__(BT) void k_batch_elem(KBatch a) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) acc += (double)x[c].re * x[c].re + (double)x[c].im * x[c].im;
       }
-      const int t0 = d.tile0, nt = d.ntiles, NT = a.ntiles;
-      seg_sum(acc, w, l, nt * a.nhalf, [t0, nt, NT](int q) { return (q / nt) * NT + t0 + (q % nt); }, a.partials,
-              a.counter, (double *)sc + a.norm_field, 0);
+      seg_store(acc, w, a.partials);
     }
   }
+}
+
+// Per-lattice sums of the block partials, in work-item order (one workgroup
+// per lattice).  mode 0: hop norm (items = the lattice's tiles) into
+// sc[norm_field] (+= with norm_accumulate); 1: CG update, |s|^2 into ss;
+// 2: norm over nhalf halves (items h * ntiles + tile) into sc[norm_field].
+// Masked lattices (done) stored no partials and are left alone.
+__global__ __launch_bounds__(BT) void k_batch_finish(KBatch a, int mode) {
+  const int l = blockIdx.x;
+  const LatDesc &d = a.desc[l];
+  CgScalars *sc = d.sc;
+  if (a.use_mask && sc->done) return;
+  const int t0 = d.tile0, nt = d.ntiles, NT = a.ntiles;
+  const int nitems = (mode == 2) ? nt * a.nhalf : nt;
+  double v[1] = {0.0};
+  for (int q = threadIdx.x; q < nitems; q += BT) v[0] += a.partials[(q / nt) * NT + t0 + (q % nt)];
+  block_sum_n<1>(v);
+  if (threadIdx.x != 0) return;
+  double *dst = (mode == 1) ? &sc->ss : (double *)sc + a.norm_field;
+  *dst = (mode == 0 && a.norm_accumulate) ? (*dst + v[0]) : v[0];
 }
 
 // Convergence flags after a CG update: one thread per lattice.  Breakdown
@@ -265,7 +254,6 @@ struct BatchRun {
   CgScalars *d_sc = nullptr;
   CgScalars *h_sc = nullptr;  // pinned
   double *partials = nullptr;
-  unsigned *counter = nullptr;
   void *vecmem = nullptr;
   std::vector<LatDesc> desc;
   hipStream_t st;
@@ -276,7 +264,6 @@ struct BatchRun {
     if (d_sc) (void)hipFree(d_sc);
     if (h_sc) (void)hipHostFree(h_sc);
     if (partials) (void)hipFree(partials);
-    if (counter) (void)hipFree(counter);
     if (vecmem) (void)hipFree(vecmem);
   }
 };
@@ -289,7 +276,6 @@ static KBatch kb(const BatchRun &R) {
   a.in = a.out = a.X = a.Y = Opnd{-1, 0};
   a.norm_field = -1;
   a.partials = R.partials;
-  a.counter = R.counter;
   a.nhalf = 1;
   a.use_mask = 1;
   return a;
@@ -314,6 +300,7 @@ static void hop_any(const BatchRun &R, wd_prec P, const KBatch &a, bool dag, int
     case WD_F16: hop_launch<WD_F16>(R, a, dag, epi, norm); break;
     case WD_BF16: hop_launch<WD_BF16>(R, a, dag, epi, norm); break;
   }
+  if (norm) hipLaunchKernelGGL(k_batch_finish, dim3((unsigned)R.n), dim3(BT), 0, R.st, a, 0);
 }
 
 template <int OP, int PA>
@@ -335,6 +322,8 @@ static void elem(const BatchRun &R, const KBatch &a, wd_prec pa, wd_prec pb) {
     case WD_F16: elem_pb<OP, WD_F16>(R, a, pb); break;
     case WD_BF16: elem_pb<OP, WD_BF16>(R, a, pb); break;
   }
+  if (OP == OP_CGU || OP == OP_NORM)
+    hipLaunchKernelGGL(k_batch_finish, dim3((unsigned)R.n), dim3(BT), 0, R.st, a, OP == OP_CGU ? 1 : 2);
 }
 
 // one CG iteration of every unconverged lattice (CGLS on the Schur operator)
@@ -411,8 +400,6 @@ wd_status solve_batch(const wd_gauge *const *gs, int n, const void *const *b, vo
   WD_HIP(hipMalloc(&R.d_sc, sizeof(CgScalars) * n));
   WD_HIP(hipHostMalloc((void **)&R.h_sc, sizeof(CgScalars) * n, hipHostMallocDefault));
   WD_HIP(hipMalloc(&R.partials, sizeof(double) * 2 * R.ntiles));
-  WD_HIP(hipMalloc(&R.counter, sizeof(unsigned) * n));
-  WD_HIP(hipMemsetAsync(R.counter, 0, sizeof(unsigned) * n, R.st));
   for (int l = 0; l < n; ++l) {
     LatDesc &d = R.desc[l];
     const Geom &G = d.g;
