@@ -63,9 +63,8 @@ __global__ __launch_bounds__(BLAS_BS) void k_norm2(KBlas k) {
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc += (double)a[c].re * a[c].re + (double)a[c].im * a[c].im;
   }
-  double v[1] = {acc}, tot[1];
-  if (grid_sum_last<1>(v, k.partials + (size_t)sys * k.nblk, k.counter + sys, k.nblk, blockIdx.x, tot))
-    k.result[sys] = tot[0];
+  double v[1] = {acc};
+  block_sum_store<1>(v, k.partials + (size_t)sys * k.nblk, k.nblk, blockIdx.x);
 }
 
 template <int P>
@@ -88,12 +87,8 @@ __global__ __launch_bounds__(BLAS_BS) void k_cdot(KBlas k) {
       im += (double)a[c].re * b[c].im - (double)a[c].im * b[c].re;
     }
   }
-  double v[2] = {re, im}, tot[2];
-  if (grid_sum_last<2>(v, k.partials + (size_t)sys * 2 * k.nblk, k.counter + sys, k.nblk, blockIdx.x,
-                                tot)) {
-    k.result[2 * sys] = tot[0];
-    k.result[2 * sys + 1] = tot[1];
-  }
+  double v[2] = {re, im};
+  block_sum_store<2>(v, k.partials + (size_t)sys * 2 * k.nblk, k.nblk, blockIdx.x);
 }
 
 // ------------------------------------------------------------ finishing sums
@@ -317,7 +312,8 @@ wd_status blas_norm2(const Geom &g, wd_prec prec, const VecRef &x, int nsys, Red
   k.partials = red.partials; k.counter = red.counter; k.result = result;
   dim3 grid(k.nblk, (unsigned)nsys);
   WD_DISPATCH_P(prec, k_norm2, grid, k, st);
-  return hip_check(hipGetLastError(), "norm2 launch");
+  WD_TRY(hip_check(hipGetLastError(), "norm2 launch"));
+  return launch_finish_sums(red.partials, k.nblk, nsys, result, 1, 0, nullptr, 1, st);
 }
 
 wd_status blas_cdot(const Geom &g, wd_prec prec, const VecRef &x, const VecRef &y, int nsys, RedBuf red,
@@ -330,7 +326,8 @@ wd_status blas_cdot(const Geom &g, wd_prec prec, const VecRef &x, const VecRef &
   k.partials = red.partials; k.counter = red.counter; k.result = result;
   dim3 grid(k.nblk, (unsigned)nsys);
   WD_DISPATCH_P(prec, k_cdot, grid, k, st);
-  return hip_check(hipGetLastError(), "cdot launch");
+  WD_TRY(hip_check(hipGetLastError(), "cdot launch"));
+  return launch_finish_sums(red.partials, k.nblk, 2 * nsys, result, 1, 0, nullptr, 1, st);
 }
 
 wd_status blas_caxpy(const Geom &g, wd_prec prec, double cre, double cim, const VecRef &x, const VecRef &y,
