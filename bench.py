@@ -164,7 +164,7 @@ def mrhs_leg(wd, torch, syn):
     B = torch.cat([canon_to_field(g, syn.point_source(dims, s, c), "f64") for s in range(4) for c in range(3)])
     X = wd.wd_new_field(dims, "f64", 12)
     out = {}
-    for prec in ("f32", "f64"):
+    for prec in ("f32", "bf16", "f64"):
         tb, tg, tr, tus = wd.wd_tune_dslash_mrhs(g, prec, 12)
         log(f"tuned mrhs hop {prec}: block {tb}, groups {tg}, rhs per lane {tr} ({tus:.1f} us)")
     for prec in ("f32", "f64"):
@@ -178,9 +178,11 @@ def mrhs_leg(wd, torch, syn):
         torch.cuda.synchronize()
         return time.perf_counter() - t, r
 
-    sec, (rc, infos) = timed(lambda: wd.wd_solve_mrhs(g, B, X, 12, kappa, tol, _defect(wd, "f32")))
-    out["mrhs12_defect_f32"] = {"seconds": round(sec, 4), "max_resid": max(i["true_rel_resid"] for i in infos),
-                                "iters": max(i["iters"] for i in infos), "status": rc}
+    for prec, tin in (("f32", 1e-3), ("bf16", 1e-2)):
+        sec, (rc, infos) = timed(lambda: wd.wd_solve_mrhs(g, B, X, 12, kappa, tol, _defect(wd, prec, tin)))
+        out[f"mrhs12_defect_{prec}"] = {"seconds": round(sec, 4),
+                                        "max_resid": max(i["true_rel_resid"] for i in infos),
+                                        "iters": max(i["iters"] for i in infos), "status": rc}
 
     def seq(params):
         res = []
@@ -197,24 +199,28 @@ def mrhs_leg(wd, torch, syn):
     base = out["sequential12_fp64_cg"]["seconds"]
     for k in out:
         out[k]["speedup_vs_fp64_cg"] = round(base / out[k]["seconds"], 3)
-    # multi-RHS hop throughput (FP32, 12 RHS): 48 spinor reals + 96/12 link reals per site per RHS
+    # multi-RHS hop throughput, 12 RHS, per site per RHS: in + out spinor
+    # (2 x 96 B FP32, 2 x 48 B BF16) + 96/12 FP32 link reals
     vh = int(np.prod(dims)) // 2
-    src = wd.wd_new_field(dims, "f32", 12, wd.WD_ODD)
-    dst = wd.wd_new_field(dims, "f32", 12, wd.WD_EVEN)
-    src.zero_()
-    for _ in range(3):
-        wd.wd_dslash_mrhs(g, src, dst, 1.0, wd.WD_EVEN, "f32", 12)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(20):
-        wd.wd_dslash_mrhs(g, src, dst, 1.0, wd.WD_EVEN, "f32", 12)
-    e1.record()
-    torch.cuda.synchronize()
-    us = e0.elapsed_time(e1) * 1e3 / 20
-    out["mrhs12_hop_f32"] = {"us_per_launch": round(us, 2),
-                             "algorithmic_GBps": round(vh * 12 * 56 * 4 / (us * 1e-6) / 1e9, 1),
-                             "site_rhs_per_s": round(vh * 12 / (us * 1e-6), 0)}
+    for prec, spin_b in (("f32", 96), ("bf16", 48)):
+        src = wd.wd_new_field(dims, prec, 12, wd.WD_ODD)
+        dst = wd.wd_new_field(dims, prec, 12, wd.WD_EVEN)
+        src.zero_()
+        for _ in range(3):
+            wd.wd_dslash_mrhs(g, src, dst, 1.0, wd.WD_EVEN, prec, 12)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            wd.wd_dslash_mrhs(g, src, dst, 1.0, wd.WD_EVEN, prec, 12)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / 20
+        per = 2 * spin_b + 96 * 4 // 12
+        out[f"mrhs12_hop_{prec}"] = {"us_per_launch": round(us, 2), "bytes_per_site_rhs": per,
+                                     "algorithmic_GBps": round(vh * 12 * per / (us * 1e-6) / 1e9, 1),
+                                     "site_rhs_per_s": round(vh * 12 / (us * 1e-6), 0)}
+        del src, dst
     g.close()
     return out
 
