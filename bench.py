@@ -360,6 +360,27 @@ def kernels_leg(wd, torch, syn, U, psi):
     t2 = ev_time(lambda: wd.wd_dslash(g, x, z, 0.124, DIMS, wd.WD_FULL))
     out["dirac_full_f64_two_pass"] = {"us": round(t2 * 1e6, 2), "GBps": round(V * 1344 / t2 / 1e9, 1),
                                       "bytes_per_site": 1344, "one_launch_speedup": round(t2 / t, 3)}
+    # one rank's share of an 8-way time decomposition (32^3 x 8 slab): the slab hop, with its two
+    # time faces read from packed face buffers, and the face packing (what a GPU would send)
+    R, nt = 8, DIMS[3] // 8
+    vs = V // DIMS[3] // 2
+    sb = nt * vs * 192
+    fb = wd.wd_halo_face_bytes(DIMS, "f64")
+    xin = wd.wd_new_field(DIMS, "f64", 1, wd.WD_ODD)
+    wd.wd_convert(g, x[V // 2 * 192:], "f64", xin, "f64", 1, 1.0)
+    slab_out = torch.empty(sb, dtype=torch.uint8, device="cuda")
+    faces = [torch.empty(fb, dtype=torch.uint8, device="cuda") for _ in range(2)]
+    r = 3
+    slab_in = xin[r * sb:(r + 1) * sb]
+    tp = ev_time(lambda: (wd.wd_halo_pack(g, slab_in, nt, 0, 0, "f64", faces[0]),
+                          wd.wd_halo_pack(g, slab_in, nt, 1, 0, "f64", faces[1])))
+    ts = ev_time(lambda: wd.wd_dslash_slab(g, slab_in, faces[1], faces[0], slab_out, 1.0, 0, r * nt, nt, 0, "f64"))
+    out["slab_32x32x32x8_of_8_f64"] = {"hop_us": round(ts * 1e6, 2),
+                                      "hop_GBps": round(nt * vs * 1152 / ts / 1e9, 1),
+                                      "pack_two_faces_us": round(tp * 1e6, 2),
+                                      "face_bytes": fb, "faces_per_hop": 2,
+                                      "xgmi_us_at_153GBps_per_link": round(fb / 153e9 * 1e6, 2)}
+    del xin, slab_out, faces
     # the PTC network (FP32 fields, BF16 activations), one application on the full lattice
     net = wd.Ptc(g, learn.init_weights(1), "bf16")
     r32 = wd.wd_new_field(DIMS, "f32")

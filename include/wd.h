@@ -185,6 +185,37 @@ wd_status wd_gaussian_field(const wd_gauge *g, void *field, int parity,
                             wd_prec prec, unsigned long long seed,
                             unsigned long long stream);
 
+/* ---------------------------------------- time-slab decomposition (one GPU's share) -- */
+/* A rank of a decomposition along x4 owns slices [t0, t0 + nt).  Its slab
+ * field of one parity holds those slices only: checkerboard sites
+ * [t0 S, (t0 + nt) S) of the half field, S = L1 L2 L3 / 2 (required to be a
+ * multiple of 64, so a slab is a chunk-aligned part of a half field and a
+ * pointer to byte t0 * S * (bytes per site) of a full-lattice half field is
+ * a valid slab).  The time neighbours of the slab's first and last slices
+ * arrive as face buffers of S projected half spinors (6 complex numbers per
+ * site: wd_halo_face_bytes), the message a GPU would send over xGMI.  Hop
+ * links come from the gauge handle of the whole lattice; since every site
+ * stores its own backward links, a rank needs no links from its neighbours.
+ * FP64 and FP32 only. */
+size_t wd_halo_face_bytes(const int dims[4], wd_prec prec);
+
+/* Pack the face a neighbour needs from an input-parity slab of nt slices:
+ * face 0 = the slab's first slice (for the rank below), 1 = its last slice
+ * (for the rank above); dagger selects the half spinor that the D_W^dag hop
+ * projects to.  Asynchronous on the handle's stream. */
+wd_status wd_halo_pack(const wd_gauge *U, const void *in_slab, int nt, int face,
+                       int dagger, wd_prec prec, void *face_buf);
+
+/* out_slab = a H_{p,1-p} in on the output-parity sites of slices
+ * [t0, t0 + nt): in_slab is the input-parity slab of the same slices,
+ * face_lo the packed face 1 of the rank below (slice t0 - 1) and face_hi the
+ * packed face 0 of the rank above (slice t0 + nt), periodic in rank order;
+ * the time-boundary sign applies at the lattice's own edge.  Same arithmetic
+ * as wd_dslash, so a set of slabs reproduces it bit for bit.  Asynchronous. */
+wd_status wd_dslash_slab(const wd_gauge *U, const void *in_slab, const void *face_lo,
+                         const void *face_hi, void *out_slab, double a, int parity,
+                         int t0, int nt, int dagger, wd_prec prec);
+
 /* --------------------------------------------------------------- solve -- */
 
 /* WD_SOLVER_CG        : FP64 even-odd CGLS (CG on the normal equations).

@@ -108,6 +108,9 @@ _decl("wd_micro_lds_copy", C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, _vp, C.
                                      C.POINTER(C.c_uint)])
 _decl("wd_micro_stream", C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_size_t, C.c_int,
                                    C.POINTER(C.c_double)])
+_decl("wd_halo_face_bytes", C.c_size_t, [_int4, C.c_int])
+_decl("wd_halo_pack", C.c_int, [_vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, _vp])
+_decl("wd_dslash_slab", C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int])
 _decl("wd_status_string", C.c_char_p, [C.c_int])
 _decl("wd_last_error", C.c_char_p, [])
 
@@ -256,6 +259,22 @@ def wd_micro_stream(nread, write, nontemporal, bytes_, reps=20, device=0):
     _check(lib.wd_micro_stream(int(device), int(nread), int(write), int(nontemporal), int(bytes_), int(reps),
                                C.byref(t)), "wd_micro_stream")
     return t.value
+
+
+def wd_halo_face_bytes(dims, prec):
+    return int(lib.wd_halo_face_bytes(_dims(dims), _prec(prec)))
+
+
+def wd_halo_pack(g, in_slab, nt, face, dagger, prec, face_buf):
+    g.sync_stream()
+    _check(lib.wd_halo_pack(g.handle, _ptr(in_slab), int(nt), int(face), int(dagger), _prec(prec), _ptr(face_buf)),
+           "wd_halo_pack")
+
+
+def wd_dslash_slab(g, in_slab, face_lo, face_hi, out_slab, a, parity, t0, nt, dagger, prec):
+    g.sync_stream()
+    _check(lib.wd_dslash_slab(g.handle, _ptr(in_slab), _ptr(face_lo), _ptr(face_hi), _ptr(out_slab), float(a),
+                              int(parity), int(t0), int(nt), int(dagger), _prec(prec)), "wd_dslash_slab")
 
 
 def wd_spinor_unpack(g, field, canon, parity=WD_FULL, prec=None):

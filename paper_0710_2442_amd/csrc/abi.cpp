@@ -192,6 +192,40 @@ wd_status wd_gaussian_field(const wd_gauge *g, void *field, int parity, wd_prec 
   return launch_gaussian(g, field, parity, prec, seed, stream, g->stream);
 }
 
+size_t wd_halo_face_bytes(const int dims[4], wd_prec prec) {
+  if (!dims || (prec != WD_F64 && prec != WD_F32)) return 0;
+  const Geom G = make_geom(dims, -1);
+  return halo_face_bytes(G, prec);
+}
+
+static wd_status slab_check(const wd_gauge *g, int t0, int nt, wd_prec prec) {
+  WD_TRY(check_handle(g));
+  if (prec != WD_F64 && prec != WD_F32) return set_error(WD_ERR_PREC, "slab: FP64 or FP32 only");
+  if (t0 < 0 || nt < 1 || t0 + nt > g->geom.L[3])
+    return set_error(WD_ERR_ARG, "slab: slices [%d, %d) outside 0..%d", t0, t0 + nt, g->geom.L[3]);
+  if (g->geom.s4 % 64)
+    return set_error(WD_ERR_DIMS, "slab: L1 L2 L3 / 2 = %d sites per slice must be a multiple of 64", g->geom.s4);
+  return set_device(g);
+}
+
+wd_status wd_halo_pack(const wd_gauge *g, const void *in_slab, int nt, int face, int dagger, wd_prec prec,
+                       void *face_buf) {
+  WD_TRY(slab_check(g, 0, nt, prec));
+  if (!in_slab || !face_buf) return set_error(WD_ERR_ARG, "halo pack: NULL pointer");
+  if (face != 0 && face != 1) return set_error(WD_ERR_ARG, "halo pack: face = %d", face);
+  return launch_halo_pack(g, in_slab, nt, face, dagger, prec, face_buf, g->stream);
+}
+
+wd_status wd_dslash_slab(const wd_gauge *g, const void *in_slab, const void *face_lo, const void *face_hi,
+                         void *out_slab, double a, int parity, int t0, int nt, int dagger, wd_prec prec) {
+  WD_TRY(slab_check(g, t0, nt, prec));
+  if (!in_slab || !face_lo || !face_hi || !out_slab) return set_error(WD_ERR_ARG, "slab hop: NULL pointer");
+  if (in_slab == out_slab) return set_error(WD_ERR_ARG, "slab hop: in and out must differ");
+  if (parity != 0 && parity != 1) return set_error(WD_ERR_ARG, "slab hop: parity = %d", parity);
+  if (!isfinite(a)) return set_error(WD_ERR_NONFINITE, "slab hop: a is not finite");
+  return launch_dslash_slab(g, in_slab, face_lo, face_hi, out_slab, a, parity, t0, nt, dagger, prec, g->stream);
+}
+
 static wd_status dslash_common(const wd_gauge *U, const void *in, void *out, double kappa, int parity, wd_prec prec,
                                int flags) {
   WD_TRY(check_handle(U));

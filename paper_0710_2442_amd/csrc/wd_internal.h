@@ -150,6 +150,13 @@ wd_status launch_dirac(const wd_gauge *g, wd_prec prec, const DiracArgs &args, h
 // entries whose skip[j * sstride] is set are left alone (blas.hip).
 wd_status launch_finish_sums(const double *partials, unsigned nblocks, int n, double *out, int ostride,
                              int accumulate, const int *skip, int sstride, hipStream_t st);
+// Time-slab decomposition (halo.hip)
+size_t halo_face_bytes(const Geom &g, wd_prec prec);
+wd_status launch_halo_pack(const wd_gauge *g, const void *in_slab, int nt, int face, int dagger, wd_prec prec,
+                           void *face_buf, hipStream_t st);
+wd_status launch_dslash_slab(const wd_gauge *g, const void *in_slab, const void *face_lo, const void *face_hi,
+                             void *out_slab, double a, int parity, int t0, int nt, int dagger, wd_prec prec,
+                             hipStream_t st);
 unsigned dslash_grid_blocks(const wd_gauge *g);
 bool dslash_variant_ok(const Geom &G, int bs, int groups);
 // grid.x of the multi-RHS hop (16 sites per block)
