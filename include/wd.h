@@ -317,7 +317,8 @@ wd_status wd_ptc_train_step(wd_ptc *n, const void *r, const void *e, int B,
  * the register budget (occ 0: compiler's
  * choice; occ 4: at least 4 waves per SIMD), the output store policy
  * (WD_TUNE_CACHED_STORE set in occ: cached stores), link preloading
- * (WD_TUNE_PRELOAD_LINKS, not FP64) and a cap on resident
+ * (WD_TUNE_PRELOAD_LINKS, not FP64), sites per lane along x4
+ * (WD_TUNE_SPL_SHIFT) and a cap on resident
  * blocks per CU (dynamic LDS in KiB << WD_TUNE_LDS_SHIFT).  Every candidate's output is
  * first compared byte for byte with the reference variant (256 threads,
  * linear, occ 0); matching candidates are timed with HIP events on
@@ -350,13 +351,17 @@ enum { WD_TUNE_CACHED_STORE = 256 };
 /* Bit of the occ value: the hop loads all 8 links of a site before its first
  * hop (more loads in flight, more registers); FP32, FP16 and BF16 only. */
 enum { WD_TUNE_PRELOAD_LINKS = 512 };
+/* Field of the occ value: (0, 1, 2) << WD_TUNE_SPL_SHIFT gives each lane
+ * (1, 2, 4) output sites along x4 (the same tile of consecutive time slices;
+ * linear tile order only). */
+enum { WD_TUNE_SPL_SHIFT = 10 };
 /* The dynamic LDS (KiB, 0..64) reserved per block, shifted into occ: it caps
  * the blocks resident on a CU and so the sites in flight per XCD. */
 enum { WD_TUNE_LDS_SHIFT = 16 };
 
 /* Set / read the hop variant used for precision prec.  occ: 0 or 4, or'ed
- * with WD_TUNE_CACHED_STORE, WD_TUNE_PRELOAD_LINKS (not FP64) and (KiB of
- * LDS << WD_TUNE_LDS_SHIFT).  WD_ERR_ARG if the variant does not fit the
+ * with WD_TUNE_CACHED_STORE, WD_TUNE_PRELOAD_LINKS (not FP64), (0, 1, 2) <<
+ * WD_TUNE_SPL_SHIFT and (KiB of LDS << WD_TUNE_LDS_SHIFT).  WD_ERR_ARG if the variant does not fit the
  * lattice (see wd_tune_dslash). */
 wd_status wd_set_dslash_variant(wd_gauge *g, wd_prec prec, int block, int groups,
                                 int occ);

@@ -27,6 +27,7 @@ WD_DAGGER = 1
 WD_ONE_PASS = 2
 WD_TUNE_CACHED_STORE = 256
 WD_TUNE_PRELOAD_LINKS = 512
+WD_TUNE_SPL_SHIFT = 10
 WD_SOLVER_CG, WD_SOLVER_DEFECT_CG, WD_SOLVER_FGCR, WD_SOLVER_DEFECT_FGCR = 0, 1, 2, 3
 
 _vp = C.c_void_p

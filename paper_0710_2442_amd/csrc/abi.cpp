@@ -108,6 +108,7 @@ wd_status wd_gauge_create(const double *U_host, const int dims[4], int t_bc, wd_
     g->hop_ntst[p] = 1;
     g->hop_lds[p] = 0;
     g->hop_pre[p] = 0;
+    g->hop_spl[p] = 1;
     g->mrhs_block[p] = (p == WD_F64) ? 16 : 128;
     g->mrhs_rpl[p] = 4;
     g->mrhs_groups[p] = dslash_variant_ok(g->geom, g->mrhs_block[p], 4) ? 4 : 0;

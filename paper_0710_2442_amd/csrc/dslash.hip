@@ -32,8 +32,21 @@ namespace wd {
 template <int P, bool DAG, int EPI, bool NORM, bool PRE>
 __device__ __forceinline__ void dslash_body(const KDslash &k) {
   if (k.skip && *k.skip) return;
-  const int i = tile_of(k) * (int)blockDim.x + (int)threadIdx.x;
-  const double nrm = dslash_site<P, DAG, EPI, NORM, PRE>(k, i);
+  double nrm;
+  if (k.spl <= 1) {
+    const int i = tile_of(k) * (int)blockDim.x + (int)threadIdx.x;
+    nrm = dslash_site<P, DAG, EPI, NORM, PRE>(k, i);
+  } else {
+    // sites per lane along x4: block b covers tile s of slices spl * tg .. spl * tg + spl - 1
+    const int T = k.tiles_per_slice, b = (int)blockIdx.x;
+    const int s = b % T, tg = b / T;
+    nrm = 0.0;
+#pragma unroll 1
+    for (int j = 0; j < k.spl; ++j) {
+      const int i = ((tg * k.spl + j) * T + s) * (int)blockDim.x + (int)threadIdx.x;
+      nrm += dslash_site<P, DAG, EPI, NORM, PRE>(k, i);
+    }
+  }
   if constexpr (NORM) {
     double v[1] = {nrm};
     block_sum_store<1>(v, k.partials, gridDim.x, blockIdx.x);
@@ -268,8 +281,13 @@ unsigned dslash_grid_blocks(const wd_gauge *g) { return (unsigned)((g->geom.vpad
 // size divides the slots and, for groups != 0, the blocks tile the time
 // slices exactly and either (G > 0) the tiles of one slice split evenly into
 // G regions or (-X < 0) the slices split evenly over X lanes.
-bool dslash_variant_ok(const Geom &G, int bs, int groups) {
+bool dslash_variant_ok(const Geom &G, int bs, int groups, int spl) {
   if (bs != 16 && bs != 64 && bs != 128 && bs != 256 && bs != 512) return false;
+  if (spl != 1 && spl != 2 && spl != 4) return false;
+  if (spl > 1) {
+    const long slice = (long)G.vh / G.L[3];
+    return groups == 0 && G.vpad == G.vh && slice % bs == 0 && G.L[3] % spl == 0;
+  }
   if (groups == 0) return true;
   if (groups < -16 || groups > 64) return false;
   const long slice = (long)G.vh / G.L[3];
@@ -296,14 +314,15 @@ wd_status launch_dslash(const wd_gauge *g, wd_prec prec, const DslashArgs &a, hi
   const bool norm = a.norm_out != nullptr;
   if (norm && (!k.partials || !k.counter)) return set_error(WD_ERR_ARG, "dslash norm: no reduction buffer");
   const int pi = (int)prec;
-  int bs = g->hop_block[pi], groups = g->hop_groups[pi];
-  if (!dslash_variant_ok(g->geom, bs, groups)) { bs = 256; groups = 0; }
+  int bs = g->hop_block[pi], groups = g->hop_groups[pi], spl = g->hop_spl[pi];
+  if (!dslash_variant_ok(g->geom, bs, groups, spl)) { bs = 256; groups = 0; spl = 1; }
   k.groups = groups;
+  k.spl = spl;
   k.occ = g->hop_occ[pi];
   k.nt_store = g->hop_ntst[pi];
   k.preload = (prec != WD_F64) ? g->hop_pre[pi] : 0;
-  k.tiles_per_slice = groups ? (int)((long)g->geom.vh / g->geom.L[3] / bs) : 0;
-  const unsigned nblk = (unsigned)((g->geom.vpad + bs - 1) / bs);
+  k.tiles_per_slice = (groups || spl > 1) ? (int)((long)g->geom.vh / g->geom.L[3] / bs) : 0;
+  const unsigned nblk = (unsigned)((g->geom.vpad + bs - 1) / bs) / (unsigned)spl;
   const unsigned lds = (unsigned)g->hop_lds[pi];
   switch (prec) {
     case WD_F64: launch_prec<WD_F64>(k, a.dagger, epi, norm, nblk, bs, lds, st); break;
@@ -340,7 +359,7 @@ static int mrhs_block_of(const wd_gauge *g, wd_prec prec, int &groups) {
   int bs = (prec == WD_F64) ? 16 : g->mrhs_block[pi];
   if (prec != WD_F64 && bs != 64 && bs != 128 && bs != 256) bs = 128;
   groups = g->mrhs_groups[pi];
-  if (!dslash_variant_ok(g->geom, bs, groups)) groups = 0;
+  if (!dslash_variant_ok(g->geom, bs, groups, 1)) groups = 0;
   return bs;
 }
 

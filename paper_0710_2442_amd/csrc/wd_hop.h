@@ -29,6 +29,7 @@ struct KDslash {
   int occ;              // register-budget variant (0 or 4), host side only
   int nt_store;         // 1: streaming output stores; 0: cached stores
   int preload;          // 1: load all 8 links before the first hop (FP32 arithmetic only), host side
+  int spl;              // sites per lane along x4 (1, 2, 4): lane covers tiles t, t + T, ... of consecutive slices
 };
 
 // Workgroups are dispatched round-robin over the XCDs (8 on MI355X), each

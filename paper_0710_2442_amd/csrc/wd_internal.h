@@ -79,6 +79,7 @@ struct wd_gauge {
   int mrhs_rpl[4];         // per precision: right-hand sides per lane of that kernel
   int hop_lds[4];          // per precision: dynamic LDS bytes per block (caps blocks per CU)
   int hop_pre[4];          // per precision: 1 = links loaded before the first hop (not FP64)
+  int hop_spl[4];          // per precision: output sites per lane along x4 (1, 2, 4)
   double *scratch_red;     // reduction partials / scalars for the BLAS entry points
   unsigned *scratch_cnt;
   wd::Workspace *ws;
@@ -158,7 +159,7 @@ wd_status launch_dslash_slab(const wd_gauge *g, const void *in_slab, const void 
                              void *out_slab, double a, int parity, int t0, int nt, int dagger, wd_prec prec,
                              hipStream_t st);
 unsigned dslash_grid_blocks(const wd_gauge *g);
-bool dslash_variant_ok(const Geom &G, int bs, int groups);
+bool dslash_variant_ok(const Geom &G, int bs, int groups, int spl = 1);
 // grid.x of the multi-RHS hop (16 sites per block)
 inline size_t mrhs_grid_blocks(const wd_gauge *g) { return ((size_t)g->geom.vpad + 15) / 16; }
 wd_status launch_dslash(const wd_gauge *g, wd_prec prec, const DslashArgs &args, hipStream_t st);

@@ -297,7 +297,7 @@ def test_every_hop_variant_is_bitwise_identical(dims, prec):
     wd.wd_set_dslash_variant(g, prec, 256, 0, 0)
     wd.wd_dslash_ex(g, src, ref, 0.9, wd.WD_EVEN, prec)
     n = 0
-    for bs, groups, occ in [(b, gr, o) for b in (64, 128, 256, 512) for gr in (0, 2, 4, 8, 16, -2, -4, -8, -16) for o in (0, 4, 256, 512, 516)]:
+    for bs, groups, occ in [(b, gr, o) for b in (64, 128, 256, 512) for gr in (0, 2, 4, 8, 16, -2, -4, -8, -16) for o in (0, 4, 256, 512, 516, 1024, 2048, 1536, 2308)]:
             try:
                 wd.wd_set_dslash_variant(g, prec, bs, groups, occ)
             except wd.WdError:
