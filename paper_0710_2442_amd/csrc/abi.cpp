@@ -149,6 +149,7 @@ wd_status wd_gauge_destroy(wd_gauge *g) {
   (void)hipSetDevice(g->device);
   if (g->own_stream) (void)hipStreamSynchronize(g->own_stream);
   workspace_free(g);
+  fgcr_free(g);
   ptc_release(g);
   if (g->links64) (void)hipFree(g->links64);
   if (g->links32) (void)hipFree(g->links32);

@@ -425,24 +425,35 @@ wd_status solve_fgcr_mixed(wd_gauge *g, const void *b, void *x, double kappa, do
   const int m = std::min(prm.fgcr_m, FG_MMAX);
   const Geom &G = g->geom;
   const size_t h64 = half_bytes(G, WD_F64), h32 = half_bytes(G, WD_F32);
-  // r64, d64 (2 h64 each); rh, e (2 h32 each); R, T, Z[m], W[m] (h32 each)
-  Buf mem, red, pin;
+  // r64, d64 (2 h64 each); rh, e (2 h32 each); R, T, Z[m], W[m] (h32 each); then the
+  // device scalars ([0, 128) CgScalars, then dots/sig/rho/rr), the reduction partials and
+  // a counter word.  Kept in the handle between solves (grown when a solve needs more).
   const unsigned nblk = (unsigned)std::min<long>(std::max<long>(1, ((long)G.vh + FG_BS - 1) / FG_BS), FG_MAX_BLOCKS);
   const size_t npart = std::max<size_t>((size_t)2 * FG_MMAX * nblk,
                                         (size_t)2 * std::max<unsigned>(dslash_grid_blocks(g), BLAS_MAX_BLOCKS));
-  WD_HIP(hipMalloc(&mem.p, 4 * h64 + 4 * h32 + (2 + 2 * (size_t)m) * h32));
-  // device scalars: [0, 64) CgScalars + dots/sig/rho/rr; then partials; then the counter
+  const size_t vec_bytes = round_up(4 * h64 + 4 * h32 + (2 + 2 * (size_t)m) * h32, 256);
   const size_t scal_bytes = 1024;
-  WD_HIP(hipMalloc(&red.p, scal_bytes + npart * sizeof(double) + 256));
-  WD_HIP(hipMemsetAsync(red.p, 0, scal_bytes, st));
-  WD_HIP(hipMemsetAsync((char *)red.p + scal_bytes + npart * sizeof(double), 0, 256, st));
-  double *hres = nullptr;
-  WD_HIP(hipHostMalloc((void **)&hres, 64 * sizeof(double), hipHostMallocDefault));
-  struct HostFree {
-    double *p;
-    ~HostFree() { (void)hipHostFree(p); }
-  } hf{hres};
-  char *c0 = (char *)mem.p;
+  const size_t need = vec_bytes + scal_bytes + npart * sizeof(double) + 256;
+  if (!g->fg_mem || g->fg_bytes < need) {
+    if (g->fg_mem) {
+      WD_HIP(hipStreamSynchronize(st));
+      WD_HIP(hipFree(g->fg_mem));
+      g->fg_mem = nullptr;
+      g->fg_bytes = 0;
+    }
+    if (hipMalloc(&g->fg_mem, need) != hipSuccess) {
+      (void)hipGetLastError();
+      g->fg_mem = nullptr;
+      return set_error(WD_ERR_OOM, "FGCR: cannot allocate %zu bytes", need);
+    }
+    g->fg_bytes = need;
+  }
+  if (!g->fg_host) WD_HIP(hipHostMalloc((void **)&g->fg_host, 64 * sizeof(double), hipHostMallocDefault));
+  double *hres = g->fg_host;
+  char *red = (char *)g->fg_mem + vec_bytes;
+  WD_HIP(hipMemsetAsync(red, 0, scal_bytes, st));
+  WD_HIP(hipMemsetAsync(red + scal_bytes + npart * sizeof(double), 0, 256, st));
+  char *c0 = (char *)g->fg_mem;
   char *r64 = c0, *d64 = c0 + 2 * h64, *rh = c0 + 4 * h64, *e32 = rh + 2 * h32;
   char *R = e32 + 2 * h32, *T = R + h32;
   char *E = e32;  // inner solution = even half of e32
@@ -453,16 +464,16 @@ wd_status solve_fgcr_mixed(wd_gauge *g, const void *b, void *x, double kappa, do
     a.Z[k] = T + (1 + (size_t)k) * h32;
     a.W[k] = T + (1 + (size_t)m + k) * h32;
   }
-  CgScalars *sc = (CgScalars *)red.p;
-  double *ds = (double *)((char *)red.p + 128);
+  CgScalars *sc = (CgScalars *)red;
+  double *ds = (double *)(red + 128);
   a.dots = ds;
   a.sig = ds + 2 * FG_MMAX;
   a.rho = a.sig + FG_MMAX;
   a.rr = a.rho + 2;
   a.r = R;
   a.e = E;
-  a.partials = (double *)((char *)red.p + scal_bytes);
-  a.counter = (unsigned *)((char *)red.p + scal_bytes + npart * sizeof(double));
+  a.partials = (double *)(red + scal_bytes);
+  a.counter = (unsigned *)(red + scal_bytes + npart * sizeof(double));
   RedBuf rb{a.partials, a.counter};
   auto read = [&](const double *dev, int n, double *out) -> wd_status {
     WD_HIP(hipMemcpyAsync(hres, dev, sizeof(double) * n, hipMemcpyDeviceToHost, st));
@@ -603,6 +614,14 @@ wd_status solve_fgcr_mixed(wd_gauge *g, const void *b, void *x, double kappa, do
   }
   info.true_rel_resid = sqrt(rn2 / bb);
   return info.true_rel_resid <= tol ? WD_OK : WD_NOT_CONVERGED;
+}
+
+void fgcr_free(wd_gauge *g) {
+  if (g->fg_mem) (void)hipFree(g->fg_mem);
+  if (g->fg_host) (void)hipHostFree(g->fg_host);
+  g->fg_mem = nullptr;
+  g->fg_host = nullptr;
+  g->fg_bytes = 0;
 }
 
 }  // namespace wd

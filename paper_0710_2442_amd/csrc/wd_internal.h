@@ -83,6 +83,9 @@ struct wd_gauge {
   double *scratch_red;     // reduction partials / scalars for the BLAS entry points
   unsigned *scratch_cnt;
   wd::Workspace *ws;
+  void *fg_mem;            // mixed FGCR: vectors + scalars + partials, kept between solves
+  size_t fg_bytes;
+  double *fg_host;         // pinned scalars read back by the mixed FGCR
 };
 
 namespace wd {

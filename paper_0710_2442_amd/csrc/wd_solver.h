@@ -12,6 +12,8 @@ wd_status solve_mrhs(wd_gauge *g, const void *b, void *x, int nrhs, double kappa
 wd_status solve_fgcr(wd_gauge *g, const void *b, void *x, double kappa, double tol, const wd_solve_params &prm,
                      wd_solve_info &info, hipStream_t st);
 void workspace_free(wd_gauge *g);
+// release the mixed FGCR's cached buffers (fgcr.hip)
+void fgcr_free(wd_gauge *g);
 wd_status solve_batch(const wd_gauge *const *gs, int n, const void *const *b, void *const *x, const double *kappa,
                       double tol, const wd_solve_params &prm, wd_solve_info *infos);
 // FP64 defect correction around an FP32 even-odd FGCR(m) with the network
