@@ -344,6 +344,15 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path,
 wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, int *block,
                               int *groups, int *rpl, double *us);
 
+/* Set / read the multi-RHS hop variant used for precision prec: block (FP64:
+ * 16; others 64, 128 or 256 sites), groups (block -> tile order, as for
+ * wd_set_dslash_variant) and rpl (FP64: 4; others 1..16 right-hand sides per
+ * lane).  WD_ERR_ARG for a value
+ * outside these or a variant that does not fit the lattice.  The variants
+ * compute the same bytes; only the time differs. */
+wd_status wd_set_dslash_mrhs_variant(wd_gauge *g, wd_prec prec, int block, int groups, int rpl);
+wd_status wd_get_dslash_mrhs_variant(const wd_gauge *g, wd_prec prec, int *block, int *groups, int *rpl);
+
 /* Bit of the occ value: the hop writes its output with ordinary (cached)
  * stores instead of streaming stores, so that a following kernel can read a
  * freshly written field from the caches. */

@@ -97,6 +97,9 @@ _decl("wd_tune_dslash_mrhs", C.c_int, [_vp, C.c_int, C.c_int, C.POINTER(C.c_int)
                                        C.POINTER(C.c_int), C.POINTER(C.c_double)])
 _decl("wd_set_dslash_variant", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int])
 _decl("wd_get_dslash_variant", C.c_int, [_vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)])
+_decl("wd_set_dslash_mrhs_variant", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int])
+_decl("wd_get_dslash_mrhs_variant", C.c_int,
+      [_vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)])
 _decl("wd_ptc_create", C.c_int, [_vp, C.POINTER(C.c_float), C.c_int, C.POINTER(_vp)])
 _decl("wd_ptc_destroy", C.c_int, [_vp])
 _decl("wd_ptc_set_weights", C.c_int, [_vp, C.POINTER(C.c_float)])
@@ -379,6 +382,19 @@ def wd_get_dslash_variant(g, prec):
     _check(lib.wd_get_dslash_variant(g.handle, _prec(prec), C.byref(b), C.byref(gr), C.byref(oc)),
            "wd_get_dslash_variant")
     return b.value, gr.value, oc.value
+
+
+def wd_set_dslash_mrhs_variant(g, prec, block, groups, rpl):
+    """Multi-RHS hop variant (block, groups, right-hand sides per lane)."""
+    _check(lib.wd_set_dslash_mrhs_variant(g.handle, _prec(prec), int(block), int(groups), int(rpl)),
+           "wd_set_dslash_mrhs_variant")
+
+
+def wd_get_dslash_mrhs_variant(g, prec):
+    b, gr, rp = C.c_int(), C.c_int(), C.c_int()
+    _check(lib.wd_get_dslash_mrhs_variant(g.handle, _prec(prec), C.byref(b), C.byref(gr), C.byref(rp)),
+           "wd_get_dslash_mrhs_variant")
+    return b.value, gr.value, rp.value
 
 
 def _fptr(a):

@@ -137,6 +137,34 @@ wd_status wd_set_dslash_variant(wd_gauge *g, wd_prec prec, int block, int groups
   return WD_OK;
 }
 
+wd_status wd_set_dslash_mrhs_variant(wd_gauge *g, wd_prec prec, int block, int groups, int rpl) {
+  if (!g) return set_error(WD_ERR_ARG, "gauge handle is NULL");
+  if ((int)prec < 0 || (int)prec > 3) return set_error(WD_ERR_PREC, "prec = %d", (int)prec);
+  if (prec == WD_F64) {
+    if (block != 16 || rpl != 4 || !dslash_variant_ok(g->geom, 16, groups))
+      return set_error(WD_ERR_ARG, "FP64 multi-RHS variant: block 16, rpl 4 and a groups value that fits");
+  } else {
+    if (block != 64 && block != 128 && block != 256)
+      return set_error(WD_ERR_ARG, "multi-RHS block %d (64, 128 or 256)", block);
+    if (rpl < 1 || rpl > 16) return set_error(WD_ERR_ARG, "multi-RHS rpl %d (1..16)", rpl);
+    if (!dslash_variant_ok(g->geom, block, groups))
+      return set_error(WD_ERR_ARG, "variant (block %d, groups %d) does not fit this lattice", block, groups);
+  }
+  g->mrhs_block[prec] = block;
+  g->mrhs_groups[prec] = groups;
+  g->mrhs_rpl[prec] = rpl;
+  return WD_OK;
+}
+
+wd_status wd_get_dslash_mrhs_variant(const wd_gauge *g, wd_prec prec, int *block, int *groups, int *rpl) {
+  if (!g || !block || !groups || !rpl) return set_error(WD_ERR_ARG, "NULL argument");
+  if ((int)prec < 0 || (int)prec > 3) return set_error(WD_ERR_PREC, "prec = %d", (int)prec);
+  *block = g->mrhs_block[prec];
+  *groups = g->mrhs_groups[prec];
+  *rpl = g->mrhs_rpl[prec];
+  return WD_OK;
+}
+
 wd_status wd_get_dslash_variant(const wd_gauge *g, wd_prec prec, int *block, int *groups, int *occ) {
   if (!g || !block || !groups || !occ) return set_error(WD_ERR_ARG, "NULL argument");
   if ((int)prec < 0 || (int)prec > 3) return set_error(WD_ERR_PREC, "prec = %d", (int)prec);

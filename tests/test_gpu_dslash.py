@@ -189,6 +189,73 @@ def test_mrhs_equals_single_rhs_bitwise(prec, nrhs):
     g.close()
 
 
+# (8, 4, 6, 16): V_h = 1536, 6, 12 or 24 tiles, no slice-aligned tile orders;
+# (16, 8, 8, 8): 8 tiles of 64 per slice, every tile order; (8, 6, 8, 4): 3
+# tiles of 64 per slice, 12 tiles (not a multiple of 8), orders 3, -2, -4
+@pytest.mark.parametrize("dims", [(8, 4, 6, 16), (16, 8, 8, 8), (8, 6, 8, 4)])
+@pytest.mark.parametrize("prec", ["f32", "f16", "bf16"])
+def test_every_mrhs_variant_is_bitwise_identical(dims, prec):
+    """Block size, tile order and RHS per lane change only the schedule:
+    every variant gives the bytes of the single-RHS hop, ragged RHS chunks
+    and a ragged last tile included."""
+    nrhs = 5
+    g = wd.Gauge(syn.gauge_field(dims, 0.3, 23), dims, -1, prec)
+    psis = syn.gaussian_spinor(dims, 24, nrhs=nrhs)
+    hb = wd.wd_field_bytes(dims, prec, 1, wd.WD_EVEN)
+    src = torch.cat([to_field(g, psis[r], prec, wd.WD_ODD) for r in range(nrhs)])
+    ref = wd.wd_new_field(dims, prec, nrhs, wd.WD_EVEN)
+    for r in range(nrhs):
+        wd.wd_dslash_ex(g, src[r * hb:(r + 1) * hb], ref[r * hb:(r + 1) * hb], 0.7, wd.WD_EVEN, prec)
+    n = 0
+    for bs in (64, 128, 256):
+        for gr in (0, 2, 3, 4, 8, -2, -4, -8):
+            for rpl in (1, 2, 3, 4, 12, 16):
+                try:
+                    wd.wd_set_dslash_mrhs_variant(g, prec, bs, gr, rpl)
+                except wd.WdError:
+                    assert gr != 0 or bs == 256  # only tile orders (or sizes) that do not fit are refused
+                    continue
+                assert wd.wd_get_dslash_mrhs_variant(g, prec) == (bs, gr, rpl)
+                out = wd.wd_new_field(dims, prec, nrhs, wd.WD_EVEN)
+                out.fill_(0xAB)
+                wd.wd_dslash_mrhs(g, src, out, 0.7, wd.WD_EVEN, prec, nrhs)
+                torch.cuda.synchronize()
+                assert torch.equal(out, ref), (bs, gr, rpl)
+                n += 1
+    assert n >= 18
+    for bad in ((96, 0, 4), (64, 0, 0), (64, 0, 17), (64, 5, 4), (64, 0, -1)):
+        with pytest.raises(wd.WdError):
+            wd.wd_set_dslash_mrhs_variant(g, prec, *bad)
+    g.close()
+
+
+def test_mrhs_solve_does_not_depend_on_rhs_per_lane():
+    """The multi-RHS solver through its fused epilogues and per-RHS norms:
+    1, 2 or all 3 right-hand sides per lane (same blocks, so the same norm
+    partials), bit-identical x, and x solves D_W x = b to 1e-10."""
+    dims = (8, 8, 4, 8)
+    nrhs = 3
+    g = wd.Gauge(syn.gauge_field(dims, 0.3, 25), dims, -1, "f64")
+    f = wd.wd_field_bytes(dims, "f64")
+    B = torch.cat([to_field(g, syn.gaussian_spinor(dims, 26 + r), "f64", wd.WD_FULL) for r in range(nrhs)])
+    xs = []
+    for rpl in (1, 2, 3):
+        wd.wd_set_dslash_mrhs_variant(g, "f32", 64, 0, rpl)
+        x = wd.wd_new_field(dims, "f64", nrhs)
+        prm = wd.wd_solve_params_default(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec="f32", inner_tol=1e-4)
+        rc, infos = wd.wd_solve_mrhs(g, B, x, nrhs, 0.12, 1e-10, prm)
+        assert rc == 0 and all(i["status"] == 0 for i in infos)
+        xs.append(x)
+    assert torch.equal(xs[0], xs[1]) and torch.equal(xs[0], xs[2])
+    U = syn.gauge_field(dims, 0.3, 25)
+    for r in range(nrhs):
+        b = syn.gaussian_spinor(dims, 26 + r)
+        xr = from_field(g, xs[1][r * f:(r + 1) * f], "f64", wd.WD_FULL)
+        res = b - wilson.dirac(U, xr, 0.12, -1)
+        assert np.linalg.norm(res) / np.linalg.norm(b) <= 1e-10
+    g.close()
+
+
 def test_blas_against_numpy():
     dims = (6, 4, 6, 10)
     g = wd.Gauge(syn.gauge_field(dims, 0.3, 31), dims, -1, "f64")
