@@ -105,6 +105,59 @@ class PairGenerator:
         return r, e
 
 
+# Weight checkpoint: a small versioned binary (little-endian).
+#   bytes 0-7   magic b"WDPTC\x00\x00\x00"
+#   8-11        format version (uint32, 1)
+#   12-15       number of float32 weights (uint32, 1152 = 576 complex)
+#   16-19       length of the JSON metadata in bytes (uint32)
+#   20-23       CRC-32 of everything after the header (metadata + weights)
+#   then the UTF-8 JSON metadata, then the weights in the library's order
+#   ([layer][h][c'][c][4][4] complex, (re, im) interleaved).
+CKPT_MAGIC = b"WDPTC\x00\x00\x00"
+CKPT_VERSION = 1
+N_WEIGHTS = 1152
+
+
+def save_weights(path, flat, meta=None):
+    """Write the 1152 FP32 network weights and a JSON-able metadata dict."""
+    import json
+    import struct
+    import zlib
+
+    w = np.ascontiguousarray(np.asarray(flat, dtype="<f4").reshape(-1))
+    if w.size != N_WEIGHTS:
+        raise ValueError(f"PTC weights: {N_WEIGHTS} floats expected, got {w.size}")
+    m = json.dumps(meta or {}, sort_keys=True).encode()
+    body = m + w.tobytes()
+    head = CKPT_MAGIC + struct.pack("<IIII", CKPT_VERSION, N_WEIGHTS, len(m), zlib.crc32(body) & 0xFFFFFFFF)
+    with open(path, "wb") as f:
+        f.write(head + body)
+
+
+def load_weights(path):
+    """Read a checkpoint written by save_weights: (float32 array of 1152, metadata dict).
+    Raises ValueError for a wrong magic, version or size, or a damaged body."""
+    import json
+    import struct
+    import zlib
+
+    with open(path, "rb") as f:
+        data = f.read()
+    if len(data) < 24 or data[:8] != CKPT_MAGIC:
+        raise ValueError("not a PTC weight checkpoint")
+    version, n, mlen, crc = struct.unpack("<IIII", data[8:24])
+    if version != CKPT_VERSION:
+        raise ValueError(f"PTC checkpoint version {version}, this library reads {CKPT_VERSION}")
+    if n != N_WEIGHTS or len(data) != 24 + mlen + 4 * n:
+        raise ValueError("PTC checkpoint: wrong size")
+    body = data[24:]
+    if zlib.crc32(body) & 0xFFFFFFFF != crc:
+        raise ValueError("PTC checkpoint: checksum mismatch")
+    meta = json.loads(body[:mlen].decode())
+    w = np.frombuffer(body[mlen:], dtype="<f4").astype(np.float32)
+    return w, meta
+
+
 def init_weights(seed, scale=1e-2):
     """Near-identity start: W^(0) = I/sqrt(2) in both layers, other hops N(0, scale^2)."""
     rng = np.random.Generator(np.random.PCG64(int(seed)))
@@ -119,8 +172,10 @@ def init_weights(seed, scale=1e-2):
     return L.ptc_weights_to_flat(W1, W2)
 
 
-def train(g, kappa, steps=300, batch=8, lr=2e-3, seed=5, act="bf16", log_every=50, log=None, ks=(0,)):
-    """Train a PTC network on lattice g.  Returns (flat weights, history dict)."""
+def train(g, kappa, steps=300, batch=8, lr=2e-3, seed=5, act="bf16", log_every=50, log=None, ks=(0,),
+          checkpoint=None):
+    """Train a PTC network on lattice g.  Returns (flat weights, history dict);
+    with checkpoint (a path) the weights are also written by save_weights."""
     gen = PairGenerator(g, kappa, seed, ks)
     net = L.Ptc(g, init_weights(seed + 1), act)
     losses = []
@@ -139,5 +194,9 @@ def train(g, kappa, steps=300, batch=8, lr=2e-3, seed=5, act="bf16", log_every=5
     wall = time.perf_counter() - t0
     W = L.wd_ptc_get_weights(net)
     net.close()
-    return W, {"losses": losses, "pairs": steps * batch, "sources": gen.sources, "seconds": wall,
-               "pair_generation_seconds": gen.solve_seconds}
+    hist = {"losses": losses, "pairs": steps * batch, "sources": gen.sources, "seconds": wall,
+            "pair_generation_seconds": gen.solve_seconds}
+    if checkpoint:
+        save_weights(checkpoint, W, {"dims": list(g.dims), "kappa": float(kappa), "steps": steps, "batch": batch,
+                                     "lr": lr, "seed": seed, "act": act, "final_loss": losses[-1][1] if losses else None})
+    return W, hist

@@ -1,5 +1,6 @@
-"""The learned preconditioner is trained on the GPU by the library's kernels
-and must beat the method without it (FGCR with N = 1) on fresh sources."""
+"""The learned preconditioner is trained on the GPU by the library's kernels,
+survives a round trip through its weight checkpoint, and must beat the
+method without it (FGCR with N = 1) on fresh sources."""
 import numpy as np
 import pytest
 
@@ -12,11 +13,15 @@ from oracle import solvers
 pytestmark = pytest.mark.gpu
 
 
-def test_training_reduces_loss_and_fgcr_iterations():
+def test_training_reduces_loss_and_fgcr_iterations(tmp_path):
     dims, kappa = (8, 8, 8, 8), 0.124
     U = syn.gauge_field(dims, 0.3, 401)
     g = wd.Gauge(U, dims, -1, "f64")
-    W, hist = learn.train(g, kappa, steps=200, batch=4, lr=3e-3, seed=7, act="bf16", log_every=20)
+    ck = tmp_path / "ptc.wdptc"
+    W0, hist = learn.train(g, kappa, steps=200, batch=4, lr=3e-3, seed=7, act="bf16", log_every=20, checkpoint=ck)
+    # the solves below use the network read back from its checkpoint
+    W, meta = learn.load_weights(ck)
+    assert np.array_equal(W, W0) and meta["dims"] == list(dims) and meta["steps"] == 200
     losses = [l for _, l in hist["losses"]]
     print("losses", losses, flush=True)
     assert losses[-1] < 0.7 * losses[0]

@@ -1,6 +1,7 @@
 """Host-side logic without a GPU: weight marshalling of the network, the
-near-identity start, the timing model of Eqs. 1-2 with MI355X numbers, and
-the benchmark's one-GPU contract."""
+near-identity start, the weight checkpoint, the timing model of Eqs. 1-2
+with MI355X numbers, and the benchmark's one-GPU contract."""
+import json
 import os
 import subprocess
 import sys
@@ -40,6 +41,26 @@ def test_near_identity_start_matches_the_oracle_network_at_h0():
     psi = syn.gaussian_spinor(dims, 6)
     y = ptc.network(U, psi, W1, W2)
     assert np.allclose(y, psi, rtol=1e-6, atol=1e-6)
+
+
+def test_weight_checkpoint_round_trip_and_damage(tmp_path):
+    flat = learn.init_weights(7, scale=0.1)
+    meta = {"dims": [16, 16, 16, 16], "kappa": 0.124, "steps": 1250, "act": "bf16"}
+    p = tmp_path / "w.wdptc"
+    learn.save_weights(p, flat, meta)
+    w, m = learn.load_weights(p)
+    assert w.dtype == np.float32 and np.array_equal(w, flat) and m == meta
+    assert p.stat().st_size == 24 + len(json.dumps(meta, sort_keys=True)) + 4 * 1152
+    raw = bytearray(p.read_bytes())
+    for pos, what in ((0, "not a PTC"), (8, "version"), (12, "size"), (len(raw) - 3, "checksum")):
+        bad = bytearray(raw)
+        bad[pos] ^= 0x01
+        q = tmp_path / f"bad{pos}"
+        q.write_bytes(bytes(bad))
+        with pytest.raises(ValueError, match=what):
+            learn.load_weights(q)
+    with pytest.raises(ValueError):
+        learn.save_weights(p, flat[:-1])
 
 
 def test_timing_model_of_the_hop():
