@@ -435,7 +435,25 @@ def cpu_leg(syn, U, psi):
         "kind": "oracle",
         "sample": f"one FP64 single-parity hop (numpy oracle) on the full 32^3x64 lattice, {dt:.1f} s",
         "host_cpus": os.cpu_count(),
+        "host_cpu_model": _cpu_model(),
     }
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _device(torch):
+    p = torch.cuda.get_device_properties(0)
+    return {"name": p.name, "arch": getattr(p, "gcnArchName", None), "compute_units": p.multi_processor_count,
+            "hbm_bytes": p.total_memory}
 
 
 def main():
@@ -546,6 +564,7 @@ def main():
             "parallelism": "single GPU",
         },
         "roofline": roof,
+        "device": _device(torch),
     }
     if "f32" in results and head != "f32":
         line["f32"] = {"value": round(results["f32"]["gbs"], 2), "unit": "GB/s",
