@@ -138,6 +138,15 @@ def solve_leg(wd, torch, syn, log_every=True):
             "true_rel_resid": info["true_rel_resid"],
             "status": rc,
         }
+        if name == "fp64_cg":
+            xref = x.clone()
+        else:
+            # |x - x_fp64cg| / |x_fp64cg| with the library's caxpy and norm (both solves
+            # are within cond(D) * 1e-10 of the exact solution)
+            d = x.clone()
+            wd.wd_caxpy(g, -1.0, xref, d, 2, "f64")
+            out[name]["rel_diff_vs_fp64_cg_solution"] = float(
+                (wd.wd_norm2(g, d, 2, "f64") / wd.wd_norm2(g, xref, 2, "f64")) ** 0.5)
         log(f"solve {name}: {wall:.3f} s, iters {info['iters']}, outer {info['outer_iters']}, "
             f"resid {info['true_rel_resid']:.2e}")
     base = out["fp64_cg"]["seconds"]
