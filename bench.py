@@ -258,6 +258,9 @@ def batch_leg(wd, torch, syn):
     sec, (rc, infos) = timed(lambda: wd.wd_solve_batch(gs, bs, xs, [kappa] * 8, tol, _defect(wd, "f32")))
     out["batch8_persistent_graph_f32"] = {"seconds": round(sec, 4), "status": rc,
                                           "max_resid": max(i["true_rel_resid"] for i in infos)}
+    sec, (rc, infos) = timed(lambda: wd.wd_solve_batch(gs, bs, xs, [kappa] * 8, tol, _defect(wd, "bf16", 1e-2)))
+    out["batch8_persistent_graph_bf16"] = {"seconds": round(sec, 4), "status": rc,
+                                           "max_resid": max(i["true_rel_resid"] for i in infos)}
     sec, res = timed(lambda: [wd.wd_solve(g, b, x, kappa, tol, _defect(wd, "f32")) for g, b, x in zip(gs, bs, xs)])
     out["sequential8_defect_f32"] = {"seconds": round(sec, 4),
                                      "max_resid": max(i["true_rel_resid"] for _, i in res)}

@@ -79,11 +79,12 @@ def test_batch_zero_source_lattice():
         assert solvers.true_residual(Us[k], bs[k], xs[k], 0.124) <= TOL
 
 
-def test_batch_eight_lattices_689408_sites():
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_batch_eight_lattices_689408_sites(prec):
     """The eight-lattice workload (8^4 ... 20^3x40), one persistent launch per kernel."""
     lats = syn.batch_lattices()
     assert sum(syn.volume(d) for d, _, _ in lats) == 689408
-    rc, infos, Us, bs, xs = _run(lats)
+    rc, infos, Us, bs, xs = _run(lats, prec=prec)
     assert rc == 0
     for (dims, eps, seed), U, b, x, info in zip(lats, Us, bs, xs, infos):
         r = solvers.true_residual(U, b, x, 0.124)
