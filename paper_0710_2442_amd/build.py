@@ -47,9 +47,18 @@ def _hipcc():
     return exe
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+# Host-only AddressSanitizer build (--asan): every -fsanitize applies to the
+# host side of the compilation only; device code is built as usual.
+ASAN_BUILD = os.path.join(ROOT, "_build_asan")
+ASAN_LIB = os.path.join(ASAN_BUILD, "libwd_asan.so")
+ASAN_FLAGS = ["-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def _compile(src, asan=False):
+    obj = os.path.join(ASAN_BUILD if asan else BUILD, os.path.basename(src) + ".o")
     flags = HIP_FLAGS if src.endswith(".hip") else CXX_FLAGS
+    if asan:
+        flags = flags + ASAN_FLAGS
     cmd = [_hipcc(), *flags, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l and l.strip())
@@ -58,24 +67,36 @@ def _compile(src):
     return obj, err
 
 
-def build(verbose=False, jobs=None):
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose=False, jobs=None, asan=False):
+    """Build libwd.so (asan: the host-sanitized copy _build_asan/libwd_asan.so,
+    for the CPU tests of the C-ABI; load it with the compiler's ASan runtime
+    preloaded)."""
+    out_dir = ASAN_BUILD if asan else BUILD
+    lib = ASAN_LIB if asan else LIB
+    os.makedirs(out_dir, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
     jobs = jobs or min(8, os.cpu_count() or 4)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        results = list(ex.map(_compile, srcs))
+        results = list(ex.map(lambda src: _compile(src, asan), srcs))
     for obj, err in results:
         if verbose and err:
             print(err, file=sys.stderr)
     objs = [o for o, _ in results]
-    tmp = LIB + ".tmp"
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    tmp = lib + ".tmp"
+    link = ["-Xarch_host", "-fsanitize=address", "-shared-libasan"] if asan else []
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *link, "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
+
+
+def asan_runtime():
+    """Path of the compiler's AddressSanitizer runtime (to preload), or None."""
+    hits = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    return hits[-1] if hits else None
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, asan="--asan" in sys.argv[1:]))

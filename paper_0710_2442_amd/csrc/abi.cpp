@@ -195,7 +195,7 @@ wd_status wd_gaussian_field(const wd_gauge *g, void *field, int parity, wd_prec 
 }
 
 size_t wd_halo_face_bytes(const int dims[4], wd_prec prec) {
-  if (!dims || (prec != WD_F64 && prec != WD_F32)) return 0;
+  if (check_dims(dims) != WD_OK || (prec != WD_F64 && prec != WD_F32)) return 0;
   const Geom G = make_geom(dims, -1);
   return halo_face_bytes(G, prec);
 }
