@@ -298,6 +298,11 @@ def learned_leg(wd, torch, syn, steps):
     cases = [("defect_fgcr_trained_bf16", dict(solver=wd.WD_SOLVER_DEFECT_FGCR, fgcr_m=4, inner_tol=1e-2,
                                                 precond=net)),
              ("defect_fgcr_identity", dict(solver=wd.WD_SOLVER_DEFECT_FGCR, fgcr_m=4, inner_tol=1e-2)),
+             # the same with the inner residual and directions stored in BF16
+             ("defect_fgcr_trained_bf16_store_bf16", dict(solver=wd.WD_SOLVER_DEFECT_FGCR, fgcr_m=4, inner_tol=1e-2,
+                                                          inner_prec="bf16", precond=net)),
+             ("defect_fgcr_identity_store_bf16", dict(solver=wd.WD_SOLVER_DEFECT_FGCR, fgcr_m=4, inner_tol=1e-2,
+                                                      inner_prec="bf16")),
              ("fgcr_trained_bf16", dict(solver=wd.WD_SOLVER_FGCR, fgcr_m=16, precond=net)),
              ("fgcr_identity", dict(solver=wd.WD_SOLVER_FGCR, fgcr_m=16)),
              ("fp64_cg", dict(solver=wd.WD_SOLVER_CG)),

@@ -229,8 +229,10 @@ wd_status wd_dslash_slab(const wd_gauge *U, const void *in_slab, const void *fac
  *                       even-odd Schur operator with right preconditioner
  *                       z = [precond (r_e, 0)]_e (identity if NULL);
  *                       classical Gram-Schmidt in fused kernels, FP64
- *                       reductions; inner_prec must be WD_F32; falls back to
- *                       FP64 CG when stalled or non-finite. */
+ *                       reductions; inner_prec WD_F32 or WD_BF16 stores the
+ *                       residual and the directions (z_j, w_j) in that
+ *                       precision, the inner solution stays FP32; falls back
+ *                       to FP64 CG when stalled or non-finite. */
 enum { WD_SOLVER_CG = 0, WD_SOLVER_DEFECT_CG = 1, WD_SOLVER_FGCR = 2, WD_SOLVER_DEFECT_FGCR = 3 };
 
 typedef struct wd_ptc wd_ptc;

@@ -380,8 +380,8 @@ static wd_status solve_args(const wd_gauge *U, const void *b, void *x, double ka
   if (prm.fgcr_m < 1 || prm.fgcr_m > 64) return set_error(WD_ERR_ARG, "solve: fgcr_m = %d", prm.fgcr_m);
   if (prm.solver == WD_SOLVER_DEFECT_FGCR && prm.fgcr_m > 16)
     return set_error(WD_ERR_ARG, "solve: the mixed FGCR keeps at most 16 directions (fgcr_m = %d)", prm.fgcr_m);
-  if (prm.solver == WD_SOLVER_DEFECT_FGCR && prm.inner_prec != WD_F32)
-    return set_error(WD_ERR_PREC, "solve: the mixed FGCR stores its inner vectors in FP32");
+  if (prm.solver == WD_SOLVER_DEFECT_FGCR && prm.inner_prec != WD_F32 && prm.inner_prec != WD_BF16)
+    return set_error(WD_ERR_PREC, "solve: the mixed FGCR stores its inner vectors in FP32 or BF16");
   return set_device(U);
 }
 

@@ -259,10 +259,11 @@ constexpr unsigned FG_MAX_BLOCKS = 2048;
 struct KFg {
   int vh;
   unsigned nblk;
-  const char *W[FG_MMAX];  // basis w_j (FP32 half fields)
+  const char *W[FG_MMAX];  // basis w_j (half fields, storage precision S)
   const char *Z[FG_MMAX];  // and z_j
-  char *wk, *zk;           // the new direction (updated in place)
-  char *r, *e;
+  char *wk, *zk;           // the new direction (updated in place; S)
+  char *r;                 // residual (S)
+  char *e;                 // solution (FP32)
   double *dots;    // [2 FG_MMAX]: <w_j, w_k>
   double *sig;     // [FG_MMAX]: |w_j|^2
   double *rho;     // [2]: <w_k, r>
@@ -284,26 +285,28 @@ __device__ __forceinline__ void site_dot(const cplx<float> (&a)[12], const cplx<
   }
 }
 
-template <int K>
+template <int S, int K>
 __global__ __launch_bounds__(FG_BS) void k_fg_dots(KFg a) {
+  using V = Spinor<S>;
   double acc[2 * K];
 #pragma unroll
   for (int j = 0; j < 2 * K; ++j) acc[j] = 0.0;
   for (long i = (long)blockIdx.x * FG_BS + threadIdx.x; i < a.vh; i += (long)a.nblk * FG_BS) {
     cplx<float> w[12];
-    F4::load(a.wk, i, w);
+    V::load(a.wk, i, w);
 #pragma unroll
     for (int j = 0; j < K; ++j) {
       cplx<float> v[12];
-      F4::load(a.W[j], i, v);
+      V::load(a.W[j], i, v);
       site_dot(v, w, acc[2 * j], acc[2 * j + 1]);
     }
   }
   block_sum_store<2 * K>(acc, a.partials, a.nblk, blockIdx.x);
 }
 
-template <int K>
+template <int S, int K>
 __global__ __launch_bounds__(FG_BS) void k_fg_orth(KFg a) {
+  using V = Spinor<S>;
   cplx<float> c[K > 0 ? K : 1];
 #pragma unroll
   for (int j = 0; j < K; ++j) {
@@ -314,25 +317,27 @@ __global__ __launch_bounds__(FG_BS) void k_fg_orth(KFg a) {
   double acc[3] = {0.0, 0.0, 0.0};
   for (long i = (long)blockIdx.x * FG_BS + threadIdx.x; i < a.vh; i += (long)a.nblk * FG_BS) {
     cplx<float> w[12], z[12];
-    F4::load(a.wk, i, w);
+    V::load(a.wk, i, w);
     if constexpr (K > 0) {
-      F4::load(a.zk, i, z);
+      V::load(a.zk, i, z);
 #pragma unroll
       for (int j = 0; j < K; ++j) {
         cplx<float> v[12];
         const cplx<float> m = {-c[j].re, -c[j].im};
-        F4::load(a.W[j], i, v);
+        V::load(a.W[j], i, v);
 #pragma unroll
         for (int q = 0; q < 12; ++q) cfma(w[q], m, v[q]);
-        F4::load(a.Z[j], i, v);
+        V::load(a.Z[j], i, v);
 #pragma unroll
         for (int q = 0; q < 12; ++q) cfma(z[q], m, v[q]);
       }
-      F4::store<false>(a.wk, i, w);
-      F4::store<false>(a.zk, i, z);
+      V::template store<false>(a.wk, i, w);
+      V::template store<false>(a.zk, i, z);
+      // the norms and products below see the stored (rounded) direction
+      if constexpr (S != WD_F32) V::load(a.wk, i, w);
     }
     cplx<float> r[12];
-    F4::load(a.r, i, r);
+    V::load(a.r, i, r);
 #pragma unroll
     for (int q = 0; q < 12; ++q) acc[0] += (double)w[q].re * w[q].re + (double)w[q].im * w[q].im;
     site_dot(w, r, acc[1], acc[2]);
@@ -340,7 +345,9 @@ __global__ __launch_bounds__(FG_BS) void k_fg_orth(KFg a) {
   block_sum_store<3>(acc, a.partials, a.nblk, blockIdx.x);
 }
 
+template <int S>
 __global__ __launch_bounds__(FG_BS) void k_fg_step(KFg a) {
+  using V = Spinor<S>;
   const double s = a.sig[a.k];
   const bool ok = s > 0.0 && s < 1e300;
   const cplx<float> al = {ok ? (float)(a.rho[0] / s) : 0.f, ok ? (float)(a.rho[1] / s) : 0.f};
@@ -348,19 +355,19 @@ __global__ __launch_bounds__(FG_BS) void k_fg_step(KFg a) {
   double acc[1] = {0.0};
   for (long i = (long)blockIdx.x * FG_BS + threadIdx.x; i < a.vh; i += (long)a.nblk * FG_BS) {
     cplx<float> z[12], w[12], e[12], r[12];
-    F4::load(a.zk, i, z);
+    V::load(a.zk, i, z);
     F4::load(a.e, i, e);
 #pragma unroll
     for (int q = 0; q < 12; ++q) cfma(e[q], al, z[q]);
     F4::store<false>(a.e, i, e);
-    F4::load(a.wk, i, w);
-    F4::load(a.r, i, r);
+    V::load(a.wk, i, w);
+    V::load(a.r, i, r);
 #pragma unroll
-    for (int q = 0; q < 12; ++q) {
-      cfma(r[q], ml, w[q]);
-      acc[0] += (double)r[q].re * r[q].re + (double)r[q].im * r[q].im;
-    }
-    F4::store<false>(a.r, i, r);
+    for (int q = 0; q < 12; ++q) cfma(r[q], ml, w[q]);
+    V::template store<false>(a.r, i, r);
+    if constexpr (S != WD_F32) V::load(a.r, i, r);  // |r|^2 of the stored residual
+#pragma unroll
+    for (int q = 0; q < 12; ++q) acc[0] += (double)r[q].re * r[q].re + (double)r[q].im * r[q].im;
   }
   block_sum_store<1>(acc, a.partials, a.nblk, blockIdx.x);
 }
@@ -380,39 +387,54 @@ __global__ __launch_bounds__(FG_FIN) void k_fg_finish(KFg a, int which) {
   else *a.rr = v[0];
 }
 
-template <int K>
+template <int S, int K>
 void launch_dots_k(const KFg &a, hipStream_t st) {
-  hipLaunchKernelGGL((k_fg_dots<K>), dim3(a.nblk), dim3(FG_BS), 0, st, a);
+  hipLaunchKernelGGL((k_fg_dots<S, K>), dim3(a.nblk), dim3(FG_BS), 0, st, a);
 }
-template <int K>
+template <int S, int K>
 void launch_orth_k(const KFg &a, hipStream_t st) {
-  hipLaunchKernelGGL((k_fg_orth<K>), dim3(a.nblk), dim3(FG_BS), 0, st, a);
+  hipLaunchKernelGGL((k_fg_orth<S, K>), dim3(a.nblk), dim3(FG_BS), 0, st, a);
 }
 
-template <int... Ks>
+template <int S, int... Ks>
 void launch_dots(const KFg &a, int k, hipStream_t st, std::integer_sequence<int, Ks...>) {
-  ((k == Ks + 1 ? launch_dots_k<Ks + 1>(a, st) : void()), ...);
+  ((k == Ks + 1 ? launch_dots_k<S, Ks + 1>(a, st) : void()), ...);
 }
-template <int... Ks>
+template <int S, int... Ks>
 void launch_orth(const KFg &a, int k, hipStream_t st, std::integer_sequence<int, Ks...>) {
-  ((k == Ks ? launch_orth_k<Ks>(a, st) : void()), ...);
+  ((k == Ks ? launch_orth_k<S, Ks>(a, st) : void()), ...);
 }
 
-// out = Mhat in = in - kappa^2 H_eo H_oe in   (FP32 even half fields; tmp: odd half)
-wd_status apply_mhat32(wd_gauge *g, const void *in, void *out, void *tmp, double kappa, hipStream_t st) {
+// One FGCR direction after w_k = Mhat z_k: orthogonalise against the k
+// earlier directions, then the step; FP32 arithmetic on S-stored vectors.
+template <int S>
+void fg_direction(const KFg &a, int k, hipStream_t st) {
+  if (k > 0) {
+    launch_dots<S>(a, k, st, std::make_integer_sequence<int, FG_MMAX - 1>{});
+    hipLaunchKernelGGL(k_fg_finish, dim3(2 * k), dim3(FG_FIN), 0, st, a, 0);
+  }
+  launch_orth<S>(a, k, st, std::make_integer_sequence<int, FG_MMAX>{});
+  hipLaunchKernelGGL(k_fg_finish, dim3(3), dim3(FG_FIN), 0, st, a, 1);
+  hipLaunchKernelGGL(k_fg_step<S>, dim3(a.nblk), dim3(FG_BS), 0, st, a);
+  hipLaunchKernelGGL(k_fg_finish, dim3(1), dim3(FG_FIN), 0, st, a, 2);
+}
+
+// out = Mhat in = in - kappa^2 H_eo H_oe in   (even half fields in precision
+// S, FP32 arithmetic; tmp: odd half)
+wd_status apply_mhat(wd_gauge *g, wd_prec S, const void *in, void *out, void *tmp, double kappa, hipStream_t st) {
   DslashArgs a;
   a.in = in;
   a.out = tmp;
   a.a = 1.0;
   a.parity = 1;
-  WD_TRY(launch_dslash(g, WD_F32, a, st));
+  WD_TRY(launch_dslash(g, S, a, st));
   DslashArgs b;
   b.in = tmp;
   b.out = out;
   b.X = in;
   b.a = -kappa * kappa;
   b.parity = 0;
-  return launch_dslash(g, WD_F32, b, st);
+  return launch_dslash(g, S, b, st);
 }
 
 }  // namespace
@@ -424,14 +446,16 @@ wd_status solve_fgcr_mixed(wd_gauge *g, const void *b, void *x, double kappa, do
     return set_error(WD_ERR_ARG, "FGCR: the preconditioner was created on another gauge handle");
   const int m = std::min(prm.fgcr_m, FG_MMAX);
   const Geom &G = g->geom;
-  const size_t h64 = half_bytes(G, WD_F64), h32 = half_bytes(G, WD_F32);
-  // r64, d64 (2 h64 each); rh, e (2 h32 each); R, T, Z[m], W[m] (h32 each); then the
+  const wd_prec S = prm.inner_prec;  // storage of R, T, Z, W (FP32 or BF16)
+  if (S != WD_F32 && S != WD_BF16) return set_error(WD_ERR_PREC, "FGCR: inner_prec must be FP32 or BF16");
+  const size_t h64 = half_bytes(G, WD_F64), h32 = half_bytes(G, WD_F32), hS = half_bytes(G, S);
+  // r64, d64 (2 h64 each); rh, e (2 h32 each); R, T, Z[m], W[m] (hS each); then the
   // device scalars ([0, 128) CgScalars, then dots/sig/rho/rr), the reduction partials and
   // a counter word.  Kept in the handle between solves (grown when a solve needs more).
   const unsigned nblk = (unsigned)std::min<long>(std::max<long>(1, ((long)G.vh + FG_BS - 1) / FG_BS), FG_MAX_BLOCKS);
   const size_t npart = std::max<size_t>((size_t)2 * FG_MMAX * nblk,
                                         (size_t)2 * std::max<unsigned>(dslash_grid_blocks(g), BLAS_MAX_BLOCKS));
-  const size_t vec_bytes = round_up(4 * h64 + 4 * h32 + (2 + 2 * (size_t)m) * h32, 256);
+  const size_t vec_bytes = round_up(4 * h64 + 4 * h32 + (2 + 2 * (size_t)m) * hS, 256);
   const size_t scal_bytes = 1024;
   const size_t need = vec_bytes + scal_bytes + npart * sizeof(double) + 256;
   if (!g->fg_mem || g->fg_bytes < need) {
@@ -455,14 +479,14 @@ wd_status solve_fgcr_mixed(wd_gauge *g, const void *b, void *x, double kappa, do
   WD_HIP(hipMemsetAsync(red + scal_bytes + npart * sizeof(double), 0, 256, st));
   char *c0 = (char *)g->fg_mem;
   char *r64 = c0, *d64 = c0 + 2 * h64, *rh = c0 + 4 * h64, *e32 = rh + 2 * h32;
-  char *R = e32 + 2 * h32, *T = R + h32;
-  char *E = e32;  // inner solution = even half of e32
+  char *R = e32 + 2 * h32, *T = R + hS;
+  char *E = e32;  // inner solution = even half of e32 (FP32)
   KFg a{};
   a.vh = G.vh;
   a.nblk = nblk;
   for (int k = 0; k < m; ++k) {
-    a.Z[k] = T + (1 + (size_t)k) * h32;
-    a.W[k] = T + (1 + (size_t)m + k) * h32;
+    a.Z[k] = T + (1 + (size_t)k) * hS;
+    a.W[k] = T + (1 + (size_t)m + k) * hS;
   }
   CgScalars *sc = (CgScalars *)red;
   double *ds = (double *)(red + 128);
@@ -523,39 +547,35 @@ wd_status solve_fgcr_mixed(wd_gauge *g, const void *b, void *x, double kappa, do
     // rh = r / |r|;  R = rh_e + kappa H_eo rh_o;  E = 0
     WD_TRY(blas_convert(G, WD_F64, vref(r64, 2), WD_F32, vref(rh, 2), 1.0, sc, 1, st));
     {
+      // FP32, staged in e32's odd half when R is stored in lower precision
       DslashArgs d;
       d.in = rh + h32;
-      d.out = R;
+      d.out = (S == WD_F32) ? R : e32 + h32;
       d.X = rh;
       d.a = kappa;
       d.parity = 0;
       WD_TRY(launch_dslash(g, WD_F32, d, st));
+      if (S != WD_F32) WD_TRY(blas_convert(G, WD_F32, vref(e32 + h32, 1), S, vref(R, 1), 1.0, nullptr, 1, st));
       calls += 1;
     }
     WD_HIP(hipMemsetAsync(E, 0, h32, st));
     double s2;
-    WD_TRY(blas_norm2(G, WD_F32, vref(R, 1), 1, rb, a.rr, st));
+    WD_TRY(blas_norm2(G, S, vref(R, 1), 1, rb, a.rr, st));
     WD_TRY(read(a.rr, 1, &s2));
     const double target = prm.inner_tol * prm.inner_tol * s2;
     double rr = s2, best = s2;
     int since = 0, k = 0;
     while (rr > target && it < prm.max_iter) {
       char *zk = (char *)a.Z[k], *wk = (char *)a.W[k];
-      if (N) WD_TRY(ptc_apply_even(N, R, zk, st));
-      else WD_TRY(blas_convert(G, WD_F32, vref(R, 1), WD_F32, vref(zk, 1), 1.0, nullptr, 1, st));
-      WD_TRY(apply_mhat32(g, zk, wk, T, kappa, st));
+      if (N) WD_TRY(ptc_apply_even(N, R, S, zk, S, st));
+      else WD_TRY(blas_convert(G, S, vref(R, 1), S, vref(zk, 1), 1.0, nullptr, 1, st));
+      WD_TRY(apply_mhat(g, S, zk, wk, T, kappa, st));
       calls += 2;
       a.wk = wk;
       a.zk = zk;
       a.k = k;
-      if (k > 0) {
-        launch_dots(a, k, st, std::make_integer_sequence<int, FG_MMAX - 1>{});
-        hipLaunchKernelGGL(k_fg_finish, dim3(2 * k), dim3(FG_FIN), 0, st, a, 0);
-      }
-      launch_orth(a, k, st, std::make_integer_sequence<int, FG_MMAX>{});
-      hipLaunchKernelGGL(k_fg_finish, dim3(3), dim3(FG_FIN), 0, st, a, 1);
-      hipLaunchKernelGGL(k_fg_step, dim3(a.nblk), dim3(FG_BS), 0, st, a);
-      hipLaunchKernelGGL(k_fg_finish, dim3(1), dim3(FG_FIN), 0, st, a, 2);
+      if (S == WD_F32) fg_direction<WD_F32>(a, k, st);
+      else fg_direction<WD_BF16>(a, k, st);
       WD_TRY(hip_check(hipGetLastError(), "fgcr launch"));
       WD_TRY(read(a.rr, 1, &rr));
       ++it;

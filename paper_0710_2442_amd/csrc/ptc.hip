@@ -488,13 +488,28 @@ static wd_status ptc_wgrad(const wd_ptc *n, int layer, const void *in, wd_prec p
 void ptc_release(wd_gauge *) {}
 
 // Even-parity restriction of the network for the even-odd solver:
-// out_e = [N (in_e, 0)]_e, F32 half fields.  The input's odd half is never
-// read (layer 1 knows it is zero) and layer 2 computes even sites only.
-wd_status ptc_apply_even(const wd_ptc *n, const void *in_even, void *out_even, hipStream_t st) {
+// out_e = [N (in_e, 0)]_e on half fields, input in pin and output in pout
+// (FP32 or BF16).  The input's odd half is never read (layer 1 knows it is
+// zero; with INPAR = 0 every read of the input lands in its even half, so a
+// half field is a valid input) and layer 2 computes even sites only.  An
+// input already in the activation precision is read in place.
+template <int PA, int PO>
+static void launch_even_l2(const KPtc &k, dim3 grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_ptc_layer<PA, PO, 2, 1>), grid, dim3(PTC_BS), 0, st, k);
+}
+
+wd_status ptc_apply_even(const wd_ptc *n, const void *in_even, wd_prec pin, void *out_even, wd_prec pout,
+                         hipStream_t st) {
   const Geom &G = n->g->geom;
-  WD_TRY(blas_convert(G, WD_F32, vref(in_even, 1), n->act, vref(n->x0, 1), 1.0, nullptr, 1, st));
+  if ((pin != WD_F32 && pin != WD_BF16) || (pout != WD_F32 && pout != WD_BF16))
+    return set_error(WD_ERR_PREC, "ptc even: FP32 or BF16 fields");
+  const void *x0 = in_even;
+  if (pin != n->act) {
+    WD_TRY(blas_convert(G, pin, vref(in_even, 1), n->act, vref(n->x0, 1), 1.0, nullptr, 1, st));
+    x0 = n->x0;
+  }
   KPtc k = ptc_k(n);
-  k.in = (const char *)n->x0;
+  k.in = (const char *)x0;
   k.out = (char *)n->y1;
   k.in_half = half_bytes(G, n->act);
   k.out_half = k.in_half;
@@ -510,12 +525,17 @@ wd_status ptc_apply_even(const wd_ptc *n, const void *in_even, void *out_even, h
   k2.out = (char *)out_even;
   k2.in_half = half_bytes(G, n->act);
   k2.in_chan = 2 * k2.in_half;
-  k2.out_half = half_bytes(G, WD_F32);
+  k2.out_half = half_bytes(G, pout);
   k2.out_chan = 2 * k2.out_half;
   k2.W = n->W + 576;
   const dim3 grid_e(grid.x, 1);  // parity 0 only
-  if (n->act == WD_BF16) hipLaunchKernelGGL((k_ptc_layer<WD_BF16, WD_F32, 2, 1>), grid_e, dim3(PTC_BS), 0, st, k2);
-  else hipLaunchKernelGGL((k_ptc_layer<WD_F32, WD_F32, 2, 1>), grid_e, dim3(PTC_BS), 0, st, k2);
+  if (n->act == WD_BF16) {
+    if (pout == WD_BF16) launch_even_l2<WD_BF16, WD_BF16>(k2, grid_e, st);
+    else launch_even_l2<WD_BF16, WD_F32>(k2, grid_e, st);
+  } else {
+    if (pout == WD_BF16) launch_even_l2<WD_F32, WD_BF16>(k2, grid_e, st);
+    else launch_even_l2<WD_F32, WD_F32>(k2, grid_e, st);
+  }
   return hip_check(hipGetLastError(), "ptc layer");
 }
 

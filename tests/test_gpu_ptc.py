@@ -208,14 +208,16 @@ def test_fgcr_falls_back_to_cg(bad):
 # ------------------------------------------------- mixed-precision even-odd FGCR
 @pytest.mark.parametrize("dims", [(8, 8, 8, 8), (6, 4, 6, 10)])
 @pytest.mark.parametrize("net", [None, "f32", "bf16"])
-def test_defect_fgcr_reaches_fp64_residual(dims, net):
-    """FP32 eo-FGCR inside FP64 defect correction: the oracle's own D_W must
-    see a true residual <= 1e-10, the reported residual must agree, and the
-    solution must agree with the oracle's FP64 eo-CGLS solution."""
+@pytest.mark.parametrize("store", ["f32", "bf16"])
+def test_defect_fgcr_reaches_fp64_residual(dims, net, store):
+    """FP32-arithmetic eo-FGCR (inner vectors stored in FP32 or BF16) inside
+    FP64 defect correction: the oracle's own D_W must see a true residual
+    <= 1e-10, the reported residual must agree, and the solution must agree
+    with the oracle's FP64 eo-CGLS solution."""
     kappa = 0.124
     flat = None if net is None else wd.ptc_weights_to_flat(*ptc.init_weights(353))
     U, b, x, rc, info = _fgcr(dims, kappa, flat, net or "bf16", m=8, solver=wd.WD_SOLVER_DEFECT_FGCR,
-                              inner_tol=1e-3)
+                              inner_tol=1e-3 if store == "f32" else 1e-2, inner_prec=store)
     assert rc == 0 and info["fallback_used"] == 0, info
     r = solvers.true_residual(U, b, x, kappa)
     assert r <= 1e-10
@@ -226,17 +228,19 @@ def test_defect_fgcr_reaches_fp64_residual(dims, net):
 
 
 @pytest.mark.parametrize("m", [1, 4, 16])
-def test_defect_fgcr_restart_lengths(m):
-    U, b, x, rc, info = _fgcr((8, 8, 8, 8), 0.124, None, m=m, solver=wd.WD_SOLVER_DEFECT_FGCR)
+@pytest.mark.parametrize("store", ["f32", "bf16"])
+def test_defect_fgcr_restart_lengths(m, store):
+    U, b, x, rc, info = _fgcr((8, 8, 8, 8), 0.124, None, m=m, solver=wd.WD_SOLVER_DEFECT_FGCR, inner_prec=store)
     assert rc == 0 and info["fallback_used"] == 0
     assert solvers.true_residual(U, b, x, 0.124) <= 1e-10
 
 
-def test_defect_fgcr_is_deterministic():
+@pytest.mark.parametrize("store", ["f32", "bf16"])
+def test_defect_fgcr_is_deterministic(store):
     a = _fgcr((8, 8, 8, 8), 0.124, wd.ptc_weights_to_flat(*ptc.init_weights(354)), "bf16", m=8,
-              solver=wd.WD_SOLVER_DEFECT_FGCR)
+              solver=wd.WD_SOLVER_DEFECT_FGCR, inner_prec=store)
     b = _fgcr((8, 8, 8, 8), 0.124, wd.ptc_weights_to_flat(*ptc.init_weights(354)), "bf16", m=8,
-              solver=wd.WD_SOLVER_DEFECT_FGCR)
+              solver=wd.WD_SOLVER_DEFECT_FGCR, inner_prec=store)
     assert a[4]["iters"] == b[4]["iters"] and np.array_equal(a[2], b[2])
 
 
@@ -245,7 +249,7 @@ def test_defect_fgcr_rejects_bad_parameters():
     g = wd.Gauge(syn.gauge_field(dims, 0.3, 355), dims, -1, "f64")
     fb = to_field(g, syn.gaussian_spinor(dims, 356))
     fx = wd.wd_new_field(dims, "f64")
-    for kw in (dict(fgcr_m=17), dict(inner_prec="f16"), dict(inner_prec="bf16")):
+    for kw in (dict(fgcr_m=17), dict(inner_prec="f16"), dict(inner_prec="f64")):
         p = wd.wd_solve_params_default(solver=wd.WD_SOLVER_DEFECT_FGCR, **kw)
         with pytest.raises(wd.WdError):
             wd.wd_solve(g, fb, fx, 0.124, 1e-10, p)
