@@ -231,8 +231,10 @@ wd_status wd_dslash_slab(const wd_gauge *U, const void *in_slab, const void *fac
  *                       classical Gram-Schmidt in fused kernels, FP64
  *                       reductions; inner_prec WD_F32 or WD_BF16 stores the
  *                       residual and the directions (z_j, w_j) in that
- *                       precision, the inner solution stays FP32; falls back
- *                       to FP64 CG when stalled or non-finite. */
+ *                       precision, the inner solution stays FP32 (with
+ *                       WD_BF16 and a BF16-activation network, the network
+ *                       runs as wd_ptc_apply_even with WD_PTC_FP16_PRODUCTS);
+ *                       falls back to FP64 CG when stalled or non-finite. */
 enum { WD_SOLVER_CG = 0, WD_SOLVER_DEFECT_CG = 1, WD_SOLVER_FGCR = 2, WD_SOLVER_DEFECT_FGCR = 3 };
 
 typedef struct wd_ptc wd_ptc;
@@ -299,6 +301,19 @@ wd_status wd_ptc_set_weights(wd_ptc *n, const float *W_host);
 wd_status wd_ptc_get_weights(const wd_ptc *n, float *W_host);
 /* out = N(in); asynchronous */
 wd_status wd_ptc_apply(const wd_ptc *n, const void *in, void *out);
+
+/* Flag of wd_ptc_apply_even: products in FP16 with FP32 sums, on FP16 copies
+ * of the links and weights (made on first use; the links copy takes 192 B
+ * per site).  The input is scaled to unit RMS before it is rounded (the
+ * network is linear) and the output scaled back.  BF16 activations only. */
+enum { WD_PTC_FP16_PRODUCTS = 1 };
+
+/* out_e = [N (in_e, 0)]_e: the network applied to a field that is zero on
+ * odd sites, even sites of the result only, as the even-odd solver uses it.
+ * in_even, out_even: even half fields in pin / pout (WD_F32 or WD_BF16).
+ * flags: 0 or WD_PTC_FP16_PRODUCTS.  Asynchronous on the handle's stream. */
+wd_status wd_ptc_apply_even(const wd_ptc *n, const void *in_even, wd_prec pin,
+                            void *out_even, wd_prec pout, int flags);
 /* Loss L = (1/B) sum_b |N(r_b) - e_b|^2 over B pairs (r and e: B consecutive
  * FP32 full fields each) and its gradient dL/dRe W + i dL/dIm W (1152 floats,
  * host; may be NULL).  Synchronous. */

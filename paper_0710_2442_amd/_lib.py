@@ -28,6 +28,7 @@ WD_ONE_PASS = 2
 WD_TUNE_CACHED_STORE = 256
 WD_TUNE_PRELOAD_LINKS = 512
 WD_TUNE_SPL_SHIFT = 10
+WD_PTC_FP16_PRODUCTS = 1
 WD_SOLVER_CG, WD_SOLVER_DEFECT_CG, WD_SOLVER_FGCR, WD_SOLVER_DEFECT_FGCR = 0, 1, 2, 3
 
 _vp = C.c_void_p
@@ -105,6 +106,7 @@ _decl("wd_ptc_destroy", C.c_int, [_vp])
 _decl("wd_ptc_set_weights", C.c_int, [_vp, C.POINTER(C.c_float)])
 _decl("wd_ptc_get_weights", C.c_int, [_vp, C.POINTER(C.c_float)])
 _decl("wd_ptc_apply", C.c_int, [_vp, _vp, _vp])
+_decl("wd_ptc_apply_even", C.c_int, [_vp, _vp, C.c_int, _vp, C.c_int, C.c_int])
 _decl("wd_ptc_loss_grad", C.c_int, [_vp, _vp, _vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_float)])
 _decl("wd_ptc_train_step", C.c_int, [_vp, _vp, _vp, C.c_int, C.c_double, C.POINTER(C.c_double)])
 _decl("wd_gaussian_field", C.c_int, [_vp, _vp, C.c_int, C.c_int, C.c_ulonglong, C.c_ulonglong])
@@ -459,6 +461,13 @@ def wd_ptc_get_weights(n):
 def wd_ptc_apply(n, x, y):
     n.g.sync_stream()
     _check(lib.wd_ptc_apply(n.handle, _ptr(x), _ptr(y)), "wd_ptc_apply")
+
+
+def wd_ptc_apply_even(n, x_even, pin, y_even, pout, flags=0):
+    """y_e = [N(x_e, 0)]_e on even half fields (flags: 0 or WD_PTC_FP16_PRODUCTS)."""
+    n.g.sync_stream()
+    _check(lib.wd_ptc_apply_even(n.handle, _ptr(x_even), _prec(pin), _ptr(y_even), _prec(pout), int(flags)),
+           "wd_ptc_apply_even")
 
 
 def wd_ptc_loss_grad(n, r, e, B):

@@ -567,7 +567,8 @@ wd_status solve_fgcr_mixed(wd_gauge *g, const void *b, void *x, double kappa, do
     int since = 0, k = 0;
     while (rr > target && it < prm.max_iter) {
       char *zk = (char *)a.Z[k], *wk = (char *)a.W[k];
-      if (N) WD_TRY(ptc_apply_even(N, R, S, zk, S, st));
+      if (N && S == WD_BF16 && ptc_act(N) == WD_BF16) WD_TRY(ptc_apply_even_h(N, R, zk, S, a.rr, st));
+      else if (N) WD_TRY(ptc_apply_even(N, R, S, zk, S, st));
       else WD_TRY(blas_convert(G, S, vref(R, 1), S, vref(zk, 1), 1.0, nullptr, 1, st));
       WD_TRY(apply_mhat(g, S, zk, wk, T, kappa, st));
       calls += 2;

@@ -403,6 +403,217 @@ __global__ void k_adam(float *w, const float *g, float *m, float *v, int n, floa
   w[j] -= lr * (mj / c1) / (sqrtf(vj / c2) + eps);
 }
 
+
+// ------------------------------------------------- FP16-product inference
+// The even-parity application inside the solver may take its products in
+// FP16 with FP32 sums (v_dot2_f32_f16: two products and an FP32 add in one
+// instruction, twice the rate of FP32 FMAs) on FP16 copies of the links and
+// weights.  The network is linear, so the input is scaled to unit RMS before
+// it is rounded to FP16 (a small residual would otherwise sink into FP16's
+// subnormal range) and the output is scaled back.
+typedef __fp16 hv2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ hv2 pkh(float a, float b) { return __builtin_amdgcn_cvt_pkrtz(a, b); }
+__device__ __forceinline__ hv2 as_hv2(uint32_t u) { return __builtin_bit_cast(hv2, u); }
+
+// v packed for products with a (re, im) pair w:
+//   acc.re += w.re v.re - w.im v.im = dot(w, (v.re, -v.im))
+//   acc.im += w.re v.im + w.im v.re = dot(w, (v.im, v.re))
+struct HPk {
+  hv2 a, b;
+};
+__device__ __forceinline__ HPk hpk(float re, float im) { return {pkh(re, -im), pkh(im, re)}; }
+__device__ __forceinline__ void hmac(cplx<float> &acc, hv2 w, const HPk &v) {
+  acc.re = __builtin_amdgcn_fdot2(w, v.a, acc.re, false);
+  acc.im = __builtin_amdgcn_fdot2(w, v.b, acc.im, false);
+}
+
+struct KPtcH {
+  Geom g;
+  const uint2 *links16;  // per parity: [chunk of 64 sites][d][3 packets][64 lanes], 2 (re, im) FP16 pairs each
+  size_t link16_par;     // uint2 per parity
+  const char *in;        // layer 1: even half (BF16); layer 2: 2 full-field channels (BF16)
+  char *out;
+  size_t in_half, in_chan, out_half, out_chan;
+  const uint32_t *W16;   // this layer's weights as (re, im) FP16 pairs, same order as the FP32 weights
+  const double *norm2;   // |network input|^2
+  double nreal;          // real components of the network input
+};
+
+// input scale: sqrt(nreal / |x|^2), so the scaled input has unit RMS
+__device__ __forceinline__ float ptc_h_scale(const KPtcH &k) {
+  const double n2 = *k.norm2;
+  return (n2 > 0.0 && n2 < 1e300) ? (float)sqrt(k.nreal / n2) : 1.0f;
+}
+
+__device__ __forceinline__ size_t link16_at(int d, int q, int i) {
+  return ((size_t)(i >> 6) * 24 + (size_t)(d * 3 + q)) * 64 + (size_t)(i & 63);
+}
+
+// FP16 hop link d at output site (p, i): rows 0-1 as stored, row 2 rebuilt
+// in FP32 from them (u[3a + b] = M_ab)
+__device__ __forceinline__ void link_h(const KPtcH &k, int p, int d, int i, hv2 (&u)[9]) {
+  const uint2 *b = k.links16 + (size_t)p * k.link16_par;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const uint2 w = b[link16_at(d, q, i)];
+    u[2 * q] = as_hv2(w.x);
+    u[2 * q + 1] = as_hv2(w.y);
+  }
+  cplx<float> f[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) f[j] = {(float)u[j].x, (float)u[j].y};
+  cplx<float> r2[3];
+  rebuild_row2(f, r2);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) u[6 + a] = pkh(r2[a].re, r2[a].im);
+}
+
+// y = sg U v on every spin
+__device__ __forceinline__ void transport_h(const hv2 (&u)[9], const HPk (&v)[12], float sg, cplx<float> (&y)[12]) {
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cplx<float> acc = {0.f, 0.f};
+#pragma unroll
+      for (int b = 0; b < 3; ++b) hmac(acc, u[3 * a + b], v[3 * sp + b]);
+      y[3 * sp + a] = {sg * acc.re, sg * acc.im};
+    }
+}
+
+// acc += W v, W: a 4x4 spin matrix as 16 packed (re, im) pairs
+__device__ __forceinline__ void spin_mat_h(const uint32_t *W, const HPk (&v)[12], cplx<float> (&acc)[12]) {
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const hv2 w = as_hv2(W[4 * sp + t]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) hmac(acc[3 * sp + a], w, v[3 * t + a]);
+    }
+}
+
+__device__ __forceinline__ void load_h(const char *base, int i, float sc, HPk (&v)[12]) {
+  cplx<float> x[12];
+  Spinor<WD_BF16>::load(base, i, x);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) v[c] = hpk(sc * x[c].re, sc * x[c].im);
+}
+
+// Layer 1 of [N (x_e, 0)]_e (1 -> 2 channels, both parities, BF16 out): an
+// even site takes only W^(0) x, an odd site only the 8 hops from its even
+// neighbours.
+__global__ __launch_bounds__(PTC_BS) void k_ptc_h_l1(KPtcH k) {
+  const int p = blockIdx.y;
+  const int i = blockIdx.x * PTC_BS + threadIdx.x;
+  if (i >= k.g.vpad) return;
+  cplx<float> acc[2][12];
+#pragma unroll
+  for (int co = 0; co < 2; ++co)
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[co][c] = {0.f, 0.f};
+  if (i < k.g.vh) {
+    const float sc = ptc_h_scale(k);
+    if (p == 0) {
+      HPk v[12];
+      load_h(k.in, i, sc, v);
+#pragma unroll
+      for (int co = 0; co < 2; ++co) spin_mat_h(k.W16 + 16 * co, v, acc[co]);
+    } else {
+      const PtcSite s = ptc_site(k.g, i, 1);
+      for (int d = 0; d < 8; ++d) {
+        HPk v[12];
+        load_h(k.in, s.nb[d], sc, v);
+        hv2 u[9];
+        link_h(k, 1, d, i, u);
+        const float sg = (d == 3) ? s.sf : ((d == 7) ? s.sb : 1.0f);
+        cplx<float> y[12];
+        transport_h(u, v, sg, y);
+        HPk yv[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) yv[c] = hpk(y[c].re, y[c].im);
+#pragma unroll
+        for (int co = 0; co < 2; ++co) spin_mat_h(k.W16 + 16 * ((d + 1) * 2 + co), yv, acc[co]);
+      }
+    }
+  }
+#pragma unroll
+  for (int co = 0; co < 2; ++co) Spinor<WD_BF16>::store(k.out + co * k.out_chan + (size_t)p * k.out_half, i, acc[co]);
+}
+
+// Layer 2 (2 -> 1 channels, even sites only; spins mixed before the
+// transport), output scaled back and stored in POUT.
+template <int POUT>
+__global__ __launch_bounds__(PTC_BS) void k_ptc_h_l2(KPtcH k) {
+  const int i = blockIdx.x * PTC_BS + threadIdx.x;
+  if (i >= k.g.vpad) return;
+  cplx<float> acc[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[c] = {0.f, 0.f};
+  if (i < k.g.vh) {
+    const PtcSite s = ptc_site(k.g, i, 0);
+#pragma unroll
+    for (int ci = 0; ci < 2; ++ci) {
+      HPk v[12];
+      load_h(k.in + ci * k.in_chan, i, 1.0f, v);
+      spin_mat_h(k.W16 + 16 * ci, v, acc);
+    }
+    for (int d = 0; d < 8; ++d) {
+      cplx<float> m[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) m[c] = {0.f, 0.f};
+#pragma unroll
+      for (int ci = 0; ci < 2; ++ci) {
+        HPk v[12];
+        load_h(k.in + ci * k.in_chan + k.in_half, s.nb[d], 1.0f, v);
+        spin_mat_h(k.W16 + 16 * ((d + 1) * 2 + ci), v, m);
+      }
+      HPk mv[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) mv[c] = hpk(m[c].re, m[c].im);
+      hv2 u[9];
+      link_h(k, 0, d, i, u);
+      const float sg = (d == 3) ? s.sf : ((d == 7) ? s.sb : 1.0f);
+      cplx<float> y[12];
+      transport_h(u, mv, sg, y);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) acc[c] = acc[c] + y[c];
+    }
+    const float inv = 1.0f / ptc_h_scale(k);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = {inv * acc[c].re, inv * acc[c].im};
+  }
+  cplx<RealOf<POUT>> o[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) o[c] = {(RealOf<POUT>)acc[c].re, (RealOf<POUT>)acc[c].im};
+  Spinor<POUT>::store(k.out, i, o);
+}
+
+// FP16 copies: the hop links of both parities, and the weights
+__global__ __launch_bounds__(256) void k_ptc_links16(const char *links32, size_t link_par, Geom g, uint2 *links16,
+                                                      size_t link16_par) {
+  const int p = blockIdx.y;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= g.vpad) return;
+  for (int d = 0; d < 8; ++d) {
+    cplx<float> u[6];
+    if (i < g.vh) Link<float>::load<false>(links32 + (size_t)p * link_par, d, i, u);
+    else
+      for (int j = 0; j < 6; ++j) u[j] = {0.f, 0.f};
+    for (int q = 0; q < 3; ++q) {
+      const hv2 a = pkh(u[2 * q].re, u[2 * q].im), b = pkh(u[2 * q + 1].re, u[2 * q + 1].im);
+      links16[(size_t)p * link16_par + link16_at(d, q, i)] =
+          uint2{__builtin_bit_cast(uint32_t, a), __builtin_bit_cast(uint32_t, b)};
+    }
+  }
+}
+
+__global__ void k_ptc_w16(const float *W, uint32_t *W16, int n) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) W16[j] = __builtin_bit_cast(uint32_t, pkh(W[2 * j], W[2 * j + 1]));
+}
+
 }  // namespace wd
 
 // ============================================================ host side
@@ -421,6 +632,12 @@ struct wd_ptc {
   double *scal;                    // [0] loss; [64..] reduction partials
   unsigned *cnt;
   int nblk;                        // blocks of a full-lattice launch (both parities)
+  // FP16-product inference (made on first use): FP16 hop links of both
+  // parities, FP16 weights, and the input norm with its reduction partials
+  uint2 *links16;
+  uint32_t *W16;
+  double *hnorm;
+  unsigned *hcnt;
 };
 
 namespace wd {
@@ -539,6 +756,62 @@ wd_status ptc_apply_even(const wd_ptc *n, const void *in_even, wd_prec pin, void
   return hip_check(hipGetLastError(), "ptc layer");
 }
 
+static size_t links16_per_parity(const Geom &G) { return (size_t)G.vpad / 64 * 24 * 64; }
+
+// FP16 links (once per handle) and FP16 weights (every call: training may
+// have changed the weights)
+static wd_status ptc_h_prepare(wd_ptc *n, hipStream_t st) {
+  const Geom &G = n->g->geom;
+  if (!n->links16) {
+    const size_t par = links16_per_parity(G);
+    WD_HIP(hipMalloc(&n->links16, 2 * par * sizeof(uint2)));
+    WD_HIP(hipMalloc(&n->W16, 576 * sizeof(uint32_t)));
+    hipLaunchKernelGGL(k_ptc_links16, dim3((G.vpad + 255) / 256, 2), dim3(256), 0, st, (const char *)n->g->links32,
+                       link_parity_bytes(G, false), G, n->links16, par);
+    WD_TRY(hip_check(hipGetLastError(), "ptc fp16 links"));
+  }
+  hipLaunchKernelGGL(k_ptc_w16, dim3(3), dim3(192), 0, st, (const float *)n->W, n->W16, 576);
+  return hip_check(hipGetLastError(), "ptc fp16 weights");
+}
+
+// [N (x_e, 0)]_e with FP16 products and FP32 sums: x_e a BF16 even half
+// field, norm2 -> |x_e|^2 on the device (sets the input scale), output in
+// pout (FP32 or BF16).  Needs BF16 activations.
+wd_status ptc_apply_even_h(const wd_ptc *nc, const void *in_even, void *out_even, wd_prec pout, const double *norm2,
+                           hipStream_t st) {
+  wd_ptc *n = const_cast<wd_ptc *>(nc);  // the FP16 copies are caches of the handle's own data
+  if (n->act != WD_BF16) return set_error(WD_ERR_PREC, "FP16-product network: BF16 activations only");
+  if (pout != WD_F32 && pout != WD_BF16) return set_error(WD_ERR_PREC, "FP16-product network: FP32 or BF16 output");
+  WD_TRY(ptc_h_prepare(n, st));
+  const Geom &G = n->g->geom;
+  KPtcH k{};
+  k.g = G;
+  k.links16 = n->links16;
+  k.link16_par = links16_per_parity(G);
+  k.in = (const char *)in_even;
+  k.out = (char *)n->y1;
+  k.out_half = half_bytes(G, WD_BF16);
+  k.out_chan = 2 * k.out_half;
+  k.W16 = n->W16;
+  k.norm2 = norm2;
+  k.nreal = 24.0 * (double)G.vh;
+  const dim3 grid = ptc_grid(G);
+  hipLaunchKernelGGL(k_ptc_h_l1, grid, dim3(PTC_BS), 0, st, k);
+  WD_TRY(hip_check(hipGetLastError(), "ptc fp16 layer 1"));
+  KPtcH k2 = k;
+  k2.in = (const char *)n->y1;
+  k2.in_half = half_bytes(G, WD_BF16);
+  k2.in_chan = 2 * k2.in_half;
+  k2.out = (char *)out_even;
+  k2.out_half = half_bytes(G, pout);
+  k2.out_chan = 2 * k2.out_half;
+  k2.W16 = n->W16 + 288;
+  const dim3 grid_e(grid.x, 1);
+  if (pout == WD_BF16) hipLaunchKernelGGL(k_ptc_h_l2<WD_BF16>, grid_e, dim3(PTC_BS), 0, st, k2);
+  else hipLaunchKernelGGL(k_ptc_h_l2<WD_F32>, grid_e, dim3(PTC_BS), 0, st, k2);
+  return hip_check(hipGetLastError(), "ptc fp16 layer 2");
+}
+
 // N(in): F32 full field -> F32 full field; input and hidden layer are stored
 // in the activation precision.
 wd_status ptc_apply(const wd_ptc *n, const void *in, void *out, hipStream_t st) {
@@ -575,7 +848,8 @@ static wd_status ptc_alloc(wd_ptc *n) {
 }
 
 static void ptc_free(wd_ptc *n) {
-  void *ps[] = {n->Wc, n->gradc, n->W, n->Wadj, n->grad, n->m, n->v, n->x0, n->y1, n->y2, n->gy2, n->gy1, n->partials, n->scal, n->cnt};
+  void *ps[] = {n->Wc,  n->gradc, n->W,  n->Wadj,     n->grad, n->m,   n->v,       n->x0,  n->y1,    n->y2,
+                n->gy2, n->gy1,   n->partials, n->scal, n->cnt, n->links16, n->W16, n->hnorm, n->hcnt};
   for (void *p : ps)
     if (p) (void)hipFree(p);
   delete n;
@@ -694,6 +968,34 @@ wd_status wd_ptc_apply(const wd_ptc *n, const void *in, void *out) {
   return ptc_apply(n, in, out, n->g->stream);
 }
 
+wd_status wd_ptc_apply_even(const wd_ptc *n, const void *in_even, wd_prec pin, void *out_even, wd_prec pout,
+                            int flags) {
+  if (!n || !in_even || !out_even) return set_error(WD_ERR_ARG, "NULL argument");
+  if (in_even == out_even) return set_error(WD_ERR_ARG, "ptc_apply_even: in and out must differ");
+  if (flags & ~WD_PTC_FP16_PRODUCTS) return set_error(WD_ERR_ARG, "ptc_apply_even: unknown flags 0x%x", flags);
+  if ((pin != WD_F32 && pin != WD_BF16) || (pout != WD_F32 && pout != WD_BF16))
+    return set_error(WD_ERR_PREC, "ptc_apply_even: FP32 or BF16 fields");
+  if ((flags & WD_PTC_FP16_PRODUCTS) && n->act != WD_BF16)
+    return set_error(WD_ERR_PREC, "ptc_apply_even: FP16 products need BF16 activations");
+  WD_HIP(hipSetDevice(n->g->device));
+  hipStream_t st = n->g->stream;
+  if (!(flags & WD_PTC_FP16_PRODUCTS)) return ptc_apply_even(n, in_even, pin, out_even, pout, st);
+  wd_ptc *m = const_cast<wd_ptc *>(n);
+  const Geom &G = n->g->geom;
+  if (!m->hnorm) {
+    WD_HIP(hipMalloc(&m->hnorm, (64 + 2 * (size_t)BLAS_MAX_BLOCKS) * sizeof(double)));
+    WD_HIP(hipMalloc(&m->hcnt, 256));
+    WD_HIP(hipMemset(m->hcnt, 0, 256));
+  }
+  const void *x = in_even;
+  if (pin != WD_BF16) {
+    WD_TRY(blas_convert(G, pin, vref(in_even, 1), WD_BF16, vref(m->x0, 1), 1.0, nullptr, 1, st));
+    x = m->x0;
+  }
+  WD_TRY(blas_norm2(G, WD_BF16, vref(x, 1), 1, RedBuf{m->hnorm + 64, m->hcnt}, m->hnorm, st));
+  return ptc_apply_even_h(n, x, out_even, pout, m->hnorm, st);
+}
+
 wd_status wd_ptc_loss_grad(wd_ptc *n, const void *r, const void *e, int B, double *loss, float *grad_host) {
   WD_TRY(check_pair_args(n, r, e, B));
   hipStream_t st = n->g->stream;
@@ -731,4 +1033,5 @@ wd_status wd_ptc_train_step(wd_ptc *n, const void *r, const void *e, int B, doub
 
 namespace wd {
 const wd_gauge *ptc_gauge(const wd_ptc *n) { return n->g; }
+wd_prec ptc_act(const wd_ptc *n) { return n->act; }
 }  // namespace wd

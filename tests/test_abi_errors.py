@@ -148,6 +148,11 @@ def test_error_paths_under_host_address_sanitizer():
     rt = B.asan_runtime()
     if not os.path.exists(B.ASAN_LIB) or rt is None:
         pytest.skip("no host-ASan build (python paper_0710_2442_amd/build.py --asan)")
+    import glob
+
+    srcs = glob.glob(os.path.join(B.CSRC, "*")) + [HEADER]
+    if max(os.path.getmtime(f) for f in srcs) > os.path.getmtime(B.ASAN_LIB):
+        pytest.skip("the host-ASan build is older than the sources (python paper_0710_2442_amd/build.py --asan)")
     env = dict(os.environ, WD_LIB=B.ASAN_LIB, LD_PRELOAD=rt, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
     p = subprocess.run([sys.executable, "-m", "pytest", "-q", "-p", "no:cacheprovider", os.path.abspath(__file__)],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)

@@ -59,6 +59,45 @@ def test_forward_matches_oracle(act):
     g.close()
 
 
+@pytest.mark.parametrize("dims", [(6, 4, 6, 10), (8, 8, 8, 8)])
+@pytest.mark.parametrize("scale", [1.0, 1e-7])
+def test_even_application_matches_oracle(dims, scale):
+    """[N(x_e, 0)]_e, as the even-odd solver applies the network, against the
+    oracle's full network on a field that is zero on odd sites.
+
+    FP32 products (flags 0): the bar of the BF16 forward test (2e-3).  FP16
+    products with FP32 sums: every operand of a product chain (input, link,
+    transported spinor, weight, mixed spinor, link, weight: 7) is rounded
+    toward zero to 11 significant bits, a relative error below 2^-10 each
+    and biased one way, so up to 7 * 2^-10 ~ 7e-3 on a component; bar 1e-2.
+    A tiny input (1e-7) checks the scaling to unit RMS: without it the FP16
+    operands would underflow."""
+    U = syn.gauge_field(dims, 0.3, 305)
+    x = syn.gaussian_spinor(dims, 306) * scale
+    W1, W2 = _weights(307)
+    g = wd.Gauge(U, dims, -1, "f32")
+    n = wd.Ptc(g, wd.ptc_weights_to_flat(W1, W2), "bf16")
+    fx = to_field(g, x, "f32", wd.WD_EVEN)
+    even = wilson.parity_mask(dims, 0)
+    xe = storage_round(x * even, "f32")
+    want = ptc.network(round_c64(U), xe, W1, W2, act_round=_bf16) * even
+    for flags, bar in ((0, 2e-3), (wd.WD_PTC_FP16_PRODUCTS, 1e-2)):
+        for pout in ("f32", "bf16"):
+            fy = wd.wd_new_field(dims, pout, 1, wd.WD_EVEN)
+            wd.wd_ptc_apply_even(n, fx, "f32", fy, pout, flags)
+            got = from_field(g, fy, pout, wd.WD_EVEN)
+            extra = 2.0 ** -8 if pout == "bf16" else 0.0  # the stored output's own rounding
+            assert rel_err(got, want) <= bar + extra, (flags, pout, rel_err(got, want))
+    with pytest.raises(wd.WdError):  # FP16 products need BF16 activations
+        n32 = wd.Ptc(g, wd.ptc_weights_to_flat(W1, W2), "f32")
+        try:
+            wd.wd_ptc_apply_even(n32, fx, "f32", fy, "f32", wd.WD_PTC_FP16_PRODUCTS)
+        finally:
+            n32.close()
+    n.close()
+    g.close()
+
+
 def test_gauge_equivariance_on_gpu():
     U = syn.gauge_field(DIMS, 0.3, 311)
     r = syn.gaussian_spinor(DIMS, 312)
