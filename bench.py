@@ -43,8 +43,9 @@ BYTES_PER_SITE = {"f64": 144 * 8, "f32": 144 * 4}
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "dslash_hop_32x32x32x64_traffic.txt")
 # pre-tuned hop variants for MI355X (written by wd_tune_dslash; used without re-timing)
 TUNE_TABLE = os.path.join(ROOT, "paper_0710_2442_amd", "tuned", "mi355x_hop.jsonl")
+# what the hop kernel is built from: its sources and the compile flags
 KERNEL_SOURCES = ["paper_0710_2442_amd/csrc/dslash.hip", "paper_0710_2442_amd/csrc/wd_hop.h",
-                  "paper_0710_2442_amd/csrc/wd_device.h", "paper_0710_2442_amd/build.py"]
+                  "paper_0710_2442_amd/csrc/wd_device.h"]
 
 
 def log(*a):
@@ -52,10 +53,16 @@ def log(*a):
 
 
 def kernel_hash():
+    """Hash of the hop kernel's sources and of the hipcc flags it is built with
+    (the flags, not the whole build script, so build options that leave the
+    library unchanged do not invalidate the counter summary)."""
+    from paper_0710_2442_amd import build as B
+
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
+    h.update(" ".join(B.HIP_FLAGS).replace(ROOT, "<root>").encode())
     return h.hexdigest()[:16]
 
 
