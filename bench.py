@@ -523,8 +523,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (its time-slab "
+              "decomposition, wd_halo_pack / wd_dslash_slab, runs a rank's share on one GPU).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
