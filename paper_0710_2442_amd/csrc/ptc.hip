@@ -450,25 +450,6 @@ __device__ __forceinline__ size_t link16_at(int d, int q, int i) {
   return ((size_t)(i >> 6) * 24 + (size_t)(d * 3 + q)) * 64 + (size_t)(i & 63);
 }
 
-// FP16 hop link d at output site (p, i): rows 0-1 as stored, row 2 rebuilt
-// in FP32 from them (u[3a + b] = M_ab)
-__device__ __forceinline__ void link_h(const KPtcH &k, int p, int d, int i, hv2 (&u)[9]) {
-  const uint2 *b = k.links16 + (size_t)p * k.link16_par;
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    const uint2 w = b[link16_at(d, q, i)];
-    u[2 * q] = as_hv2(w.x);
-    u[2 * q + 1] = as_hv2(w.y);
-  }
-  cplx<float> f[6];
-#pragma unroll
-  for (int j = 0; j < 6; ++j) f[j] = {(float)u[j].x, (float)u[j].y};
-  cplx<float> r2[3];
-  rebuild_row2(f, r2);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) u[6 + a] = pkh(r2[a].re, r2[a].im);
-}
-
 // y = sg U v on every spin
 __device__ __forceinline__ void transport_h(const hv2 (&u)[9], const HPk (&v)[12], float sg, cplx<float> (&y)[12]) {
 #pragma unroll
@@ -501,6 +482,47 @@ __device__ __forceinline__ void load_h(const char *base, int i, float sc, HPk (&
   for (int c = 0; c < 12; ++c) v[c] = hpk(sc * x[c].re, sc * x[c].im);
 }
 
+// In both layers the neighbour spinor(s) and link of hop d + 1 are loaded
+// (raw) before hop d is computed, so a wave keeps loads in flight while it
+// computes (9% faster than loading at the top of each hop).
+struct RawH {
+  v4u q[3];  // a BF16 spinor's 3 packets
+  uint2 l[3];  // an FP16 link's 3 packets
+};
+__device__ __forceinline__ void raw_h(const KPtcH &k, const char *base, int site, int p, int d, int i, RawH &r) {
+  const v4u *b = (const v4u *)base + chunk_base<Spinor<WD_BF16>::CHUNK>(site);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) r.q[q] = b[64 * q];
+  const uint2 *lb = k.links16 + (size_t)p * k.link16_par;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) r.l[q] = lb[link16_at(d, q, i)];
+}
+__device__ __forceinline__ void unpack_spinor_h(const v4u (&q)[3], float sc, HPk (&v)[12]) {
+#pragma unroll
+  for (int kq = 0; kq < 3; ++kq) {
+    const uint32_t w[4] = {q[kq].x, q[kq].y, q[kq].z, q[kq].w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      v[4 * kq + j] = hpk(sc * bf16_to_f32((uint16_t)(w[j] & 0xffffu)), sc * bf16_to_f32((uint16_t)(w[j] >> 16)));
+  }
+}
+// an FP16 hop link: rows 0-1 as stored, row 2 rebuilt in FP32 from them
+// (u[3a + b] = M_ab)
+__device__ __forceinline__ void unpack_link_h(const uint2 (&l)[3], hv2 (&u)[9]) {
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    u[2 * q] = as_hv2(l[q].x);
+    u[2 * q + 1] = as_hv2(l[q].y);
+  }
+  cplx<float> f[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) f[j] = {(float)u[j].x, (float)u[j].y};
+  cplx<float> r2[3];
+  rebuild_row2(f, r2);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) u[6 + a] = pkh(r2[a].re, r2[a].im);
+}
+
 // Layer 1 of [N (x_e, 0)]_e (1 -> 2 channels, both parities, BF16 out): an
 // even site takes only W^(0) x, an odd site only the 8 hops from its even
 // neighbours.
@@ -522,11 +544,16 @@ __global__ __launch_bounds__(PTC_BS) void k_ptc_h_l1(KPtcH k) {
       for (int co = 0; co < 2; ++co) spin_mat_h(k.W16 + 16 * co, v, acc[co]);
     } else {
       const PtcSite s = ptc_site(k.g, i, 1);
+      RawH nx;
+      raw_h(k, k.in, s.nb[0], 1, 0, i, nx);
+#pragma unroll
       for (int d = 0; d < 8; ++d) {
+        const RawH cur = nx;
+        if (d < 7) raw_h(k, k.in, s.nb[d + 1], 1, d + 1, i, nx);
         HPk v[12];
-        load_h(k.in, s.nb[d], sc, v);
+        unpack_spinor_h(cur.q, sc, v);
         hv2 u[9];
-        link_h(k, 1, d, i, u);
+        unpack_link_h(cur.l, u);
         const float sg = (d == 3) ? s.sf : ((d == 7) ? s.sb : 1.0f);
         cplx<float> y[12];
         transport_h(u, v, sg, y);
@@ -542,6 +569,14 @@ __global__ __launch_bounds__(PTC_BS) void k_ptc_h_l1(KPtcH k) {
   for (int co = 0; co < 2; ++co) Spinor<WD_BF16>::store(k.out + co * k.out_chan + (size_t)p * k.out_half, i, acc[co]);
 }
 
+// a[d] without dynamic register indexing (a rolled loop would spill it)
+__device__ __forceinline__ int pick8(const int (&a)[8], int d) {
+  int r = a[0];
+#pragma unroll
+  for (int j = 1; j < 8; ++j) r = (d == j) ? a[j] : r;
+  return r;
+}
+
 // Layer 2 (2 -> 1 channels, even sites only; spins mixed before the
 // transport), output scaled back and stored in POUT.
 template <int POUT>
@@ -553,27 +588,45 @@ __global__ __launch_bounds__(PTC_BS) void k_ptc_h_l2(KPtcH k) {
   for (int c = 0; c < 12; ++c) acc[c] = {0.f, 0.f};
   if (i < k.g.vh) {
     const PtcSite s = ptc_site(k.g, i, 0);
+    RawH n0, n1;  // the two channels at the next neighbour (links in n0)
+    raw_h(k, k.in + k.in_half, s.nb[0], 0, 0, i, n0);
+    {
+      const v4u *b = (const v4u *)(k.in + k.in_chan + k.in_half) + chunk_base<Spinor<WD_BF16>::CHUNK>(s.nb[0]);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) n1.q[q] = b[64 * q];
+    }
 #pragma unroll
     for (int ci = 0; ci < 2; ++ci) {
       HPk v[12];
       load_h(k.in + ci * k.in_chan, i, 1.0f, v);
       spin_mat_h(k.W16 + 16 * ci, v, acc);
     }
+#pragma unroll 1
     for (int d = 0; d < 8; ++d) {
+      const RawH c0 = n0;
+      const v4u c1[3] = {n1.q[0], n1.q[1], n1.q[2]};
+      if (d < 7) {
+        const int nb = pick8(s.nb, d + 1);
+        raw_h(k, k.in + k.in_half, nb, 0, d + 1, i, n0);
+        const v4u *b = (const v4u *)(k.in + k.in_chan + k.in_half) + chunk_base<Spinor<WD_BF16>::CHUNK>(nb);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) n1.q[q] = b[64 * q];
+      }
       cplx<float> m[12];
 #pragma unroll
       for (int c = 0; c < 12; ++c) m[c] = {0.f, 0.f};
-#pragma unroll
-      for (int ci = 0; ci < 2; ++ci) {
+      {
         HPk v[12];
-        load_h(k.in + ci * k.in_chan + k.in_half, s.nb[d], 1.0f, v);
-        spin_mat_h(k.W16 + 16 * ((d + 1) * 2 + ci), v, m);
+        unpack_spinor_h(c0.q, 1.0f, v);
+        spin_mat_h(k.W16 + 16 * ((d + 1) * 2), v, m);
+        unpack_spinor_h(c1, 1.0f, v);
+        spin_mat_h(k.W16 + 16 * ((d + 1) * 2 + 1), v, m);
       }
       HPk mv[12];
 #pragma unroll
       for (int c = 0; c < 12; ++c) mv[c] = hpk(m[c].re, m[c].im);
       hv2 u[9];
-      link_h(k, 0, d, i, u);
+      unpack_link_h(c0.l, u);
       const float sg = (d == 3) ? s.sf : ((d == 7) ? s.sb : 1.0f);
       cplx<float> y[12];
       transport_h(u, mv, sg, y);
