@@ -168,7 +168,7 @@ def _defect(wd, prec, tol_inner=1e-3):
     return wd.wd_solve_params_default(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec=prec, inner_tol=tol_inner)
 
 
-def mrhs_leg(wd, torch, syn):
+def mrhs_leg(wd, torch, syn, table=None, retune=False):
     """12 spin-colour point sources on 24^3x48 (kappa 0.124, eps 0.3), solved together."""
     from paper_0710_2442_amd.fields import canon_to_field
 
@@ -181,10 +181,10 @@ def mrhs_leg(wd, torch, syn):
     X = wd.wd_new_field(dims, "f64", 12)
     out = {}
     for prec in ("f32", "bf16", "f64"):
-        tb, tg, tr, tus = wd.wd_tune_dslash_mrhs(g, prec, 12)
+        tb, tg, tr, tus = wd.wd_tune_dslash_mrhs(g, prec, 12, table, force=retune)
         log(f"tuned mrhs hop {prec}: block {tb}, groups {tg}, rhs per lane {tr} ({tus:.1f} us)")
     for prec in ("f32", "f64"):
-        wd.wd_tune_dslash(g, prec)
+        wd.wd_tune_dslash(g, prec, table, force=retune)
 
     def timed(fn):
         fn()  # warm-up
@@ -625,7 +625,7 @@ def main():
     if not args.no_solve:
         line["solve_32x32x32x64_kappa0124"] = solve_leg(wd, torch, syn)
     if not args.no_mrhs:
-        line["mrhs_24x24x24x48_12_point_sources"] = mrhs_leg(wd, torch, syn)
+        line["mrhs_24x24x24x48_12_point_sources"] = mrhs_leg(wd, torch, syn, args.tune_table, args.retune)
     if not args.no_batch:
         line["batch_8_lattices_689408_sites"] = batch_leg(wd, torch, syn)
     if not args.no_learn:

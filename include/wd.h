@@ -356,9 +356,11 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path,
  * tuned: block size (64, 128, 256 sites), rpl (1..16) and block -> tile
  * order (groups as above).  FP64: fixed 16-site x RHS tiles; tuned: tile
  * order.  Candidates are checked byte for byte against the linear variant,
- * then timed; the fastest is kept in the handle.  Outputs may be NULL.
- * Synchronous. */
-wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, int *block,
+ * then timed; the fastest is kept in the handle.  cache_path and force as
+ * for wd_tune_dslash (the key adds nrhs; the cache line's third field is
+ * "rpl").  Outputs may be NULL.  Synchronous. */
+wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs,
+                              const char *cache_path, int force, int *block,
                               int *groups, int *rpl, double *us);
 
 /* Set / read the multi-RHS hop variant used for precision prec: block (FP64:

@@ -94,8 +94,8 @@ _decl("wd_solve_batch", C.c_int, [C.POINTER(_vp), C.c_int, C.POINTER(_vp), C.POI
                                    C.c_double, C.POINTER(wd_solve_params), C.POINTER(wd_solve_info)])
 _decl("wd_tune_dslash", C.c_int, [_vp, C.c_int, C.c_char_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                    C.POINTER(C.c_int), C.POINTER(C.c_double)])
-_decl("wd_tune_dslash_mrhs", C.c_int, [_vp, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
-                                       C.POINTER(C.c_int), C.POINTER(C.c_double)])
+_decl("wd_tune_dslash_mrhs", C.c_int, [_vp, C.c_int, C.c_int, C.c_char_p, C.c_int, C.POINTER(C.c_int),
+                                       C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double)])
 _decl("wd_set_dslash_variant", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int])
 _decl("wd_get_dslash_variant", C.c_int, [_vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)])
 _decl("wd_set_dslash_mrhs_variant", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int])
@@ -502,11 +502,13 @@ def wd_solve_batch(gauges, bs, xs, kappas, tol, params):
     return rc, [i.as_dict() for i in infos]
 
 
-def wd_tune_dslash_mrhs(g, prec, nrhs):
-    """Tune the multi-RHS hop (block size, tile order, RHS per lane);
-    returns (block, groups, rpl, microseconds per launch)."""
+def wd_tune_dslash_mrhs(g, prec, nrhs, cache_path=None, force=False):
+    """Tune the multi-RHS hop (block size, tile order, RHS per lane), or take
+    the variant from the JSON-lines cache; returns (block, groups, rpl,
+    microseconds per launch)."""
     g.sync_stream()
     bs, gr, rp, us = C.c_int(), C.c_int(), C.c_int(), C.c_double()
-    _check(lib.wd_tune_dslash_mrhs(g.handle, _prec(prec), int(nrhs), C.byref(bs), C.byref(gr), C.byref(rp),
-                                   C.byref(us)), "wd_tune_dslash_mrhs")
+    cp = cache_path.encode() if cache_path else None
+    _check(lib.wd_tune_dslash_mrhs(g.handle, _prec(prec), int(nrhs), cp, int(force), C.byref(bs), C.byref(gr),
+                                   C.byref(rp), C.byref(us)), "wd_tune_dslash_mrhs")
     return bs.value, gr.value, rp.value, us.value

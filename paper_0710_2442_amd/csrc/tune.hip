@@ -7,7 +7,8 @@
 // arithmetic is the same in every variant (the comparison runs on the
 // device) -- and then timed with HIP events.  The fastest valid candidate is stored in the handle
 // and, if a cache path is given, appended to a JSON-lines cache keyed by
-// (architecture, kernel, precision, lattice).
+// (architecture, kernel, precision, lattice; and the number of right-hand
+// sides for the multi-RHS hop).
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -19,7 +20,7 @@
 
 namespace wd {
 
-static std::string tune_key(const wd_gauge *g, wd_prec prec) {
+static std::string tune_key(const wd_gauge *g, wd_prec prec, int nrhs = 0) {
   hipDeviceProp_t prop;
   char arch[64] = "unknown";
   if (hipGetDeviceProperties(&prop, g->device) == hipSuccess) {
@@ -27,13 +28,18 @@ static std::string tune_key(const wd_gauge *g, wd_prec prec) {
     char *colon = strchr(arch, ':');
     if (colon) *colon = 0;
   }
+  char kern[32] = "hop";
+  if (nrhs > 0) snprintf(kern, sizeof kern, "hop_mrhs%d", nrhs);
   char buf[160];
-  snprintf(buf, sizeof buf, "%s/hop/p%d/%dx%dx%dx%d", arch, (int)prec, g->dims[0], g->dims[1], g->dims[2],
+  snprintf(buf, sizeof buf, "%s/%s/p%d/%dx%dx%dx%d", arch, kern, (int)prec, g->dims[0], g->dims[1], g->dims[2],
            g->dims[3]);
   return buf;
 }
 
-static bool cache_lookup(const char *path, const std::string &key, int &bs, int &groups, int &occ, double &us) {
+// A cache line: {"key": K, "block": B, "groups": G, "<third>": V, "us": T}
+// with <third> "occ" (single-RHS hop) or "rpl" (multi-RHS hop).
+static bool cache_lookup(const char *path, const std::string &key, int &bs, int &groups, int &occ, double &us,
+                         const char *third = "occ") {
   FILE *f = fopen(path, "r");
   if (!f) return false;
   char line[512];
@@ -42,9 +48,10 @@ static bool cache_lookup(const char *path, const std::string &key, int &bs, int 
     char k[200];
     int b, gr, oc;
     double t;
-    if (sscanf(line, " {\"key\": \"%199[^\"]\", \"block\": %d, \"groups\": %d, \"occ\": %d, \"us\": %lf", k, &b,
-               &gr, &oc, &t) == 5 &&
-        key == k) {
+    char fmt[128];
+    snprintf(fmt, sizeof fmt, " {\"key\": \"%%199[^\"]\", \"block\": %%d, \"groups\": %%d, \"%s\": %%d, \"us\": %%lf",
+             third);
+    if (sscanf(line, fmt, k, &b, &gr, &oc, &t) == 5 && key == k) {
       bs = b; groups = gr; occ = oc; us = t; found = true;  // last entry wins
     }
   }
@@ -52,11 +59,12 @@ static bool cache_lookup(const char *path, const std::string &key, int &bs, int 
   return found;
 }
 
-static void cache_append(const char *path, const std::string &key, int bs, int groups, int occ, double us) {
+static void cache_append(const char *path, const std::string &key, int bs, int groups, int occ, double us,
+                         const char *third = "occ") {
   FILE *f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "{\"key\": \"%s\", \"block\": %d, \"groups\": %d, \"occ\": %d, \"us\": %.3f}\n", key.c_str(), bs,
-          groups, occ, us);
+  fprintf(f, "{\"key\": \"%s\", \"block\": %d, \"groups\": %d, \"%s\": %d, \"us\": %.3f}\n", key.c_str(), bs,
+          groups, third, occ, us);
   fclose(f);
 }
 
@@ -318,12 +326,25 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
 // fixed 16-site tiles), the right-hand sides per lane (FP32 arithmetic) and
 // the block -> tile order for nrhs right-hand sides; candidates checked byte
 // for byte against the linear 128-site, 4-RHS (FP64: 16-site) variant.
-wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, int *out_block, int *out_groups, int *out_rpl,
-                              double *out_us) {
+wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, const char *cache_path, int force,
+                              int *out_block, int *out_groups, int *out_rpl, double *out_us) {
   if (!g) return set_error(WD_ERR_ARG, "gauge handle is NULL");
   if ((int)prec < 0 || (int)prec > 3) return set_error(WD_ERR_PREC, "prec = %d", (int)prec);
   if (nrhs < 1 || nrhs > 64) return set_error(WD_ERR_ARG, "nrhs = %d", nrhs);
   WD_HIP(hipSetDevice(g->device));
+  const std::string key = tune_key(g, prec, nrhs);
+  {
+    int cb, cg, cr;
+    double cus;
+    if (cache_path && !force && cache_lookup(cache_path, key, cb, cg, cr, cus, "rpl") &&
+        wd_set_dslash_mrhs_variant(g, prec, cb, cg, cr) == WD_OK) {
+      if (out_block) *out_block = cb;
+      if (out_groups) *out_groups = cg;
+      if (out_rpl) *out_rpl = cr;
+      if (out_us) *out_us = cus;
+      return WD_OK;
+    }
+  }
   const Geom &G = g->geom;
   const size_t hb = half_bytes(G, prec) * (size_t)nrhs;
   hipStream_t st = g->own_stream;
@@ -404,6 +425,7 @@ wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, int *out_bloc
   if (cand) (void)hipFree(cand);
   if (flag) (void)hipFree(flag);
   if (rc != WD_OK) return rc;
+  if (cache_path) cache_append(cache_path, key, best_b, best_g, best_r, best_us, "rpl");
   if (out_block) *out_block = best_b;
   if (out_rpl) *out_rpl = best_r;
   if (out_groups) *out_groups = best_g;

@@ -256,6 +256,34 @@ def test_mrhs_solve_does_not_depend_on_rhs_per_lane():
     g.close()
 
 
+def test_tuning_cache_round_trip(tmp_path):
+    """Both tuners append their choice to the JSON-lines cache and take it
+    back from there (same variant, the stored time) without timing again;
+    force retunes; the multi-RHS key includes the number of RHS."""
+    dims = (8, 8, 8, 16)
+    g = wd.Gauge(syn.gauge_field(dims, 0.3, 27), dims, -1, "f64")
+    path = str(tmp_path / "tune.jsonl")
+
+    def lines():
+        return open(path).read().splitlines()
+
+    a = wd.wd_tune_dslash(g, "f32", path)
+    assert len(lines()) == 1 and '"occ"' in lines()[0] and "/hop/p1/8x8x8x16" in lines()[0]
+    b = wd.wd_tune_dslash(g, "f32", path)
+    assert b[:3] == a[:3] and abs(b[3] - a[3]) < 1e-3 and len(lines()) == 1
+    m = wd.wd_tune_dslash_mrhs(g, "bf16", 5, path)
+    assert len(lines()) == 2 and '"rpl"' in lines()[1] and "/hop_mrhs5/p3/8x8x8x16" in lines()[1]
+    wd.wd_set_dslash_mrhs_variant(g, "bf16", 256, 0, 1)
+    m2 = wd.wd_tune_dslash_mrhs(g, "bf16", 5, path)
+    assert m2[:3] == m[:3] and wd.wd_get_dslash_mrhs_variant(g, "bf16") == m[:3]
+    assert abs(m2[3] - m[3]) < 1e-3 and len(lines()) == 2
+    wd.wd_tune_dslash_mrhs(g, "bf16", 5, path, force=True)
+    assert len(lines()) == 3
+    wd.wd_tune_dslash_mrhs(g, "bf16", 3, path)
+    assert len(lines()) == 4 and "/hop_mrhs3/" in lines()[3]
+    g.close()
+
+
 def test_blas_against_numpy():
     dims = (6, 4, 6, 10)
     g = wd.Gauge(syn.gauge_field(dims, 0.3, 31), dims, -1, "f64")
