@@ -111,7 +111,15 @@ def time_hop(wd, torch, g, psi, prec, steps, warmup):
     return ms / 1e3 / (2 * steps), 2 * steps, ms
 
 
-def solve_leg(wd, torch, syn, log_every=True):
+def use_tuned(wd, g, table, retune, precs=("f64", "f32", "f16", "bf16")):
+    """Hop variants for every storage precision a solver may use, from the
+    tuning table (tuned and appended where it has no entry)."""
+    for prec in precs:
+        b, gr, oc, us = wd.wd_tune_dslash(g, prec, table, force=retune)
+        log(f"hop {prec} {g.dims}: block {b}, groups {gr}, occ {oc} ({us:.1f} us)")
+
+
+def solve_leg(wd, torch, syn, log_every=True, table=None, retune=False):
     """Time to |b - D x|/|b| <= 1e-10 on 32^3x64, kappa = 0.124."""
     from paper_0710_2442_amd.fields import canon_to_field
 
@@ -120,6 +128,7 @@ def solve_leg(wd, torch, syn, log_every=True):
     U = syn.gauge_field(DIMS, 0.3, gseed)
     b = syn.gaussian_spinor(DIMS, sseed)
     g = wd.Gauge(U, DIMS, -1, "f64")
+    use_tuned(wd, g, table, retune)
     fb = canon_to_field(g, b, "f64")
     x = wd.wd_new_field(DIMS, "f64")
     out = {}
@@ -183,8 +192,7 @@ def mrhs_leg(wd, torch, syn, table=None, retune=False):
     for prec in ("f32", "bf16", "f64"):
         tb, tg, tr, tus = wd.wd_tune_dslash_mrhs(g, prec, 12, table, force=retune)
         log(f"tuned mrhs hop {prec}: block {tb}, groups {tg}, rhs per lane {tr} ({tus:.1f} us)")
-    for prec in ("f32", "f64"):
-        wd.wd_tune_dslash(g, prec, table, force=retune)
+    use_tuned(wd, g, table, retune)
 
     def timed(fn):
         fn()  # warm-up
@@ -283,7 +291,7 @@ def batch_leg(wd, torch, syn):
     return out
 
 
-def learned_leg(wd, torch, syn, steps):
+def learned_leg(wd, torch, syn, steps, table=None, retune=False):
     """Train the PTC network on 16^4 (kappa 0.124, eps 0.3); test FGCR on 32^3x64."""
     from paper_0710_2442_amd import learn
     from paper_0710_2442_amd.fields import canon_to_field
@@ -299,6 +307,7 @@ def learned_leg(wd, torch, syn, steps):
                         "pair_generation_seconds": round(hist["pair_generation_seconds"], 2),
                         "loss_first": hist["losses"][0][1], "loss_last": hist["losses"][-1][1]}}
     gt = wd.Gauge(syn.gauge_field(DIMS, 0.3, gseed + 100), DIMS, -1, "f64")
+    use_tuned(wd, gt, table, retune)
     fb = canon_to_field(gt, syn.gaussian_spinor(DIMS, sseed + 100), "f64")
     fx = wd.wd_new_field(DIMS, "f64")
     net = wd.Ptc(gt, W, "bf16")
@@ -623,13 +632,14 @@ def main():
                        "frac": round(results["f32"]["gbs"] / HBM_PEAK_GBS, 4),
                        "avg_launch_us": round(results["f32"]["sec_per_launch"] * 1e6, 2)}
     if not args.no_solve:
-        line["solve_32x32x32x64_kappa0124"] = solve_leg(wd, torch, syn)
+        line["solve_32x32x32x64_kappa0124"] = solve_leg(wd, torch, syn, table=args.tune_table, retune=args.retune)
     if not args.no_mrhs:
         line["mrhs_24x24x24x48_12_point_sources"] = mrhs_leg(wd, torch, syn, args.tune_table, args.retune)
     if not args.no_batch:
         line["batch_8_lattices_689408_sites"] = batch_leg(wd, torch, syn)
     if not args.no_learn:
-        line["learned_ptc_fgcr_32x32x32x64"] = learned_leg(wd, torch, syn, args.learn_steps)
+        line["learned_ptc_fgcr_32x32x32x64"] = learned_leg(wd, torch, syn, args.learn_steps, args.tune_table,
+                                                          args.retune)
     if not args.no_kernels:
         line["kernels_32x32x32x64"] = kernels_leg(wd, torch, syn, U, psi)
         line["micro_lds_copy_eq4_fit"] = micro_leg(wd)
