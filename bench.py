@@ -355,6 +355,8 @@ def kernels_leg(wd, torch, syn, U, psi):
     """Level-1 kernels (Sec. 4's caxpy), full D_W and the network at 32^3x64."""
     import numpy as np
 
+    from paper_0710_2442_amd import perf_model
+
     from paper_0710_2442_amd import learn
     from paper_0710_2442_amd.fields import canon_to_field
 
@@ -382,7 +384,8 @@ def kernels_leg(wd, torch, syn, U, psi):
     gbs = V * 576 / t / 1e9
     out["caxpy_f64"] = {"us": round(t * 1e6, 2), "GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
                         "eps_fp": round(V * 96 / t / FP64_PEAK_FLOPS, 5),
-                        "eps_fp_hbm_bound": round(96 / 576 * HBM_PEAK_GBS * 1e9 / FP64_PEAK_FLOPS, 5)}
+                        "eps_fp_hbm_bound": round(96 / 576 * HBM_PEAK_GBS * 1e9 / FP64_PEAK_FLOPS, 5),
+                        "model_eq1_eq2_us": round(perf_model.caxpy_model(V) * 1e6, 1)}
     # |x|^2 with the result read back (one synchronisation per call)
     for _ in range(3):
         wd.wd_norm2(g, x, 2, "f64")
@@ -633,7 +636,17 @@ def main():
                        "frac": round(results["f32"]["gbs"] / HBM_PEAK_GBS, 4),
                        "avg_launch_us": round(results["f32"]["sec_per_launch"] * 1e6, 2)}
     if not args.no_solve:
-        line["solve_32x32x32x64_kappa0124"] = solve_leg(wd, torch, syn, table=args.tune_table, retune=args.retune)
+        sl = solve_leg(wd, torch, syn, table=args.tune_table, retune=args.retune)
+        if head == "f64":
+            # Eqs. 1-2 for one eo-CGLS iteration against the measured time per iteration
+            cg = perf_model.cg_iteration_model(vh, "f64", ratio or 1.0)
+            meas = sl["fp64_cg"]["seconds"] / sl["fp64_cg"]["iters"]
+            sl["fp64_cg"]["model_eq1_eq2"] = {
+                "bytes_per_site": perf_model.cg_iteration_bytes("f64"),
+                "T_hops_us": round(cg["T_hops"] * 1e6, 1), "T_blas_us": round(cg["T_blas"] * 1e6, 1),
+                "T_iter_us": round(cg["T_iter"] * 1e6, 1), "measured_us_per_iter": round(meas * 1e6, 1),
+                "measured_over_model": round(meas / cg["T_iter"], 3)}
+        line["solve_32x32x32x64_kappa0124"] = sl
     if not args.no_mrhs:
         line["mrhs_24x24x24x48_12_point_sources"] = mrhs_leg(wd, torch, syn, args.tune_table, args.retune)
     if not args.no_batch:

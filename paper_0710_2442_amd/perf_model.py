@@ -11,8 +11,10 @@ from __future__ import annotations
 
 MI355X = {
     "hbm_peak": 8.0e12,          # B/s, data sheet
-    "hbm_read_ceiling": 6.3e12,  # B/s, streaming-read kernel measured on the box
-    "copy_ceiling": 5.5e12,      # B/s, copy kernel (read + write) measured on the box
+    # measured with the library's streaming probe (wd_micro_stream, 16-byte lanes):
+    "hbm_read_ceiling": 6.3e12,  # B/s, one read stream, cached loads
+    "copy_ceiling": 6.65e12,     # B/s, one read + one write stream, non-temporal
+    "hop_mix_ceiling": 6.05e12,  # B/s, five read + one write streams (the hop's mix), non-temporal
     "fp64_vector": 78.6e12,      # flop/s
     "fp32_vector": 157.3e12,
     "cus": 256,
@@ -46,3 +48,31 @@ def report(sites, prec, measured_s, traffic_ratio=None):
         out["T_measured_traffic_at_read_ceiling_us"] = 1e6 * hop_model(
             sites, prec, traffic_ratio, MI355X["hbm_read_ceiling"])["T_hbm"]
     return {k: round(v, 2) for k, v in out.items()}
+
+
+# One FP64 eo-CGLS iteration (the library's cgls_iteration), bytes per even
+# site: q = M p is a plain hop and a hop with the xpay epilogue (+1 spinor
+# read) and norm; the CG update reads x, p, s, q and writes x, s; r = M^dag s
+# is the same two hops; p = r + beta p reads two spinors and writes one.
+SPINOR_BYTES = {"f64": 24 * 8, "f32": 24 * 4}
+
+
+def cg_iteration_bytes(prec="f64"):
+    sp = SPINOR_BYTES[prec]
+    hop = HOP_BYTES[prec]
+    return {"hops": 2 * hop + 2 * (hop + sp), "blas": 6 * sp + 3 * sp}
+
+
+def cg_iteration_model(vh, prec="f64", hop_traffic_ratio=1.0):
+    """Eqs. 1-2 for one eo-CGLS iteration on vh even sites: the hops' bytes
+    (times the measured traffic ratio) at the hop-mix ceiling, the BLAS bytes
+    at the copy ceiling; the tasks run one after another (T = sum)."""
+    b = cg_iteration_bytes(prec)
+    t_hops = vh * b["hops"] * hop_traffic_ratio / MI355X["hop_mix_ceiling"]
+    t_blas = vh * b["blas"] / MI355X["copy_ceiling"]
+    return {"T_hops": t_hops, "T_blas": t_blas, "T_iter": t_hops + t_blas}
+
+
+def caxpy_model(sites, prec="f64"):
+    """Eqs. 1-2 for y += c x over `sites` sites: 2 spinors read, 1 written."""
+    return 3 * SPINOR_BYTES[prec] * sites / MI355X["copy_ceiling"]
