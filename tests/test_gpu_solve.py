@@ -138,9 +138,12 @@ def test_free_field_solve_matches_fft_16x4():
 def test_free_field_solves_at_full_size_32x32x32x64():
     """The solver workloads' lattice (32^3x64, kappa 0.124) with unit links,
     where the exact D^{-1} b is the oracle's FFT solution: plain FP64 CG,
-    BF16-storage defect correction and the mixed even-odd FGCR must all land
-    within cond(D) * tol of it.  Free-field cond(D) here is ~134
-    (lambda_min(D^dag D) = 2.2e-4)."""
+    BF16-storage defect correction and the mixed even-odd FGCR (FP32 storage
+    without a network; BF16 storage with a network, which then runs with
+    FP16 products) must all land within cond(D) * tol of it.  Free-field
+    cond(D) here is ~134 (lambda_min(D^dag D) = 2.2e-4)."""
+    from paper_0710_2442_amd import learn
+
     dims, kappa = (32, 32, 32, 64), 0.124
     lo, hi = free_field.lambda_min_normal(dims, kappa)
     cond = np.sqrt(hi / lo)
@@ -152,14 +155,17 @@ def test_free_field_solves_at_full_size_32x32x32x64():
     fb = to_field(g, b)
     fx = wd.wd_new_field(dims, "f64")
     xs = free_field.solve(b, kappa)
+    net = wd.Ptc(g, learn.init_weights(11, scale=0.05), "bf16")
     for kw in (dict(solver=wd.WD_SOLVER_CG),
                dict(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec="bf16", inner_tol=1e-2),
-               dict(solver=wd.WD_SOLVER_DEFECT_FGCR, fgcr_m=4, inner_tol=1e-2)):
+               dict(solver=wd.WD_SOLVER_DEFECT_FGCR, fgcr_m=4, inner_tol=1e-2),
+               dict(solver=wd.WD_SOLVER_DEFECT_FGCR, fgcr_m=4, inner_tol=1e-2, inner_prec="bf16", precond=net)):
         rc, info = wd.wd_solve(g, fb, fx, kappa, TOL, wd.wd_solve_params_default(**kw))
         assert rc == 0 and info["true_rel_resid"] <= TOL, (kw, info)
         err = rel_err(from_field(g, fx), xs)
         print(kw["solver"], info["iters"], info["true_rel_resid"], err, flush=True)
         assert err <= 2 * cond * TOL, (kw, err)
+    net.close()
     g.close()
 
 
