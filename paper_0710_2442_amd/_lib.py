@@ -18,6 +18,11 @@ if not os.path.exists(LIB_PATH):
         "(python -c 'import __graft_entry__; __graft_entry__.build()')"
     )
 
+# torch first: libwd.so then binds to the HIP runtime torch has already
+# loaded (one runtime per process, the one that owns torch's device memory
+# and streams) instead of loading a second copy of its own
+import torch  # noqa: E402,F401
+
 lib = C.CDLL(LIB_PATH)
 
 WD_F64, WD_F32, WD_F16, WD_BF16 = 0, 1, 2, 3
