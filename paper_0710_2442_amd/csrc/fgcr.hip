@@ -268,6 +268,7 @@ struct KFg {
   double *sig;     // [FG_MMAX]: |w_j|^2
   double *rho;     // [2]: <w_k, r>
   double *rr;      // |r|^2
+  float *alpha;    // [2 FG_MMAX]: the step lengths of the current cycle (re, im)
   int k;
   double *partials;
   unsigned *counter;
@@ -345,6 +346,8 @@ __global__ __launch_bounds__(FG_BS) void k_fg_orth(KFg a) {
   block_sum_store<3>(acc, a.partials, a.nblk, blockIdx.x);
 }
 
+// r -= alpha w_k, |r|^2; alpha_k is kept for the solution update, which is
+// applied once per restart cycle (k_fg_accum)
 template <int S>
 __global__ __launch_bounds__(FG_BS) void k_fg_step(KFg a) {
   using V = Spinor<S>;
@@ -352,14 +355,13 @@ __global__ __launch_bounds__(FG_BS) void k_fg_step(KFg a) {
   const bool ok = s > 0.0 && s < 1e300;
   const cplx<float> al = {ok ? (float)(a.rho[0] / s) : 0.f, ok ? (float)(a.rho[1] / s) : 0.f};
   const cplx<float> ml = {-al.re, -al.im};
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.alpha[2 * a.k] = al.re;
+    a.alpha[2 * a.k + 1] = al.im;
+  }
   double acc[1] = {0.0};
   for (long i = (long)blockIdx.x * FG_BS + threadIdx.x; i < a.vh; i += (long)a.nblk * FG_BS) {
-    cplx<float> z[12], w[12], e[12], r[12];
-    V::load(a.zk, i, z);
-    F4::load(a.e, i, e);
-#pragma unroll
-    for (int q = 0; q < 12; ++q) cfma(e[q], al, z[q]);
-    F4::store<false>(a.e, i, e);
+    cplx<float> w[12], r[12];
     V::load(a.wk, i, w);
     V::load(a.r, i, r);
 #pragma unroll
@@ -370,6 +372,28 @@ __global__ __launch_bounds__(FG_BS) void k_fg_step(KFg a) {
     for (int q = 0; q < 12; ++q) acc[0] += (double)r[q].re * r[q].re + (double)r[q].im * r[q].im;
   }
   block_sum_store<1>(acc, a.partials, a.nblk, blockIdx.x);
+}
+
+// e += sum_{j < K} alpha_j z_j for the K steps of a cycle, in step order
+// (the same FP32 operations, in the same order, as updating e at every step)
+template <int S, int K>
+__global__ __launch_bounds__(FG_BS) void k_fg_accum(KFg a) {
+  using V = Spinor<S>;
+  cplx<float> al[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) al[j] = {a.alpha[2 * j], a.alpha[2 * j + 1]};
+  for (long i = (long)blockIdx.x * FG_BS + threadIdx.x; i < a.vh; i += (long)a.nblk * FG_BS) {
+    cplx<float> e[12];
+    F4::load(a.e, i, e);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      cplx<float> z[12];
+      V::load(a.Z[j], i, z);
+#pragma unroll
+      for (int q = 0; q < 12; ++q) cfma(e[q], al[j], z[q]);
+    }
+    F4::store<false>(a.e, i, e);
+  }
 }
 
 // Second stage of the three kernels above: value j = sum of the block
@@ -403,6 +427,15 @@ void launch_dots(const KFg &a, int k, hipStream_t st, std::integer_sequence<int,
 template <int S, int... Ks>
 void launch_orth(const KFg &a, int k, hipStream_t st, std::integer_sequence<int, Ks...>) {
   ((k == Ks ? launch_orth_k<S, Ks>(a, st) : void()), ...);
+}
+
+template <int S, int K>
+void launch_accum_k(const KFg &a, hipStream_t st) {
+  hipLaunchKernelGGL((k_fg_accum<S, K>), dim3(a.nblk), dim3(FG_BS), 0, st, a);
+}
+template <int S, int... Ks>
+void launch_accum(const KFg &a, int K, hipStream_t st, std::integer_sequence<int, Ks...>) {
+  ((K == Ks + 1 ? launch_accum_k<S, Ks + 1>(a, st) : void()), ...);
 }
 
 // One FGCR direction after w_k = Mhat z_k: orthogonalise against the k
@@ -494,11 +527,16 @@ wd_status solve_fgcr_mixed(wd_gauge *g, const void *b, void *x, double kappa, do
   a.sig = ds + 2 * FG_MMAX;
   a.rho = a.sig + FG_MMAX;
   a.rr = a.rho + 2;
+  a.alpha = (float *)(red + 640);  // 2 FG_MMAX floats inside the scalar block
   a.r = R;
   a.e = E;
   a.partials = (double *)(red + scal_bytes);
   a.counter = (unsigned *)(red + scal_bytes + npart * sizeof(double));
   RedBuf rb{a.partials, a.counter};
+  auto accum = [&](int K) {
+    if (S == WD_F32) launch_accum<WD_F32>(a, K, st, std::make_integer_sequence<int, FG_MMAX>{});
+    else launch_accum<WD_BF16>(a, K, st, std::make_integer_sequence<int, FG_MMAX>{});
+  };
   auto read = [&](const double *dev, int n, double *out) -> wd_status {
     WD_HIP(hipMemcpyAsync(hres, dev, sizeof(double) * n, hipMemcpyDeviceToHost, st));
     WD_HIP(hipStreamSynchronize(st));
@@ -591,9 +629,15 @@ wd_status solve_fgcr_mixed(wd_gauge *g, const void *b, void *x, double kappa, do
         fallback = true;
         break;
       }
-      k = (k + 1 == m) ? 0 : k + 1;
+      // the cycle's steps enter the solution when the basis wraps (and after the loop)
+      k = k + 1;
+      if (k == m) {
+        accum(k);
+        k = 0;
+      }
     }
     if (fallback) break;
+    if (k > 0) accum(k);
     // e_o = rh_o + kappa H_oe E;  x += |r| e;  r = b - D x
     {
       DslashArgs d;
