@@ -81,3 +81,37 @@ def test_status_strings_and_defaults(lib):
     p = wd.wd_solve_params_default()
     assert p.struct_size == ctypes.sizeof(p)
     assert p.max_iter > 0 and p.check_every > 0
+
+
+def test_a_c99_program_compiles_links_and_calls_the_library(tmp_path):
+    """The header is plain C99 (no C++ in it) and a C program links against
+    libwd.so and calls its host-side entry points."""
+    import shutil
+    import subprocess
+
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use_wd.c"
+    src.write_text(
+        '#include <stdio.h>\n#include "wd.h"\n'
+        "int main(void) {\n"
+        "  int dims[4] = {8, 8, 8, 8};\n"
+        "  wd_solve_params p;\n"
+        "  wd_solve_params_default(&p);\n"
+        "  printf(\"%zu %zu %d %d %s\\n\", wd_field_bytes(dims, WD_F64, 1, WD_FULL), p.struct_size, p.solver,\n"
+        "         (int)wd_dslash(NULL, NULL, NULL, 0.1, dims, WD_FULL), wd_status_string(WD_ERR_ARG));\n"
+        "  return 0;\n}\n")
+    exe = tmp_path / "use_wd"
+    lib_dir = os.path.dirname(LIB)
+    cc = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", os.path.dirname(HEADER),
+                         str(src), "-L", lib_dir, "-lwd", f"-Wl,-rpath,{lib_dir}", "-o", str(exe)],
+                        capture_output=True, text=True)
+    assert cc.returncode == 0, cc.stderr
+    run = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert run.returncode == 0, run.stderr
+    nbytes, size, solver, rc, msg = run.stdout.split(maxsplit=4)
+    import paper_0710_2442_amd as wd
+    assert int(nbytes) == wd.wd_field_bytes((8, 8, 8, 8), "f64")
+    assert int(size) == wd.wd_solve_params_default().struct_size and int(solver) == wd.WD_SOLVER_CG
+    assert int(rc) == -1 and msg.strip()
