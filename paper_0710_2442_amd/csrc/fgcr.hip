@@ -483,7 +483,8 @@ wd_status solve_fgcr_mixed(wd_gauge *g, const void *b, void *x, double kappa, do
   if (S != WD_F32 && S != WD_BF16) return set_error(WD_ERR_PREC, "FGCR: inner_prec must be FP32 or BF16");
   const size_t h64 = half_bytes(G, WD_F64), h32 = half_bytes(G, WD_F32), hS = half_bytes(G, S);
   // r64, d64 (2 h64 each); rh, e (2 h32 each); R, T, Z[m], W[m] (hS each); then the
-  // device scalars ([0, 128) CgScalars, then dots/sig/rho/rr), the reduction partials and
+  // device scalars ([0, 128) CgScalars, [128, 536) dots/sig/rho/rr, [640, 768) the cycle's
+  // step lengths), the reduction partials and
   // a counter word.  Kept in the handle between solves (grown when a solve needs more).
   const unsigned nblk = (unsigned)std::min<long>(std::max<long>(1, ((long)G.vh + FG_BS - 1) / FG_BS), FG_MAX_BLOCKS);
   const size_t npart = std::max<size_t>((size_t)2 * FG_MMAX * nblk,
@@ -528,6 +529,9 @@ wd_status solve_fgcr_mixed(wd_gauge *g, const void *b, void *x, double kappa, do
   a.rho = a.sig + FG_MMAX;
   a.rr = a.rho + 2;
   a.alpha = (float *)(red + 640);  // 2 FG_MMAX floats inside the scalar block
+  static_assert(sizeof(CgScalars) <= 128, "CgScalars exceed their slot");
+  static_assert(128 + (2 * FG_MMAX + FG_MMAX + 3) * sizeof(double) <= 640, "FGCR scalars overlap");
+  static_assert(640 + 2 * FG_MMAX * sizeof(float) <= 1024, "FGCR step lengths exceed the scalar block");
   a.r = R;
   a.e = E;
   a.partials = (double *)(red + scal_bytes);
