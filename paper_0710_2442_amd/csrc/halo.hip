@@ -99,11 +99,16 @@ __device__ __forceinline__ void time_hop_from_half(cplx<RealOf<P>> (&acc)[12], c
   reconstruct_add<3, S>(acc, g);
 }
 
+// 64-site blocks: a rank's share is small (131,072 sites per parity at
+// 32^3x8; a face 16,384 sites), and 64-site blocks spread it over every CU
+// where 256-site blocks left most of them idle
+constexpr int SLAB_BS = 64;
+
 template <int P, bool DAG>
-__global__ __launch_bounds__(256) void k_dslash_slab(KSlab k) {
+__global__ __launch_bounds__(SLAB_BS) void k_dslash_slab(KSlab k) {
   using T = RealOf<P>;
   const int vs = k.g.s4;  // sites of one parity per slice
-  const int il = blockIdx.x * 256 + threadIdx.x;
+  const int il = blockIdx.x * SLAB_BS + threadIdx.x;
   if (il >= k.nt * vs) return;
   const int base = k.t0 * vs;
   const int i = base + il;  // global checkerboard index
@@ -157,9 +162,9 @@ __global__ __launch_bounds__(256) void k_dslash_slab(KSlab k) {
 // face[j] = the (LOWER) half of input site (slice ts, in-slice index j) of a
 // rank's slab.
 template <int P, bool LOWER>
-__global__ __launch_bounds__(256) void k_halo_pack(const char *in, int local_slice, int vs, char *face) {
+__global__ __launch_bounds__(SLAB_BS) void k_halo_pack(const char *in, int local_slice, int vs, char *face) {
   using T = RealOf<P>;
-  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int j = blockIdx.x * SLAB_BS + threadIdx.x;
   if (j >= vs) return;
   cplx<T> h[6];
   Spinor<P>::template load_half<LOWER>(in, (size_t)local_slice * vs + j, h);
@@ -180,12 +185,14 @@ wd_status launch_halo_pack(const wd_gauge *g, const void *in_slab, int nt, int f
   // the top face the rank above's backward one; F = +1, or -1 for the dagger
   const bool lower = (face == 0) ? (dagger != 0) : (dagger == 0);
   const int ls = (face == 0) ? 0 : nt - 1;
-  const dim3 grid((unsigned)((G.s4 + 255) / 256));
-#define WD_PK(PR)                                                                                              \
-  if (lower) hipLaunchKernelGGL((k_halo_pack<PR, true>), grid, dim3(256), 0, st, (const char *)in_slab, ls, G.s4, \
-                                (char *)face_buf);                                                             \
-  else hipLaunchKernelGGL((k_halo_pack<PR, false>), grid, dim3(256), 0, st, (const char *)in_slab, ls, G.s4,     \
-                          (char *)face_buf);
+  const dim3 grid((unsigned)((G.s4 + SLAB_BS - 1) / SLAB_BS));
+#define WD_PK(PR)                                                                                        \
+  if (lower)                                                                                             \
+    hipLaunchKernelGGL((k_halo_pack<PR, true>), grid, dim3(SLAB_BS), 0, st, (const char *)in_slab, ls, G.s4, \
+                       (char *)face_buf);                                                                \
+  else                                                                                                   \
+    hipLaunchKernelGGL((k_halo_pack<PR, false>), grid, dim3(SLAB_BS), 0, st, (const char *)in_slab, ls, G.s4, \
+                       (char *)face_buf);
   if (prec == WD_F64) { WD_PK(WD_F64) } else { WD_PK(WD_F32) }
 #undef WD_PK
   return hip_check(hipGetLastError(), "halo pack launch");
@@ -206,10 +213,10 @@ wd_status launch_dslash_slab(const wd_gauge *g, const void *in_slab, const void 
   k.links = (const char *)(f64 ? g->links64 : g->links32) + (size_t)parity * link_parity_bytes(g->geom, f64);
   k.a = a;
   k.parity = parity;
-  const dim3 grid((unsigned)(((size_t)nt * k.g.s4 + 255) / 256));
+  const dim3 grid((unsigned)(((size_t)nt * k.g.s4 + SLAB_BS - 1) / SLAB_BS));
 #define WD_SL(PR)                                                                                        \
-  if (dagger) hipLaunchKernelGGL((k_dslash_slab<PR, true>), grid, dim3(256), 0, st, k);                 \
-  else hipLaunchKernelGGL((k_dslash_slab<PR, false>), grid, dim3(256), 0, st, k);
+  if (dagger) hipLaunchKernelGGL((k_dslash_slab<PR, true>), grid, dim3(SLAB_BS), 0, st, k);             \
+  else hipLaunchKernelGGL((k_dslash_slab<PR, false>), grid, dim3(SLAB_BS), 0, st, k);
   if (f64) { WD_SL(WD_F64) } else { WD_SL(WD_F32) }
 #undef WD_SL
   return hip_check(hipGetLastError(), "slab hop launch");
