@@ -363,6 +363,7 @@ def kernels_leg(wd, torch, syn, U, psi):
     V = int(np.prod(DIMS))
     out = {}
     g = wd.Gauge(U, DIMS, -1, "f64")
+    use_tuned(wd, g, TUNE_TABLE, False, ("f64", "f32"))
     x = canon_to_field(g, psi, "f64")
     y = x.clone()
     z = wd.wd_new_field(DIMS, "f64")
