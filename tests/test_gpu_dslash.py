@@ -170,7 +170,7 @@ def test_bitwise_deterministic():
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
-@pytest.mark.parametrize("nrhs", [1, 5, 12])
+@pytest.mark.parametrize("nrhs", [1, 5, 12, 24])
 def test_mrhs_equals_single_rhs_bitwise(prec, nrhs):
     dims = (8, 8, 8, 16)
     U = syn.gauge_field(dims, 0.3, 21)
