@@ -195,6 +195,26 @@ def test_multi_rhs_point_sources(prec):
     g.close()
 
 
+def test_multi_rhs_solve_beyond_one_chunk():
+    """24 Gaussian sources in one multi-RHS solve (BF16 storage; more RHS than
+    one chunk of the multi-RHS hop, the count the training uses): every
+    system reaches the tolerance by the oracle's own D_W."""
+    dims, kappa, n = (8, 4, 6, 8), 0.124, 24
+    U = syn.gauge_field(dims, 0.3, 31)
+    bs = syn.gaussian_spinor(dims, 32, nrhs=n)
+    g = wd.Gauge(U, dims, -1, "f64")
+    fb = torch.cat([to_field(g, bs[r]) for r in range(n)])
+    fx = wd.wd_new_field(dims, "f64", n)
+    p = wd.wd_solve_params_default(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec="bf16", inner_tol=1e-2)
+    rc, infos = wd.wd_solve_mrhs(g, fb, fx, n, kappa, TOL, p)
+    assert rc == 0
+    nb = wd.wd_field_bytes(dims, "f64")
+    for r in range(n):
+        res = solvers.true_residual(U, bs[r], from_field(g, fx[r * nb:(r + 1) * nb]), kappa)
+        assert res <= TOL, (r, res)
+    g.close()
+
+
 def test_multi_rhs_mixed_convergence_masks():
     """Systems that converge early stop consuming work; others continue to tolerance."""
     dims, kappa = (6, 4, 6, 10), 0.124
