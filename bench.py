@@ -486,7 +486,7 @@ def cpu_leg(syn, U, psi):
 def paper_context(sites_per_s):
     """The paper's Cell BE numbers for the same hop, quoted beside this run as
     context (other hardware, model estimates; not a target)."""
-    # Table 1 (Sec. 6), data in main memory: the memory time per site is
+    # Table 1 (Sec. 5), data in main memory: the memory time per site is
     # 120 DP words (spinor in, 4 links, spinor out) = 960 B over 25.6 GB/s.
     cell_sites = 25.6e9 / 960.0
     return {
@@ -494,10 +494,10 @@ def paper_context(sites_per_s):
             "msite_per_s": round(cell_sites / 1e6, 1),
             "gflop_per_s": round(cell_sites * 1320 / 1e9, 1),
             "eps_fp": 0.34,
-            "basis": "Table 1 (Sec. 6), 8^3 slices streamed from main memory: 960 B per site at 25.6 GB/s; "
+            "basis": "Table 1 (Sec. 5), 8^3 slices streamed from main memory: 960 B per site at 25.6 GB/s; "
                      "model estimate for a chip not yet built",
         },
-        "cell_measurements": "Sec. 6: a benchmark of the hop's access pattern ran within 20% of the memory-time "
+        "cell_measurements": "Sec. 5: a benchmark of the hop's access pattern ran within 20% of the memory-time "
                              "prediction; Sec. 4: caxpy at <= 4.1% of peak on PS3 / QS20 / Mercury CAB "
                              "(single-precision benchmarks)",
         "this_run_fp64_hop_msite_per_s": round(sites_per_s / 1e6, 1),

@@ -264,7 +264,10 @@ typedef struct {
 /* Fill params with defaults (plain FP64 even-odd CG on the normal equations). */
 void wd_solve_params_default(wd_solve_params *p);
 
-/* Solve D_W x = b to |b - D_W x| / |b| <= tol (FP64 true residual).  b and x
+/* Solve D_W x = b to |b - D_W x| / |b| <= tol (FP64 true residual).  The
+ * paper names an iterative solver that applies Eq. 3 repeatedly (Sec. 5, data
+ * in on-chip memory) without choosing one; the default here is CG on the
+ * normal equations of the even-odd Schur operator.  b and x
  * are full FP64 fields (device); x is output only (the initial guess is 0).
  * p = NULL selects FP64 even-odd CGLS; see wd_solve_params for the mixed
  * precision and FGCR forms.  Synchronous.  b = 0 gives x = 0 and WD_OK.

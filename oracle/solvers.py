@@ -1,8 +1,7 @@
 """Krylov solvers for D_W x = b, written out plainly (test infrastructure only).
 
-The paper names "an entire iterative solver with repeated computation of
-Eq. 3" (Sec. 5, data in on-chip memory) without fixing which one.  The
-readings used throughout:
+The paper leaves the solver that applies Eq. 3 over and over unspecified
+(Sec. 5, data in on-chip memory).  The readings used throughout:
 
 * CGLS: CG on the normal equations D^dag D x = D^dag b, started from x = 0,
   with the recursive residual s = b - D x carried explicitly so that the

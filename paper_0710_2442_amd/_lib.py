@@ -149,13 +149,37 @@ def _dims(d):
     return _int4(*[int(x) for x in d])
 
 
-def _ptr(t):
-    """Device (or host) address of a torch tensor or numpy array."""
+def _need(dims, prec, nrhs, parity):
+    """Bytes of nrhs fields (0 for arguments the library itself rejects)."""
+    try:
+        return int(lib.wd_field_bytes(_dims(dims), _prec(prec), int(nrhs), int(parity)))
+    except (KeyError, ValueError, TypeError):
+        return 0
+
+
+def _buf(t, nbytes, what):
+    """Address of a caller buffer for the library, after checking it on the
+    host: a contiguous torch tensor on a GPU holding at least nbytes bytes.
+    The library cannot see buffer sizes, so a short buffer would be read or
+    written past its end on the device."""
     if t is None:
         return None
-    if isinstance(t, np.ndarray):
-        return t.ctypes.data
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what}: a torch device tensor is expected, got {type(t).__name__}")
+    if not t.is_cuda:
+        raise ValueError(f"{what}: the tensor is not in GPU memory")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: the tensor is not contiguous")
+    have = t.numel() * t.element_size()
+    if have < nbytes:
+        raise ValueError(f"{what}: {have} bytes given, {nbytes} needed")
     return t.data_ptr()
+
+
+def _canon_bytes(dims):
+    return int(np.prod([int(d) for d in dims])) * 12 * 16
 
 
 def _stream():
@@ -239,13 +263,15 @@ def wd_last_error():
 def wd_spinor_pack(g, canon, field, parity=WD_FULL, prec=None):
     g.sync_stream()
     p = g.prec if prec is None else _prec(prec)
-    _check(lib.wd_spinor_pack(g.handle, _ptr(canon), _ptr(field), int(parity), p), "wd_spinor_pack")
+    _check(lib.wd_spinor_pack(g.handle, _buf(canon, _canon_bytes(g.dims), "canon"),
+                              _buf(field, _need(g.dims, p, 1, parity), "field"), int(parity), p), "wd_spinor_pack")
 
 
 def wd_gaussian_field(g, field, parity, prec, seed, stream):
     """Fill a field with i.i.d. N(0,1) stored components (Philox4x64-10 + Box-Muller, on the device)."""
     g.sync_stream()
-    _check(lib.wd_gaussian_field(g.handle, _ptr(field), int(parity), _prec(prec), int(seed) & (2**64 - 1),
+    _check(lib.wd_gaussian_field(g.handle, _buf(field, _need(g.dims, prec, 1, parity), "field"), int(parity),
+                                 _prec(prec), int(seed) & (2**64 - 1),
                                  int(stream) & (2**64 - 1)), "wd_gaussian_field")
 
 
@@ -276,65 +302,94 @@ def wd_halo_face_bytes(dims, prec):
     return int(lib.wd_halo_face_bytes(_dims(dims), _prec(prec)))
 
 
+def _slab_bytes(g, nt, prec):
+    slot = {WD_F64: 192, WD_F32: 96}.get(_prec(prec), 0)
+    L1, L2, L3, _ = g.dims
+    return max(int(nt), 0) * (L1 * L2 * L3 // 2) * slot
+
+
 def wd_halo_pack(g, in_slab, nt, face, dagger, prec, face_buf):
     g.sync_stream()
-    _check(lib.wd_halo_pack(g.handle, _ptr(in_slab), int(nt), int(face), int(dagger), _prec(prec), _ptr(face_buf)),
+    _check(lib.wd_halo_pack(g.handle, _buf(in_slab, _slab_bytes(g, nt, prec), "in_slab"), int(nt), int(face),
+                            int(dagger), _prec(prec), _buf(face_buf, wd_halo_face_bytes(g.dims, prec), "face_buf")),
            "wd_halo_pack")
 
 
 def wd_dslash_slab(g, in_slab, face_lo, face_hi, out_slab, a, parity, t0, nt, dagger, prec):
     g.sync_stream()
-    _check(lib.wd_dslash_slab(g.handle, _ptr(in_slab), _ptr(face_lo), _ptr(face_hi), _ptr(out_slab), float(a),
+    sb, fb = _slab_bytes(g, nt, prec), wd_halo_face_bytes(g.dims, prec)
+    _check(lib.wd_dslash_slab(g.handle, _buf(in_slab, sb, "in_slab"), _buf(face_lo, fb, "face_lo"),
+                              _buf(face_hi, fb, "face_hi"), _buf(out_slab, sb, "out_slab"), float(a),
                               int(parity), int(t0), int(nt), int(dagger), _prec(prec)), "wd_dslash_slab")
 
 
 def wd_spinor_unpack(g, field, canon, parity=WD_FULL, prec=None):
     g.sync_stream()
     p = g.prec if prec is None else _prec(prec)
-    _check(lib.wd_spinor_unpack(g.handle, _ptr(field), _ptr(canon), int(parity), p), "wd_spinor_unpack")
+    _check(lib.wd_spinor_unpack(g.handle, _buf(field, _need(g.dims, p, 1, parity), "field"),
+                                _buf(canon, _canon_bytes(g.dims), "canon"), int(parity), p), "wd_spinor_unpack")
+
+
+def _hop_fields(g, prec, parity, nrhs=1):
+    """(input bytes, output bytes) of a hop of output parity `parity`."""
+    if int(parity) in (WD_EVEN, WD_ODD):
+        return _need(g.dims, prec, nrhs, 1 - int(parity)), _need(g.dims, prec, nrhs, parity)
+    return _need(g.dims, prec, nrhs, parity), _need(g.dims, prec, nrhs, parity)
 
 
 def wd_dslash(g, psi_in, psi_out, kappa, dims, parity):
     g.sync_stream()
-    _check(lib.wd_dslash(g.handle, _ptr(psi_in), _ptr(psi_out), float(kappa), _dims(dims), int(parity)),
-           "wd_dslash")
+    ni, no = _hop_fields(g, g.prec, parity)
+    _check(lib.wd_dslash(g.handle, _buf(psi_in, ni, "psi_in"), _buf(psi_out, no, "psi_out"), float(kappa),
+                         _dims(dims), int(parity)), "wd_dslash")
 
 
 def wd_dslash_ex(g, psi_in, psi_out, kappa, parity, prec, flags=0):
     g.sync_stream()
-    _check(lib.wd_dslash_ex(g.handle, _ptr(psi_in), _ptr(psi_out), float(kappa), int(parity), _prec(prec),
-                            int(flags)), "wd_dslash_ex")
+    ni, no = _hop_fields(g, prec, parity)
+    _check(lib.wd_dslash_ex(g.handle, _buf(psi_in, ni, "psi_in"), _buf(psi_out, no, "psi_out"), float(kappa),
+                            int(parity), _prec(prec), int(flags)), "wd_dslash_ex")
 
 
 def wd_dslash_mrhs(g, psi_in, psi_out, kappa, parity, prec, nrhs):
     g.sync_stream()
-    _check(lib.wd_dslash_mrhs(g.handle, _ptr(psi_in), _ptr(psi_out), float(kappa), int(parity), _prec(prec),
-                              int(nrhs)), "wd_dslash_mrhs")
+    ni, no = _hop_fields(g, prec, parity, max(int(nrhs), 1))
+    _check(lib.wd_dslash_mrhs(g.handle, _buf(psi_in, ni, "psi_in"), _buf(psi_out, no, "psi_out"), float(kappa),
+                              int(parity), _prec(prec), int(nrhs)), "wd_dslash_mrhs")
+
+
+def _halves(g, prec, nhalf):
+    return _need(g.dims, prec, max(int(nhalf), 1), WD_EVEN)
 
 
 def wd_caxpy(g, c, x, y, nhalf, prec):
     g.sync_stream()
     c = complex(c)
-    _check(lib.wd_caxpy(g.handle, c.real, c.imag, _ptr(x), _ptr(y), int(nhalf), _prec(prec)), "wd_caxpy")
+    n = _halves(g, prec, nhalf)
+    _check(lib.wd_caxpy(g.handle, c.real, c.imag, _buf(x, n, "x"), _buf(y, n, "y"), int(nhalf), _prec(prec)),
+           "wd_caxpy")
 
 
 def wd_cdot(g, x, y, nhalf, prec):
     g.sync_stream()
     out = (C.c_double * 2)()
-    _check(lib.wd_cdot(g.handle, _ptr(x), _ptr(y), int(nhalf), _prec(prec), out), "wd_cdot")
+    n = _halves(g, prec, nhalf)
+    _check(lib.wd_cdot(g.handle, _buf(x, n, "x"), _buf(y, n, "y"), int(nhalf), _prec(prec), out), "wd_cdot")
     return complex(out[0], out[1])
 
 
 def wd_norm2(g, x, nhalf, prec):
     g.sync_stream()
     out = C.c_double()
-    _check(lib.wd_norm2(g.handle, _ptr(x), int(nhalf), _prec(prec), C.byref(out)), "wd_norm2")
+    _check(lib.wd_norm2(g.handle, _buf(x, _halves(g, prec, nhalf), "x"), int(nhalf), _prec(prec), C.byref(out)),
+           "wd_norm2")
     return out.value
 
 
 def wd_convert(g, x, pin, y, pout, nhalf, scale=1.0):
     g.sync_stream()
-    _check(lib.wd_convert(g.handle, _ptr(x), _prec(pin), _ptr(y), _prec(pout), int(nhalf), float(scale)),
+    _check(lib.wd_convert(g.handle, _buf(x, _halves(g, pin, nhalf), "in"), _prec(pin),
+                          _buf(y, _halves(g, pout, nhalf), "out"), _prec(pout), int(nhalf), float(scale)),
            "wd_convert")
 
 
@@ -355,7 +410,8 @@ def wd_solve(g, b, x, kappa, tol, params=None):
     g.sync_stream()
     info = wd_solve_info()
     pp = C.byref(params) if params is not None else None
-    rc = lib.wd_solve(g.handle, _ptr(b), _ptr(x), float(kappa), float(tol), pp, C.byref(info))
+    n = _need(g.dims, WD_F64, 1, WD_FULL)
+    rc = lib.wd_solve(g.handle, _buf(b, n, "b"), _buf(x, n, "x"), float(kappa), float(tol), pp, C.byref(info))
     _check(rc, "wd_solve", allow_not_converged=True)
     return rc, info.as_dict()
 
@@ -363,8 +419,9 @@ def wd_solve(g, b, x, kappa, tol, params=None):
 def wd_solve_mrhs(g, b, x, nrhs, kappa, tol, params):
     g.sync_stream()
     infos = (wd_solve_info * int(nrhs))()
-    rc = lib.wd_solve_mrhs(g.handle, _ptr(b), _ptr(x), int(nrhs), float(kappa), float(tol), C.byref(params),
-                           infos)
+    n = _need(g.dims, WD_F64, max(int(nrhs), 1), WD_FULL)
+    rc = lib.wd_solve_mrhs(g.handle, _buf(b, n, "b"), _buf(x, n, "x"), int(nrhs), float(kappa), float(tol),
+                           C.byref(params), infos)
     _check(rc, "wd_solve_mrhs", allow_not_converged=True)
     return rc, [i.as_dict() for i in infos]
 
@@ -465,21 +522,24 @@ def wd_ptc_get_weights(n):
 
 def wd_ptc_apply(n, x, y):
     n.g.sync_stream()
-    _check(lib.wd_ptc_apply(n.handle, _ptr(x), _ptr(y)), "wd_ptc_apply")
+    nb = _need(n.g.dims, WD_F32, 1, WD_FULL)
+    _check(lib.wd_ptc_apply(n.handle, _buf(x, nb, "in"), _buf(y, nb, "out")), "wd_ptc_apply")
 
 
 def wd_ptc_apply_even(n, x_even, pin, y_even, pout, flags=0):
     """y_e = [N(x_e, 0)]_e on even half fields (flags: 0 or WD_PTC_FP16_PRODUCTS)."""
     n.g.sync_stream()
-    _check(lib.wd_ptc_apply_even(n.handle, _ptr(x_even), _prec(pin), _ptr(y_even), _prec(pout), int(flags)),
-           "wd_ptc_apply_even")
+    _check(lib.wd_ptc_apply_even(n.handle, _buf(x_even, _need(n.g.dims, pin, 1, WD_EVEN), "in_even"), _prec(pin),
+                                 _buf(y_even, _need(n.g.dims, pout, 1, WD_EVEN), "out_even"), _prec(pout),
+                                 int(flags)), "wd_ptc_apply_even")
 
 
 def wd_ptc_loss_grad(n, r, e, B):
     n.g.sync_stream()
     loss = C.c_double()
     grad = np.empty(1152, np.float32)
-    _check(lib.wd_ptc_loss_grad(n.handle, _ptr(r), _ptr(e), int(B), C.byref(loss),
+    nb = _need(n.g.dims, WD_F32, max(int(B), 1), WD_FULL)
+    _check(lib.wd_ptc_loss_grad(n.handle, _buf(r, nb, "r"), _buf(e, nb, "e"), int(B), C.byref(loss),
                                 grad.ctypes.data_as(C.POINTER(C.c_float))), "wd_ptc_loss_grad")
     return loss.value, grad
 
@@ -487,7 +547,8 @@ def wd_ptc_loss_grad(n, r, e, B):
 def wd_ptc_train_step(n, r, e, B, lr, want_loss=True):
     n.g.sync_stream()
     loss = C.c_double()
-    _check(lib.wd_ptc_train_step(n.handle, _ptr(r), _ptr(e), int(B), float(lr),
+    nb = _need(n.g.dims, WD_F32, max(int(B), 1), WD_FULL)
+    _check(lib.wd_ptc_train_step(n.handle, _buf(r, nb, "r"), _buf(e, nb, "e"), int(B), float(lr),
                                  C.byref(loss) if want_loss else None), "wd_ptc_train_step")
     return loss.value if want_loss else None
 
@@ -498,8 +559,9 @@ def wd_solve_batch(gauges, bs, xs, kappas, tol, params):
     for g in gauges:
         g.sync_stream()
     hs = (_vp * n)(*[g.handle for g in gauges])
-    pb = (_vp * n)(*[_ptr(b) for b in bs])
-    px = (_vp * n)(*[_ptr(x) for x in xs])
+    nbs = [_need(g.dims, WD_F64, 1, WD_FULL) for g in gauges]
+    pb = (_vp * n)(*[_buf(b, k, "b") for b, k in zip(bs, nbs)])
+    px = (_vp * n)(*[_buf(x, k, "x") for x, k in zip(xs, nbs)])
     ks = (C.c_double * n)(*[float(k) for k in kappas])
     infos = (wd_solve_info * n)()
     rc = lib.wd_solve_batch(hs, n, pb, px, ks, float(tol), C.byref(params), infos)

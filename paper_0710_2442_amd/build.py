@@ -47,18 +47,22 @@ def _hipcc():
     return exe
 
 
-# Host-only AddressSanitizer build (--asan): every -fsanitize applies to the
-# host side of the compilation only; device code is built as usual.
+# Host AddressSanitizer build (--asan): the host side of every source is
+# compiled with -fsanitize=address and the device side is not compiled at all
+# (--offload-host-only), so the copy checks the C-ABI's host code (argument
+# checks, error paths, bookkeeping) on a machine without a GPU and builds in
+# seconds; its kernels cannot run.
 ASAN_BUILD = os.path.join(ROOT, "_build_asan")
 ASAN_LIB = os.path.join(ASAN_BUILD, "libwd_asan.so")
-ASAN_FLAGS = ["-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
+ASAN_FLAGS = ["--offload-host-only", "-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host",
+              "-fno-omit-frame-pointer"]
 
 
-def _compile(src, asan=False):
-    obj = os.path.join(ASAN_BUILD if asan else BUILD, os.path.basename(src) + ".o")
+def _compile(src, asan=False, out_dir=None):
+    obj = os.path.join(out_dir or (ASAN_BUILD if asan else BUILD), os.path.basename(src) + ".o")
     flags = HIP_FLAGS if src.endswith(".hip") else CXX_FLAGS
     if asan:
-        flags = flags + ASAN_FLAGS
+        flags = flags + (ASAN_FLAGS if src.endswith(".hip") else ASAN_FLAGS[1:])
     cmd = [_hipcc(), *flags, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l and l.strip())
@@ -67,21 +71,23 @@ def _compile(src, asan=False):
     return obj, err
 
 
-def build(verbose=False, jobs=None, asan=False):
-    """Build libwd.so (asan: the host-sanitized copy _build_asan/libwd_asan.so,
-    for the CPU tests of the C-ABI; load it with the compiler's ASan runtime
-    preloaded)."""
-    out_dir = ASAN_BUILD if asan else BUILD
-    lib = ASAN_LIB if asan else LIB
+def build(verbose=False, jobs=None, asan=False, out_dir=None):
+    """Build libwd.so (asan: the host-sanitized, host-only copy libwd_asan.so
+    in out_dir, default _build_asan/, for the CPU tests of the C-ABI; load it
+    with the compiler's ASan runtime preloaded)."""
+    out_dir = out_dir or (ASAN_BUILD if asan else BUILD)
+    lib = os.path.join(out_dir, "libwd_asan.so") if asan else LIB
     os.makedirs(out_dir, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
     jobs = jobs or min(8, os.cpu_count() or 4)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        results = list(ex.map(lambda src: _compile(src, asan), srcs))
+        results = list(ex.map(lambda src: _compile(src, asan, out_dir), srcs))
     for obj, err in results:
         if verbose and err:
             print(err, file=sys.stderr)
     objs = [o for o, _ in results]
+    if asan:
+        objs.append(_empty_fatbins(objs, out_dir))
     tmp = lib + ".tmp"
     link = ["-Xarch_host", "-fsanitize=address", "-shared-libasan"] if asan else []
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *link, "-o", tmp, *objs]
@@ -90,6 +96,23 @@ def build(verbose=False, jobs=None, asan=False):
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
     os.replace(tmp, lib)
     return lib
+
+
+def _empty_fatbins(objs, out_dir):
+    """The host-only objects refer to one device-code bundle per source
+    (__hip_fatbin_<id>).  Define each as a clang offload bundle with no
+    entries, so the copy loads and registers no device code."""
+    names = set()
+    for o in objs:
+        r = subprocess.run(["nm", "-u", o], capture_output=True, text=True, check=True)
+        names.update(l.split()[-1] for l in r.stdout.splitlines() if "__hip_fatbin_" in l)
+    src = os.path.join(out_dir, "empty_fatbins.c")
+    with open(src, "w") as f:
+        for n in sorted(names):
+            f.write('const char %s[32] __attribute__((aligned(4096))) = "__CLANG_OFFLOAD_BUNDLE__";\n' % n)
+    obj = src + ".o"
+    subprocess.run(["gcc", "-c", "-fPIC", src, "-o", obj], check=True)
+    return obj
 
 
 def asan_runtime():

@@ -361,9 +361,11 @@ __global__ void k_ptc_rotate(const float *M, float *out, int n) {
     }
 }
 
-// Loss pieces: d = y - e (FP32 full fields); gy = scale * d; partial |d|^2.
+// Loss pieces: d = y - e (FP32 full fields); gy = scale * d; each block
+// stores its FP64 partial sum of |d|^2, which the finishing kernel adds up in
+// block order.
 __global__ __launch_bounds__(256) void k_ptc_loss(const char *y, const char *e, char *gy, Geom g, float scale,
-                                                  double *partials, unsigned *counter, double *loss) {
+                                                  double *partials) {
   const int p = blockIdx.y;
   const int i = blockIdx.x * 256 + threadIdx.x;
   const size_t hb = (size_t)96 * g.vpad;  // one FP32 half field
@@ -385,9 +387,8 @@ __global__ __launch_bounds__(256) void k_ptc_loss(const char *y, const char *e, 
     }
     Spinor<WD_F32>::store(gy + p * hb, i, a);
   }
-  double v[1] = {acc}, tot[1];
-  const unsigned nb = gridDim.x * gridDim.y, bid = blockIdx.y * gridDim.x + blockIdx.x;
-  if (grid_sum_last<1>(v, partials, counter, nb, bid, tot)) *loss += tot[0];
+  double v[1] = {acc};
+  block_sum_store<1>(v, partials, gridDim.x * gridDim.y, blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 // Adam on the 1152 real parameters (real and imaginary parts separately).
@@ -683,7 +684,6 @@ struct wd_ptc {
   void *x0, *y1, *y2, *gy2, *gy1;  // activations / gradients of one sample
   double *partials;                // wgrad partials: layer 1 then layer 2, nblk x 576 each
   double *scal;                    // [0] loss; [64..] reduction partials
-  unsigned *cnt;
   int nblk;                        // blocks of a full-lattice launch (both parities)
   // FP16-product inference (made on first use): FP16 hop links of both
   // parities, FP16 weights, and the input norm with its reduction partials
@@ -895,14 +895,12 @@ static wd_status ptc_alloc(wd_ptc *n) {
   WD_HIP(hipMalloc(&n->gy1, 2 * f32));
   WD_HIP(hipMalloc(&n->partials, (size_t)2 * n->nblk * 576 * sizeof(double)));
   WD_HIP(hipMalloc(&n->scal, (size_t)(n->nblk + 64) * sizeof(double)));
-  WD_HIP(hipMalloc(&n->cnt, 256));
-  WD_HIP(hipMemset(n->cnt, 0, 256));
   return WD_OK;
 }
 
 static void ptc_free(wd_ptc *n) {
   void *ps[] = {n->Wc,  n->gradc, n->W,  n->Wadj,     n->grad, n->m,   n->v,       n->x0,  n->y1,    n->y2,
-                n->gy2, n->gy1,   n->partials, n->scal, n->cnt, n->links16, n->W16, n->hnorm, n->hcnt};
+                n->gy2, n->gy1,   n->partials, n->scal, n->links16, n->W16, n->hnorm, n->hcnt};
   for (void *p : ps)
     if (p) (void)hipFree(p);
   delete n;
@@ -925,8 +923,9 @@ static wd_status ptc_loss_grad(wd_ptc *n, const void *r, const void *e, int B, h
     WD_TRY(ptc_layer(n, n->W, n->x0, n->act, 1, n->y1, n->act, 2, st));
     WD_TRY(ptc_layer(n, n->W + 576, n->y1, n->act, 2, n->y2, WD_F32, 1, st));
     hipLaunchKernelGGL(k_ptc_loss, ptc_grid(G), dim3(256), 0, st, (const char *)n->y2, eb, (char *)n->gy2, G,
-                       2.0f / (float)B, n->scal + 64, n->cnt, n->scal);
+                       2.0f / (float)B, n->scal + 64);
     WD_HIP(hipGetLastError());
+    WD_TRY(launch_finish_sums(n->scal + 64, (unsigned)n->nblk, 1, n->scal, 1, 1, nullptr, 1, st));
     WD_TRY(ptc_wgrad(n, 1, n->y1, n->act, n->gy2, b > 0, st));
     // input gradient of layer 2 (adjoint weights: 1 -> 2 channels)
     WD_TRY(ptc_layer(n, n->Wadj + 576, n->gy2, WD_F32, 1, n->gy1, WD_F32, 2, st));

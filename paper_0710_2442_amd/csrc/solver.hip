@@ -3,8 +3,8 @@
 // * FP64 even-odd CGLS: CG on the normal equations of the Schur operator
 //   M = 1 - k^2 H_eo H_oe (M^dag = 1 - k^2 H^dag_eo H^dag_oe), right-hand
 //   side b_e + k H_eo b_o, odd sites x_o = b_o + k H_oe x_e.  The paper
-//   names "an entire iterative solver with repeated computation of Eq. 3"
-//   (Sec. 5) without choosing one; CGLS is the reading used here.
+//   leaves the solver that applies Eq. 3 over and over unspecified (Sec. 5,
+//   data in on-chip memory); CGLS is the reading used here.
 // * Defect correction: FP64 outer residual r = b - D x, inner even-odd CGLS
 //   in FP32 arithmetic on r/|r| with vectors stored in FP32, FP16 (+ per-site
 //   scale) or BF16, x += |r| e in FP64.

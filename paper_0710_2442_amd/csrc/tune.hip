@@ -14,6 +14,7 @@
 #include <string.h>
 
 #include <string>
+#include <array>
 #include <vector>
 
 #include "wd_internal.h"
@@ -241,51 +242,57 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, g->device) == hipSuccess) lds_max = prop.sharedMemPerBlock;
       }
+      // the candidates, listed first so that one loop runs them and a failure
+      // ends the whole search
+      struct Cand { int spl, pre, lkb, nts, oc, b, gr; };
+      std::vector<Cand> cands;
       for (int spl : {1, 2, 4})
-      for (int pre : {0, 1})
-      for (int lkb : {0, 24, 40, 60})
-      for (int nts : {1, 0})
-      for (int oc : {0, 4})
-      for (int b : blocks) {
-        for (int gr : grps) {
-          if (!dslash_variant_ok(G, b, gr, spl)) continue;
-          if (pre && prec == WD_F64) continue;
-          if (oc == 4 && lkb != 0) continue;  // both only lower occupancy; keep the grid small
-          if ((size_t)lkb * 1024 + 1024 > lds_max) continue;
-          g->hop_block[prec] = b; g->hop_groups[prec] = gr; g->hop_occ[prec] = oc; g->hop_ntst[prec] = nts;
-          g->hop_lds[prec] = lkb * 1024;
-          g->hop_pre[prec] = pre;
-          g->hop_spl[prec] = spl;
-          if ((rc = launch_pack_spinor(g, canon, in, WD_ODD, prec, st)) != WD_OK) break;
-          a.out = cand;
-          if ((rc = hip_check(hipMemsetAsync(cand, 0xff, hb, st), "memset")) != WD_OK) break;
-          if ((rc = launch_dslash(g, prec, a, st)) != WD_OK) break;
-          bool same = false;
-          if ((rc = same_bytes(ref, cand, hb, flag, same, st)) != WD_OK) break;
-          if (!same) continue;  // parity first
-          // time the pattern of a solver: even and odd hops alternate, so the
-          // two parities' link arrays stream through the caches in turn
-          const int reps = 6;
-          DslashArgs b2 = a;
-          b2.in = cand; b2.out = in; b2.parity = WD_ODD;
-          auto pair = [&]() { (void)launch_dslash(g, prec, a, st); (void)launch_dslash(g, prec, b2, st); };
-          for (int w = 0; w < 2; ++w) pair();
-          (void)hipEventRecord(e0, st);
-          for (int r = 0; r < reps; ++r) pair();
-          (void)hipEventRecord(e1, st);
-          if ((rc = hip_check(hipEventSynchronize(e1), "tune timing")) != WD_OK) break;
-          float ms = 0.f;
-          (void)hipEventElapsedTime(&ms, e0, e1);
-          const double us = 1e3 * ms / (2 * reps);
-          if (getenv("WD_TUNE_VERBOSE"))
-            fprintf(stderr, "tune %s: block %d groups %d occ %d ntstore %d lds %dK preload %d spl %d: %.2f us\n",
-                    key.c_str(), b, gr, oc, nts, lkb, pre, spl, us);
-          if (us < best_us) {
-            best_us = us; nbest_b = b; nbest_g = gr; nbest_o = oc; nbest_n = nts; nbest_l = lkb; nbest_p = pre;
-            nbest_s = spl;
-          }
+        for (int pre : {0, 1})
+          for (int lkb : {0, 24, 40, 60})
+            for (int nts : {1, 0})
+              for (int oc : {0, 4})
+                for (int b : blocks)
+                  for (int gr : grps) {
+                    if (!dslash_variant_ok(G, b, gr, spl)) continue;
+                    if (pre && prec == WD_F64) continue;
+                    if (oc == 4 && lkb != 0) continue;  // both only lower occupancy; keep the grid small
+                    if ((size_t)lkb * 1024 + 1024 > lds_max) continue;
+                    cands.push_back({spl, pre, lkb, nts, oc, b, gr});
+                  }
+      for (const Cand &c : cands) {
+        const int spl = c.spl, pre = c.pre, lkb = c.lkb, nts = c.nts, oc = c.oc, b = c.b, gr = c.gr;
+        g->hop_block[prec] = b; g->hop_groups[prec] = gr; g->hop_occ[prec] = oc; g->hop_ntst[prec] = nts;
+        g->hop_lds[prec] = lkb * 1024;
+        g->hop_pre[prec] = pre;
+        g->hop_spl[prec] = spl;
+        if ((rc = launch_pack_spinor(g, canon, in, WD_ODD, prec, st)) != WD_OK) break;
+        a.out = cand;
+        if ((rc = hip_check(hipMemsetAsync(cand, 0xff, hb, st), "memset")) != WD_OK) break;
+        if ((rc = launch_dslash(g, prec, a, st)) != WD_OK) break;
+        bool same = false;
+        if ((rc = same_bytes(ref, cand, hb, flag, same, st)) != WD_OK) break;
+        if (!same) continue;  // parity first
+        // time the pattern of a solver: even and odd hops alternate, so the
+        // two parities' link arrays stream through the caches in turn
+        const int reps = 6;
+        DslashArgs b2 = a;
+        b2.in = cand; b2.out = in; b2.parity = WD_ODD;
+        auto pair = [&]() { (void)launch_dslash(g, prec, a, st); (void)launch_dslash(g, prec, b2, st); };
+        for (int w = 0; w < 2; ++w) pair();
+        (void)hipEventRecord(e0, st);
+        for (int r = 0; r < reps; ++r) pair();
+        (void)hipEventRecord(e1, st);
+        if ((rc = hip_check(hipEventSynchronize(e1), "tune timing")) != WD_OK) break;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const double us = 1e3 * ms / (2 * reps);
+        if (getenv("WD_TUNE_VERBOSE"))
+          fprintf(stderr, "tune %s: block %d groups %d occ %d ntstore %d lds %dK preload %d spl %d: %.2f us\n",
+                  key.c_str(), b, gr, oc, nts, lkb, pre, spl, us);
+        if (us < best_us) {
+          best_us = us; nbest_b = b; nbest_g = gr; nbest_o = oc; nbest_n = nts; nbest_l = lkb; nbest_p = pre;
+          nbest_s = spl;
         }
-        if (rc != WD_OK) break;
       }
       if (rc != WD_OK) {
         g->hop_block[prec] = save_b; g->hop_groups[prec] = save_g; g->hop_occ[prec] = save_o;
@@ -388,10 +395,14 @@ wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, const char *c
       for (int r : {1, 2, 3, 4, 6, 8, 12, 16})
         if (r <= nrhs) rpls.push_back(r);
     }
+    // candidates listed first: one loop runs them, and a failure ends the search
+    std::vector<std::array<int, 3>> cands;
     for (int rp : rpls)
-    for (int bs : blocks)
-    for (int gr : {0, 2, 4, 8, -8, -16}) {
-      if (!dslash_variant_ok(G, bs, gr)) continue;
+      for (int bs : blocks)
+        for (int gr : {0, 2, 4, 8, -8, -16})
+          if (dslash_variant_ok(G, bs, gr)) cands.push_back({rp, bs, gr});
+    for (const auto &c : cands) {
+      const int rp = c[0], bs = c[1], gr = c[2];
       g->mrhs_groups[prec] = gr;
       g->mrhs_block[prec] = bs;
       g->mrhs_rpl[prec] = rp;

@@ -465,8 +465,7 @@ __device__ __forceinline__ void block_sum_n(double (&v)[N]) {
 // Block sums of v (fixed order) stored as this block's partials,
 // partials[j * nblocks + bid]; a finishing kernel (launch_finish_sums) adds
 // them up after the launch.  No atomics and no fences: the kernel boundary
-// makes the stores visible.  Used where a launch has many blocks, for which
-// the last-block scheme below serialises on its counter.
+// makes the stores visible.
 template <int N>
 __device__ __forceinline__ void block_sum_store(double (&v)[N], double *partials, unsigned nblocks, unsigned bid) {
   block_sum_n<N>(v);
@@ -474,45 +473,6 @@ __device__ __forceinline__ void block_sum_store(double (&v)[N], double *partials
 #pragma unroll
     for (int j = 0; j < N; ++j) partials[(size_t)j * nblocks + bid] = v[j];
   }
-}
-
-// Grid-wide sum: every block stores its partial(s); the block that arrives
-// last adds all partials in index order (deterministic whichever block that
-// is), writes the totals and re-arms the counter.  Returns true in thread 0 of
-// the last block, with the totals in `tot`.
-template <int N>
-__device__ __forceinline__ bool grid_sum_last(double (&v)[N], double *partials, unsigned *counter,
-                                              unsigned nblocks, unsigned bid, double (&tot)[N]) {
-  block_sum_n<N>(v);
-  __shared__ int is_last;
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int j = 0; j < N; ++j)
-      __hip_atomic_store(&partials[(size_t)j * nblocks + bid], v[j], __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    const unsigned ticket = atomicAdd(counter, 1u);
-    is_last = (ticket == nblocks - 1);
-  }
-  __syncthreads();
-  if (!is_last) return false;
-  __threadfence();
-  double acc[N];
-#pragma unroll
-  for (int j = 0; j < N; ++j) {
-    double s = 0.0;
-    for (unsigned b = threadIdx.x; b < nblocks; b += blockDim.x)
-      s += __hip_atomic_load(&partials[(size_t)j * nblocks + b], __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-    acc[j] = s;
-  }
-  block_sum_n<N>(acc);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int j = 0; j < N; ++j) tot[j] = acc[j];
-    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  return threadIdx.x == 0;
 }
 
 }  // namespace wd

@@ -28,7 +28,15 @@ from . import _lib as L
 
 
 class PairGenerator:
-    """Streams normalised (r, e) pairs, FP32 full fields, on one lattice."""
+    """Streams normalised (r, e) pairs, FP32 full fields, on one lattice.
+
+    Every buffer is allocated once: the sources of one solve call, and two
+    rings of nsrc * len(ks) FP32 pair slots into which the library writes
+    each normalised pair directly (in a random slot order, so a run of
+    consecutive slots is a random sample of the call's pairs).  batch()
+    hands out consecutive slots as views; they stay valid until the next
+    call of batch() and are written only by work queued on the same stream
+    after the caller's own use of them."""
 
     def __init__(self, g, kappa, seed, ks=(0,), target_tol=1e-6, nsrc=24, inner_prec="bf16", inner_tol=1e-2):
         import torch
@@ -46,71 +54,77 @@ class PairGenerator:
         self.dims = g.dims
         self.f64 = L.wd_field_bytes(self.dims, "f64")
         self.f32 = L.wd_field_bytes(self.dims, "f32")
-        self.pool_r, self.pool_e = [], []
+        self.slots = self.nsrc * len(self.ks)
         self.sources = 0
         self.solve_seconds = 0.0
+        self._B = L.wd_new_field(self.dims, "f64", self.nsrc)
         self._xs = L.wd_new_field(self.dims, "f64", self.nsrc)
         self._xk = L.wd_new_field(self.dims, "f64")
         self._dx = L.wd_new_field(self.dims, "f64")
+        self._r1 = L.wd_new_field(self.dims, "f64")
+        self._e1 = L.wd_new_field(self.dims, "f64")
+        self._pr = L.wd_new_field(self.dims, "f32", self.slots)
+        self._pe = L.wd_new_field(self.dims, "f32", self.slots)
+        self._next = self.slots  # first slot not yet handed out
+        self._perm = None
 
-    def _source(self):
-        """A Gaussian source drawn on the device (counter-based generator:
-        stream = the source's running index, so every source differs)."""
-        f = L.wd_new_field(self.dims, "f64")
-        L.wd_gaussian_field(self.g, f, L.WD_FULL, "f64", self.seed, self.sources)
-        self.sources += 1
-        return f
+    def _field(self, buf, i, nbytes):
+        return buf[i * nbytes:(i + 1) * nbytes]
 
-    def _push(self, r, e):
-        """Normalise the pair by |r| and keep it as two FP32 full fields."""
+    def _push(self, j, r, e):
+        """Normalise pair j of this refill by |r| into its FP32 slot."""
         nr = np.sqrt(L.wd_norm2(self.g, r, 2, "f64"))
-        r32 = L.wd_new_field(self.dims, "f32")
-        e32 = L.wd_new_field(self.dims, "f32")
-        L.wd_convert(self.g, r, "f64", r32, "f32", 2, 1.0 / nr)
-        L.wd_convert(self.g, e, "f64", e32, "f32", 2, 1.0 / nr)
-        self.pool_r.append(r32)
-        self.pool_e.append(e32)
+        slot = int(self._perm[j])
+        L.wd_convert(self.g, r, "f64", self._field(self._pr, slot, self.f32), "f32", 2, 1.0 / nr)
+        L.wd_convert(self.g, e, "f64", self._field(self._pe, slot, self.f32), "f32", 2, 1.0 / nr)
 
     def _refill(self):
         t = time.perf_counter()
         n = self.nsrc
-        B = self.torch.cat([self._source() for _ in range(n)])
+        # Gaussian sources drawn on the device (counter-based generator:
+        # stream = the source's running index, so every source differs)
+        for y in range(n):
+            L.wd_gaussian_field(self.g, self._field(self._B, y, self.f64), L.WD_FULL, "f64", self.seed, self.sources)
+            self.sources += 1
         prm = L.wd_solve_params_default(solver=L.WD_SOLVER_DEFECT_CG, inner_prec=self.inner_prec,
                                         inner_tol=self.inner_tol)
-        rc, infos = L.wd_solve_mrhs(self.g, B, self._xs, n, self.kappa, self.target_tol, prm)
+        rc, infos = L.wd_solve_mrhs(self.g, self._B, self._xs, n, self.kappa, self.target_tol, prm)
         if rc != 0:
             bad = [y for y, i in enumerate(infos) if i["status"] != 0]
             raise RuntimeError(f"pair generation: sources {bad} did not reach {self.target_tol}")
-        f = self.f64
+        self._perm = self.rng.permutation(self.slots)
+        j = 0
         for y in range(n):
-            fb, xs = B[y * f:(y + 1) * f], self._xs[y * f:(y + 1) * f]
+            fb, xs = self._field(self._B, y, self.f64), self._field(self._xs, y, self.f64)
             for k in self.ks:
                 if k == 0:  # x_0 = 0: r = b, e = x*
-                    self._push(fb, xs)
-                    continue
-                L.wd_solve(self.g, fb, self._xk, self.kappa, 1e-14,
-                           L.wd_solve_params_default(solver=L.WD_SOLVER_CG, max_iter=k))
-                # r = b - D x_k  ;  e = x* - x_k
-                L.wd_dslash(self.g, self._xk, self._dx, self.kappa, self.dims, L.WD_FULL)
-                r = fb.clone()
-                L.wd_caxpy(self.g, -1.0, self._dx, r, 2, "f64")
-                e = xs.clone()
-                L.wd_caxpy(self.g, -1.0, self._xk, e, 2, "f64")
-                self._push(r, e)
+                    self._push(j, fb, xs)
+                else:
+                    L.wd_solve(self.g, fb, self._xk, self.kappa, 1e-14,
+                               L.wd_solve_params_default(solver=L.WD_SOLVER_CG, max_iter=k))
+                    # r = b - D x_k  ;  e = x* - x_k
+                    L.wd_dslash(self.g, self._xk, self._dx, self.kappa, self.dims, L.WD_FULL)
+                    self._r1.copy_(fb)
+                    L.wd_caxpy(self.g, -1.0, self._dx, self._r1, 2, "f64")
+                    self._e1.copy_(xs)
+                    L.wd_caxpy(self.g, -1.0, self._xk, self._e1, 2, "f64")
+                    self._push(j, self._r1, self._e1)
+                j += 1
+        self._next = 0
         self.torch.cuda.synchronize()
         self.solve_seconds += time.perf_counter() - t
 
     def batch(self, B):
-        """B pairs as two tensors of B consecutive FP32 full fields."""
-        while len(self.pool_r) < B:
+        """B pairs as two views of B consecutive FP32 full fields each (valid
+        until the next call).  A refill's last slots that cannot fill a whole
+        batch are dropped."""
+        B = int(B)
+        if B > self.slots:
+            raise ValueError(f"batch of {B} pairs, but one refill makes {self.slots}")
+        if self._next + B > self.slots:
             self._refill()
-        order = self.rng.permutation(len(self.pool_r))[:B]
-        r = self.torch.cat([self.pool_r[i] for i in order])
-        e = self.torch.cat([self.pool_e[i] for i in order])
-        keep = [i for i in range(len(self.pool_r)) if i not in set(order.tolist())]
-        self.pool_r = [self.pool_r[i] for i in keep]
-        self.pool_e = [self.pool_e[i] for i in keep]
-        return r, e
+        a, self._next = self._next, self._next + B
+        return (self._pr[a * self.f32:(a + B) * self.f32], self._pe[a * self.f32:(a + B) * self.f32])
 
 
 # Weight checkpoint: a small versioned binary (little-endian).

@@ -1,0 +1,131 @@
+"""The benchmark's solve workloads at full size, judged by the oracle's own D_W.
+
+32^3x64 with eps = 0.3 random links, kappa = 0.124 (the mixed-precision and
+learned-preconditioner workload): every solver the benchmark times, in the
+launch configuration it times (the committed tuned hop variants), must
+return an x whose FP64 true residual |b - D_W x|/|b|, computed by the
+oracle, is <= 1e-10, and the library's own reported residual must agree
+with the oracle's.  24^3x48 with the 12 spin-colour point sources, solved
+together by the multi-RHS defect correction (FP32 and BF16 inner storage):
+each of the 12 systems is judged the same way.  One oracle D_W costs
+~18 s at 32^3x64 and ~6 s at 24^3x48 on one host core.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import paper_0710_2442_amd as wd
+import synthetic as syn
+from gpu_util import from_field, to_field
+from oracle import solvers
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+KAPPA = 0.124
+TABLE = os.path.join(os.path.dirname(wd.__file__), "tuned", "mi355x_hop.jsonl")
+
+
+def _use_table(g):
+    for prec in ("f64", "f32", "f16", "bf16"):
+        wd.wd_tune_dslash(g, prec, TABLE)
+
+
+@pytest.fixture(scope="module")
+def c3():
+    dims = (32, 32, 32, 64)
+    gseed, sseed = syn.CONFIG_SEEDS["mixed_32x32x32x64"]
+    print("case: 32^3x64 eps 0.3 fields", flush=True)
+    U = syn.gauge_field(dims, 0.3, gseed)
+    b = syn.gaussian_spinor(dims, sseed)
+    g = wd.Gauge(U, dims, -1, "f64")
+    _use_table(g)
+    fb = to_field(g, b)
+    yield dims, U, b, g, fb
+    g.close()
+
+
+@pytest.fixture(scope="module")
+def trained_weights():
+    """A BF16-activation network trained briefly on 16^4 (the benchmark trains
+    longer; any network must leave the solve's result to the FP64 judge)."""
+    from paper_0710_2442_amd import learn
+
+    dims = (16, 16, 16, 16)
+    gseed, sseed = syn.CONFIG_SEEDS["ptc_16x16x16x16"]
+    gtr = wd.Gauge(syn.gauge_field(dims, 0.3, gseed), dims, -1, "f64")
+    W, hist = learn.train(gtr, KAPPA, steps=100, batch=8, lr=2e-3, seed=sseed, act="bf16", log_every=50)
+    gtr.close()
+    print(f"trained 100 steps: loss {hist['losses'][0][1]:.3f} -> {hist['losses'][-1][1]:.3f}", flush=True)
+    return W
+
+
+C3_CASES = {
+    "fp64_cg": dict(solver=wd.WD_SOLVER_CG),
+    "defect_f32": dict(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec="f32", inner_tol=1e-4),
+    "defect_f16": dict(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec="f16", inner_tol=1e-2),
+    "defect_bf16": dict(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec="bf16", inner_tol=1e-2),
+    "defect_fgcr_f32_identity": dict(solver=wd.WD_SOLVER_DEFECT_FGCR, fgcr_m=4, inner_tol=1e-2),
+    "defect_fgcr_bf16_network": dict(solver=wd.WD_SOLVER_DEFECT_FGCR, fgcr_m=4, inner_tol=1e-2,
+                                     inner_prec="bf16"),
+}
+
+
+@pytest.mark.parametrize("name", list(C3_CASES))
+def test_random_link_solves_at_full_size(c3, name, request):
+    dims, U, b, g, fb = c3
+    kw = dict(C3_CASES[name])
+    net = None
+    if name.endswith("network"):
+        net = wd.Ptc(g, request.getfixturevalue("trained_weights"), "bf16")
+        kw["precond"] = net
+    print(f"case: 32^3x64 eps 0.3 kappa {KAPPA} solver {name}", flush=True)
+    fx = wd.wd_new_field(dims, "f64")
+    rc, info = wd.wd_solve(g, fb, fx, KAPPA, TOL, wd.wd_solve_params_default(**kw))
+    x = from_field(g, fx)
+    if net is not None:
+        net.close()
+    print(f"  status {rc}, iters {info['iters']}, outer {info['outer_iters']}, "
+          f"library residual {info['true_rel_resid']:.3e}", flush=True)
+    assert rc == 0 and info["fallback_used"] == 0, info
+    r = solvers.true_residual(U, b, x, KAPPA)
+    print(f"  oracle residual {r:.3e}", flush=True)
+    assert r <= TOL
+    assert abs(r - info["true_rel_resid"]) <= 1e-3 * TOL + 1e-15
+
+
+@pytest.fixture(scope="module")
+def c4():
+    dims = (24, 24, 24, 48)
+    gseed, _ = syn.CONFIG_SEEDS["mrhs_24x24x24x48"]
+    print("case: 24^3x48 eps 0.3 fields", flush=True)
+    U = syn.gauge_field(dims, 0.3, gseed)
+    g = wd.Gauge(U, dims, -1, "f64")
+    _use_table(g)
+    for prec in ("f32", "bf16"):
+        wd.wd_tune_dslash_mrhs(g, prec, 12, TABLE)
+    B = torch.cat([to_field(g, syn.point_source(dims, s, c)) for s in range(4) for c in range(3)])
+    yield dims, U, g, B
+    g.close()
+
+
+@pytest.mark.parametrize("prec,inner_tol", [("f32", 1e-3), ("bf16", 1e-2)])
+def test_twelve_point_sources_at_full_size(c4, prec, inner_tol):
+    dims, U, g, B = c4
+    print(f"case: 24^3x48 12 point sources, multi-RHS defect correction, {prec} storage", flush=True)
+    X = wd.wd_new_field(dims, "f64", 12)
+    p = wd.wd_solve_params_default(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec=prec, inner_tol=inner_tol)
+    rc, infos = wd.wd_solve_mrhs(g, B, X, 12, KAPPA, TOL, p)
+    assert rc == 0
+    nb = wd.wd_field_bytes(dims, "f64")
+    worst = 0.0
+    for r in range(12):
+        s, c = divmod(r, 3)
+        x = from_field(g, X[r * nb:(r + 1) * nb])
+        res = solvers.true_residual(U, syn.point_source(dims, s, c), x, KAPPA)
+        worst = max(worst, res)
+        assert res <= TOL, (r, res)
+        assert abs(res - infos[r]["true_rel_resid"]) <= 1e-3 * TOL + 1e-15, (r, res, infos[r])
+    print(f"  worst oracle residual over the 12 systems {worst:.3e}", flush=True)

@@ -118,3 +118,49 @@ def test_adam_first_step_is_lr_sign():
     d = w2 - w
     assert np.allclose(d.real, -1e-3 * np.sign(g.real))
     assert np.allclose(d.imag, -1e-3 * np.sign(g.imag))
+
+
+def test_adam_constant_gradient_steps_by_lr_at_every_step():
+    """Kingma & Ba's bias corrections make m_hat = g and v_hat = g^2 exactly
+    when the gradient never changes, so every step (t = 1, 2, 3, ...) moves
+    each coordinate by lr * g / (|g| + eps).  Without the corrections step 2
+    would be (0.19 / sqrt(0.001999)) lr = 4.25 lr."""
+    g = np.array([0.5 - 2.0j, -3.0 + 0.25j, 1e-3 + 7.0j])
+    w = np.zeros(3, dtype=np.complex128)
+    m = np.zeros((2, 3)); v = np.zeros((2, 3))
+    lr, eps = 1e-2, 1e-8
+    want_re = lr * g.real / (np.abs(g.real) + eps)
+    want_im = lr * g.imag / (np.abs(g.imag) + eps)
+    for t in (1, 2, 3, 4):
+        w2, m, v = ptc.adam_step(w, g, m, v, t, lr=lr, eps=eps)
+        d = w - w2
+        assert np.allclose(d.real, want_re, rtol=1e-12, atol=0), t
+        assert np.allclose(d.imag, want_im, rtol=1e-12, atol=0), t
+        w = w2
+
+
+def test_adam_three_steps_hand_computed():
+    """Gradients 1, 2, -1 on one real coordinate (and 0 on its imaginary
+    part), beta = (0.9, 0.999), eps negligible (1e-300), worked out by hand from the
+    definitions m_t = b1 m + (1 - b1) g, v_t = b2 v + (1 - b2) g^2,
+    step = lr (m_t / (1 - b1^t)) / sqrt(v_t / (1 - b2^t)):
+      t=1: m = 0.1,  v = 0.001,    step = lr
+      t=2: m = 0.29, v = 0.004999, m_hat = 0.29/0.19, v_hat = 0.004999/0.001999
+      t=3: m = 0.161, v = 0.005994001, m_hat = 0.161/0.271,
+           v_hat = 0.005994001/0.002997001
+    A swapped beta pair, a missing or squared correction, or a sign slip
+    changes the second or third step by more than 1%."""
+    lr = 1.0
+    w = np.zeros(1, dtype=np.complex128)
+    m = np.zeros((2, 1)); v = np.zeros((2, 1))
+    steps = []
+    for t, gv in enumerate((1.0, 2.0, -1.0), start=1):
+        w2, m, v = ptc.adam_step(w, np.array([gv + 0j]), m, v, t, lr=lr, eps=1e-300)
+        steps.append(float((w - w2).real[0]))
+        assert (w2 - w).imag[0] == 0.0
+        w = w2
+    want = [1.0,
+            (0.29 / 0.19) / np.sqrt(0.004999 / 0.001999),
+            (0.161 / 0.271) / np.sqrt(0.005994001 / 0.002997001)]
+    assert np.allclose(steps, want, rtol=1e-12, atol=0), (steps, want)
+    assert abs(steps[1] - 0.96518) < 1e-4 and abs(steps[2] - 0.42009) < 1e-4

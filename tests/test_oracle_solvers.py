@@ -141,3 +141,47 @@ def test_fgcr_falls_back_on_bad_preconditioner():
     x, it, fb, _ = solvers.fgcr(Dop, zero_net, b, 1e-10, cg_fallback=fallback)
     assert fb
     assert solvers.true_residual(U, b, x, k) <= 1e-10
+
+
+def test_round_storage_f16_hand_values():
+    """FP16 storage with a per-site scale (reading A11): the site's largest
+    |real| m is kept exactly, every real is divided by m, rounded to IEEE half
+    (to nearest, ties to even, with subnormals) and multiplied back.  One site
+    with m = 2 (so the scaling is exact), worked out by hand:
+      x/m = 1 - 2^-12   : halfway between 1 - 2^-11 (odd) and 1 (even) -> 1
+      x/m = 1 - 3*2^-12 : halfway between 1 - 2^-10 (even) and 1 - 2^-11 -> 1 - 2^-10
+      x/m = 2^-20       : a half subnormal (16 * 2^-24), exact
+      x/m = 0.75*2^-24  : nearer 2^-24 than 0 -> 2^-24
+      x/m = -0.5*2^-24  : halfway between -0 (even) and -2^-24 -> -0
+      x/m = 0.1         : half 0x2E66 = 0.0999755859375
+    """
+    vals = np.array([2.0, 2 * (1 - 2.0 ** -12), 2 * (1 - 3 * 2.0 ** -12), 2 * 2.0 ** -20,
+                     2 * 0.75 * 2.0 ** -24, -2 * 0.5 * 2.0 ** -24, 0.2, 0.0, 0.0, 0.0, 0.0, 0.0])
+    want = np.array([2.0, 2.0, 2 * (1 - 2.0 ** -10), 2 * 2.0 ** -20, 2 * 2.0 ** -24, 0.0,
+                     2 * 0.0999755859375, 0.0, 0.0, 0.0, 0.0, 0.0])
+    site = (vals + 1j * vals[::-1]).reshape(1, 4, 3)
+    got = solvers.round_storage(site, "f16").astype(np.complex128).reshape(-1)
+    assert np.array_equal(got.real, want), got.real - want
+    assert np.array_equal(got.imag, want[::-1]), got.imag - want[::-1]
+
+
+def test_round_storage_f16_scale_and_bound():
+    """On random fields of very different site magnitudes: each site's largest
+    stored |real| equals its largest input |real| (after FP32 rounding) exactly,
+    and every real is within (2^-12 + 2^-23) of that maximum of its input: the
+    scaled values lie in [-1, 1], where half's largest rounding error is half
+    an ulp of [1/2, 1), 2^-12; the FP32 product adds at most 2^-24 of m."""
+    rng = np.random.default_rng(41)
+    psi = rng.standard_normal((500, 4, 3)) + 1j * rng.standard_normal((500, 4, 3))
+    psi *= 10.0 ** rng.uniform(-12, 6, size=(500, 1, 1))
+    got = solvers.round_storage(psi, "f16").astype(np.complex128)
+    c32 = psi.astype(np.complex64).astype(np.complex128)
+    m_in = np.maximum(np.abs(c32.real), np.abs(c32.imag)).max(axis=(1, 2))
+    m_out = np.maximum(np.abs(got.real), np.abs(got.imag)).max(axis=(1, 2))
+    assert np.array_equal(m_in, m_out)
+    err = np.maximum(np.abs(got.real - c32.real), np.abs(got.imag - c32.imag)).max(axis=(1, 2))
+    assert np.all(err <= (2.0 ** -12 + 2.0 ** -23) * m_in)
+    # the bound is reached to within a factor of two (rounding really happens)
+    assert np.max(err / m_in) > 2.0 ** -13
+    # a zero site stays zero
+    assert np.all(solvers.round_storage(np.zeros((2, 4, 3), complex), "f16") == 0)
