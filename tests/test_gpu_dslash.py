@@ -420,14 +420,17 @@ def test_full_size_plane_wave():
     dims = (32, 32, 32, 64)
     U = syn.unit_gauge(dims)
     g = wd.Gauge(U, dims, -1, "f64")
-    p = [2 * np.pi * 3 / 32, 2 * np.pi * 30 / 32, 2 * np.pi * 1 / 32, 2 * np.pi * (7 + 0.5) / 64]
+    n = (3, 30, 1, 7)
+    p = free_field.momentum_of(dims, n)  # p_4 = 2 pi (7 + 1/2) / 64
     u = syn.gaussian_spinor((2, 2, 2, 2), 5)[0, 0, 0, 0]
-    psi = free_field.plane_wave(dims, p, u)
+    # phases reduced exactly: unreduced, the rounding of p.x (up to ~260 here)
+    # alone would put ~3e-14 into every site
+    psi = free_field.plane_wave_n(dims, n, u)
     src = to_field(g, psi)
     out = wd.wd_new_field(dims, "f64")
     wd.wd_dslash(g, src, out, 0.124, dims, wd.WD_FULL)
     got = from_field(g, out)
-    want = free_field.plane_wave(dims, p, free_field.symbol(p, 0.124) @ u)
+    want = free_field.plane_wave_n(dims, n, free_field.symbol(p, 0.124) @ u)
     assert_close(got, want, "f64", what="32^3x64 plane wave")
     g.close()
 
