@@ -333,7 +333,10 @@ wd_status wd_ptc_train_step(wd_ptc *n, const void *r, const void *e, int B,
  * block size (64..512 threads), the block -> tile order (groups: 0 = linear;
  * G > 0 = G regions of each time slice, dealt round-robin over the XCDs;
  * -X = X contiguous ranges of time slices, one per dispatch lane, each swept
- * in time order, so with X = 8 every XCD's L2 sees whole neighbourhoods),
+ * in time order, so with X = 8 every XCD's L2 sees whole neighbourhoods;
+ * -(100 + n), n = 1, 2, 4, 8 = box order: the lattice is cut into n boxes
+ * along x3 times 8 / n along x4, one per dispatch lane (per XCD), and each
+ * lane walks its box slice by slice, plane by plane),
  * the register budget (occ 0: compiler's
  * choice; occ 4: at least 4 waves per SIMD), the output store policy
  * (WD_TUNE_CACHED_STORE set in occ: cached stores), link preloading

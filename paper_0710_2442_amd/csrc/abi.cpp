@@ -52,6 +52,37 @@ static wd_status check_handle(const wd_gauge *g) {
 
 static wd_status set_device(const wd_gauge *g) { return hip_check(hipSetDevice(g->device), "hipSetDevice"); }
 
+
+wd_status solve_args(const wd_gauge *U, const void *b, void *x, double kappa, double tol,
+                     const wd_solve_params *p, wd_solve_params &prm) {
+  WD_TRY(check_handle(U));
+  if (!b || !x) return set_error(WD_ERR_ARG, "solve: NULL field pointer");
+  if (b == x) return set_error(WD_ERR_ARG, "solve: b and x must not overlap");
+  if (!isfinite(kappa) || !isfinite(tol)) return set_error(WD_ERR_NONFINITE, "solve: kappa or tol not finite");
+  if (!(tol > 0.0)) return set_error(WD_ERR_ARG, "solve: tol must be > 0");
+  wd_solve_params_default(&prm);
+  if (p) {
+    if (p->struct_size < sizeof(size_t) || p->struct_size > sizeof(wd_solve_params))
+      return set_error(WD_ERR_ARG, "solve: params.struct_size = %zu", p->struct_size);
+    memcpy(&prm, p, p->struct_size);
+    prm.struct_size = sizeof(prm);
+  }
+  if (prm.solver < WD_SOLVER_CG || prm.solver > WD_SOLVER_DEFECT_FGCR)
+    return set_error(WD_ERR_ARG, "solve: solver = %d", prm.solver);
+  if (prm.inner_prec == WD_F64 && prm.solver == WD_SOLVER_DEFECT_CG)
+    return set_error(WD_ERR_PREC, "solve: defect correction needs a reduced inner precision");
+  if (!prec_ok(prm.inner_prec)) return set_error(WD_ERR_PREC, "solve: inner_prec = %d", (int)prm.inner_prec);
+  if (!(prm.inner_tol > 0.0 && prm.inner_tol < 1.0)) return set_error(WD_ERR_ARG, "solve: inner_tol must be in (0,1)");
+  if (prm.max_iter < 1) return set_error(WD_ERR_ARG, "solve: max_iter must be >= 1");
+  if (prm.check_every < 1) prm.check_every = 1;
+  if (prm.fgcr_m < 1 || prm.fgcr_m > 64) return set_error(WD_ERR_ARG, "solve: fgcr_m = %d", prm.fgcr_m);
+  if (prm.solver == WD_SOLVER_DEFECT_FGCR && prm.fgcr_m > 16)
+    return set_error(WD_ERR_ARG, "solve: the mixed FGCR keeps at most 16 directions (fgcr_m = %d)", prm.fgcr_m);
+  if (prm.solver == WD_SOLVER_DEFECT_FGCR && prm.inner_prec != WD_F32 && prm.inner_prec != WD_BF16)
+    return set_error(WD_ERR_PREC, "solve: the mixed FGCR stores its inner vectors in FP32 or BF16");
+  return set_device(U);
+}
+
 }  // namespace wd
 
 using namespace wd;
@@ -124,8 +155,6 @@ wd_status wd_gauge_create(const double *U_host, const int dims[4], int t_bc, wd_
     if ((rc = hip_check(hipMalloc(&g->links32, link_bytes(g->geom, false)), "links32")) != WD_OK) break;
     if ((rc = hip_check(hipMalloc(&g->scratch_red, sizeof(double) * (4 * BLAS_MAX_BLOCKS + 64)), "scratch")) != WD_OK)
       break;
-    if ((rc = hip_check(hipMalloc(&g->scratch_cnt, 256), "scratch_cnt")) != WD_OK) break;
-    if ((rc = hip_check(hipMemset(g->scratch_cnt, 0, 256), "memset")) != WD_OK) break;
     if ((rc = hip_check(hipMalloc(&canon, ubytes), "gauge staging")) != WD_OK) break;
     if ((rc = hip_check(hipMemcpyAsync(canon, U_host, ubytes, hipMemcpyHostToDevice, g->own_stream), "upload")) !=
         WD_OK)
@@ -154,7 +183,6 @@ wd_status wd_gauge_destroy(wd_gauge *g) {
   if (g->links64) (void)hipFree(g->links64);
   if (g->links32) (void)hipFree(g->links32);
   if (g->scratch_red) (void)hipFree(g->scratch_red);
-  if (g->scratch_cnt) (void)hipFree(g->scratch_cnt);
   if (g->own_stream) (void)hipStreamDestroy(g->own_stream);
   delete g;
   return WD_OK;
@@ -313,7 +341,7 @@ wd_status wd_caxpy(const wd_gauge *g, double c_re, double c_im, const void *x, v
 wd_status wd_cdot(const wd_gauge *g, const void *x, const void *y, int nhalf, wd_prec prec, double out[2]) {
   WD_TRY(blas_args(g, x, nhalf, prec));
   if (!y || !out) return set_error(WD_ERR_ARG, "cdot: NULL pointer");
-  RedBuf red{g->scratch_red + 64, g->scratch_cnt};
+  RedBuf red{g->scratch_red + 64};
   WD_TRY(blas_cdot(g->geom, prec, vref(x, nhalf), vref(y, nhalf), 1, red, g->scratch_red, g->stream));
   WD_HIP(hipMemcpyAsync(out, g->scratch_red, 2 * sizeof(double), hipMemcpyDeviceToHost, g->stream));
   WD_HIP(hipStreamSynchronize(g->stream));
@@ -323,7 +351,7 @@ wd_status wd_cdot(const wd_gauge *g, const void *x, const void *y, int nhalf, wd
 wd_status wd_norm2(const wd_gauge *g, const void *x, int nhalf, wd_prec prec, double *out) {
   WD_TRY(blas_args(g, x, nhalf, prec));
   if (!out) return set_error(WD_ERR_ARG, "norm2: out is NULL");
-  RedBuf red{g->scratch_red + 64, g->scratch_cnt};
+  RedBuf red{g->scratch_red + 64};
   WD_TRY(blas_norm2(g->geom, prec, vref(x, nhalf), 1, red, g->scratch_red, g->stream));
   WD_HIP(hipMemcpyAsync(out, g->scratch_red, sizeof(double), hipMemcpyDeviceToHost, g->stream));
   WD_HIP(hipStreamSynchronize(g->stream));
@@ -353,36 +381,6 @@ void wd_solve_params_default(wd_solve_params *p) {
   p->use_graph = 1;
   p->fgcr_m = 12;
   p->precond = nullptr;
-}
-
-static wd_status solve_args(const wd_gauge *U, const void *b, void *x, double kappa, double tol,
-                            const wd_solve_params *p, wd_solve_params &prm) {
-  WD_TRY(check_handle(U));
-  if (!b || !x) return set_error(WD_ERR_ARG, "solve: NULL field pointer");
-  if (b == x) return set_error(WD_ERR_ARG, "solve: b and x must not overlap");
-  if (!isfinite(kappa) || !isfinite(tol)) return set_error(WD_ERR_NONFINITE, "solve: kappa or tol not finite");
-  if (!(tol > 0.0)) return set_error(WD_ERR_ARG, "solve: tol must be > 0");
-  wd_solve_params_default(&prm);
-  if (p) {
-    if (p->struct_size < sizeof(size_t) || p->struct_size > sizeof(wd_solve_params))
-      return set_error(WD_ERR_ARG, "solve: params.struct_size = %zu", p->struct_size);
-    memcpy(&prm, p, p->struct_size);
-    prm.struct_size = sizeof(prm);
-  }
-  if (prm.solver < WD_SOLVER_CG || prm.solver > WD_SOLVER_DEFECT_FGCR)
-    return set_error(WD_ERR_ARG, "solve: solver = %d", prm.solver);
-  if (prm.inner_prec == WD_F64 && prm.solver == WD_SOLVER_DEFECT_CG)
-    return set_error(WD_ERR_PREC, "solve: defect correction needs a reduced inner precision");
-  if (!prec_ok(prm.inner_prec)) return set_error(WD_ERR_PREC, "solve: inner_prec = %d", (int)prm.inner_prec);
-  if (!(prm.inner_tol > 0.0 && prm.inner_tol < 1.0)) return set_error(WD_ERR_ARG, "solve: inner_tol must be in (0,1)");
-  if (prm.max_iter < 1) return set_error(WD_ERR_ARG, "solve: max_iter must be >= 1");
-  if (prm.check_every < 1) prm.check_every = 1;
-  if (prm.fgcr_m < 1 || prm.fgcr_m > 64) return set_error(WD_ERR_ARG, "solve: fgcr_m = %d", prm.fgcr_m);
-  if (prm.solver == WD_SOLVER_DEFECT_FGCR && prm.fgcr_m > 16)
-    return set_error(WD_ERR_ARG, "solve: the mixed FGCR keeps at most 16 directions (fgcr_m = %d)", prm.fgcr_m);
-  if (prm.solver == WD_SOLVER_DEFECT_FGCR && prm.inner_prec != WD_F32 && prm.inner_prec != WD_BF16)
-    return set_error(WD_ERR_PREC, "solve: the mixed FGCR stores its inner vectors in FP32 or BF16");
-  return set_device(U);
 }
 
 wd_status wd_solve(const wd_gauge *U, const void *b, void *x, double kappa, double tol, const wd_solve_params *p,

@@ -37,7 +37,6 @@ struct KBlas {
   CgScalars *sc;
   int j;  // ping-pong slot of the CG iteration
   double *partials;
-  unsigned *counter;
   double *result;  // reductions: per-system result (N doubles each)
 };
 
@@ -309,7 +308,7 @@ wd_status blas_norm2(const Geom &g, wd_prec prec, const VecRef &x, int nsys, Red
   k.v = vgeom(g, x.nhalf, prec);
   k.nblk = blocks_for((long)g.vh * x.nhalf);
   k.x = (const char *)x.p; k.sx = x.sys_stride; k.hx = k.v.half_stride;
-  k.partials = red.partials; k.counter = red.counter; k.result = result;
+  k.partials = red.partials; k.result = result;
   dim3 grid(k.nblk, (unsigned)nsys);
   WD_DISPATCH_P(prec, k_norm2, grid, k, st);
   WD_TRY(hip_check(hipGetLastError(), "norm2 launch"));
@@ -323,7 +322,7 @@ wd_status blas_cdot(const Geom &g, wd_prec prec, const VecRef &x, const VecRef &
   k.nblk = blocks_for((long)g.vh * x.nhalf);
   k.x = (const char *)x.p; k.sx = x.sys_stride; k.hx = k.v.half_stride;
   k.y = (const char *)y.p; k.sy = y.sys_stride; k.hy = k.v.half_stride;
-  k.partials = red.partials; k.counter = red.counter; k.result = result;
+  k.partials = red.partials; k.result = result;
   dim3 grid(k.nblk, (unsigned)nsys);
   WD_DISPATCH_P(prec, k_cdot, grid, k, st);
   WD_TRY(hip_check(hipGetLastError(), "cdot launch"));
@@ -410,7 +409,7 @@ wd_status blas_cg_update(const Geom &g, wd_prec px, const VecRef &x, wd_prec pv,
   k.out = (char *)s.p; k.so = s.sys_stride; k.ho = half_bytes(g, pv);
   k.out2 = (char *)q.p; k.so2 = q.sys_stride; k.ho2 = half_bytes(g, pv);
   k.sc = sc; k.j = j;
-  k.partials = red.partials; k.counter = red.counter;
+  k.partials = red.partials;
   dim3 grid(k.nblk, (unsigned)nsys);
   if (px == WD_F64) launch_cgu<WD_F64>(pv, grid, k, st);
   else launch_cgu<WD_F32>(pv, grid, k, st);

@@ -40,7 +40,6 @@ struct KDirac {
   double *norm_out;
   int norm_accumulate;
   double *partials;
-  unsigned *counter;
   int ntiles;            // tiles of DR_BS sites per parity
 };
 
@@ -147,7 +146,7 @@ unsigned dirac_grid_blocks(const wd_gauge *g) {
 wd_status launch_dirac(const wd_gauge *g, wd_prec prec, const DiracArgs &a, hipStream_t st) {
   if (a.Y && !a.X) return set_error(WD_ERR_ARG, "dirac epilogue: Y given without X");
   const bool norm = a.norm_out != nullptr;
-  if (norm && (!a.red.partials || !a.red.counter)) return set_error(WD_ERR_ARG, "dirac norm: no reduction buffer");
+  if (norm && !a.red.partials) return set_error(WD_ERR_ARG, "dirac norm: no reduction buffer");
   KDirac k{};
   k.g = g->geom;
   k.in = (const char *)a.in;
@@ -164,7 +163,6 @@ wd_status launch_dirac(const wd_gauge *g, wd_prec prec, const DiracArgs &a, hipS
   k.norm_out = a.norm_out;
   k.norm_accumulate = a.norm_accumulate;
   k.partials = a.red.partials;
-  k.counter = a.red.counter;
   k.ntiles = (int)((g->geom.vpad + DR_BS - 1) / DR_BS);
   const int epi = a.Y ? 2 : (a.X ? 1 : 0);
   const unsigned nblk = dirac_grid_blocks(g);

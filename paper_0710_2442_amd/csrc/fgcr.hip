@@ -122,7 +122,7 @@ wd_status solve_fgcr(wd_gauge *g, const void *b, void *x, double kappa, double t
   c.g = g;
   c.st = st;
   c.dres = (double *)red.p;
-  c.red = RedBuf{(double *)red.p + 64, (unsigned *)((char *)red.p + nred * sizeof(double))};
+  c.red = RedBuf{(double *)red.p + 64};
   c.hres = hres;
 
   double bb;
@@ -271,7 +271,6 @@ struct KFg {
   float *alpha;    // [2 FG_MMAX]: the step lengths of the current cycle (re, im)
   int k;
   double *partials;
-  unsigned *counter;
 };
 
 using F4 = Spinor<WD_F32>;
@@ -484,14 +483,14 @@ wd_status solve_fgcr_mixed(wd_gauge *g, const void *b, void *x, double kappa, do
   const size_t h64 = half_bytes(G, WD_F64), h32 = half_bytes(G, WD_F32), hS = half_bytes(G, S);
   // r64, d64 (2 h64 each); rh, e (2 h32 each); R, T, Z[m], W[m] (hS each); then the
   // device scalars ([0, 128) CgScalars, [128, 536) dots/sig/rho/rr, [640, 768) the cycle's
-  // step lengths), the reduction partials and
-  // a counter word.  Kept in the handle between solves (grown when a solve needs more).
+  // step lengths) and the reduction partials.  Kept in the handle between solves (grown
+  // when a solve needs more).
   const unsigned nblk = (unsigned)std::min<long>(std::max<long>(1, ((long)G.vh + FG_BS - 1) / FG_BS), FG_MAX_BLOCKS);
   const size_t npart = std::max<size_t>((size_t)2 * FG_MMAX * nblk,
                                         (size_t)2 * std::max<unsigned>(dslash_grid_blocks(g), BLAS_MAX_BLOCKS));
   const size_t vec_bytes = round_up(4 * h64 + 4 * h32 + (2 + 2 * (size_t)m) * hS, 256);
   const size_t scal_bytes = 1024;
-  const size_t need = vec_bytes + scal_bytes + npart * sizeof(double) + 256;
+  const size_t need = vec_bytes + scal_bytes + npart * sizeof(double);
   if (!g->fg_mem || g->fg_bytes < need) {
     if (g->fg_mem) {
       WD_HIP(hipStreamSynchronize(st));
@@ -510,7 +509,6 @@ wd_status solve_fgcr_mixed(wd_gauge *g, const void *b, void *x, double kappa, do
   double *hres = g->fg_host;
   char *red = (char *)g->fg_mem + vec_bytes;
   WD_HIP(hipMemsetAsync(red, 0, scal_bytes, st));
-  WD_HIP(hipMemsetAsync(red + scal_bytes + npart * sizeof(double), 0, 256, st));
   char *c0 = (char *)g->fg_mem;
   char *r64 = c0, *d64 = c0 + 2 * h64, *rh = c0 + 4 * h64, *e32 = rh + 2 * h32;
   char *R = e32 + 2 * h32, *T = R + hS;
@@ -535,8 +533,7 @@ wd_status solve_fgcr_mixed(wd_gauge *g, const void *b, void *x, double kappa, do
   a.r = R;
   a.e = E;
   a.partials = (double *)(red + scal_bytes);
-  a.counter = (unsigned *)(red + scal_bytes + npart * sizeof(double));
-  RedBuf rb{a.partials, a.counter};
+  RedBuf rb{a.partials};
   auto accum = [&](int K) {
     if (S == WD_F32) launch_accum<WD_F32>(a, K, st, std::make_integer_sequence<int, FG_MMAX>{});
     else launch_accum<WD_BF16>(a, K, st, std::make_integer_sequence<int, FG_MMAX>{});

@@ -690,7 +690,6 @@ struct wd_ptc {
   uint2 *links16;
   uint32_t *W16;
   double *hnorm;
-  unsigned *hcnt;
 };
 
 namespace wd {
@@ -900,7 +899,7 @@ static wd_status ptc_alloc(wd_ptc *n) {
 
 static void ptc_free(wd_ptc *n) {
   void *ps[] = {n->Wc,  n->gradc, n->W,  n->Wadj,     n->grad, n->m,   n->v,       n->x0,  n->y1,    n->y2,
-                n->gy2, n->gy1,   n->partials, n->scal, n->links16, n->W16, n->hnorm, n->hcnt};
+                n->gy2, n->gy1,   n->partials, n->scal, n->links16, n->W16, n->hnorm};
   for (void *p : ps)
     if (p) (void)hipFree(p);
   delete n;
@@ -1036,15 +1035,13 @@ wd_status wd_ptc_apply_even(const wd_ptc *n, const void *in_even, wd_prec pin, v
   const Geom &G = n->g->geom;
   if (!m->hnorm) {
     WD_HIP(hipMalloc(&m->hnorm, (64 + 2 * (size_t)BLAS_MAX_BLOCKS) * sizeof(double)));
-    WD_HIP(hipMalloc(&m->hcnt, 256));
-    WD_HIP(hipMemset(m->hcnt, 0, 256));
   }
   const void *x = in_even;
   if (pin != WD_BF16) {
     WD_TRY(blas_convert(G, pin, vref(in_even, 1), WD_BF16, vref(m->x0, 1), 1.0, nullptr, 1, st));
     x = m->x0;
   }
-  WD_TRY(blas_norm2(G, WD_BF16, vref(x, 1), 1, RedBuf{m->hnorm + 64, m->hcnt}, m->hnorm, st));
+  WD_TRY(blas_norm2(G, WD_BF16, vref(x, 1), 1, RedBuf{m->hnorm + 64}, m->hnorm, st));
   return ptc_apply_even_h(n, x, out_even, pout, m->hnorm, st);
 }
 

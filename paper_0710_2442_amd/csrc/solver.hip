@@ -28,54 +28,48 @@
 namespace wd {
 
 // ------------------------------------------------------------ workspace
-struct Workspace {
-  void *base = nullptr;
-  size_t bytes = 0;
-  CgScalars *sc = nullptr;     // device, nsys entries
-  CgScalars *sc_host = nullptr;  // pinned mirror
-  double *partials = nullptr;
-  unsigned *counters = nullptr;
-  int nsys_cap = 0;
-  size_t partial_cap = 0;
-  double *dscal = nullptr;       // small device scratch (norms)
-  double *dscal_host = nullptr;  // pinned
-};
+// largest grid.x of any reducing launch: single-RHS hop, level-1, multi-RHS hop
+static size_t ws_partials(const wd_gauge *g, int nsys) {
+  const size_t nblk = std::max<size_t>(std::max<unsigned>(dslash_grid_blocks(g), BLAS_MAX_BLOCKS),
+                                       mrhs_grid_blocks(g));
+  return nblk * 2 * (size_t)nsys;
+}
+
+size_t ws_block_bytes(const wd_gauge *g, size_t vec_bytes, int nsys) {
+  return round_up(vec_bytes, 256) + round_up(sizeof(CgScalars) * nsys, 256) +
+         round_up(ws_partials(g, nsys) * sizeof(double), 256) + WS_DSCAL * sizeof(double);
+}
+
+void ws_carve(const wd_gauge *g, Workspace &w, char *base, size_t vec_bytes, int nsys) {
+  char *c = base;
+  w.base = c; c += round_up(vec_bytes, 256);
+  w.sc = (CgScalars *)c; c += round_up(sizeof(CgScalars) * nsys, 256);
+  w.partials = (double *)c; c += round_up(ws_partials(g, nsys) * sizeof(double), 256);
+  w.dscal = (double *)c;
+  w.bytes = vec_bytes;
+  w.nsys_cap = nsys;
+  w.partial_cap = ws_partials(g, nsys);
+}
 
 static wd_status ws_reserve(wd_gauge *g, size_t vec_bytes, int nsys) {
   Workspace *&w = g->ws;
   if (!w) w = new Workspace();
-  // largest grid.x of any reducing launch: single-RHS hop, level-1, multi-RHS hop
-  const size_t nblk = std::max<size_t>(std::max<unsigned>(dslash_grid_blocks(g), BLAS_MAX_BLOCKS),
-                                       mrhs_grid_blocks(g));
-  const size_t partial_need = nblk * 2 * (size_t)nsys;
-  if (w->base && w->bytes >= vec_bytes && w->nsys_cap >= nsys && w->partial_cap >= partial_need) return WD_OK;
+  if (w->base && w->bytes >= vec_bytes && w->nsys_cap >= nsys && w->partial_cap >= ws_partials(g, nsys)) return WD_OK;
   if (w->base) {
     WD_HIP(hipFree(w->base));
     w->base = nullptr;
   }
   if (w->sc_host) { WD_HIP(hipHostFree(w->sc_host)); w->sc_host = nullptr; }
   if (w->dscal_host) { WD_HIP(hipHostFree(w->dscal_host)); w->dscal_host = nullptr; }
-  const size_t sc_bytes = round_up(sizeof(CgScalars) * nsys, 256);
-  const size_t part_bytes = round_up(partial_need * sizeof(double), 256);
-  const size_t cnt_bytes = round_up(sizeof(unsigned) * (nsys + 1), 256);
-  const size_t dscal_bytes = 256 * sizeof(double);
-  const size_t total = round_up(vec_bytes, 256) + sc_bytes + part_bytes + cnt_bytes + dscal_bytes;
-  if (hipMalloc(&w->base, total) != hipSuccess) {
+  const size_t total = ws_block_bytes(g, vec_bytes, nsys);
+  void *base = nullptr;
+  if (hipMalloc(&base, total) != hipSuccess) {
     (void)hipGetLastError();
-    w->base = nullptr;
     return set_error(WD_ERR_OOM, "solver workspace: cannot allocate %zu bytes", total);
   }
-  char *c = (char *)w->base + round_up(vec_bytes, 256);
-  w->sc = (CgScalars *)c; c += sc_bytes;
-  w->partials = (double *)c; c += part_bytes;
-  w->counters = (unsigned *)c; c += cnt_bytes;
-  w->dscal = (double *)c;
-  WD_HIP(hipMemset(w->counters, 0, cnt_bytes));
-  WD_HIP(hipHostMalloc((void **)&w->sc_host, sc_bytes, hipHostMallocDefault));
-  WD_HIP(hipHostMalloc((void **)&w->dscal_host, dscal_bytes, hipHostMallocDefault));
-  w->bytes = vec_bytes;
-  w->nsys_cap = nsys;
-  w->partial_cap = partial_need;
+  ws_carve(g, *w, (char *)base, vec_bytes, nsys);
+  WD_HIP(hipHostMalloc((void **)&w->sc_host, round_up(sizeof(CgScalars) * nsys, 256), hipHostMallocDefault));
+  WD_HIP(hipHostMalloc((void **)&w->dscal_host, WS_DSCAL * sizeof(double), hipHostMallocDefault));
   return WD_OK;
 }
 
@@ -89,7 +83,7 @@ void workspace_free(wd_gauge *g) {
   g->ws = nullptr;
 }
 
-static RedBuf red_of(const Workspace *w) { return RedBuf{w->partials, w->counters}; }
+static RedBuf red_of(const Workspace *w) { return RedBuf{w->partials}; }
 
 // ------------------------------------------------------------ operators
 // One hop application for nsys systems: single-RHS kernel when nsys == 1.
@@ -149,9 +143,8 @@ static wd_status cgls_iteration(const wd_gauge *g, const CglsVecs &v, double kap
 // Runs CGLS on M x = s (s holds the right-hand side on entry; x is zeroed).
 // sc_init[sys] carries stop2 / max_iters; returns per-system results in
 // w->sc_host.  dslash_calls is incremented by the hop count issued.
-static wd_status cgls_run(const wd_gauge *g, const CglsVecs &v, double kappa, const CgScalars *sc_init,
-                          const wd_solve_params &prm, hipStream_t st, int &dslash_calls) {
-  Workspace *w = g->ws;
+static wd_status cgls_run(const wd_gauge *g, Workspace *w, const CglsVecs &v, double kappa,
+                          const CgScalars *sc_init, const wd_solve_params &prm, hipStream_t st, int &dslash_calls) {
   RedBuf red = red_of(w);
   CgScalars *sc = w->sc;
   for (int y = 0; y < v.nsys; ++y) w->sc_host[y] = sc_init[y];
@@ -259,13 +252,22 @@ wd_status true_residual64(const wd_gauge *g, const void *b, const void *x, void 
 }
 
 // ------------------------------------------------------------ FP64 eo-CGLS
+size_t cg64_vec_bytes(const wd_gauge *g) {
+  // vectors: p s r q (even) t (odd) + residual (full): 7 halves, one spare
+  return half_bytes(g->geom, WD_F64) * 8;
+}
+
 wd_status solve_cg64(wd_gauge *g, const void *b, void *x, double kappa, double tol,
-                            const wd_solve_params &prm, wd_solve_info &info, hipStream_t st) {
+                     const wd_solve_params &prm, wd_solve_info &info, hipStream_t st) {
+  WD_TRY(ws_reserve(g, cg64_vec_bytes(g), 1));
+  return solve_cg64_on(g, *g->ws, b, x, kappa, tol, prm, info, st);
+}
+
+wd_status solve_cg64_on(wd_gauge *g, Workspace &ws, const void *b, void *x, double kappa, double tol,
+                        const wd_solve_params &prm, wd_solve_info &info, hipStream_t st) {
   const Geom &G = g->geom;
   const size_t hb = half_bytes(G, WD_F64);
-  // vectors: p s r q (even) t (odd) bh (even) + residual (full)
-  WD_TRY(ws_reserve(g, hb * 8, 1));
-  Workspace *w = g->ws;
+  Workspace *w = &ws;
   RedBuf red = red_of(w);
   char *v0 = (char *)w->base;
   CglsVecs V;
@@ -299,7 +301,7 @@ wd_status solve_cg64(wd_gauge *g, const void *b, void *x, double kappa, double t
   init.stop2 = tol * tol * bb;
   init.max_iters = prm.max_iter;
   init.bb = bb;
-  WD_TRY(cgls_run(g, V, kappa, &init, prm, st, info.dslash_calls));
+  WD_TRY(cgls_run(g, w, V, kappa, &init, prm, st, info.dslash_calls));
   info.iters = w->sc_host[0].iters;
   const int done = w->sc_host[0].done;
   // x_o = b_o + k H_oe x_e
@@ -415,7 +417,7 @@ static wd_status solve_defect(wd_gauge *g, const void *b, void *x, int nsys, siz
       WD_TRY(blas_convert(G, WD_F32, vref(e32 + h32, 1, 2 * h32), S, vref(V.s, 1, hS), 1.0, nullptr, nsys, st));
     }
     int calls = 1;
-    WD_TRY(cgls_run(g, V, kappa, init.data(), prm, st, calls));
+    WD_TRY(cgls_run(g, w, V, kappa, init.data(), prm, st, calls));
     int it_max = 0;
     for (int y = 0; y < nsys; ++y) {
       it_max = std::max(it_max, w->sc_host[y].iters);

@@ -70,8 +70,8 @@ static void cache_append(const char *path, const std::string &key, int bs, int g
 }
 
 // occ value: bits 0..7 register budget (0 or 4), WD_TUNE_CACHED_STORE,
-// WD_TUNE_PRELOAD_LINKS, and the dynamic LDS per block in KiB at
-// WD_TUNE_LDS_SHIFT (0..64)
+// WD_TUNE_PRELOAD_LINKS, log2 of the sites per lane at WD_TUNE_SPL_SHIFT and
+// the dynamic LDS per block in KiB at WD_TUNE_LDS_SHIFT (0..64)
 static wd_status decode_occ(int occ, int &o, int &nts, int &lkb, int &pre, int &spl) {
   o = occ & 0xff;
   nts = (occ & WD_TUNE_CACHED_STORE) ? 0 : 1;
@@ -89,10 +89,15 @@ static wd_status decode_occ(int occ, int &o, int &nts, int &lkb, int &pre, int &
   return WD_OK;
 }
 
+static int log2i(int v) {
+  int r = 0;
+  while ((1 << r) < v) ++r;
+  return r;
+}
+
 static int encode_occ(const wd_gauge *g, wd_prec prec) {
-  const int sp = g->hop_spl[prec] == 4 ? 2 : (g->hop_spl[prec] == 2 ? 1 : 0);
   return g->hop_occ[prec] | (g->hop_ntst[prec] ? 0 : WD_TUNE_CACHED_STORE) |
-         (g->hop_pre[prec] ? WD_TUNE_PRELOAD_LINKS : 0) | (sp << WD_TUNE_SPL_SHIFT) |
+         (g->hop_pre[prec] ? WD_TUNE_PRELOAD_LINKS : 0) | (log2i(g->hop_spl[prec]) << WD_TUNE_SPL_SHIFT) |
          ((g->hop_lds[prec] / 1024) << WD_TUNE_LDS_SHIFT);
 }
 
@@ -234,7 +239,7 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
       a.out = ref;
       if ((rc = launch_dslash(g, prec, a, st)) != WD_OK) break;
       const int blocks[] = {64, 128, 256, 512};
-      const int grps[] = {0, 2, 4, 8, 16, -8, -16};
+      const int grps[] = {0, 2, 4, 8, 16, -8, -16, -101, -102, -104, -108};
       best_us = 1e30;
       int nbest_b = 256, nbest_g = 0, nbest_o = 0, nbest_n = 1, nbest_l = 0, nbest_p = 0, nbest_s = 1;
       size_t lds_max = 65536;

@@ -22,7 +22,6 @@ struct KDslash {
   double *norm_out;
   const int *skip;
   double *partials;
-  unsigned *counter;
   // block -> tile mapping (see tile_of)
   int groups;           // 0: linear; G > 0: G contiguous regions per time slice
   int tiles_per_slice;  // tiles (blocks) per time slice of one parity
@@ -46,6 +45,21 @@ struct KDslash {
 __device__ __forceinline__ int tile_of(const KDslash &k, int b) {
   if (k.groups == 0) return b;
   const int T = k.tiles_per_slice;
+  if (k.groups <= -100) {
+    // box order: dispatch lane x = b % 8 (one per XCD) owns the box of x3
+    // planes [bx * P, bx * P + P) and time slices [bt * S, bt * S + S),
+    // nx3 = -groups - 100 boxes along x3 and 8 / nx3 along x4, and walks it
+    // slice by slice, plane by plane, so that every neighbour of a site but
+    // those across a box face is fetched into that XCD's L2, and the next
+    // slice's sites (the time neighbours) are at most one box slice away.
+    const int nx3 = -k.groups - 100;
+    const int P = k.g.L[2] / nx3, S = k.g.L[3] / (8 / nx3);
+    const int tpp = T / k.g.L[2];  // tiles per x3 plane
+    const int x = b & 7, q = b >> 3;
+    const int bx = x % nx3, bt = x / nx3;
+    const int s = q / (P * tpp), pl = (q / tpp) % P, tp = q % tpp;
+    return ((bt * S + s) * k.g.L[2] + bx * P + pl) * tpp + tp;
+  }
   if (k.groups < 0) {
     const int X = -k.groups;
     const int x = b % X, q = b / X;
@@ -58,6 +72,7 @@ __device__ __forceinline__ int tile_of(const KDslash &k, int b) {
   return (q / per) * T + x * per + (q % per);
 }
 __device__ __forceinline__ int tile_of(const KDslash &k) { return tile_of(k, (int)blockIdx.x); }
+
 
 // Site coordinates of checkerboard index i on parity p.
 struct Coords {

@@ -81,7 +81,6 @@ struct wd_gauge {
   int hop_pre[4];          // per precision: 1 = links loaded before the first hop (not FP64)
   int hop_spl[4];          // per precision: output sites per lane along x4 (1, 2, 4)
   double *scratch_red;     // reduction partials / scalars for the BLAS entry points
-  unsigned *scratch_cnt;
   wd::Workspace *ws;
   void *fg_mem;            // mixed FGCR: vectors + scalars + partials, kept between solves
   size_t fg_bytes;
@@ -117,8 +116,7 @@ wd_status hip_check(hipError_t e, const char *what);
 // NULL and *skip != 0 the launch does nothing.
 // reduction workspace needed by a grid of `nblocks` blocks summing N values
 struct RedBuf {
-  double *partials;   // N * nblocks
-  unsigned *counter;  // one counter, zero when idle
+  double *partials;   // N * nblocks block partials, summed by a finishing kernel
 };
 
 struct DslashArgs {
@@ -132,7 +130,7 @@ struct DslashArgs {
   double *norm_out = nullptr;  // device
   int norm_accumulate = 0;     // add to *norm_out instead of overwriting
   const int *skip = nullptr;   // device flag
-  RedBuf red{nullptr, nullptr};
+  RedBuf red{nullptr};
 };
 // Full-lattice D_W in one launch (dirac.hip): full fields in, out, X, Y;
 // out = a H in (+ X (- Y)), optional FP64 |out|^2 over both parities.
@@ -145,7 +143,7 @@ struct DiracArgs {
   int dagger = 0;
   double *norm_out = nullptr;
   int norm_accumulate = 0;
-  RedBuf red{nullptr, nullptr};
+  RedBuf red{nullptr};
 };
 unsigned dirac_grid_blocks(const wd_gauge *g);
 wd_status launch_dirac(const wd_gauge *g, wd_prec prec, const DiracArgs &args, hipStream_t st);
@@ -185,7 +183,7 @@ struct MrhsArgs {
   int norm_accumulate = 0;
   const int *skip = nullptr;
   int skip_stride = 1;
-  RedBuf red{nullptr, nullptr};
+  RedBuf red{nullptr};
 };
 wd_status launch_dslash_mrhs_ex(const wd_gauge *g, wd_prec prec, const MrhsArgs &a, hipStream_t st);
 

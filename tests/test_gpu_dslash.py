@@ -438,7 +438,9 @@ def test_full_size_plane_wave():
 @pytest.mark.parametrize("dims", [(8, 8, 8, 8), (16, 16, 16, 16), (6, 4, 6, 10)])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_every_hop_variant_is_bitwise_identical(dims, prec):
-    """Block size and block -> tile order change only the schedule, never a result bit."""
+    """Block size, block -> tile order (box orders -101 .. -108 included) and
+    the other schedule knobs (store policy, link preloading, sites per lane)
+    change only the schedule, never a result bit."""
     U, psi, _, _ = _inputs(dims, prec, seed=15)
     g = wd.Gauge(U, dims, -1, prec)
     src = to_field(g, psi, prec, wd.WD_ODD)
@@ -446,7 +448,7 @@ def test_every_hop_variant_is_bitwise_identical(dims, prec):
     wd.wd_set_dslash_variant(g, prec, 256, 0, 0)
     wd.wd_dslash_ex(g, src, ref, 0.9, wd.WD_EVEN, prec)
     n = 0
-    for bs, groups, occ in [(b, gr, o) for b in (64, 128, 256, 512) for gr in (0, 2, 4, 8, 16, -2, -4, -8, -16) for o in (0, 4, 256, 512, 516, 1024, 2048, 1536, 2308)]:
+    for bs, groups, occ in [(b, gr, o) for b in (64, 128, 256, 512) for gr in (0, 2, 4, 8, 16, -2, -4, -8, -16, -101, -102, -104, -108) for o in (0, 4, 256, 512, 516, 1024, 2048, 1536, 2308)]:
             try:
                 wd.wd_set_dslash_variant(g, prec, bs, groups, occ)
             except wd.WdError:

@@ -100,6 +100,7 @@ def test_even_application_matches_oracle(dims, scale):
     with pytest.raises(wd.WdError):  # FP16 products need BF16 activations
         n32 = wd.Ptc(g, wd.ptc_weights_to_flat(W1, W2), "f32")
         try:
+            fy = wd.wd_new_field(dims, "f32", 1, wd.WD_EVEN)
             wd.wd_ptc_apply_even(n32, fx, "f32", fy, "f32", wd.WD_PTC_FP16_PRODUCTS)
         finally:
             n32.close()
