@@ -282,6 +282,26 @@ wd_status wd_solve_mrhs(const wd_gauge *U, const void *b, void *x, int nrhs,
                         double kappa, double tol, const wd_solve_params *p,
                         wd_solve_info *info);
 
+/* Allocation-free form of wd_solve, for callers that cannot allocate device
+ * memory on the call (serving loops that must not allocate, harnesses that
+ * forbid hipMalloc).  It runs wd_solve's FP64 even-odd CGLS (p NULL or
+ * p->solver == WD_SOLVER_CG; p->use_graph is ignored: the iterations are
+ * launched one by one, which gives the same bits) with the solver's workspace
+ * (eight FP64 half fields, the CG scalars and the reduction partials) in one
+ * static device array of WD_NOALLOC_SCRATCH_BYTES that every GPU running the
+ * library holds until the process ends; it calls no hipMalloc, hipFree,
+ * hipHostMalloc or hipEventCreate and no graph.  The gauge handle, b and x are
+ * the caller's, as for wd_solve.  Lattices whose workspace exceeds the array
+ * (V/2 above about 43,000 sites; 16^4 fits) give WD_ERR_ARG, as do other
+ * solvers.  Runs on the handle's stream (wd_gauge_set_stream)
+ * and returns when the solve is done.  Results equal wd_solve's bit for bit.
+ * All calls on one GPU share the array: calls that overlap on one GPU (other
+ * threads, other streams) race; calls in sequence are safe, since every part
+ * of the workspace is written before it is read. */
+#define WD_NOALLOC_SCRATCH_BYTES (64u << 20)
+wd_status wd_solve_noalloc(const wd_gauge *U, const void *b, void *x, double kappa,
+                           double tol, const wd_solve_params *p, wd_solve_info *info);
+
 /* ------------------------------------------------- learned preconditioner -- */
 /* Gauge-covariant parallel-transport convolution network (not in the paper):
  * two layers, 1 -> 2 -> 1 spinor channels,

@@ -93,6 +93,8 @@ _decl("wd_convert", C.c_int, [_vp, _vp, C.c_int, _vp, C.c_int, C.c_int, C.c_doub
 _decl("wd_solve_params_default", None, [C.POINTER(wd_solve_params)])
 _decl("wd_solve", C.c_int, [_vp, _vp, _vp, C.c_double, C.c_double, C.POINTER(wd_solve_params),
                              C.POINTER(wd_solve_info)])
+_decl("wd_solve_noalloc", C.c_int, [_vp, _vp, _vp, C.c_double, C.c_double, C.POINTER(wd_solve_params),
+                                     C.POINTER(wd_solve_info)])
 _decl("wd_solve_mrhs", C.c_int, [_vp, _vp, _vp, C.c_int, C.c_double, C.c_double,
                                   C.POINTER(wd_solve_params), C.POINTER(wd_solve_info)])
 _decl("wd_solve_batch", C.c_int, [C.POINTER(_vp), C.c_int, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(C.c_double),
@@ -413,6 +415,19 @@ def wd_solve(g, b, x, kappa, tol, params=None):
     n = _need(g.dims, WD_F64, 1, WD_FULL)
     rc = lib.wd_solve(g.handle, _buf(b, n, "b"), _buf(x, n, "x"), float(kappa), float(tol), pp, C.byref(info))
     _check(rc, "wd_solve", allow_not_converged=True)
+    return rc, info.as_dict()
+
+
+def wd_solve_noalloc(g, b, x, kappa, tol, params=None):
+    """wd_solve's FP64 CG with its workspace in the library's static device
+    array (no device allocation).  Returns (status, info dict)."""
+    g.sync_stream()
+    info = wd_solve_info()
+    pp = C.byref(params) if params is not None else None
+    n = _need(g.dims, WD_F64, 1, WD_FULL)
+    rc = lib.wd_solve_noalloc(g.handle, _buf(b, n, "b"), _buf(x, n, "x"), float(kappa), float(tol), pp,
+                              C.byref(info))
+    _check(rc, "wd_solve_noalloc", allow_not_converged=True)
     return rc, info.as_dict()
 
 
