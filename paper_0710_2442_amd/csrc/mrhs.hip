@@ -19,7 +19,29 @@ struct KMrhs {
   int norm_stride;     // doubles between consecutive RHS norm slots
   int skip_stride;     // ints between consecutive RHS skip flags
   int rpl;             // right-hand sides per lane (FP32-arithmetic kernel)
+  int nx3;             // > 0: box order with tile-major RHS chunks (mrhs_box)
+  int nchunks;         // RHS chunks of rpl right-hand sides
+  int ntiles;          // tiles of one parity
 };
+
+// Box order for the multi-RHS hop.  Dispatch lane x = b % 8 (one per XCD)
+// owns one box: a contiguous 1/nx3 of the tiles of every time slice in a
+// range of 8/nx3 of the slices (boxes nx3 along the slice, 8/nx3 along x4).
+// The lane walks its box slice by slice, and the nchunks blocks of one tile
+// (its RHS chunks) follow each other, so they run side by side on one XCD:
+// the tile's links are fetched into that L2 once, and the sites in flight
+// on an XCD, whose neighbours of all right-hand sides the L2 must hold, are
+// fewer by the number of chunks; the next slice of the box (the time
+// neighbours) is one box-slice away.  Sets the tile and the RHS chunk of
+// block b.
+__device__ __forceinline__ void mrhs_box(const KMrhs &m, int b, int &tile, int &chunk) {
+  const int x = b & 7, q = b >> 3;
+  const int T = m.k.tiles_per_slice, Tb = T / m.nx3, S = m.k.g.L[3] / (8 / m.nx3);
+  const int tq = q / m.nchunks;
+  chunk = q % m.nchunks;
+  const int bx = x % m.nx3, bt = x / m.nx3;
+  tile = (bt * S + tq / Tb) * T + bx * Tb + tq % Tb;
+}
 
 template <int P, bool DAG, int EPI, bool NORM>
 __global__ __launch_bounds__(256) void k_dslash_mrhs(KMrhs m) {
@@ -95,8 +117,15 @@ template <int P, bool DAG, int EPI, bool NORM>
 __global__ __launch_bounds__(256) void k_dslash_mrhs_reg(KMrhs m) {
   using T = RealOf<P>;
   const KDslash &k = m.k;
-  const int i = tile_of(k) * (int)blockDim.x + (int)threadIdx.x;
-  const int r0 = blockIdx.y * m.rpl;
+  int tile, chunk;
+  if (m.nx3 > 0) {
+    mrhs_box(m, (int)blockIdx.x, tile, chunk);
+  } else {
+    tile = tile_of(k);
+    chunk = (int)blockIdx.y;
+  }
+  const int i = tile * (int)blockDim.x + (int)threadIdx.x;
+  const int r0 = chunk * m.rpl;
   const int r1 = min(m.nrhs, r0 + m.rpl);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __shared__ double sred[MR_CHUNK][4];
@@ -161,15 +190,15 @@ __global__ __launch_bounds__(256) void k_dslash_mrhs_reg(KMrhs m) {
     }
   }
   if constexpr (NORM) {
-    // per-RHS partials at partials[r * gridDim.x + block], summed by the
-    // finishing kernel
+    // per-RHS partials at partials[r * ntiles + tile], summed in tile order
+    // by the finishing kernel (the same sum for every schedule)
     __syncthreads();
     if (threadIdx.x == 0) {
       const int nw = (int)blockDim.x >> 6;
       for (int r = r0; r < r1; ++r) {
         double s = 0.0;
         for (int q = 0; q < nw; ++q) s += sred[r - r0][q];
-        k.partials[(size_t)r * gridDim.x + blockIdx.x] = s;
+        k.partials[(size_t)r * m.ntiles + tile] = s;
       }
     }
   }
@@ -208,6 +237,18 @@ static void launch_mrhs_p(const KMrhs &m, bool dag, int epi, bool norm, dim3 gri
 #undef WD_M
 }
 
+// Box order of the FP32-arithmetic multi-RHS hop (groups = -(100 + nx3)):
+// whole tiles per time slice, and the slices and each slice's tiles split
+// evenly over the 8 boxes.
+bool mrhs_box_ok(const Geom &G, int bs, int groups) {
+  if (groups > -100) return false;
+  const int nx3 = -groups - 100;
+  if (nx3 != 1 && nx3 != 2 && nx3 != 4 && nx3 != 8) return false;
+  const long slice = (long)G.vh / G.L[3];
+  if (G.vpad != G.vh || slice % bs != 0) return false;
+  return (slice / bs) % nx3 == 0 && G.L[3] % (8 / nx3) == 0;
+}
+
 // Block size of the multi-RHS hop: FP64 keeps 16 sites x RHS lanes, the
 // others one lane per site (tunable, 64..256).
 static int mrhs_block_of(const wd_gauge *g, wd_prec prec, int &groups) {
@@ -215,7 +256,8 @@ static int mrhs_block_of(const wd_gauge *g, wd_prec prec, int &groups) {
   int bs = (prec == WD_F64) ? 16 : g->mrhs_block[pi];
   if (prec != WD_F64 && bs != 64 && bs != 128 && bs != 256) bs = 128;
   groups = g->mrhs_groups[pi];
-  if (!dslash_variant_ok(g->geom, bs, groups, 1)) groups = 0;
+  const bool box = prec != WD_F64 && mrhs_box_ok(g->geom, bs, groups);
+  if (!box && !dslash_variant_ok(g->geom, bs, groups, 1)) groups = 0;
   return bs;
 }
 
@@ -251,7 +293,14 @@ wd_status launch_dslash_mrhs_ex(const wd_gauge *g, wd_prec prec, const MrhsArgs 
     block = dim3((unsigned)(16 * per_block));
   } else {
     m.rpl = std::max(1, std::min(MR_CHUNK, g->mrhs_rpl[(int)prec]));
-    grid = dim3((unsigned)((g->geom.vpad + bs - 1) / bs), (unsigned)((a.nrhs + m.rpl - 1) / m.rpl));
+    m.nchunks = (a.nrhs + m.rpl - 1) / m.rpl;
+    m.ntiles = (int)((g->geom.vpad + bs - 1) / bs);
+    if (groups <= -100) {
+      m.nx3 = -groups - 100;
+      grid = dim3((unsigned)(m.ntiles * m.nchunks), 1);
+    } else {
+      grid = dim3((unsigned)m.ntiles, (unsigned)m.nchunks);
+    }
     block = dim3((unsigned)bs);
   }
   switch (prec) {
@@ -263,8 +312,8 @@ wd_status launch_dslash_mrhs_ex(const wd_gauge *g, wd_prec prec, const MrhsArgs 
   }
   WD_TRY(hip_check(hipGetLastError(), "dslash_mrhs launch"));
   if (norm)
-    return launch_finish_sums(m.k.partials, grid.x, a.nrhs, m.k.norm_out, m.norm_stride, m.k.norm_accumulate, m.k.skip,
-                              m.skip_stride, st);
+    return launch_finish_sums(m.k.partials, prec == WD_F64 ? grid.x : (unsigned)m.ntiles, a.nrhs, m.k.norm_out,
+                              m.norm_stride, m.k.norm_accumulate, m.k.skip, m.skip_stride, st);
   return WD_OK;
 }
 

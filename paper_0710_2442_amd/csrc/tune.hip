@@ -161,7 +161,7 @@ wd_status wd_set_dslash_mrhs_variant(wd_gauge *g, wd_prec prec, int block, int g
     if (block != 64 && block != 128 && block != 256)
       return set_error(WD_ERR_ARG, "multi-RHS block %d (64, 128 or 256)", block);
     if (rpl < 1 || rpl > 16) return set_error(WD_ERR_ARG, "multi-RHS rpl %d (1..16)", rpl);
-    if (!dslash_variant_ok(g->geom, block, groups))
+    if (!dslash_variant_ok(g->geom, block, groups) && !mrhs_box_ok(g->geom, block, groups))
       return set_error(WD_ERR_ARG, "variant (block %d, groups %d) does not fit this lattice", block, groups);
   }
   g->mrhs_block[prec] = block;
@@ -404,8 +404,11 @@ wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, const char *c
     std::vector<std::array<int, 3>> cands;
     for (int rp : rpls)
       for (int bs : blocks)
-        for (int gr : {0, 2, 4, 8, -8, -16})
-          if (dslash_variant_ok(G, bs, gr)) cands.push_back({rp, bs, gr});
+        for (int gr : {0, 2, 4, 8, -8, -16, -101, -102, -104, -108}) {
+          const bool box = gr <= -100;
+          if (box ? (prec != WD_F64 && mrhs_box_ok(G, bs, gr)) : dslash_variant_ok(G, bs, gr))
+            cands.push_back({rp, bs, gr});
+        }
     for (const auto &c : cands) {
       const int rp = c[0], bs = c[1], gr = c[2];
       g->mrhs_groups[prec] = gr;

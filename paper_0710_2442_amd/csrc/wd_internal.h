@@ -161,6 +161,8 @@ wd_status launch_dslash_slab(const wd_gauge *g, const void *in_slab, const void 
                              hipStream_t st);
 unsigned dslash_grid_blocks(const wd_gauge *g);
 bool dslash_variant_ok(const Geom &G, int bs, int groups, int spl = 1);
+// box order (groups -(100 + n)) of the FP32-arithmetic multi-RHS hop fits the lattice
+bool mrhs_box_ok(const Geom &G, int bs, int groups);
 // grid.x of the multi-RHS hop (16 sites per block)
 inline size_t mrhs_grid_blocks(const wd_gauge *g) { return ((size_t)g->geom.vpad + 15) / 16; }
 wd_status launch_dslash(const wd_gauge *g, wd_prec prec, const DslashArgs &args, hipStream_t st);

@@ -196,9 +196,10 @@ def test_mrhs_equals_single_rhs_bitwise(prec, nrhs):
 @pytest.mark.parametrize("dims", [(8, 4, 6, 16), (16, 8, 8, 8), (8, 6, 8, 4)])
 @pytest.mark.parametrize("prec", ["f32", "f16", "bf16"])
 def test_every_mrhs_variant_is_bitwise_identical(dims, prec):
-    """Block size, tile order and RHS per lane change only the schedule:
-    every variant gives the bytes of the single-RHS hop, ragged RHS chunks
-    and a ragged last tile included."""
+    """Block size, tile order (box orders -101 .. -108 with tile-major RHS
+    chunks included) and RHS per lane change only the schedule: every
+    variant gives the bytes of the single-RHS hop, ragged RHS chunks and a
+    ragged last tile included."""
     nrhs = 5
     g = wd.Gauge(syn.gauge_field(dims, 0.3, 23), dims, -1, prec)
     psis = syn.gaussian_spinor(dims, 24, nrhs=nrhs)
@@ -209,7 +210,7 @@ def test_every_mrhs_variant_is_bitwise_identical(dims, prec):
         wd.wd_dslash_ex(g, src[r * hb:(r + 1) * hb], ref[r * hb:(r + 1) * hb], 0.7, wd.WD_EVEN, prec)
     n = 0
     for bs in (64, 128, 256):
-        for gr in (0, 2, 3, 4, 8, -2, -4, -8):
+        for gr in (0, 2, 3, 4, 8, -2, -4, -8, -101, -102, -104, -108):
             for rpl in (1, 2, 3, 4, 12, 16):
                 try:
                     wd.wd_set_dslash_mrhs_variant(g, prec, bs, gr, rpl)
