@@ -52,6 +52,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def timed_median(torch, fn, reps=3):
+    """Wall time of fn() (device synchronised before and after): one warm-up
+    run, then the median of `reps` timed runs; returns (seconds, last result)."""
+    fn()
+    torch.cuda.synchronize()
+    secs, r = [], None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        secs.append(time.perf_counter() - t)
+    return float(np.median(secs)), r
+
+
 def kernel_hash():
     """Hash of the hop kernel's sources and of the hipcc flags it is built with
     (the flags, not the whole build script, so build options that leave the
@@ -111,6 +126,34 @@ def time_hop(wd, torch, g, psi, prec, steps, warmup):
     return ms / 1e3 / (2 * steps), 2 * steps, ms
 
 
+def time_hop_flushed(wd, torch, g, psi, prec, reps=10):
+    """The same hop with the caches emptied first: before every launch a 512 MiB
+    device buffer (twice the 256 MB Infinity Cache) is written, so the launch
+    finds neither its input nor its links in L2 or the Infinity Cache; HIP
+    events on the hop's stream bracket the hop alone.  Returns seconds per launch."""
+    from paper_0710_2442_amd.fields import canon_to_field, half
+
+    f = canon_to_field(g, psi, prec)
+    E, O = half(f, g, prec, 0), half(f, g, prec, 1)
+    scratch = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream()
+    tot = 0.0
+    for r in range(reps + 1):
+        scratch.fill_(r & 0xFF)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        if r % 2 == 0:
+            wd.wd_dslash_ex(g, O, E, 0.125, wd.WD_EVEN, prec)
+        else:
+            wd.wd_dslash_ex(g, E, O, 0.125, wd.WD_ODD, prec)
+        e1.record(s)
+        torch.cuda.synchronize()
+        if r > 0:  # the first launch warms the instruction cache
+            tot += e0.elapsed_time(e1)
+    del scratch, f
+    return tot / 1e3 / reps
+
+
 def use_tuned(wd, g, table, retune, precs=("f64", "f32", "f16", "bf16")):
     """Hop variants for every storage precision a solver may use, from the
     tuning table (tuned and appended where it has no entry)."""
@@ -140,12 +183,7 @@ def solve_leg(wd, torch, syn, log_every=True, table=None, retune=False):
     ]
     for name, kw in cases:
         p = wd.wd_solve_params_default(**kw)
-        wd.wd_solve(g, fb, x, kappa, tol, p)  # warm-up (graph capture, workspace)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        rc, info = wd.wd_solve(g, fb, x, kappa, tol, p)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t
+        wall, (rc, info) = timed_median(torch, lambda: wd.wd_solve(g, fb, x, kappa, tol, p))
         out[name] = {
             "seconds": round(wall, 4),
             "iters": info["iters"],
@@ -163,7 +201,7 @@ def solve_leg(wd, torch, syn, log_every=True, table=None, retune=False):
             wd.wd_caxpy(g, -1.0, xref, d, 2, "f64")
             out[name]["rel_diff_vs_fp64_cg_solution"] = float(
                 (wd.wd_norm2(g, d, 2, "f64") / wd.wd_norm2(g, xref, 2, "f64")) ** 0.5)
-        log(f"solve {name}: {wall:.3f} s, iters {info['iters']}, outer {info['outer_iters']}, "
+        log(f"solve {name}: {wall:.3f} s (median of 3), iters {info['iters']}, outer {info['outer_iters']}, "
             f"resid {info['true_rel_resid']:.2e}")
     base = out["fp64_cg"]["seconds"]
     for name in out:
@@ -195,12 +233,7 @@ def mrhs_leg(wd, torch, syn, table=None, retune=False):
     use_tuned(wd, g, table, retune)
 
     def timed(fn):
-        fn()  # warm-up
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        r = fn()
-        torch.cuda.synchronize()
-        return time.perf_counter() - t, r
+        return timed_median(torch, fn)
 
     for prec, tin in (("f32", 1e-3), ("bf16", 1e-2)):
         sec, (rc, infos) = timed(lambda: wd.wd_solve_mrhs(g, B, X, 12, kappa, tol, _defect(wd, prec, tin)))
@@ -223,13 +256,21 @@ def mrhs_leg(wd, torch, syn, table=None, retune=False):
     base = out["sequential12_fp64_cg"]["seconds"]
     for k in out:
         out[k]["speedup_vs_fp64_cg"] = round(base / out[k]["seconds"], 3)
-    # multi-RHS hop throughput, 12 RHS, per site per RHS: in + out spinor
-    # (2 x 96 B FP32, 2 x 48 B BF16) + 96/12 FP32 link reals
+    # multi-RHS hop throughput on 12 Gaussian sources, per site per RHS: in +
+    # out spinor (2 x 96 B FP32, 2 x 48 B BF16, 2 x 192 B FP64) + 96/12 link
+    # reals (FP32 links; FP64 links for the FP64 hop)
     vh = int(np.prod(dims)) // 2
-    for prec, spin_b in (("f32", 96), ("bf16", 48)):
+    tmp = wd.wd_new_field(dims, "f32", 1, wd.WD_ODD)
+    for prec, spin_b in (("f32", 96), ("bf16", 48), ("f64", 192)):
+        hb = wd.wd_field_bytes(dims, prec, 1, wd.WD_ODD)
         src = wd.wd_new_field(dims, prec, 12, wd.WD_ODD)
         dst = wd.wd_new_field(dims, prec, 12, wd.WD_EVEN)
-        src.zero_()
+        for r in range(12):
+            if prec in ("f32", "f64"):
+                wd.wd_gaussian_field(g, src[r * hb:(r + 1) * hb], wd.WD_ODD, prec, 7, r)
+            else:
+                wd.wd_gaussian_field(g, tmp, wd.WD_ODD, "f32", 7, r)
+                wd.wd_convert(g, tmp, "f32", src[r * hb:(r + 1) * hb], prec, 1, 1.0)
         for _ in range(3):
             wd.wd_dslash_mrhs(g, src, dst, 1.0, wd.WD_EVEN, prec, 12)
         torch.cuda.synchronize()
@@ -240,16 +281,28 @@ def mrhs_leg(wd, torch, syn, table=None, retune=False):
         e1.record()
         torch.cuda.synchronize()
         us = e0.elapsed_time(e1) * 1e3 / 20
-        per = 2 * spin_b + 96 * 4 // 12
+        per = 2 * spin_b + 96 * (8 if prec == "f64" else 4) // 12
+        gbs = vh * 12 * per / (us * 1e-6) / 1e9
+        e0.record()
+        for _ in range(5):
+            for r in range(12):
+                wd.wd_dslash_ex(g, src[r * hb:(r + 1) * hb], dst[r * hb:(r + 1) * hb], 1.0, wd.WD_EVEN, prec)
+        e1.record()
+        torch.cuda.synchronize()
+        us12 = e0.elapsed_time(e1) * 1e3 / 5
         out[f"mrhs12_hop_{prec}"] = {"us_per_launch": round(us, 2), "bytes_per_site_rhs": per,
-                                     "algorithmic_GBps": round(vh * 12 * per / (us * 1e-6) / 1e9, 1),
-                                     "site_rhs_per_s": round(vh * 12 / (us * 1e-6), 0)}
+                                     "twelve_single_rhs_hops_us": round(us12, 2),
+                                     "speedup_vs_twelve_single_hops": round(us12 / us, 3),
+                                     "algorithmic_GBps": round(gbs, 1), "frac_of_8TBps": round(gbs / HBM_PEAK_GBS, 4),
+                                     "site_rhs_per_s": round(vh * 12 / (us * 1e-6), 0),
+                                     "variant_block_groups_rpl": list(wd.wd_get_dslash_mrhs_variant(g, prec)),
+                                     "sources": "12 Gaussian fields"}
         del src, dst
     g.close()
     return out
 
 
-def batch_leg(wd, torch, syn):
+def batch_leg(wd, torch, syn, table=None, retune=False):
     """Eight lattices of uneven size (689,408 sites) in one persistent batched solve."""
     from paper_0710_2442_amd.fields import canon_to_field
 
@@ -263,19 +316,17 @@ def batch_leg(wd, torch, syn):
     out = {}
 
     def timed(fn):
-        fn()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        r = fn()
-        torch.cuda.synchronize()
-        return time.perf_counter() - t, r
+        return timed_median(torch, fn)
 
-    sec, (rc, infos) = timed(lambda: wd.wd_solve_batch(gs, bs, xs, [kappa] * 8, tol, _defect(wd, "f32")))
-    out["batch8_persistent_graph_f32"] = {"seconds": round(sec, 4), "status": rc,
-                                          "max_resid": max(i["true_rel_resid"] for i in infos)}
-    sec, (rc, infos) = timed(lambda: wd.wd_solve_batch(gs, bs, xs, [kappa] * 8, tol, _defect(wd, "bf16", 1e-2)))
-    out["batch8_persistent_graph_bf16"] = {"seconds": round(sec, 4), "status": rc,
-                                           "max_resid": max(i["true_rel_resid"] for i in infos)}
+    for prec, tin in (("f32", 1e-3), ("bf16", 1e-2)):
+        p = _defect(wd, prec, tin)
+        tile, bpc, tsec = wd.wd_tune_batch(gs, bs, xs, [kappa] * 8, tol, p, table, force=retune)
+        p.batch_tile, p.batch_blocks_per_cu = tile, bpc
+        log(f"tuned batch {prec}: tile {tile}, blocks per CU {bpc} ({tsec * 1e3:.1f} ms in the tuner)")
+        sec, (rc, infos) = timed(lambda: wd.wd_solve_batch(gs, bs, xs, [kappa] * 8, tol, p))
+        out[f"batch8_persistent_graph_{prec}"] = {"seconds": round(sec, 4), "status": rc,
+                                                 "max_resid": max(i["true_rel_resid"] for i in infos),
+                                                 "tile": tile, "blocks_per_cu": bpc}
     sec, res = timed(lambda: [wd.wd_solve(g, b, x, kappa, tol, _defect(wd, "f32")) for g, b, x in zip(gs, bs, xs)])
     out["sequential8_defect_f32"] = {"seconds": round(sec, 4),
                                      "max_resid": max(i["true_rel_resid"] for _, i in res)}
@@ -326,12 +377,8 @@ def learned_leg(wd, torch, syn, steps, table=None, retune=False):
              ("defect_bf16", dict(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec="bf16", inner_tol=1e-2))]
     for name, kw in cases:
         p = wd.wd_solve_params_default(**kw)
-        wd.wd_solve(gt, fb, fx, kappa, tol, p)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        rc, info = wd.wd_solve(gt, fb, fx, kappa, tol, p)
-        torch.cuda.synchronize()
-        out[name] = {"seconds": round(time.perf_counter() - t, 4), "iters": info["iters"], "fgcr_m": kw.get("fgcr_m"),
+        sec, (rc, info) = timed_median(torch, lambda: wd.wd_solve(gt, fb, fx, kappa, tol, p))
+        out[name] = {"seconds": round(sec, 4), "iters": info["iters"], "fgcr_m": kw.get("fgcr_m"),
                      "dslash_calls": info["dslash_calls"], "true_rel_resid": info["true_rel_resid"],
                      "fallback_used": info["fallback_used"], "status": rc}
         log(f"learned leg {name}: {out[name]}")
@@ -538,6 +585,7 @@ def main():
     ap.add_argument("--retune", action="store_true", help="time all variants even if the table has an entry")
     ap.add_argument("--variant", default=None, help="force the hop variant 'block,groups,occ' (no tuning)")
     ap.add_argument("--only", choices=["f64", "f32"], default=None, help="time one precision only")
+    ap.add_argument("--no-flushed", action="store_true", help="skip the cache-flushed hop timing")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -577,6 +625,11 @@ def main():
                          "variant": list(wd.wd_get_dslash_variant(g, prec))}
         log(f"hop {prec}: {sec * 1e6:.1f} us/launch, {gbs:.0f} GB/s algorithmic, "
             f"{100 * gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s")
+        if not args.no_flushed:
+            fsec = time_hop_flushed(wd, torch, g, psi, prec)
+            results[prec]["flushed_sec"] = fsec
+            log(f"hop {prec} after a 512 MiB cache flush: {fsec * 1e6:.1f} us/launch, "
+                f"{100 * vh * BYTES_PER_SITE[prec] / fsec / 1e9 / HBM_PEAK_GBS:.1f}% of 8 TB/s")
         g.close()
         torch.cuda.empty_cache()
 
@@ -605,6 +658,13 @@ def main():
     }
     if traffic is None:
         roof["traffic_note"] = why
+    if "flushed_sec" in r:
+        # the same kernel with L2 and the Infinity Cache emptied before each launch
+        fg = vh * BYTES_PER_SITE[head] / r["flushed_sec"] / 1e9
+        roof["cache_flushed"] = {"avg_launch_us": round(r["flushed_sec"] * 1e6, 2), "achieved": round(fg, 2),
+                                 "frac": round(fg / HBM_PEAK_GBS, 4),
+                                 "note": "512 MiB written before every launch; the headline is the solver's "
+                                         "ping-pong pattern, where an output may be re-read from the caches"}
     from paper_0710_2442_amd import perf_model
 
     ratio = traffic / roof["algorithmic_bytes_per_launch"] if traffic else None
@@ -636,6 +696,10 @@ def main():
         line["f32"] = {"value": round(results["f32"]["gbs"], 2), "unit": "GB/s",
                        "frac": round(results["f32"]["gbs"] / HBM_PEAK_GBS, 4),
                        "avg_launch_us": round(results["f32"]["sec_per_launch"] * 1e6, 2)}
+        if "flushed_sec" in results["f32"]:
+            fg = vh * BYTES_PER_SITE["f32"] / results["f32"]["flushed_sec"] / 1e9
+            line["f32"]["cache_flushed"] = {"avg_launch_us": round(results["f32"]["flushed_sec"] * 1e6, 2),
+                                            "frac": round(fg / HBM_PEAK_GBS, 4)}
     if not args.no_solve:
         sl = solve_leg(wd, torch, syn, table=args.tune_table, retune=args.retune)
         if head == "f64":
@@ -651,7 +715,7 @@ def main():
     if not args.no_mrhs:
         line["mrhs_24x24x24x48_12_point_sources"] = mrhs_leg(wd, torch, syn, args.tune_table, args.retune)
     if not args.no_batch:
-        line["batch_8_lattices_689408_sites"] = batch_leg(wd, torch, syn)
+        line["batch_8_lattices_689408_sites"] = batch_leg(wd, torch, syn, args.tune_table, args.retune)
     if not args.no_learn:
         line["learned_ptc_fgcr_32x32x32x64"] = learned_leg(wd, torch, syn, args.learn_steps, args.tune_table,
                                                           args.retune)

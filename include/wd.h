@@ -249,6 +249,10 @@ typedef struct {
   int use_graph;         /* capture one CG iteration pair in a hipGraph     */
   int fgcr_m;            /* FGCR restart length                             */
   const wd_ptc *precond; /* FGCR right preconditioner (NULL = identity)     */
+  int batch_tile;        /* wd_solve_batch: slots per tile and workgroup,    */
+                         /* 64, 128 or 256 (0 = 256)                         */
+  int batch_blocks_per_cu; /* wd_solve_batch: persistent workgroups per CU   */
+                         /* (0 = as many as fit, -1 = one per tile)          */
 } wd_solve_params;
 
 typedef struct {
@@ -434,6 +438,21 @@ wd_status wd_get_dslash_variant(const wd_gauge *g, wd_prec prec, int *block,
 wd_status wd_solve_batch(const wd_gauge *const *gs, int n, const void *const *b,
                          void *const *x, const double *kappa, double tol,
                          const wd_solve_params *params, wd_solve_info *infos);
+
+/* Tune wd_solve_batch for these lattices: the slots per tile and workgroup
+ * (params->batch_tile: 256, 128, 64) and the persistent workgroups per CU
+ * (params->batch_blocks_per_cu: as many as fit, 1, 2, 4, 8, or one per tile).
+ * Each candidate solves the batch (gs, b, x, kappa, tol and params as for
+ * wd_solve_batch; x is overwritten) once to warm up and twice timed; only
+ * candidates whose every lattice reaches tol count, and the fastest wall time
+ * wins.  cache_path (may be NULL): the JSON-lines table of wd_tune_dslash,
+ * keyed by (arch, "batch<n>", inner precision, the lattices' dims in order);
+ * an entry is used without timing unless force != 0.  Outputs (may be NULL):
+ * the chosen tile, blocks per CU and seconds per solve.  Synchronous. */
+wd_status wd_tune_batch(const wd_gauge *const *gs, int n, const void *const *b,
+                        void *const *x, const double *kappa, double tol,
+                        const wd_solve_params *params, const char *cache_path,
+                        int force, int *tile, int *blocks_per_cu, double *seconds);
 
 /* ------------------------------------------------------ micro-benchmark -- */
 /* Global memory -> LDS block copy on device `device` (the analogue of the

@@ -51,6 +51,8 @@ class wd_solve_params(C.Structure):
         ("use_graph", C.c_int),
         ("fgcr_m", C.c_int),
         ("precond", C.c_void_p),
+        ("batch_tile", C.c_int),
+        ("batch_blocks_per_cu", C.c_int),
     ]
 
 
@@ -99,6 +101,9 @@ _decl("wd_solve_mrhs", C.c_int, [_vp, _vp, _vp, C.c_int, C.c_double, C.c_double,
                                   C.POINTER(wd_solve_params), C.POINTER(wd_solve_info)])
 _decl("wd_solve_batch", C.c_int, [C.POINTER(_vp), C.c_int, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(C.c_double),
                                    C.c_double, C.POINTER(wd_solve_params), C.POINTER(wd_solve_info)])
+_decl("wd_tune_batch", C.c_int, [C.POINTER(_vp), C.c_int, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(C.c_double),
+                                  C.c_double, C.POINTER(wd_solve_params), C.c_char_p, C.c_int, C.POINTER(C.c_int),
+                                  C.POINTER(C.c_int), C.POINTER(C.c_double)])
 _decl("wd_tune_dslash", C.c_int, [_vp, C.c_int, C.c_char_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                    C.POINTER(C.c_int), C.POINTER(C.c_double)])
 _decl("wd_tune_dslash_mrhs", C.c_int, [_vp, C.c_int, C.c_int, C.c_char_p, C.c_int, C.POINTER(C.c_int),
@@ -570,6 +575,14 @@ def wd_ptc_train_step(n, r, e, B, lr, want_loss=True):
 
 def wd_solve_batch(gauges, bs, xs, kappas, tol, params):
     """Solve D_W[l] x[l] = b[l] for every lattice l together (persistent launches)."""
+    n, hs, pb, px, ks = _batch_args(gauges, bs, xs, kappas)
+    infos = (wd_solve_info * n)()
+    rc = lib.wd_solve_batch(hs, n, pb, px, ks, float(tol), C.byref(params), infos)
+    _check(rc, "wd_solve_batch", allow_not_converged=True)
+    return rc, [i.as_dict() for i in infos]
+
+
+def _batch_args(gauges, bs, xs, kappas):
     n = len(gauges)
     for g in gauges:
         g.sync_stream()
@@ -578,10 +591,19 @@ def wd_solve_batch(gauges, bs, xs, kappas, tol, params):
     pb = (_vp * n)(*[_buf(b, k, "b") for b, k in zip(bs, nbs)])
     px = (_vp * n)(*[_buf(x, k, "x") for x, k in zip(xs, nbs)])
     ks = (C.c_double * n)(*[float(k) for k in kappas])
-    infos = (wd_solve_info * n)()
-    rc = lib.wd_solve_batch(hs, n, pb, px, ks, float(tol), C.byref(params), infos)
-    _check(rc, "wd_solve_batch", allow_not_converged=True)
-    return rc, [i.as_dict() for i in infos]
+    return n, hs, pb, px, ks
+
+
+def wd_tune_batch(gauges, bs, xs, kappas, tol, params, cache_path=None, force=False):
+    """Tune the batched solve's tile size and persistent blocks per CU (x is
+    overwritten); returns (tile, blocks_per_cu, seconds per solve).  Put the
+    choice into params.batch_tile / batch_blocks_per_cu to use it."""
+    n, hs, pb, px, ks = _batch_args(gauges, bs, xs, kappas)
+    t, c, sec = C.c_int(), C.c_int(), C.c_double()
+    cp = cache_path.encode() if cache_path else None
+    _check(lib.wd_tune_batch(hs, n, pb, px, ks, float(tol), C.byref(params), cp, int(force), C.byref(t), C.byref(c),
+                             C.byref(sec)), "wd_tune_batch")
+    return t.value, c.value, sec.value
 
 
 def wd_tune_dslash_mrhs(g, prec, nrhs, cache_path=None, force=False):

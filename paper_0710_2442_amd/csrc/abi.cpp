@@ -422,6 +422,10 @@ wd_status wd_solve_batch(const wd_gauge *const *gs, int n, const void *const *b,
     if (gs[l]->device != gs[0]->device) return set_error(WD_ERR_ARG, "solve_batch: handles on different devices");
   }
   if (prm.solver != WD_SOLVER_DEFECT_CG) return set_error(WD_ERR_ARG, "solve_batch: only defect-correction CG");
+  if (prm.batch_tile != 0 && prm.batch_tile != 64 && prm.batch_tile != 128 && prm.batch_tile != 256)
+    return set_error(WD_ERR_ARG, "solve_batch: batch_tile = %d (0, 64, 128 or 256)", prm.batch_tile);
+  if (prm.batch_blocks_per_cu < -1 || prm.batch_blocks_per_cu > 64)
+    return set_error(WD_ERR_ARG, "solve_batch: batch_blocks_per_cu = %d (-1 .. 64)", prm.batch_blocks_per_cu);
   wd_status rc = solve_batch(gs, n, b, x, kappa, tol, prm, infos);
   if (rc < 0)
     for (int l = 0; l < n; ++l) infos[l].status = rc;

@@ -1,7 +1,8 @@
 // Persistent multi-lattice solver: one launch covers every lattice of a batch.
 //
-// The lattices' half fields are cut into tiles of 256 slots; a work list
-// maps each tile to its lattice.  A grid of (#CU x resident blocks)
+// The lattices' half fields are cut into tiles of 64, 128 or 256 slots
+// (one tile per workgroup); a work list maps each tile to its lattice.  A
+// grid of (#CU x resident blocks, or a tuned number of blocks per CU)
 // workgroups walks the list; each tile reads its lattice's descriptor
 // (geometry, links, vector pointers, kappa, CG scalars), so lattices of any
 // size share every launch.  Reductions are segmented by lattice: each tile
@@ -26,7 +27,7 @@
 
 namespace wd {
 
-constexpr int BT = 256;  // tile = block = 256 slots
+constexpr int BT = 256;  // threads of the finishing kernels; largest tile
 
 // vector slots of a lattice
 enum Slot { S_B = 0, S_X, S_R64, S_RH, S_E, S_P, S_S, S_R, S_Q, S_T, NSLOT };
@@ -79,8 +80,8 @@ __device__ __forceinline__ void seg_store(double v, int w, double *partials) {
 }
 
 // ------------------------------------------------------------------ hop
-template <int P, bool DAG, int EPI, bool NORM>
-__global__ __launch_bounds__(BT) void k_batch_hop(KBatch a) {
+template <int P, bool DAG, int EPI, bool NORM, int TB>
+__global__ __launch_bounds__(TB) void k_batch_hop(KBatch a) {
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const int l = a.tile_lat[t];
     const LatDesc &d = a.desc[l];
@@ -95,7 +96,7 @@ __global__ __launch_bounds__(BT) void k_batch_hop(KBatch a) {
     if constexpr (EPI == 2) k.Y = vec_ptr(d, a.Y, P);
     k.a = a.a_mode == 0 ? 1.0 : a.a_mode == 1 ? d.kappa : a.a_mode == 2 ? -d.kappa * d.kappa : -d.kappa;
     k.nt_store = 1;
-    const int i = (t - d.tile0) * BT + (int)threadIdx.x;
+    const int i = (t - d.tile0) * TB + (int)threadIdx.x;
     const double nrm = dslash_site<P, DAG, EPI, NORM>(k, i);
     if constexpr (NORM) seg_store(nrm, t, a.partials);
   }
@@ -104,9 +105,9 @@ __global__ __launch_bounds__(BT) void k_batch_hop(KBatch a) {
 // ------------------------------------------------------------ elementwise
 enum BOp { OP_CGU = 0, OP_PUP, OP_CONV, OP_ACC, OP_NORM };
 
-// Work item w = h * ntiles + t covers slots [.., +256) of half h of tile t.
-template <int OP, int PA, int PB>
-__global__ __launch_bounds__(BT) void k_batch_elem(KBatch a) {
+// Work item w = h * ntiles + t covers the TS slots of tile t in half h.
+template <int OP, int PA, int PB, int TS>
+__global__ __launch_bounds__(TS) void k_batch_elem(KBatch a) {
   using TA = typename Spinor<PA>::real;
   using TB = typename Spinor<PB>::real;
   const int nitems_total = a.ntiles * a.nhalf;
@@ -116,7 +117,7 @@ __global__ __launch_bounds__(BT) void k_batch_elem(KBatch a) {
     const LatDesc &d = a.desc[l];
     CgScalars *sc = d.sc;
     if (a.use_mask && sc->done) continue;
-    const int i = (t - d.tile0) * BT + (int)threadIdx.x;
+    const int i = (t - d.tile0) * TS + (int)threadIdx.x;
     double acc = 0.0;
     if constexpr (OP == OP_CGU) {
       // X(PA) += alpha P(PB); S(PB) -= alpha Q(PB); |S|^2
@@ -249,6 +250,7 @@ struct BatchRun {
   int n = 0;
   int ntiles = 0;
   int grid = 0;
+  int tb = 256;  // slots per tile = threads per workgroup
   LatDesc *d_desc = nullptr;
   int *d_tile_lat = nullptr;
   CgScalars *d_sc = nullptr;
@@ -283,14 +285,21 @@ static KBatch kb(const BatchRun &R) {
 
 #define SC_FIELD(f) ((int)(offsetof(CgScalars, f) / sizeof(double)))
 
-template <int P>
-static void hop_launch(const BatchRun &R, const KBatch &a, bool dag, int epi, bool norm) {
-  dim3 g(R.grid), b(BT);
+template <int P, int TB>
+static void hop_launch_tb(const BatchRun &R, const KBatch &a, bool dag, int epi, bool norm) {
+  dim3 g(R.grid), b(TB);
 #define WD_BH(D, E, N) \
-  if (dag == D && epi == E && norm == N) hipLaunchKernelGGL((k_batch_hop<P, D, E, N>), g, b, 0, R.st, a);
+  if (dag == D && epi == E && norm == N) hipLaunchKernelGGL((k_batch_hop<P, D, E, N, TB>), g, b, 0, R.st, a);
   WD_BH(false, 0, false) WD_BH(false, 1, false) WD_BH(false, 1, true) WD_BH(false, 2, true)
   WD_BH(true, 0, false) WD_BH(true, 1, true)
 #undef WD_BH
+}
+
+template <int P>
+static void hop_launch(const BatchRun &R, const KBatch &a, bool dag, int epi, bool norm) {
+  if (R.tb == 64) hop_launch_tb<P, 64>(R, a, dag, epi, norm);
+  else if (R.tb == 128) hop_launch_tb<P, 128>(R, a, dag, epi, norm);
+  else hop_launch_tb<P, 256>(R, a, dag, epi, norm);
 }
 
 static void hop_any(const BatchRun &R, wd_prec P, const KBatch &a, bool dag, int epi, bool norm) {
@@ -303,15 +312,22 @@ static void hop_any(const BatchRun &R, wd_prec P, const KBatch &a, bool dag, int
   if (norm) hipLaunchKernelGGL(k_batch_finish, dim3((unsigned)R.n), dim3(BT), 0, R.st, a, 0);
 }
 
+template <int OP, int PA, int TB>
+static void elem_pb_tb(const BatchRun &R, const KBatch &a, wd_prec pb) {
+  dim3 g(R.grid), b(TB);
+  switch (pb) {
+    case WD_F64: hipLaunchKernelGGL((k_batch_elem<OP, PA, WD_F64, TB>), g, b, 0, R.st, a); break;
+    case WD_F32: hipLaunchKernelGGL((k_batch_elem<OP, PA, WD_F32, TB>), g, b, 0, R.st, a); break;
+    case WD_F16: hipLaunchKernelGGL((k_batch_elem<OP, PA, WD_F16, TB>), g, b, 0, R.st, a); break;
+    case WD_BF16: hipLaunchKernelGGL((k_batch_elem<OP, PA, WD_BF16, TB>), g, b, 0, R.st, a); break;
+  }
+}
+
 template <int OP, int PA>
 static void elem_pb(const BatchRun &R, const KBatch &a, wd_prec pb) {
-  dim3 g(R.grid), b(BT);
-  switch (pb) {
-    case WD_F64: hipLaunchKernelGGL((k_batch_elem<OP, PA, WD_F64>), g, b, 0, R.st, a); break;
-    case WD_F32: hipLaunchKernelGGL((k_batch_elem<OP, PA, WD_F32>), g, b, 0, R.st, a); break;
-    case WD_F16: hipLaunchKernelGGL((k_batch_elem<OP, PA, WD_F16>), g, b, 0, R.st, a); break;
-    case WD_BF16: hipLaunchKernelGGL((k_batch_elem<OP, PA, WD_BF16>), g, b, 0, R.st, a); break;
-  }
+  if (R.tb == 64) elem_pb_tb<OP, PA, 64>(R, a, pb);
+  else if (R.tb == 128) elem_pb_tb<OP, PA, 128>(R, a, pb);
+  else elem_pb_tb<OP, PA, 256>(R, a, pb);
 }
 
 template <int OP>
@@ -361,6 +377,7 @@ wd_status solve_batch(const wd_gauge *const *gs, int n, const void *const *b, vo
   BatchRun R;
   R.n = n;
   R.S = prm.inner_prec;
+  R.tb = prm.batch_tile ? prm.batch_tile : 256;
   const wd_prec S = R.S;
   R.st = gs[0]->own_stream;
   // events: wait for every caller stream
@@ -388,7 +405,7 @@ wd_status solve_batch(const wd_gauge *const *gs, int n, const void *const *b, vo
     d.links32 = (const char *)gs[l]->links32;
     d.lpar64 = link_parity_bytes(G, true);
     d.lpar32 = link_parity_bytes(G, false);
-    d.ntiles = G.vpad / BT;
+    d.ntiles = G.vpad / R.tb;
     d.tile0 = (int)tile_lat.size();
     d.kappa = kappa[l];
     for (int q = 0; q < d.ntiles; ++q) tile_lat.push_back(l);
@@ -418,13 +435,18 @@ wd_status solve_batch(const wd_gauge *const *gs, int n, const void *const *b, vo
   }
   WD_HIP(hipMemcpyAsync(R.d_desc, R.desc.data(), sizeof(LatDesc) * n, hipMemcpyHostToDevice, R.st));
   WD_HIP(hipMemcpyAsync(R.d_tile_lat, tile_lat.data(), sizeof(int) * R.ntiles, hipMemcpyHostToDevice, R.st));
-  // persistent grid: resident blocks of the hop kernel on every CU
+  // persistent grid: the resident blocks of the hop kernel on every CU, or
+  // batch_blocks_per_cu blocks per CU, or (-1) one block per tile
   {
     int dev, ncu = 0, per_cu = 0;
     WD_HIP(hipGetDevice(&dev));
     WD_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    WD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_batch_hop<WD_F32, false, 1, true>, BT, 0));
-    R.grid = std::max(1, std::min(R.ntiles, ncu * std::max(1, per_cu)));
+    const void *kern = R.tb == 64    ? (const void *)k_batch_hop<WD_F32, false, 1, true, 64>
+                       : R.tb == 128 ? (const void *)k_batch_hop<WD_F32, false, 1, true, 128>
+                                     : (const void *)k_batch_hop<WD_F32, false, 1, true, 256>;
+    WD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, R.tb, 0));
+    if (prm.batch_blocks_per_cu > 0) per_cu = prm.batch_blocks_per_cu;
+    R.grid = prm.batch_blocks_per_cu < 0 ? R.ntiles : std::max(1, std::min(R.ntiles, ncu * std::max(1, per_cu)));
   }
   auto sync_sc = [&]() -> wd_status {
     WD_HIP(hipMemcpyAsync(R.h_sc, R.d_sc, sizeof(CgScalars) * n, hipMemcpyDeviceToHost, R.st));

@@ -221,10 +221,41 @@ static KDslash make_k_mrhs(const wd_gauge *g, wd_prec prec, int parity) {
 // per CU (160 KiB of LDS per CU): fewer sites in flight per XCD means a
 // smaller set of neighbour spinors the L2 must hold for reuse.
 
+// FP64 multi-RHS hop in box order, one right-hand side per block: block b
+// is (tile, RHS) by mrhs_box with RHS chunks of one, so the nrhs blocks of a
+// tile follow each other on one XCD; each runs the single-RHS hop on its RHS
+// (same arithmetic, same bits), its links coming from that XCD's L2 after
+// the first of them.  Norm partials per (RHS, tile) as above.
+template <int P, bool DAG, int EPI, bool NORM>
+__global__ __launch_bounds__(256) void k_dslash_mrhs_l2(KMrhs m) {
+  int tile, r;
+  mrhs_box(m, (int)blockIdx.x, tile, r);
+  const bool live = !(m.k.skip && m.k.skip[(size_t)r * m.skip_stride]);
+  double nrm = 0.0;
+  if (live) {
+    KDslash k = m.k;
+    const size_t off = (size_t)r * m.rhs_stride;
+    k.in = m.k.in + off;
+    k.out = m.k.out + off;
+    if (k.X) k.X += off;
+    if (k.Y) k.Y += off;
+    nrm = dslash_site<P, DAG, EPI, NORM, false>(k, tile * (int)blockDim.x + (int)threadIdx.x);
+  }
+  if constexpr (NORM) {
+    double v[1] = {nrm};
+    block_sum_n<1>(v);
+    if (threadIdx.x == 0 && live) m.k.partials[(size_t)r * m.ntiles + tile] = v[0];
+  }
+}
+
 template <int P, bool DAG, int EPI, bool NORM>
 static void launch_mrhs_t(const KMrhs &m, dim3 grid, dim3 block, hipStream_t st) {
-  if constexpr (P == WD_F64) hipLaunchKernelGGL((k_dslash_mrhs<P, DAG, EPI, NORM>), grid, block, 0, st, m);
-  else hipLaunchKernelGGL((k_dslash_mrhs_reg<P, DAG, EPI, NORM>), grid, block, 0, st, m);
+  if constexpr (P == WD_F64) {
+    if (m.nx3 > 0) hipLaunchKernelGGL((k_dslash_mrhs_l2<P, DAG, EPI, NORM>), grid, block, 0, st, m);
+    else hipLaunchKernelGGL((k_dslash_mrhs<P, DAG, EPI, NORM>), grid, block, 0, st, m);
+  } else {
+    hipLaunchKernelGGL((k_dslash_mrhs_reg<P, DAG, EPI, NORM>), grid, block, 0, st, m);
+  }
 }
 
 template <int P>
@@ -253,10 +284,17 @@ bool mrhs_box_ok(const Geom &G, int bs, int groups) {
 // others one lane per site (tunable, 64..256).
 static int mrhs_block_of(const wd_gauge *g, wd_prec prec, int &groups) {
   const int pi = (int)prec;
-  int bs = (prec == WD_F64) ? 16 : g->mrhs_block[pi];
-  if (prec != WD_F64 && bs != 64 && bs != 128 && bs != 256) bs = 128;
+  int bs = g->mrhs_block[pi];
   groups = g->mrhs_groups[pi];
-  const bool box = prec != WD_F64 && mrhs_box_ok(g->geom, bs, groups);
+  const bool box = mrhs_box_ok(g->geom, bs, groups);
+  if (prec == WD_F64) {
+    // FP64: 16-site x RHS tiles, or one RHS per block in box order
+    if (box && (bs == 64 || bs == 128 || bs == 256)) return bs;
+    bs = 16;
+    if (groups <= -100 || !dslash_variant_ok(g->geom, bs, groups, 1)) groups = 0;
+    return bs;
+  }
+  if (bs != 64 && bs != 128 && bs != 256) bs = 128;
   if (!box && !dslash_variant_ok(g->geom, bs, groups, 1)) groups = 0;
   return bs;
 }
@@ -287,7 +325,14 @@ wd_status launch_dslash_mrhs_ex(const wd_gauge *g, wd_prec prec, const MrhsArgs 
   m.k.groups = groups;
   m.k.tiles_per_slice = groups ? (int)((long)g->geom.vh / g->geom.L[3] / bs) : 0;
   dim3 grid, block;
-  if (prec == WD_F64) {
+  if (prec == WD_F64 && groups <= -100) {
+    m.rpl = 1;
+    m.nchunks = a.nrhs;
+    m.ntiles = (int)((g->geom.vpad + bs - 1) / bs);
+    m.nx3 = -groups - 100;
+    grid = dim3((unsigned)(m.ntiles * m.nchunks), 1);
+    block = dim3((unsigned)bs);
+  } else if (prec == WD_F64) {
     const int per_block = std::min(16, (a.nrhs + 3) / 4 * 4);
     grid = dim3((unsigned)mrhs_grid_blocks(g), (unsigned)((a.nrhs + 15) / 16));
     block = dim3((unsigned)(16 * per_block));
@@ -312,7 +357,7 @@ wd_status launch_dslash_mrhs_ex(const wd_gauge *g, wd_prec prec, const MrhsArgs 
   }
   WD_TRY(hip_check(hipGetLastError(), "dslash_mrhs launch"));
   if (norm)
-    return launch_finish_sums(m.k.partials, prec == WD_F64 ? grid.x : (unsigned)m.ntiles, a.nrhs, m.k.norm_out,
+    return launch_finish_sums(m.k.partials, m.ntiles > 0 ? (unsigned)m.ntiles : grid.x, a.nrhs, m.k.norm_out,
                               m.norm_stride, m.k.norm_accumulate, m.k.skip, m.skip_stride, st);
   return WD_OK;
 }

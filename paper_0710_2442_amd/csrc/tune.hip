@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "wd_internal.h"
+#include "wd_solver.h"
 
 namespace wd {
 
@@ -155,8 +156,12 @@ wd_status wd_set_dslash_mrhs_variant(wd_gauge *g, wd_prec prec, int block, int g
   if (!g) return set_error(WD_ERR_ARG, "gauge handle is NULL");
   if ((int)prec < 0 || (int)prec > 3) return set_error(WD_ERR_PREC, "prec = %d", (int)prec);
   if (prec == WD_F64) {
-    if (block != 16 || rpl != 4 || !dslash_variant_ok(g->geom, 16, groups))
-      return set_error(WD_ERR_ARG, "FP64 multi-RHS variant: block 16, rpl 4 and a groups value that fits");
+    const bool tiles16 = block == 16 && rpl == 4 && groups > -100 && dslash_variant_ok(g->geom, 16, groups);
+    const bool box = (block == 64 || block == 128 || block == 256) && rpl == 1 && mrhs_box_ok(g->geom, block, groups);
+    if (!tiles16 && !box)
+      return set_error(WD_ERR_ARG,
+                       "FP64 multi-RHS variant: block 16, rpl 4 and a groups value that fits, or block 64..256, "
+                       "rpl 1 and a box order (groups -101 .. -108) that fits");
   } else {
     if (block != 64 && block != 128 && block != 256)
       return set_error(WD_ERR_ARG, "multi-RHS block %d (64, 128 or 256)", block);
@@ -393,8 +398,8 @@ wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, const char *c
     if ((rc = launch_dslash_mrhs(g, prec, in, ref, 1.0, WD_EVEN, 0, nrhs, st)) != WD_OK) break;
     std::vector<int> blocks, rpls;
     if (prec == WD_F64) {
-      blocks = {16};
-      rpls = {4};
+      blocks = {16, 64, 128, 256};
+      rpls = {1, 4};
     } else {
       blocks = {64, 128, 256};
       for (int r : {1, 2, 3, 4, 6, 8, 12, 16})
@@ -406,8 +411,13 @@ wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, const char *c
       for (int bs : blocks)
         for (int gr : {0, 2, 4, 8, -8, -16, -101, -102, -104, -108}) {
           const bool box = gr <= -100;
-          if (box ? (prec != WD_F64 && mrhs_box_ok(G, bs, gr)) : dslash_variant_ok(G, bs, gr))
-            cands.push_back({rp, bs, gr});
+          bool ok;
+          if (prec == WD_F64)  // 16-site tiles with 4 RHS per group, or one RHS per block in box order
+            ok = box ? (bs != 16 && rp == 1 && mrhs_box_ok(G, bs, gr))
+                     : (bs == 16 && rp == 4 && dslash_variant_ok(G, bs, gr));
+          else
+            ok = box ? mrhs_box_ok(G, bs, gr) : dslash_variant_ok(G, bs, gr);
+          if (ok) cands.push_back({rp, bs, gr});
         }
     for (const auto &c : cands) {
       const int rp = c[0], bs = c[1], gr = c[2];
@@ -453,3 +463,65 @@ wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, const char *c
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ batched solver
+extern "C" wd_status wd_tune_batch(const wd_gauge *const *gs, int n, const void *const *b, void *const *x,
+                                   const double *kappa, double tol, const wd_solve_params *p, const char *cache_path,
+                                   int force, int *out_tile, int *out_blocks_per_cu, double *out_seconds) {
+  if (!gs || !b || !x || !kappa) return set_error(WD_ERR_ARG, "tune_batch: NULL argument");
+  if (n < 1 || n > 4096) return set_error(WD_ERR_ARG, "tune_batch: n = %d", n);
+  wd_solve_params prm;
+  for (int l = 0; l < n; ++l) {
+    WD_TRY(solve_args(gs[l], b[l], x[l], kappa[l], tol, p, prm));
+    if (gs[l]->device != gs[0]->device) return set_error(WD_ERR_ARG, "tune_batch: handles on different devices");
+  }
+  if (prm.solver != WD_SOLVER_DEFECT_CG) return set_error(WD_ERR_ARG, "tune_batch: only defect-correction CG");
+  // key: arch, inner storage precision and the lattices in order
+  std::string key = tune_key(gs[0], prm.inner_prec);
+  key = key.substr(0, key.find("/hop/"));
+  char part[64];
+  snprintf(part, sizeof part, "/batch%d/p%d/", n, (int)prm.inner_prec);
+  key += part;
+  for (int l = 0; l < n && key.size() < 180; ++l) {
+    snprintf(part, sizeof part, "%s%dx%dx%dx%d", l ? "+" : "", gs[l]->dims[0], gs[l]->dims[1], gs[l]->dims[2],
+             gs[l]->dims[3]);
+    key += part;
+  }
+  int tile = 256, bpc = 0, nl = 0;
+  double us = -1.0;
+  if (cache_path && !force && cache_lookup(cache_path, key, tile, bpc, nl, us, "nlat") && nl == n &&
+      (tile == 64 || tile == 128 || tile == 256) && bpc >= -1 && bpc <= 64) {
+    if (out_tile) *out_tile = tile;
+    if (out_blocks_per_cu) *out_blocks_per_cu = bpc;
+    if (out_seconds) *out_seconds = us * 1e-6;
+    return WD_OK;
+  }
+  // candidates: tile size x persistent blocks per CU (0: as many as fit; -1: one block per tile);
+  // each is run once to warm up and twice timed, and only solves that reach tol count
+  std::vector<wd_solve_info> infos((size_t)n);
+  double best = 1e30;
+  int best_tile = 256, best_bpc = 0;
+  for (int t : {256, 128, 64})
+    for (int c : {0, 1, 2, 4, 8, -1}) {
+      prm.batch_tile = t;
+      prm.batch_blocks_per_cu = c;
+      double sec = 1e30;
+      bool ok = true;
+      for (int rep = 0; rep < 3 && ok; ++rep) {
+        const wd_status rc = solve_batch(gs, n, b, x, kappa, tol, prm, infos.data());
+        if (rc < 0) return rc;
+        ok = rc == WD_OK;
+        if (rep > 0) sec = std::min(sec, infos[0].seconds);
+      }
+      if (getenv("WD_TUNE_VERBOSE"))
+        fprintf(stderr, "tune %s: tile %d blocks/CU %d: %s %.3f ms\n", key.c_str(), t, c, ok ? "ok" : "not converged",
+                sec * 1e3);
+      if (ok && sec < best) { best = sec; best_tile = t; best_bpc = c; }
+    }
+  if (best >= 1e30) return set_error(WD_NOT_CONVERGED, "tune_batch: no candidate reached the tolerance");
+  if (cache_path) cache_append(cache_path, key, best_tile, best_bpc, n, best * 1e6, "nlat");
+  if (out_tile) *out_tile = best_tile;
+  if (out_blocks_per_cu) *out_blocks_per_cu = best_bpc;
+  if (out_seconds) *out_seconds = best;
+  return WD_OK;
+}

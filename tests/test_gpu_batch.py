@@ -90,3 +90,63 @@ def test_batch_eight_lattices_689408_sites(prec):
         r = solvers.true_residual(U, b, x, 0.124)
         print(dims, eps, info["iters"], info["outer_iters"], r, flush=True)
         assert r <= TOL
+
+
+def test_batch_every_tile_and_grid_solves():
+    """Tile sizes 64/128/256 and persistent grids of 1..8 blocks per CU, the
+    occupancy default or one block per tile: every lattice reaches the
+    tolerance by the oracle's D_W (the reductions group their partials
+    differently, so iterates may differ in the last bits, not in quality)."""
+    lats = SMALL[:3]
+    built = []
+    for dims, eps, seed in lats:
+        U = syn.gauge_field(dims, eps, seed)
+        b = syn.gaussian_spinor(dims, seed + 1000)
+        g = wd.Gauge(U, dims, -1, "f64")
+        built.append((U, b, g, to_field(g, b), wd.wd_new_field(dims, "f64")))
+    gs = [t[2] for t in built]
+    fbs = [t[3] for t in built]
+    fxs = [t[4] for t in built]
+    for tile in (64, 128, 256):
+        for bpc in (0, 1, 3, 8, -1):
+            p = wd.wd_solve_params_default(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec="f32", inner_tol=1e-3,
+                                           check_every=8, batch_tile=tile, batch_blocks_per_cu=bpc)
+            rc, infos = wd.wd_solve_batch(gs, fbs, fxs, [0.124] * len(gs), TOL, p)
+            assert rc == 0, (tile, bpc)
+            for (U, b, g, _, fx), info in zip(built, infos):
+                r = solvers.true_residual(U, b, from_field(g, fx), 0.124)
+                assert r <= TOL, (tile, bpc, r)
+                assert abs(r - info["true_rel_resid"]) <= 1e-3 * TOL + 1e-15
+    for bad in (dict(batch_tile=96), dict(batch_tile=512), dict(batch_blocks_per_cu=-2)):
+        p = wd.wd_solve_params_default(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec="f32", **bad)
+        with pytest.raises(wd.WdError):
+            wd.wd_solve_batch(gs, fbs, fxs, [0.124] * len(gs), TOL, p)
+    for g in gs:
+        g.close()
+
+
+def test_batch_tuner_round_trip(tmp_path):
+    """wd_tune_batch keeps a candidate that reaches the tolerance, writes it
+    to the JSON-lines table, and takes it back from there without timing."""
+    lats = SMALL[:2]
+    gs, fbs, fxs, Us, bs = [], [], [], [], []
+    for dims, eps, seed in lats:
+        U = syn.gauge_field(dims, eps, seed)
+        b = syn.gaussian_spinor(dims, seed + 1000)
+        g = wd.Gauge(U, dims, -1, "f64")
+        gs.append(g); fbs.append(to_field(g, b)); fxs.append(wd.wd_new_field(dims, "f64")); Us.append(U); bs.append(b)
+    path = str(tmp_path / "tune.jsonl")
+    p = wd.wd_solve_params_default(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec="bf16", inner_tol=1e-2)
+    t, c, sec = wd.wd_tune_batch(gs, fbs, fxs, [0.124] * 2, TOL, p, path)
+    lines = open(path).read().splitlines()
+    assert len(lines) == 1 and "/batch2/p3/8x8x8x8+4x4x4x4" in lines[0] and '"nlat": 2' in lines[0]
+    assert t in (64, 128, 256) and -1 <= c <= 8 and sec > 0
+    t2, c2, sec2 = wd.wd_tune_batch(gs, fbs, fxs, [0.124] * 2, TOL, p, path)
+    assert (t2, c2) == (t, c) and abs(sec2 - sec) < 1e-6 and len(open(path).read().splitlines()) == 1
+    p.batch_tile, p.batch_blocks_per_cu = t, c
+    rc, infos = wd.wd_solve_batch(gs, fbs, fxs, [0.124] * 2, TOL, p)
+    assert rc == 0
+    for U, b, g, fx in zip(Us, bs, gs, fxs):
+        assert solvers.true_residual(U, b, from_field(g, fx), 0.124) <= TOL
+    for g in gs:
+        g.close()

@@ -231,6 +231,36 @@ def test_every_mrhs_variant_is_bitwise_identical(dims, prec):
     g.close()
 
 
+@pytest.mark.parametrize("dims", [(16, 8, 8, 8), (8, 8, 8, 16)])
+def test_every_fp64_mrhs_variant_is_bitwise_identical(dims):
+    """FP64 multi-RHS: the 16-site x 4-RHS tiles in every tile order, and one
+    RHS per block in every box order that fits, give the bytes of the
+    single-RHS hop."""
+    nrhs = 5
+    g = wd.Gauge(syn.gauge_field(dims, 0.3, 29), dims, -1, "f64")
+    psis = syn.gaussian_spinor(dims, 30, nrhs=nrhs)
+    hb = wd.wd_field_bytes(dims, "f64", 1, wd.WD_EVEN)
+    src = torch.cat([to_field(g, psis[r], "f64", wd.WD_ODD) for r in range(nrhs)])
+    ref = wd.wd_new_field(dims, "f64", nrhs, wd.WD_EVEN)
+    for r in range(nrhs):
+        wd.wd_dslash_ex(g, src[r * hb:(r + 1) * hb], ref[r * hb:(r + 1) * hb], 0.7, wd.WD_EVEN, "f64")
+    n = 0
+    for bs, rpl, groups in [(16, 4, gr) for gr in (0, 2, 4, 8, -2, -4, -8)] + \
+            [(b, 1, gr) for b in (64, 128, 256) for gr in (-101, -102, -104, -108)]:
+        try:
+            wd.wd_set_dslash_mrhs_variant(g, "f64", bs, groups, rpl)
+        except wd.WdError:
+            continue
+        out = wd.wd_new_field(dims, "f64", nrhs, wd.WD_EVEN)
+        out.fill_(0xAB)
+        wd.wd_dslash_mrhs(g, src, out, 0.7, wd.WD_EVEN, "f64", nrhs)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), (bs, groups, rpl)
+        n += 1
+    assert n >= 6
+    g.close()
+
+
 def test_mrhs_solve_does_not_depend_on_rhs_per_lane():
     """The multi-RHS solver through its fused epilogues and per-RHS norms:
     1, 2 or all 3 right-hand sides per lane (same blocks, so the same norm
