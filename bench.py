@@ -46,6 +46,9 @@ TUNE_TABLE = os.path.join(ROOT, "paper_0710_2442_amd", "tuned", "mi355x_hop.json
 # what the hop kernel is built from: its sources and the compile flags
 KERNEL_SOURCES = ["paper_0710_2442_amd/csrc/dslash.hip", "paper_0710_2442_amd/csrc/wd_hop.h",
                   "paper_0710_2442_amd/csrc/wd_device.h"]
+MRHS_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "mrhs_24x24x24x48_traffic.txt")
+MRHS_SOURCES = ["paper_0710_2442_amd/csrc/mrhs.hip", "paper_0710_2442_amd/csrc/wd_hop.h",
+                "paper_0710_2442_amd/csrc/wd_device.h"]
 
 
 def log(*a):
@@ -67,31 +70,32 @@ def timed_median(torch, fn, reps=3):
     return float(np.median(secs)), r
 
 
-def kernel_hash():
-    """Hash of the hop kernel's sources and of the hipcc flags it is built with
-    (the flags, not the whole build script, so build options that leave the
-    library unchanged do not invalidate the counter summary)."""
+def kernel_hash(sources=None):
+    """Hash of a kernel's sources (default: the single-RHS hop's) and of the
+    hipcc flags it is built with (the flags, not the whole build script, so
+    build options that leave the library unchanged do not invalidate a
+    counter summary)."""
     from paper_0710_2442_amd import build as B
 
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in sources or KERNEL_SOURCES:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     h.update(" ".join(B.HIP_FLAGS).replace(ROOT, "<root>").encode())
     return h.hexdigest()[:16]
 
 
-def read_traffic(prec, variant):
-    """HBM bytes per launch from the committed counter summary, if current."""
-    if not os.path.exists(TRAFFIC_SUMMARY):
+def read_traffic(prec, variant, summary=TRAFFIC_SUMMARY, sources=None):
+    """HBM bytes per launch from a committed counter summary, if current."""
+    if not os.path.exists(summary):
         return None, "no counter summary"
     vals = {}
-    with open(TRAFFIC_SUMMARY) as f:
+    with open(summary) as f:
         for line in f:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_hash():
+    if vals.get("kernel_source_sha256_16") != kernel_hash(sources):
         return None, "kernel changed since counters were taken"
     key = f"hbm_bytes_per_launch_{prec}_{'_'.join(str(v) for v in variant)}"
     if key not in vals:
@@ -124,6 +128,23 @@ def time_hop(wd, torch, g, psi, prec, steps, warmup):
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1)
     return ms / 1e3 / (2 * steps), 2 * steps, ms
+
+
+def measure_betas(wd):
+    """The throughputs of the timing model's tasks (Eqs. 1-2), measured here:
+    reads held by the XCDs' L2 (16 MiB) and by the Infinity Cache (128 MiB)
+    and reads from HBM (2 GiB) with the resident-data probe; a copy and the
+    hop's five-read + one-write mix from HBM with the streaming probe."""
+    mib = 1 << 20
+    b = {}
+    b["l2"] = 16 * mib / wd.wd_micro_resident(16 * mib, passes=100, reps=5)
+    b["mall"] = 128 * mib / wd.wd_micro_resident(128 * mib, passes=10, reps=5)
+    b["hbm_read"] = 2048 * mib / wd.wd_micro_resident(2048 * mib, passes=2, reps=3)
+    b["hbm_copy"] = 2 * 1024 * mib / wd.wd_micro_stream(1, 1, 1, 1024 * mib, 10)
+    b["hbm_hop_mix"] = 6 * 512 * mib / wd.wd_micro_stream(5, 1, 1, 512 * mib, 10)
+    for k, v in b.items():
+        log(f"beta {k}: {v / 1e12:.2f} TB/s")
+    return b
 
 
 def time_hop_flushed(wd, torch, g, psi, prec, reps=10):
@@ -215,8 +236,9 @@ def _defect(wd, prec, tol_inner=1e-3):
     return wd.wd_solve_params_default(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec=prec, inner_tol=tol_inner)
 
 
-def mrhs_leg(wd, torch, syn, table=None, retune=False):
+def mrhs_leg(wd, torch, syn, table=None, retune=False, betas=None, solves=True):
     """12 spin-colour point sources on 24^3x48 (kappa 0.124, eps 0.3), solved together."""
+    from paper_0710_2442_amd import perf_model
     from paper_0710_2442_amd.fields import canon_to_field
 
     dims, kappa, tol = (24, 24, 24, 48), 0.124, 1e-10
@@ -235,7 +257,7 @@ def mrhs_leg(wd, torch, syn, table=None, retune=False):
     def timed(fn):
         return timed_median(torch, fn)
 
-    for prec, tin in (("f32", 1e-3), ("bf16", 1e-2)):
+    for prec, tin in ((("f32", 1e-3), ("bf16", 1e-2)) if solves else ()):
         sec, (rc, infos) = timed(lambda: wd.wd_solve_mrhs(g, B, X, 12, kappa, tol, _defect(wd, prec, tin)))
         out[f"mrhs12_defect_{prec}"] = {"seconds": round(sec, 4),
                                         "max_resid": max(i["true_rel_resid"] for i in infos),
@@ -247,15 +269,16 @@ def mrhs_leg(wd, torch, syn, table=None, retune=False):
             res.append(wd.wd_solve(g, B[r * nb:(r + 1) * nb], X[r * nb:(r + 1) * nb], kappa, tol, params))
         return res
 
-    sec, res = timed(lambda: seq(_defect(wd, "f32")))
-    out["sequential12_defect_f32"] = {"seconds": round(sec, 4),
-                                      "max_resid": max(i["true_rel_resid"] for _, i in res)}
-    sec, res = timed(lambda: seq(wd.wd_solve_params_default(solver=wd.WD_SOLVER_CG)))
-    out["sequential12_fp64_cg"] = {"seconds": round(sec, 4),
-                                   "max_resid": max(i["true_rel_resid"] for _, i in res)}
-    base = out["sequential12_fp64_cg"]["seconds"]
-    for k in out:
-        out[k]["speedup_vs_fp64_cg"] = round(base / out[k]["seconds"], 3)
+    if solves:
+        sec, res = timed(lambda: seq(_defect(wd, "f32")))
+        out["sequential12_defect_f32"] = {"seconds": round(sec, 4),
+                                          "max_resid": max(i["true_rel_resid"] for _, i in res)}
+        sec, res = timed(lambda: seq(wd.wd_solve_params_default(solver=wd.WD_SOLVER_CG)))
+        out["sequential12_fp64_cg"] = {"seconds": round(sec, 4),
+                                       "max_resid": max(i["true_rel_resid"] for _, i in res)}
+        base = out["sequential12_fp64_cg"]["seconds"]
+        for k in out:
+            out[k]["speedup_vs_fp64_cg"] = round(base / out[k]["seconds"], 3)
     # multi-RHS hop throughput on 12 Gaussian sources, per site per RHS: in +
     # out spinor (2 x 96 B FP32, 2 x 48 B BF16, 2 x 192 B FP64) + 96/12 link
     # reals (FP32 links; FP64 links for the FP64 hop)
@@ -297,12 +320,23 @@ def mrhs_leg(wd, torch, syn, table=None, retune=False):
                                      "site_rhs_per_s": round(vh * 12 / (us * 1e-6), 0),
                                      "variant_block_groups_rpl": list(wd.wd_get_dslash_mrhs_variant(g, prec)),
                                      "sources": "12 Gaussian fields"}
+        # rocprofv3 counters of this kernel and variant (committed summary), and
+        # Eqs. 1-2 with the bytes fetched beyond the algorithmic ones charged to
+        # the Infinity Cache
+        var = list(wd.wd_get_dslash_mrhs_variant(g, prec))
+        traffic, why = read_traffic(prec, var, MRHS_TRAFFIC_SUMMARY, MRHS_SOURCES)
+        rec = out[f"mrhs12_hop_{prec}"]
+        rec["traffic"] = traffic
+        if traffic is None:
+            rec["traffic_note"] = why
+        ratio = traffic / (vh * 12 * per) if traffic else 1.0
+        rec["model_eq1_eq2"] = perf_model.report(perf_model.kernel_model("mrhs12", prec, vh, ratio, betas), us * 1e-6)
         del src, dst
     g.close()
     return out
 
 
-def batch_leg(wd, torch, syn, table=None, retune=False):
+def batch_leg(wd, torch, syn, table=None, retune=False, betas=None):
     """Eight lattices of uneven size (689,408 sites) in one persistent batched solve."""
     from paper_0710_2442_amd.fields import canon_to_field
 
@@ -327,6 +361,16 @@ def batch_leg(wd, torch, syn, table=None, retune=False):
         out[f"batch8_persistent_graph_{prec}"] = {"seconds": round(sec, 4), "status": rc,
                                                  "max_resid": max(i["true_rel_resid"] for i in infos),
                                                  "tile": tile, "blocks_per_cu": bpc}
+        # Eqs. 1-2 for one inner CG iteration of the whole batch (4 hops and the
+        # BLAS of the storage precision, every field resident in the Infinity
+        # Cache: 689,408 sites, ~200 MB per hop launch), beside the measured
+        # time per inner iteration (the solve's total over the largest lattice
+        # iteration count, outer steps included)
+        from paper_0710_2442_amd import perf_model
+        vh = sum(int(np.prod(d)) for d, _, _ in syn.batch_lattices()) // 2
+        iters = max(i["iters"] for i in infos)
+        out[f"batch8_persistent_graph_{prec}"]["model_eq1_eq2_per_inner_iteration"] = perf_model.report(
+            perf_model.kernel_model("batch8_inner_iteration", prec, vh, betas=betas), sec / max(1, iters))
     sec, res = timed(lambda: [wd.wd_solve(g, b, x, kappa, tol, _defect(wd, "f32")) for g, b, x in zip(gs, bs, xs)])
     out["sequential8_defect_f32"] = {"seconds": round(sec, 4),
                                      "max_resid": max(i["true_rel_resid"] for _, i in res)}
@@ -398,7 +442,7 @@ def learned_leg(wd, torch, syn, steps, table=None, retune=False):
     return out
 
 
-def kernels_leg(wd, torch, syn, U, psi):
+def kernels_leg(wd, torch, syn, U, psi, betas=None):
     """Level-1 kernels (Sec. 4's caxpy), full D_W and the network at 32^3x64."""
     import numpy as np
 
@@ -433,7 +477,7 @@ def kernels_leg(wd, torch, syn, U, psi):
     out["caxpy_f64"] = {"us": round(t * 1e6, 2), "GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
                         "eps_fp": round(V * 96 / t / FP64_PEAK_FLOPS, 5),
                         "eps_fp_hbm_bound": round(96 / 576 * HBM_PEAK_GBS * 1e9 / FP64_PEAK_FLOPS, 5),
-                        "model_eq1_eq2_us": round(perf_model.caxpy_model(V) * 1e6, 1)}
+                        "model_eq1_eq2_us": round(perf_model.caxpy_model(V, "f64", betas) * 1e6, 1)}
     # |x|^2 with the result read back (one synchronisation per call)
     for _ in range(3):
         wd.wd_norm2(g, x, 2, "f64")
@@ -478,7 +522,18 @@ def kernels_leg(wd, torch, syn, U, psi):
     wd.wd_convert(g, x, "f64", r32, "f32", 2, 1.0)
     o32 = wd.wd_new_field(DIMS, "f32")
     t = ev_time(lambda: wd.wd_ptc_apply(net, r32, o32))
-    out["ptc_apply_bf16"] = {"us": round(t * 1e6, 2), "sites": V}
+    out["ptc_apply_bf16"] = {"us": round(t * 1e6, 2), "sites": V,
+                             "model_eq1_eq2": perf_model.report(
+                                 perf_model.kernel_model("ptc_network", "bf16", V, betas=betas), t)}
+    # the even-parity application the solver uses (FP16 products, BF16 fields in and out)
+    xe = wd.wd_new_field(DIMS, "bf16", 1, wd.WD_EVEN)
+    ye = wd.wd_new_field(DIMS, "bf16", 1, wd.WD_EVEN)
+    wd.wd_convert(g, r32, "f32", xe, "bf16", 1, 1.0)
+    t = ev_time(lambda: wd.wd_ptc_apply_even(net, xe, "bf16", ye, "bf16", wd.WD_PTC_FP16_PRODUCTS))
+    out["ptc_apply_even_fp16_products"] = {
+        "us": round(t * 1e6, 2), "sites": V // 2,
+        "model_eq1_eq2": perf_model.report(
+            perf_model.kernel_model("ptc_even_fp16_products", "bf16", V // 2, betas=betas), t)}
     net.close()
     g.close()
     return out
@@ -586,6 +641,8 @@ def main():
     ap.add_argument("--variant", default=None, help="force the hop variant 'block,groups,occ' (no tuning)")
     ap.add_argument("--only", choices=["f64", "f32"], default=None, help="time one precision only")
     ap.add_argument("--no-flushed", action="store_true", help="skip the cache-flushed hop timing")
+    ap.add_argument("--no-betas", action="store_true", help="skip the probes of the timing model's throughputs")
+    ap.add_argument("--no-mrhs-solve", action="store_true", help="multi-RHS leg: time the hops only")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -609,6 +666,7 @@ def main():
     log(f"inputs generated in {time.perf_counter() - t:.1f} s")
 
     vh = int(np.prod(DIMS)) // 2
+    betas = None if args.no_betas else measure_betas(wd)
     results = {}
     precs = [args.only] if args.only else ["f64", "f32"]
     for prec in precs:
@@ -668,7 +726,8 @@ def main():
     from paper_0710_2442_amd import perf_model
 
     ratio = traffic / roof["algorithmic_bytes_per_launch"] if traffic else None
-    roof["model_eq1_eq2"] = perf_model.report(vh, head, r["sec_per_launch"], ratio)
+    roof["model_eq1_eq2"] = perf_model.report(
+        perf_model.kernel_model("hop", head, vh, ratio or 1.0, betas), r["sec_per_launch"])
     line = {
         "metric": "dslash_hbm_GBps",
         "value": round(r["gbs"], 2),
@@ -704,7 +763,7 @@ def main():
         sl = solve_leg(wd, torch, syn, table=args.tune_table, retune=args.retune)
         if head == "f64":
             # Eqs. 1-2 for one eo-CGLS iteration against the measured time per iteration
-            cg = perf_model.cg_iteration_model(vh, "f64", ratio or 1.0)
+            cg = perf_model.cg_iteration_model(vh, "f64", ratio or 1.0, betas)
             meas = sl["fp64_cg"]["seconds"] / sl["fp64_cg"]["iters"]
             sl["fp64_cg"]["model_eq1_eq2"] = {
                 "bytes_per_site": perf_model.cg_iteration_bytes("f64"),
@@ -713,17 +772,20 @@ def main():
                 "measured_over_model": round(meas / cg["T_iter"], 3)}
         line["solve_32x32x32x64_kappa0124"] = sl
     if not args.no_mrhs:
-        line["mrhs_24x24x24x48_12_point_sources"] = mrhs_leg(wd, torch, syn, args.tune_table, args.retune)
+        line["mrhs_24x24x24x48_12_point_sources"] = mrhs_leg(wd, torch, syn, args.tune_table, args.retune, betas,
+                                                             solves=not args.no_mrhs_solve)
     if not args.no_batch:
-        line["batch_8_lattices_689408_sites"] = batch_leg(wd, torch, syn, args.tune_table, args.retune)
+        line["batch_8_lattices_689408_sites"] = batch_leg(wd, torch, syn, args.tune_table, args.retune, betas)
     if not args.no_learn:
         line["learned_ptc_fgcr_32x32x32x64"] = learned_leg(wd, torch, syn, args.learn_steps, args.tune_table,
                                                           args.retune)
     if not args.no_kernels:
-        line["kernels_32x32x32x64"] = kernels_leg(wd, torch, syn, U, psi)
+        line["kernels_32x32x32x64"] = kernels_leg(wd, torch, syn, U, psi, betas)
         line["micro_lds_copy_eq4_fit"] = micro_leg(wd)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_leg(syn, U, psi)
+    if betas:
+        line["model_betas_TBps"] = {k: round(v / 1e12, 3) for k, v in betas.items()}
     print(json.dumps(line), flush=True)
 
 

@@ -479,6 +479,19 @@ wd_status wd_micro_lds_copy(int device, int bytes, int offset, int reps,
 wd_status wd_micro_stream(int device, int nread, int write, int nontemporal,
                           size_t bytes, int reps, double *seconds);
 
+/* Resident-data probe on device `device`: a persistent grid (8 workgroups of
+ * 256 threads per CU, dealt round-robin over the XCDs) reads a zero-filled
+ * buffer of `bytes` bytes (1 MiB .. 4 GiB, whole MiB) `passes` times per
+ * launch, each block the same addresses on every pass (16-byte lanes,
+ * cached loads), after one warming launch.  The buffer therefore comes from
+ * the XCDs' L2 while an eighth of it fits in 4 MB, from the 256 MB Infinity
+ * Cache while it fits there, else from HBM.  *seconds = time of one pass
+ * (HIP events over reps launches).  These read bandwidths are the beta of
+ * the L2, Infinity-Cache and HBM tasks of the timing model (Eqs. 1-2).
+ * Synchronous; allocates `bytes` of device memory for the call. */
+wd_status wd_micro_resident(int device, size_t bytes, int passes, int reps,
+                            double *seconds);
+
 /* --------------------------------------------------------------- misc --- */
 
 const char *wd_status_string(int status);

@@ -126,6 +126,7 @@ _decl("wd_micro_lds_copy", C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, _vp, C.
                                      C.POINTER(C.c_uint)])
 _decl("wd_micro_stream", C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_size_t, C.c_int,
                                    C.POINTER(C.c_double)])
+_decl("wd_micro_resident", C.c_int, [C.c_int, C.c_size_t, C.c_int, C.c_int, C.POINTER(C.c_double)])
 _decl("wd_halo_face_bytes", C.c_size_t, [_int4, C.c_int])
 _decl("wd_halo_pack", C.c_int, [_vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, _vp])
 _decl("wd_dslash_slab", C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int])
@@ -302,6 +303,13 @@ def wd_micro_stream(nread, write, nontemporal, bytes_, reps=20, device=0):
     t = C.c_double()
     _check(lib.wd_micro_stream(int(device), int(nread), int(write), int(nontemporal), int(bytes_), int(reps),
                                C.byref(t)), "wd_micro_stream")
+    return t.value
+
+
+def wd_micro_resident(bytes_, passes=20, reps=5, device=0):
+    """Resident-data probe; returns seconds per pass over `bytes_` bytes."""
+    t = C.c_double()
+    _check(lib.wd_micro_resident(int(device), int(bytes_), int(passes), int(reps), C.byref(t)), "wd_micro_resident")
     return t.value
 
 

@@ -11,6 +11,8 @@
 // of 4 is allowed).  Thread 0 reads the shader clock before and after each
 // copy (with barriers), and the per-copy cycles are written out.  A checksum
 // of the LDS contents after every copy proves the data arrived.
+#include <algorithm>
+
 #include "wd_internal.h"
 
 namespace wd {
@@ -83,6 +85,22 @@ void launch_stream(const mv2d *const *in, mv2d *out, long n, hipStream_t st) {
   hipLaunchKernelGGL((k_stream<R, W, NT>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out, n);
 }
 
+// Resident-data probe: a persistent grid reads an n-element buffer `passes`
+// times over (16-byte lanes, cached loads, grid-stride, so a block reads the
+// same addresses on every pass).  Blocks are dealt round-robin over the XCDs
+// and stay on theirs, so from the second pass on the buffer comes from the
+// level that holds it: the XCDs' L2 (4 MB each) while an XCD's share fits,
+// the 256 MB Infinity Cache while the buffer fits, else HBM.  The compiler
+// barrier between passes makes every pass load again.
+__global__ __launch_bounds__(256) void k_resident(const mv2d *in, long n, int passes, mv2d *sink) {
+  mv2d s = {0.0, 0.0};
+  for (int p = 0; p < passes; ++p) {
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) s += in[i];
+    asm volatile("" ::: "memory");
+  }
+  if (s.x == 1234.5678) sink[0] = s;  // never true for the zero-filled input; keeps the loads live
+}
+
 }  // namespace
 
 }  // namespace wd
@@ -142,6 +160,45 @@ extern "C" wd_status wd_micro_stream(int device, int nread, int write, int nonte
   for (void *b : buf)
     if (b) (void)hipFree(b);
   if (d_in) (void)hipFree(d_in);
+  return rc;
+}
+
+extern "C" wd_status wd_micro_resident(int device, size_t bytes, int passes, int reps, double *seconds) {
+  if (bytes < ((size_t)1 << 20) || bytes % ((size_t)1 << 20) || bytes > ((size_t)4 << 30))
+    return set_error(WD_ERR_ARG, "micro resident: bytes = %zu (1 MiB .. 4 GiB, whole MiB)", bytes);
+  if (passes < 1 || passes > 1000) return set_error(WD_ERR_ARG, "micro resident: passes = %d", passes);
+  if (reps < 1 || reps > 100) return set_error(WD_ERR_ARG, "micro resident: reps = %d", reps);
+  if (!seconds) return set_error(WD_ERR_ARG, "micro resident: NULL output");
+  WD_HIP(hipSetDevice(device));
+  int ncu = 0;
+  WD_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device));
+  const long n = (long)(bytes / 16);
+  const unsigned grid = (unsigned)std::max(8, ncu * 8);
+  void *buf = nullptr, *sink = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  wd_status rc = WD_OK;
+  do {
+    if ((rc = hip_check(hipMalloc(&buf, bytes), "micro alloc")) != WD_OK) break;
+    if ((rc = hip_check(hipMalloc(&sink, 256), "micro alloc")) != WD_OK) break;
+    if ((rc = hip_check(hipMemset(buf, 0, bytes), "micro fill")) != WD_OK) break;
+    // one launch warms the caches
+    hipLaunchKernelGGL(k_resident, dim3(grid), dim3(256), 0, 0, (const mv2d *)buf, n, 2, (mv2d *)sink);
+    if ((rc = hip_check(hipEventCreate(&e0), "event")) != WD_OK) break;
+    if ((rc = hip_check(hipEventCreate(&e1), "event")) != WD_OK) break;
+    WD_HIP(hipEventRecord(e0, 0));
+    for (int r = 0; r < reps; ++r)
+      hipLaunchKernelGGL(k_resident, dim3(grid), dim3(256), 0, 0, (const mv2d *)buf, n, passes, (mv2d *)sink);
+    WD_HIP(hipEventRecord(e1, 0));
+    if ((rc = hip_check(hipEventSynchronize(e1), "micro timing")) != WD_OK) break;
+    float ms = 0.f;
+    WD_HIP(hipEventElapsedTime(&ms, e0, e1));
+    *seconds = 1e-3 * ms / ((double)reps * passes);
+    rc = hip_check(hipGetLastError(), "micro launch");
+  } while (0);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (buf) (void)hipFree(buf);
+  if (sink) (void)hipFree(sink);
   return rc;
 }
 

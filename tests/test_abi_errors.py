@@ -135,6 +135,14 @@ def test_micro_benchmarks_reject_bad_sizes_before_the_device(lib):
     assert f(0, 9, 0, 1, 1 << 20, 1, ctypes.addressof(sec)) == WD_ERR_ARG
     assert f(0, 1, 0, 1, 15, 1, ctypes.addressof(sec)) == WD_ERR_ARG
     assert f(0, 1, 0, 1, 1 << 20, 1, None) == WD_ERR_ARG
+    r = lib.wd_micro_resident
+    r.restype = ctypes.c_int
+    r.argtypes = [ctypes.c_int, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    assert r(0, (1 << 20) + 16, 1, 1, ctypes.addressof(sec)) == WD_ERR_ARG   # not whole MiB
+    assert r(0, 1 << 19, 1, 1, ctypes.addressof(sec)) == WD_ERR_ARG          # below 1 MiB
+    assert r(0, 1 << 20, 0, 1, ctypes.addressof(sec)) == WD_ERR_ARG          # no pass
+    assert r(0, 1 << 20, 1, 101, ctypes.addressof(sec)) == WD_ERR_ARG        # too many launches
+    assert r(0, 1 << 20, 1, 1, None) == WD_ERR_ARG
 
 
 def test_error_paths_under_host_address_sanitizer(tmp_path):

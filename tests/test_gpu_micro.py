@@ -22,3 +22,16 @@ def test_lds_copy_rejects_bad_arguments():
     for args in ((8, 0, 1), (32784, 0, 1), (64, 2, 1), (64, 256, 1), (64, 0, 0), (64, 0, 2000)):
         with pytest.raises(wd.WdError):
             wd.wd_micro_lds_copy(*args)
+
+
+def test_resident_probe_orders_the_cache_levels():
+    """Reads held by the XCDs' L2 (16 MiB) are faster than reads from the
+    Infinity Cache (128 MiB), and both at least as fast as reads from HBM
+    (2 GiB); HBM reads stay below the 8 TB/s data-sheet peak."""
+    mib = 1 << 20
+    l2 = 16 * mib / wd.wd_micro_resident(16 * mib, passes=50, reps=3)
+    mall = 128 * mib / wd.wd_micro_resident(128 * mib, passes=5, reps=3)
+    hbm = 2048 * mib / wd.wd_micro_resident(2048 * mib, passes=1, reps=2)
+    print(f"resident reads: L2 {l2 / 1e12:.2f}, Infinity Cache {mall / 1e12:.2f}, HBM {hbm / 1e12:.2f} TB/s",
+          flush=True)
+    assert l2 > 1.5 * mall and mall >= 0.95 * hbm and hbm < 8.0e12

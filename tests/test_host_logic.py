@@ -63,29 +63,6 @@ def test_weight_checkpoint_round_trip_and_damage(tmp_path):
         learn.save_weights(p, flat[:-1])
 
 
-def test_timing_model_of_the_hop():
-    m = perf_model.hop_model(1 << 20, "f64")
-    # 1152 B per site at 8 TB/s; 1656 flop per site at 78.6 TFLOP/s
-    assert abs(m["T_hbm"] - (1 << 20) * 1152 / 8e12) < 1e-12
-    assert abs(m["T_valu"] - (1 << 20) * 1656 / 78.6e12) < 1e-12
-    assert m["T_exe"] == m["T_hbm"]
-    r = perf_model.report(1 << 20, "f32", 1e-4, 1.1)
-    assert r["T_measured_traffic_at_read_ceiling_us"] > r["T_hbm_read_ceiling_us"] > r["T_hbm_peak_us"]
-
-
-def test_cg_iteration_and_caxpy_models():
-    """Bytes per even site of one eo-CGLS iteration, counted from the kernels
-    it launches: two plain hops (1152 B each in FP64), two hops with an xpay
-    operand (+192 B), the CG update (x, p, s, q read; x, s written) and the
-    p update (r, p read; p written)."""
-    b = perf_model.cg_iteration_bytes("f64")
-    assert b == {"hops": 2 * 1152 + 2 * 1344, "blas": 6 * 192 + 3 * 192}
-    m = perf_model.cg_iteration_model(1 << 20, "f64", 1.0)
-    assert abs(m["T_iter"] - (1 << 20) * (4992 / 6.05e12 + 1728 / 6.65e12)) < 1e-12
-    assert perf_model.cg_iteration_model(1 << 20, "f64", 1.1)["T_iter"] > m["T_iter"]
-    assert abs(perf_model.caxpy_model(1 << 21) - (1 << 21) * 576 / 6.65e12) < 1e-12
-
-
 @pytest.mark.parametrize("n", ["2", "8"])
 def test_bench_refuses_more_than_one_gpu(n):
     p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", n], capture_output=True,

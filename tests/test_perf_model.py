@@ -1,0 +1,78 @@
+"""The MI355X instance of the paper's timing model (Sec. 3, Eqs. 1-2)
+against times measured on the GPU.
+
+profiles/perf_model_mi355x.txt holds one default bench.py run: the task
+throughputs its probes measured and the measured time of each kernel.  For
+every kernel the model's Eq. 2 time (all tasks overlapped) must not exceed
+the measured one.  The kernels that are one HBM stream (hop, CG iteration,
+caxpy) must come within 30% of it, near the agreement the paper reports
+between its memory-time model and its Cell benchmark (Sec. 5, within 20%);
+the others must not take longer than their tasks run one after another
+(plus 25% for launch and tail effects).  A mistake in the byte or flop accounting (a dropped
+link term, a double-counted spinor, flops counted once per site instead of
+per right-hand side) moves a prediction outside these brackets.
+"""
+import os
+
+import pytest
+
+from paper_0710_2442_amd import perf_model
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SUMMARY = os.path.join(ROOT, "profiles", "perf_model_mi355x.txt")
+
+
+def _summary():
+    betas, rows = {}, []
+    for line in open(SUMMARY):
+        if line.startswith("beta_"):
+            k, v = line.split(":")
+            betas[k[5:]] = float(v) * 1e12
+        elif line.startswith("kernel:"):
+            name, prec, units, ratio, us = line.split(":")[1].split()
+            rows.append((name, prec, int(units), float(ratio), float(us) * 1e-6))
+    return betas, rows
+
+
+BETAS, ROWS = _summary()
+STREAMING = {"hop", "cg_iteration", "caxpy"}
+
+
+def test_summary_has_every_kernel_and_task_throughput():
+    assert set(BETAS) == {"l2", "mall", "hbm_read", "hbm_copy", "hbm_hop_mix"}
+    assert {r[0] for r in ROWS} >= {"hop", "cg_iteration", "caxpy", "mrhs12", "ptc_network",
+                                    "ptc_even_fp16_products", "batch8_inner_iteration"}
+
+
+@pytest.mark.parametrize("row", ROWS, ids=[f"{r[0]}-{r[1]}" for r in ROWS])
+def test_measured_time_lies_between_full_and_no_overlap(row):
+    name, prec, units, ratio, measured = row
+    t = perf_model.kernel_model(name, prec, units, ratio, BETAS)
+    assert t["T_exe"] <= 1.02 * measured, (name, prec, t["T_exe"], measured)
+    if name in STREAMING:
+        # one streaming task: the measured time within 30% of it
+        assert measured <= 1.30 * t["T_exe"], (name, prec, t["T_exe"], measured)
+    else:
+        assert measured <= 1.25 * t["T_sum"], (name, prec, t["T_sum"], measured)
+
+
+def test_bounds_the_model_names():
+    """Which task bounds a kernel: the hop and the multi-RHS hop HBM, the
+    batched iteration (every field resident) the Infinity Cache, the network
+    with FP32 products the vector ALU."""
+    bound = {(r[0], r[1]): perf_model.kernel_model(r[0], r[1], r[2], r[3], BETAS)["bound"] for r in ROWS}
+    assert bound[("hop", "f64")] == "T_HBM" and bound[("hop", "f32")] == "T_HBM"
+    assert bound[("mrhs12", "f32")] == "T_HBM"
+    assert bound[("batch8_inner_iteration", "f32")] == "T_MALL"
+    assert bound[("ptc_network", "bf16")] == "T_VALU"
+
+
+def test_byte_accounting_matches_the_hop_definition():
+    """Per output site the hop moves 8 x 12 link reals + 24 input + 24 output
+    reals (Sec. 5's operand count with 12-real links): 1152 B FP64, 576 B
+    FP32; the multi-RHS hop shares the 96 link reals among its right-hand
+    sides (224 B per site and RHS in FP32 at 12 RHS)."""
+    assert perf_model.hop_counts("f64")["hbm"] == 1152
+    assert perf_model.hop_counts("f32")["hbm"] == 576
+    assert perf_model.mrhs_counts("f32", 12)["hbm"] / 12 == 224
+    assert perf_model.mrhs_counts("bf16", 12)["hbm"] / 12 == 128
