@@ -334,11 +334,19 @@ wd_status wd_ptc_apply(const wd_ptc *n, const void *in, void *out);
  * per site).  The input is scaled to unit RMS before it is rounded (the
  * network is linear) and the output scaled back.  BF16 activations only. */
 enum { WD_PTC_FP16_PRODUCTS = 1 };
+/* Flag of wd_ptc_apply_even: the spin mixing on the matrix cores (BF16
+ * operands, FP32 sums) and the transports as BF16 dot products with FP32
+ * sums, on a BF16 copy of the links (made on first use, 192 B per site); the
+ * two spin matrices of the h = 0 terms are multiplied once.  No input
+ * scaling (BF16 has FP32's exponent range).  BF16 activations only; not
+ * together with WD_PTC_FP16_PRODUCTS. */
+enum { WD_PTC_BF16_MFMA = 2 };
 
 /* out_e = [N (in_e, 0)]_e: the network applied to a field that is zero on
  * odd sites, even sites of the result only, as the even-odd solver uses it.
  * in_even, out_even: even half fields in pin / pout (WD_F32 or WD_BF16).
- * flags: 0 or WD_PTC_FP16_PRODUCTS.  Asynchronous on the handle's stream. */
+ * flags: 0, WD_PTC_FP16_PRODUCTS or WD_PTC_BF16_MFMA.  Asynchronous on the
+ * handle's stream. */
 wd_status wd_ptc_apply_even(const wd_ptc *n, const void *in_even, wd_prec pin,
                             void *out_even, wd_prec pout, int flags);
 /* Loss L = (1/B) sum_b |N(r_b) - e_b|^2 over B pairs (r and e: B consecutive

@@ -34,6 +34,7 @@ WD_TUNE_CACHED_STORE = 256
 WD_TUNE_PRELOAD_LINKS = 512
 WD_TUNE_SPL_SHIFT = 10
 WD_PTC_FP16_PRODUCTS = 1
+WD_PTC_BF16_MFMA = 2
 WD_SOLVER_CG, WD_SOLVER_DEFECT_CG, WD_SOLVER_FGCR, WD_SOLVER_DEFECT_FGCR = 0, 1, 2, 3
 
 _vp = C.c_void_p
@@ -555,7 +556,7 @@ def wd_ptc_apply(n, x, y):
 
 
 def wd_ptc_apply_even(n, x_even, pin, y_even, pout, flags=0):
-    """y_e = [N(x_e, 0)]_e on even half fields (flags: 0 or WD_PTC_FP16_PRODUCTS)."""
+    """y_e = [N(x_e, 0)]_e on even half fields (flags: 0, WD_PTC_FP16_PRODUCTS or WD_PTC_BF16_MFMA)."""
     n.g.sync_stream()
     _check(lib.wd_ptc_apply_even(n.handle, _buf(x_even, _need(n.g.dims, pin, 1, WD_EVEN), "in_even"), _prec(pin),
                                  _buf(y_even, _need(n.g.dims, pout, 1, WD_EVEN), "out_even"), _prec(pout),

@@ -34,6 +34,8 @@ HIP_FLAGS = [
     # kernel's rounding never depends on how the compiler schedules it: the
     # multi-RHS, batched and single-RHS hops agree bit for bit
     "-ffp-contract=off",
+    # matrix-core results in ordinary VGPRs (no accumulator-register copies)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I", os.path.join(ROOT, "include"),
 ]
 CXX_FLAGS = ["-x", "c++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__",

@@ -239,7 +239,8 @@ wd_status solve_fgcr(wd_gauge *g, const void *b, void *x, double kappa, double t
 // residual meets tol.
 //
 // Inner (FP32 vectors, FP64 reductions), one direction per iteration:
-//   z_k = [N (r, 0)]_e   (the network restricted to the even sites; z = r
+//   z_k = [N (r, 0)]_e   (the network restricted to the even sites, on the
+//                         matrix cores when its activations are BF16; z = r
 //                         without a network)
 //   w_k = Mhat z_k
 //   c_j = <w_j, w_k> / |w_j|^2 (j < k, one fused pass: classical Gram-Schmidt
@@ -606,7 +607,7 @@ wd_status solve_fgcr_mixed(wd_gauge *g, const void *b, void *x, double kappa, do
     int since = 0, k = 0;
     while (rr > target && it < prm.max_iter) {
       char *zk = (char *)a.Z[k], *wk = (char *)a.W[k];
-      if (N && S == WD_BF16 && ptc_act(N) == WD_BF16) WD_TRY(ptc_apply_even_h(N, R, zk, S, a.rr, st));
+      if (N && ptc_act(N) == WD_BF16) WD_TRY(ptc_apply_even_b(N, R, S, zk, S, st));
       else if (N) WD_TRY(ptc_apply_even(N, R, S, zk, S, st));
       else WD_TRY(blas_convert(G, S, vref(R, 1), S, vref(zk, 1), 1.0, nullptr, 1, st));
       WD_TRY(apply_mhat(g, S, zk, wk, T, kappa, st));

@@ -668,6 +668,450 @@ __global__ void k_ptc_w16(const float *W, uint32_t *W16, int n) {
   if (j < n) W16[j] = __builtin_bit_cast(uint32_t, pkh(W[2 * j], W[2 * j + 1]));
 }
 
+// ------------------------------------------------- BF16 matrix-core inference
+// [N (x_e, 0)]_e in two launches, BF16 operands, FP32 sums, BF16 hidden
+// channels:
+//   launch 1, odd sites o:  y_c(o) = sum_{h >= 1} W1^(h)_{c0} (T_h x)(o),  c = 0, 1
+//   launch 2, even sites e: z(e) = Wc x(e) + sum_d s_d U_d(e) m_d(e),
+//                           m_d(e) = sum_c W2^(d+1)_{0c} y_c(e + d)
+// with Wc = sum_c W2^(0)_{0c} W1^(0)_{c0}: on the even sites layer 1 holds
+// only W1^(0) x, which the h = 0 term of layer 2 multiplies by W2^(0), so the
+// two spin matrices are multiplied once (per launch) instead of both being
+// applied at every site.
+//
+// The spin mixing applies the same weights at every site: a contraction that
+// runs on the matrix cores as v_mfma_f32_16x16x32_bf16 with 16 sites as the
+// columns.  A wave takes 16 sites at a time; lane l serves site l % 16 and
+// lane group g = l / 16 supplies the K values 8g .. 8g+7 of that site's
+// column: the 4 spins (re, im) of one colour of one transported spinor (a
+// direction in launch 1, a (direction, channel) pair in launch 2).  The 16
+// rows of A are (channel or direction slot, spin, re/im) of the output; the
+// weights enter A in real form, [[Wr, -Wi], [Wi, Wr]].  The transports (a
+// different 3x3 matrix at every site) stay on the vector units as
+// v_dot2_f32_bf16: two BF16 products added in FP32, with the spinor words
+// used as stored (re, im) and the link entry in the forms (re, -im) and
+// (im, re).  BF16 keeps FP32's exponent range, so no input scaling is needed.
+//
+// Lane layouts of v_mfma_f32_16x16x32_bf16 (wave64): A[m][k] in lane
+// m + 16 (k / 8), element k % 8; B[k][n] in lane n + 16 (k / 8), element
+// k % 8; D[m][n] in lane n + 16 (m / 4), element m % 4.
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t pk_bf(float re, float im) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f2v){re, im}, bf2v));
+}
+__device__ __forceinline__ float bdot(uint32_t a, uint32_t b, float c) {
+  return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf2v, a), __builtin_bit_cast(bf2v, b), c, false);
+}
+// the same with the sum starting from zero: the three-operand encoding takes
+// the constant, where the builtin's two-operand form needs a register zeroed
+// first (one extra instruction per chain)
+__device__ __forceinline__ float bdot0(uint32_t a, uint32_t b) {
+  float r;
+  asm("v_dot2_f32_bf16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ bf8v bf8_of(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  return __builtin_bit_cast(bf8v, v4u{a, b, c, d});
+}
+__device__ __forceinline__ f4v mfma_bf16(bf8v a, bf8v b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// q = n / d for n < 2^31 (umulhi(n, m) + n cannot overflow), with
+// m = floor(2^32 (2^s - d) / d) + 1 and s = ceil(log2 d): the round-up
+// multiplier of Granlund and Montgomery (PLDI 1994), exact for n < 2^32 / d * 2^s.
+struct FDiv {
+  uint32_t m;
+  int s;
+};
+__device__ __forceinline__ int fdiv(int n, FDiv d) { return (int)((__umulhi((uint32_t)n, d.m) + (uint32_t)n) >> d.s); }
+
+struct KPtcB {
+  Geom g;
+  FDiv dl1h, dl2, dl3;   // division by L1/2, L2, L3
+  const uint2 *links;    // BF16 hop links, parity 0 then 1 (rows 0, 1 as (re, im) pairs; links16 layout)
+  size_t link_par;       // uint2 per parity
+  const char *x;         // BF16 even half (the network input)
+  char *y;               // 2 BF16 odd half fields (hidden channels), colour-major: word 4a + s of a slot
+  size_t y_chan;         // bytes per hidden channel
+  char *out;             // even half, precision of launch 2's template argument
+  const v4u *tabs;       // the A operands, per lane (see k_ptc_b_tables)
+  int ngroups;           // groups of 16 sites: ceil(vh / 16)
+};
+
+// Coordinates of checkerboard site i on parity p, and its neighbours in
+// direction mu (0..3, a per-lane value) forward (f) and backward (b), with the
+// boundary factors of the time hops.
+struct NbMu {
+  int f, b;
+  float sf, sb;
+};
+__device__ __forceinline__ NbMu nb_mu(const KPtcB &k, int i, int p, int mu) {
+  const Geom &g = k.g;
+  const int rest = fdiv(i, k.dl1h);
+  const int x1h = i - rest * g.L1h;
+  const int r2 = fdiv(rest, k.dl2);
+  const int x2 = rest - r2 * g.L[1];
+  const int x4 = fdiv(r2, k.dl3);
+  const int x3 = r2 - x4 * g.L[2];
+  NbMu n;
+  // mu = 0
+  const int x1 = 2 * x1h + ((p + x2 + x3 + x4) & 1);
+  const int f0 = (((x1 + 1 == g.L[0]) ? 0 : x1 + 1) >> 1) + g.L1h * rest;
+  const int b0 = (((x1 == 0) ? g.L[0] - 1 : x1 - 1) >> 1) + g.L1h * rest;
+  // mu = 1..3: the coordinate, extent and stride of that direction
+  const int x = (mu == 1) ? x2 : ((mu == 2) ? x3 : x4);
+  const int L = (mu == 1) ? g.L[1] : ((mu == 2) ? g.L[2] : g.L[3]);
+  const int s = (mu == 1) ? g.s2 : ((mu == 2) ? g.s3 : g.s4);
+  const int fm = i + ((x == L - 1) ? -(L - 1) * s : s);
+  const int bm = i + ((x == 0) ? (L - 1) * s : -s);
+  n.f = (mu == 0) ? f0 : fm;
+  n.b = (mu == 0) ? b0 : bm;
+  n.sf = (mu == 3 && x4 == g.L[3] - 1) ? g.tbc : 1.0f;
+  n.sb = (mu == 3 && x4 == 0) ? g.tbc : 1.0f;
+  return n;
+}
+
+// The raw operands of one transport: a BF16 spinor (12 (re, im) words) and
+// a BF16 link (rows 0, 1: 6 words).
+struct RawB {
+  v4u q[3];
+  uint2 l[3];
+};
+// Loads at 32-bit byte offsets from a wave-uniform base (one address VGPR
+// per load instead of a 64-bit add).
+template <class T>
+__device__ __forceinline__ T ld_at(const void *base, uint32_t off) {
+  return *(const T *)((const char *)base + off);
+}
+// byte offset of packet q of BF16 spinor slot i
+__device__ __forceinline__ uint32_t sp_off(int i, int q) {
+  return (uint32_t)(((i >> 6) * Spinor<WD_BF16>::CHUNK + 64 * q + (i & 63)) * 16);
+}
+// byte offset of packet q of hop d's BF16 link at site i (links16 layout)
+__device__ __forceinline__ uint32_t lk_off(int d, int q, int i) {
+  return (uint32_t)((((i >> 6) * 24 + d * 3 + q) * 64 + (i & 63)) * 8);
+}
+__device__ __forceinline__ void load_spinor_b(const char *base, uint32_t chan_off, int site, v4u (&q)[3]) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j) q[j] = ld_at<v4u>(base, chan_off + sp_off(site, j));
+}
+// links are read once per launch: streaming loads, so that they do not push
+// the re-read spinors out of the L2
+typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void load_link_b(const uint2 *lb, int d, int i, uint2 (&l)[3]) {
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const v2u v = __builtin_nontemporal_load((const v2u *)((const char *)lb + lk_off(d, q, i)));
+    l[q] = uint2{v.x, v.y};
+  }
+}
+__device__ __forceinline__ uint32_t word_of(const v4u (&q)[3], int c) {
+  const v4u v = q[c >> 2];
+  return (c & 3) == 0 ? v.x : ((c & 3) == 1 ? v.y : ((c & 3) == 2 ? v.z : v.w));
+}
+
+// The 9 link entries M_ab in the two forms the dot products take:
+// fr = (re, -im) gives Re(M_ab v_b), fi = (im, re) gives Im(M_ab v_b).  Row 2
+// = conj(row0 x row1) is rebuilt from the forms of the BF16 rows with the
+// same dot products (exact BF16 products, FP32 sums) and rounded to BF16:
+//   row2_c = conj(a_p b_q - a_q b_p), (p, q) = (1, 2), (2, 0), (0, 1),
+//   Re = Re(a_p b_q) - Re(a_q b_p),  -Im = Im(a_q b_p) - Im(a_p b_q),
+// where -fr and -fi are the forms with both halves' signs flipped.  neg =
+// 0x80008000 negates the whole link (a time-boundary factor of -1); it is
+// nonzero only on the boundary slices, so the wave skips it elsewhere.
+struct LinkB {
+  uint32_t fr[9], fi[9];
+};
+__device__ __forceinline__ uint32_t rot16(uint32_t u) { return __builtin_amdgcn_alignbit(u, u, 16); }
+__device__ __forceinline__ void link_forms(const uint2 (&l)[3], uint32_t neg, LinkB &L) {
+  uint32_t u[6];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    u[2 * q] = l[q].x;
+    u[2 * q + 1] = l[q].y;
+  }
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    L.fr[j] = u[j] ^ 0x80000000u;
+    L.fi[j] = rot16(u[j]);
+  }
+  constexpr int P[3] = {1, 2, 0}, Q[3] = {2, 0, 1};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int p = P[c], q = Q[c];
+    const float re = bdot(L.fr[p], u[3 + q], bdot0(L.fr[q] ^ 0x80008000u, u[3 + p]));
+    const float im = bdot(L.fi[q], u[3 + p], bdot0(L.fi[p] ^ 0x80008000u, u[3 + q]));
+    const uint32_t w = pk_bf(re, im);
+    L.fr[6 + c] = w ^ 0x80000000u;
+    L.fi[6 + c] = rot16(w);
+  }
+  if (__any(neg != 0u)) {
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      L.fr[j] ^= neg;
+      L.fi[j] ^= neg;
+    }
+  }
+}
+// y = M v for one spin (v: its 3 colours as (re, im) words)
+__device__ __forceinline__ void su3_b(const LinkB &L, uint32_t v0, uint32_t v1, uint32_t v2, cplx<float> (&y)[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    y[a].re = bdot(L.fr[3 * a + 2], v2, bdot(L.fr[3 * a + 1], v1, bdot0(L.fr[3 * a], v0)));
+    y[a].im = bdot(L.fi[3 * a + 2], v2, bdot(L.fi[3 * a + 1], v1, bdot0(L.fi[3 * a], v0)));
+  }
+}
+// y += M v for one spin
+__device__ __forceinline__ void su3_b_acc(const LinkB &L, uint32_t v0, uint32_t v1, uint32_t v2,
+                                          cplx<float> (&y)[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    y[a].re = bdot(L.fr[3 * a + 2], v2, bdot(L.fr[3 * a + 1], v1, bdot(L.fr[3 * a], v0, y[a].re)));
+    y[a].im = bdot(L.fi[3 * a + 2], v2, bdot(L.fi[3 * a + 1], v1, bdot(L.fi[3 * a], v0, y[a].im)));
+  }
+}
+
+// W in real form for A: row (.., s', rho), column (.., s, sigma) of the
+// complex entry w = W_{s's}: rho = sigma -> Re w; (re, im) -> -Im w; (im, re) -> Im w
+__device__ __forceinline__ float wreal(float wr, float wi, int rho, int sigma) {
+  return (rho == sigma) ? wr : (rho == 0 ? -wi : wi);
+}
+
+// Groups of 16 sites per wave, in a grid-stride loop over the lattice in
+// site order.  (Sweeps that give each XCD a box of the lattice, with grids
+// of only the resident blocks, fetched more from beyond the L2, not less, and
+// ran 3-5% slower.)
+#define GROUP_SWEEP(k) \
+  for (int grp = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6); grp < (k).ngroups; grp += (int)gridDim.x * 4)
+
+// Padding lanes (site >= vh) compute on site vh - 1 and store nothing: a
+// column of the matrix product depends only on its own site's data.
+//
+// Launch 1 (odd sites).  A: row m = 8c + 2s' + rho; K step j, lane group g:
+// direction d = g + 4j (forward hops for j = 0, backward for j = 1).
+__global__ __launch_bounds__(256) void k_ptc_b_l1(KPtcB k) {
+  const int lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+  const bf8v A[2] = {__builtin_bit_cast(bf8v, k.tabs[lane]), __builtin_bit_cast(bf8v, k.tabs[64 + lane])};
+  const uint2 *lb = k.links + k.link_par;  // odd-site links
+  const int c_out = g >> 1, h_out = g & 1;
+  const uint32_t y_off = (uint32_t)(c_out * k.y_chan);
+  GROUP_SWEEP(k) {
+    const int i0 = grp * 16 + col;
+    const int i = min(i0, k.g.vh - 1);
+    RawB r[2];
+    const NbMu n = nb_mu(k, i, 1, g);
+    load_spinor_b(k.x, 0, n.f, r[0].q);
+    load_link_b(lb, g, i, r[0].l);
+    load_spinor_b(k.x, 0, n.b, r[1].q);
+    load_link_b(lb, g + 4, i, r[1].l);
+    const uint32_t neg[2] = {n.sf < 0.f ? 0x80008000u : 0u, n.sb < 0.f ? 0x80008000u : 0u};
+    f4v D[3];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      LinkB L;
+      link_forms(r[j].l, neg[j], L);
+      uint32_t bw[12];  // transported spinor, word 3s + a
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        cplx<float> y[3];
+        su3_b(L, word_of(r[j].q, 3 * s), word_of(r[j].q, 3 * s + 1), word_of(r[j].q, 3 * s + 2), y);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) bw[3 * s + a] = pk_bf(y[a].re, y[a].im);
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        D[a] = mfma_bf16(A[j], bf8_of(bw[a], bw[3 + a], bw[6 + a], bw[9 + a]),
+                         j == 0 ? (f4v){0.f, 0.f, 0.f, 0.f} : D[a]);
+    }
+    if (i0 < k.g.vh) {
+      // rows 4g .. 4g+3: channel g / 2, spins 2h, 2h + 1 (h = g & 1), (re, im):
+      // words 4a + 2h, 4a + 2h + 1 of the colour-major hidden channel
+      char *yb = k.y + y_off;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        *(uint2 *)(yb + sp_off(i, a) + 8 * h_out) = uint2{pk_bf(D[a][0], D[a][1]), pk_bf(D[a][2], D[a][3])};
+    }
+  }
+}
+
+// Launch 2 (even sites).  A (step j): row m = 8 slot + 2s' + rho, slot 0 ->
+// direction j, slot 1 -> direction j + 4; lane group g supplies slot g / 2,
+// channel g & 1, so A is zero where the row's slot is not the lane group's.
+// D then holds m_d for lane group g's slot, spins 2 (g & 1) + t: each lane
+// transports its two spins with U_d and keeps the sum over its slot's
+// directions; lanes l and l ^ 32 (the two slots) add up at the end.  The
+// Wc x(e) term is one more product with A nonzero only for slot 0 and lane
+// group 0.
+template <int POUT>
+__global__ __launch_bounds__(256) void k_ptc_b_l2(KPtcB k) {
+  const int lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+  bf8v A[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) A[j] = __builtin_bit_cast(bf8v, k.tabs[(2 + j) * 64 + lane]);
+  const bf8v Ax = __builtin_bit_cast(bf8v, k.tabs[6 * 64 + lane]);
+  const uint2 *lb = k.links;  // even-site links
+  const int slot = g >> 1;
+  const uint32_t y_off = (uint32_t)((g & 1) * k.y_chan);
+  GROUP_SWEEP(k) {
+    const int i0 = grp * 16 + col;
+    const int i = min(i0, k.g.vh - 1);
+    // slot 0: forward hops d = j, slot 1: backward hops d = j + 4, for mu = j
+    int nb[4];
+    uint32_t neg3 = 0u;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const NbMu n = nb_mu(k, i, 0, j);
+      nb[j] = slot ? n.b : n.f;
+      if (j == 3) neg3 = ((slot ? n.sb : n.sf) < 0.f) ? 0x80008000u : 0u;
+    }
+    // the Wc x(e) term first: it starts the sums (nonzero on lane groups 0, 1 only)
+    cplx<float> acc[2][3];
+    {
+      v4u xq[3];
+      load_spinor_b(k.x, 0, i, xq);
+      f4v X[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        X[a] = mfma_bf16(Ax, bf8_of(word_of(xq, a), word_of(xq, 3 + a), word_of(xq, 6 + a), word_of(xq, 9 + a)),
+                         (f4v){0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc[t][a] = {X[a][2 * t], X[a][2 * t + 1]};
+    }
+    // two steps in flight: step j + 2 is loaded once step j's operands are used
+    RawB cur[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      load_spinor_b(k.y, y_off, nb[j], cur[j].q);
+      load_link_b(lb, j + 4 * slot, i, cur[j].l);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      f4v M[3];  // the hidden channels are colour-major: packet a holds colour a's 4 spins
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        M[a] = mfma_bf16(A[j], __builtin_bit_cast(bf8v, cur[j & 1].q[a]), (f4v){0.f, 0.f, 0.f, 0.f});
+      LinkB L;
+      link_forms(cur[j & 1].l, 0u, L);
+      if (j < 2) {
+        load_spinor_b(k.y, y_off, nb[j + 2], cur[j].q);
+        load_link_b(lb, j + 2 + 4 * slot, i, cur[j].l);
+      }
+      // the time-boundary factor of the x4 hops (step 3) on the mixed spinor
+      const uint32_t ng = (j == 3) ? neg3 : 0u;
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+        su3_b_acc(L, pk_bf(M[0][2 * t], M[0][2 * t + 1]) ^ ng, pk_bf(M[1][2 * t], M[1][2 * t + 1]) ^ ng,
+                  pk_bf(M[2][2 * t], M[2][2 * t + 1]) ^ ng, acc[t]);
+      // one step at a time: the scheduler would otherwise start every step's
+      // products first and hold all their results (occupancy 3 instead of 4)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // the two slots: lanes l (slot 0) and l + 32 (slot 1) hold the same spins
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        acc[t][a].re += __shfl_xor(acc[t][a].re, 32, 64);
+        acc[t][a].im += __shfl_xor(acc[t][a].im, 32, 64);
+      }
+    if (i0 < k.g.vh && g < 2) {
+      // components 6h .. 6h+5, h = g: (t, a) -> 3t + a
+      const int h = g;
+      if constexpr (POUT == WD_BF16) {
+        uint32_t w[6];
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int a = 0; a < 3; ++a) w[3 * t + a] = pk_bf(acc[t][a].re, acc[t][a].im);
+        if (h == 0) {
+          *(v4u *)(k.out + sp_off(i, 0)) = v4u{w[0], w[1], w[2], w[3]};
+          *(uint2 *)(k.out + sp_off(i, 1)) = uint2{w[4], w[5]};
+        } else {
+          *(uint2 *)(k.out + sp_off(i, 1) + 8) = uint2{w[0], w[1]};
+          *(v4u *)(k.out + sp_off(i, 2)) = v4u{w[2], w[3], w[4], w[5]};
+        }
+      } else {
+        v4f *p = (v4f *)k.out + chunk_base<Spinor<WD_F32>::CHUNK>(i) + 3 * 64 * h;
+        const cplx<float> *z = &acc[0][0];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) p[64 * q] = v4f{z[2 * q].re, z[2 * q].im, z[2 * q + 1].re, z[2 * q + 1].im};
+      }
+    }
+  }
+}
+
+// The A operands of both launches for each of the 64 lanes, from the
+// storage-basis weights W (both layers): T[j * 64 + lane], j = 0, 1: launch 1
+// (K steps); 2..5: launch 2 (steps 0..3); 6: the Wc x(e) product.
+constexpr int PTC_B_TABS = 7 * 64;  // v4u
+__global__ __launch_bounds__(64) void k_ptc_b_tables(const float *W, v4u *T) {
+  const int lane = threadIdx.x, g = lane >> 4, m = lane & 15;
+  const int sp = (m >> 1) & 3, rho = m & 1;
+  auto put = [&](int j, const float (&v)[8]) {
+    T[j * 64 + lane] = v4u{pk_bf(v[0], v[1]), pk_bf(v[2], v[3]), pk_bf(v[4], v[5]), pk_bf(v[6], v[7])};
+  };
+  // launch 1: row m = 8c + 2s' + rho, K step j, lane group g: h = g + 4j + 1
+  for (int j = 0; j < 2; ++j) {
+    const int h = g + 4 * j + 1, c = m >> 3;
+    float v[8];
+    for (int e = 0; e < 8; ++e) {
+      const float *w = W + 32 * (h * 2 + c) + 2 * (4 * sp + (e >> 1));
+      v[e] = wreal(w[0], w[1], rho, e & 1);
+    }
+    put(j, v);
+  }
+  // launch 2: row m = 8 slot + 2s' + rho, lane group g: slot g / 2, channel g & 1
+  const float *W2 = W + 576;
+  const int slot_m = m >> 3;
+  for (int j = 0; j < 4; ++j) {
+    const int h = j + 4 * slot_m + 1, c = g & 1;
+    float v[8];
+    for (int e = 0; e < 8; ++e) {
+      const float *w = W2 + 32 * (h * 2 + c) + 2 * (4 * sp + (e >> 1));
+      v[e] = (slot_m == (g >> 1)) ? wreal(w[0], w[1], rho, e & 1) : 0.f;
+    }
+    put(2 + j, v);
+  }
+  // Wc[s'][s] = sum_c sum_t W2^(0)_{0c}[s'][t] W1^(0)_{c0}[t][s], slot 0 rows, lane group 0
+  float v[8];
+  for (int e = 0; e < 8; ++e) {
+    const int s = e >> 1;
+    cplx<float> wc = {0.f, 0.f};
+    for (int c = 0; c < 2; ++c)
+      for (int t = 0; t < 4; ++t) {
+        const float *a = W2 + 32 * c + 2 * (4 * sp + t);
+        const float *b = W + 32 * c + 2 * (4 * t + s);
+        cfma(wc, cplx<float>{a[0], a[1]}, cplx<float>{b[0], b[1]});
+      }
+    v[e] = (slot_m == 0 && g == 0) ? wreal(wc.re, wc.im, rho, e & 1) : 0.f;
+  }
+  put(6, v);
+}
+
+// BF16 copy of the hop links of both parities (rows 0, 1; links16 layout)
+__global__ __launch_bounds__(256) void k_ptc_links_bf16(const char *links32, size_t link_par, Geom g, uint2 *lb,
+                                                         size_t lb_par) {
+  const int p = blockIdx.y;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= g.vpad) return;
+  for (int d = 0; d < 8; ++d) {
+    cplx<float> u[6];
+    if (i < g.vh) Link<float>::load<false>(links32 + (size_t)p * link_par, d, i, u);
+    else
+      for (int j = 0; j < 6; ++j) u[j] = {0.f, 0.f};
+    for (int q = 0; q < 3; ++q)
+      lb[(size_t)p * lb_par + link16_at(d, q, i)] =
+          uint2{pk_bf(u[2 * q].re, u[2 * q].im), pk_bf(u[2 * q + 1].re, u[2 * q + 1].im)};
+  }
+}
+
 }  // namespace wd
 
 // ============================================================ host side
@@ -690,6 +1134,10 @@ struct wd_ptc {
   uint2 *links16;
   uint32_t *W16;
   double *hnorm;
+  // matrix-core inference: BF16 hop links of both parities (made on first
+  // use) and the A operand tables (rebuilt whenever the weights change)
+  uint2 *linksb;
+  wd::v4u *tabs;
 };
 
 namespace wd {
@@ -864,6 +1312,60 @@ wd_status ptc_apply_even_h(const wd_ptc *nc, const void *in_even, void *out_even
   return hip_check(hipGetLastError(), "ptc fp16 layer 2");
 }
 
+static FDiv make_fdiv(int d) {
+  int s = 0;
+  while ((1u << s) < (unsigned)d) ++s;
+  const uint64_t m = (((uint64_t)1 << 32) * (((uint64_t)1 << s) - (uint64_t)d)) / (uint64_t)d + 1;
+  return FDiv{(uint32_t)m, s};
+}
+
+// [N (x_e, 0)]_e on the matrix cores: x_e an even half field in pin (FP32
+// input is first rounded to BF16 in the handle's x0 buffer), output in pout
+// (FP32 or BF16).  Needs BF16 activations (the hidden channels are the
+// handle's y1 buffer, odd halves only).
+wd_status ptc_apply_even_b(const wd_ptc *nc, const void *in_even, wd_prec pin, void *out_even, wd_prec pout,
+                           hipStream_t st) {
+  wd_ptc *n = const_cast<wd_ptc *>(nc);  // the BF16 links are a cache of the handle's own data
+  if (n->act != WD_BF16) return set_error(WD_ERR_PREC, "matrix-core network: BF16 activations only");
+  if ((pin != WD_F32 && pin != WD_BF16) || (pout != WD_F32 && pout != WD_BF16))
+    return set_error(WD_ERR_PREC, "matrix-core network: FP32 or BF16 fields");
+  const Geom &G = n->g->geom;
+  if ((size_t)G.vpad * 192 > 0xffffffffu)
+    return set_error(WD_ERR_DIMS, "matrix-core network: %d sites per parity exceed its 32-bit offsets", G.vh);
+  if (pin != WD_BF16) {
+    WD_TRY(blas_convert(G, pin, vref(in_even, 1), WD_BF16, vref(n->x0, 1), 1.0, nullptr, 1, st));
+    in_even = n->x0;
+  }
+  const size_t par = links16_per_parity(G);
+  if (!n->linksb) {
+    WD_HIP(hipMalloc(&n->linksb, 2 * par * sizeof(uint2)));
+    hipLaunchKernelGGL(k_ptc_links_bf16, dim3((G.vpad + 255) / 256, 2), dim3(256), 0, st,
+                       (const char *)n->g->links32, link_parity_bytes(G, false), G, n->linksb, par);
+    WD_TRY(hip_check(hipGetLastError(), "ptc bf16 links"));
+  }
+  KPtcB k{};
+  k.g = G;
+  k.dl1h = make_fdiv(G.L1h);
+  k.dl2 = make_fdiv(G.L[1]);
+  k.dl3 = make_fdiv(G.L[2]);
+  k.links = n->linksb;
+  k.link_par = par;
+  k.x = (const char *)in_even;
+  k.y = (char *)n->y1;
+  k.y_chan = half_bytes(G, WD_BF16);
+  k.out = (char *)out_even;
+  k.tabs = n->tabs;
+  k.ngroups = (G.vh + 15) / 16;
+  // 4 groups per block pass, at most 16 blocks per CU of 256 (the loop
+  // strides over the rest)
+  const unsigned nblk = (unsigned)std::max(1L, std::min<long>(((long)k.ngroups + 3) / 4, 256L * 16));
+  hipLaunchKernelGGL(k_ptc_b_l1, dim3(nblk), dim3(256), 0, st, k);
+  WD_TRY(hip_check(hipGetLastError(), "ptc matrix-core layer 1"));
+  if (pout == WD_BF16) hipLaunchKernelGGL(k_ptc_b_l2<WD_BF16>, dim3(nblk), dim3(256), 0, st, k);
+  else hipLaunchKernelGGL(k_ptc_b_l2<WD_F32>, dim3(nblk), dim3(256), 0, st, k);
+  return hip_check(hipGetLastError(), "ptc matrix-core layer 2");
+}
+
 // N(in): F32 full field -> F32 full field; input and hidden layer are stored
 // in the activation precision.
 wd_status ptc_apply(const wd_ptc *n, const void *in, void *out, hipStream_t st) {
@@ -894,12 +1396,13 @@ static wd_status ptc_alloc(wd_ptc *n) {
   WD_HIP(hipMalloc(&n->gy1, 2 * f32));
   WD_HIP(hipMalloc(&n->partials, (size_t)2 * n->nblk * 576 * sizeof(double)));
   WD_HIP(hipMalloc(&n->scal, (size_t)(n->nblk + 64) * sizeof(double)));
+  WD_HIP(hipMalloc(&n->tabs, PTC_B_TABS * sizeof(v4u)));
   return WD_OK;
 }
 
 static void ptc_free(wd_ptc *n) {
   void *ps[] = {n->Wc,  n->gradc, n->W,  n->Wadj,     n->grad, n->m,   n->v,       n->x0,  n->y1,    n->y2,
-                n->gy2, n->gy1,   n->partials, n->scal, n->links16, n->W16, n->hnorm};
+                n->gy2, n->gy1,   n->partials, n->scal, n->links16, n->W16, n->hnorm, n->linksb, n->tabs};
   for (void *p : ps)
     if (p) (void)hipFree(p);
   delete n;
@@ -942,6 +1445,7 @@ static wd_status ptc_loss_grad(wd_ptc *n, const void *r, const void *e, int B, h
 // kernels' weights <- parameters (rotate every 4x4 block into the storage basis)
 static wd_status ptc_sync_weights(wd_ptc *n, hipStream_t st) {
   hipLaunchKernelGGL(k_ptc_rotate, dim3(1), dim3(128), 0, st, (const float *)n->Wc, n->W, PTC_NW / 32);
+  hipLaunchKernelGGL(k_ptc_b_tables, dim3(1), dim3(64), 0, st, (const float *)n->W, n->tabs);
   return hip_check(hipGetLastError(), "ptc rotate");
 }
 
@@ -1023,16 +1527,18 @@ wd_status wd_ptc_apply_even(const wd_ptc *n, const void *in_even, wd_prec pin, v
                             int flags) {
   if (!n || !in_even || !out_even) return set_error(WD_ERR_ARG, "NULL argument");
   if (in_even == out_even) return set_error(WD_ERR_ARG, "ptc_apply_even: in and out must differ");
-  if (flags & ~WD_PTC_FP16_PRODUCTS) return set_error(WD_ERR_ARG, "ptc_apply_even: unknown flags 0x%x", flags);
+  if ((flags & ~(WD_PTC_FP16_PRODUCTS | WD_PTC_BF16_MFMA)) || flags == (WD_PTC_FP16_PRODUCTS | WD_PTC_BF16_MFMA))
+    return set_error(WD_ERR_ARG, "ptc_apply_even: unknown flags 0x%x", flags);
   if ((pin != WD_F32 && pin != WD_BF16) || (pout != WD_F32 && pout != WD_BF16))
     return set_error(WD_ERR_PREC, "ptc_apply_even: FP32 or BF16 fields");
-  if ((flags & WD_PTC_FP16_PRODUCTS) && n->act != WD_BF16)
-    return set_error(WD_ERR_PREC, "ptc_apply_even: FP16 products need BF16 activations");
+  if (flags && n->act != WD_BF16)
+    return set_error(WD_ERR_PREC, "ptc_apply_even: FP16 or BF16 products need BF16 activations");
   WD_HIP(hipSetDevice(n->g->device));
   hipStream_t st = n->g->stream;
-  if (!(flags & WD_PTC_FP16_PRODUCTS)) return ptc_apply_even(n, in_even, pin, out_even, pout, st);
+  if (!flags) return ptc_apply_even(n, in_even, pin, out_even, pout, st);
   wd_ptc *m = const_cast<wd_ptc *>(n);
   const Geom &G = n->g->geom;
+  if (flags & WD_PTC_BF16_MFMA) return ptc_apply_even_b(n, in_even, pin, out_even, pout, st);
   if (!m->hnorm) {
     WD_HIP(hipMalloc(&m->hnorm, (64 + 2 * (size_t)BLAS_MAX_BLOCKS) * sizeof(double)));
   }

@@ -14,6 +14,10 @@ wd_status ptc_apply_even(const wd_ptc *n, const void *in_even, wd_prec pin, void
 // norm2 -> |in_even|^2 on the device; needs BF16 activations.
 wd_status ptc_apply_even_h(const wd_ptc *n, const void *in_even, void *out_even, wd_prec pout, const double *norm2,
                            hipStream_t st);
+// The same on the matrix cores (BF16 operands, FP32 sums); FP32 input is
+// rounded to BF16 first.  Needs BF16 activations.
+wd_status ptc_apply_even_b(const wd_ptc *n, const void *in_even, wd_prec pin, void *out_even, wd_prec pout,
+                           hipStream_t st);
 const wd_gauge *ptc_gauge(const wd_ptc *n);
 wd_prec ptc_act(const wd_ptc *n);
 }  // namespace wd

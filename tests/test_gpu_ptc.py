@@ -67,7 +67,7 @@ def test_forward_matches_oracle(act):
     g.close()
 
 
-@pytest.mark.parametrize("dims", [(6, 4, 6, 10), (8, 8, 8, 8)])
+@pytest.mark.parametrize("dims", [(6, 4, 6, 10), (8, 8, 8, 8), (6, 2, 2, 6)])
 @pytest.mark.parametrize("scale", [1.0, 1e-7])
 def test_even_application_matches_oracle(dims, scale):
     """[N(x_e, 0)]_e, as the even-odd solver applies the network, against the
@@ -79,7 +79,12 @@ def test_even_application_matches_oracle(dims, scale):
     toward zero to 11 significant bits, a relative error below 2^-10 each
     and biased one way, so up to 7 * 2^-10 ~ 7e-3 on a component; bar 1e-2.
     A tiny input (1e-7) checks the scaling to unit RMS: without it the FP16
-    operands would underflow."""
+    operands would underflow.  BF16 operands on the matrix cores: every
+    operand of a chain (input, link rows, rebuilt link row, transported
+    spinor, weight, hidden channel, weight, mixed spinor, link) is rounded to
+    nearest at 8 significant bits, below 2^-9 relative each, so up to
+    9 * 2^-9 ~ 1.8e-2 on a component; bar 2e-2, per site 2^-3.  BF16 keeps
+    FP32's exponent range, so the tiny input needs no scaling there."""
     U = syn.gauge_field(dims, 0.3, 305)
     x = syn.gaussian_spinor(dims, 306) * scale
     W1, W2 = _weights(307)
@@ -89,7 +94,8 @@ def test_even_application_matches_oracle(dims, scale):
     even = wilson.parity_mask(dims, 0)
     xe = storage_round(x * even, "f32")
     want = ptc.network(round_c64(U), xe, W1, W2, act_round=_bf16) * even
-    for flags, bar, sbar in ((0, 2e-3, 2.0 ** -5), (wd.WD_PTC_FP16_PRODUCTS, 1e-2, 2.0 ** -4)):
+    for flags, bar, sbar in ((0, 2e-3, 2.0 ** -5), (wd.WD_PTC_FP16_PRODUCTS, 1e-2, 2.0 ** -4),
+                             (wd.WD_PTC_BF16_MFMA, 2e-2, 2.0 ** -3)):
         for pout in ("f32", "bf16"):
             fy = wd.wd_new_field(dims, pout, 1, wd.WD_EVEN)
             wd.wd_ptc_apply_even(n, fx, "f32", fy, pout, flags)
