@@ -201,6 +201,8 @@ def solve_leg(wd, torch, syn, log_every=True, table=None, retune=False):
         ("defect_f32", dict(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec="f32", inner_tol=1e-4)),
         ("defect_f16", dict(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec="f16", inner_tol=1e-2)),
         ("defect_bf16", dict(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec="bf16", inner_tol=1e-2)),
+        # context: CGLS on the full-lattice D_W, without the even-odd reduction
+        ("fp64_cgls_full_lattice", dict(solver=wd.WD_SOLVER_CGLS_FULL)),
     ]
     for name, kw in cases:
         p = wd.wd_solve_params_default(**kw)
@@ -525,7 +527,7 @@ def kernels_leg(wd, torch, syn, U, psi, betas=None):
     out["ptc_apply_bf16"] = {"us": round(t * 1e6, 2), "sites": V,
                              "model_eq1_eq2": perf_model.report(
                                  perf_model.kernel_model("ptc_network", "bf16", V, betas=betas), t)}
-    # the even-parity application the solver uses (FP16 products, BF16 fields in and out)
+    # the even-parity application with FP16 products (BF16 fields in and out)
     xe = wd.wd_new_field(DIMS, "bf16", 1, wd.WD_EVEN)
     ye = wd.wd_new_field(DIMS, "bf16", 1, wd.WD_EVEN)
     wd.wd_convert(g, r32, "f32", xe, "bf16", 1, 1.0)
@@ -534,6 +536,12 @@ def kernels_leg(wd, torch, syn, U, psi, betas=None):
         "us": round(t * 1e6, 2), "sites": V // 2,
         "model_eq1_eq2": perf_model.report(
             perf_model.kernel_model("ptc_even_fp16_products", "bf16", V // 2, betas=betas), t)}
+    # the same on the matrix cores (the path the mixed FGCR takes)
+    t = ev_time(lambda: wd.wd_ptc_apply_even(net, xe, "bf16", ye, "bf16", wd.WD_PTC_BF16_MFMA))
+    out["ptc_apply_even_bf16_mfma"] = {
+        "us": round(t * 1e6, 2), "sites": V // 2,
+        "model_eq1_eq2": perf_model.report(
+            perf_model.kernel_model("ptc_even_bf16_mfma", "bf16", V // 2, betas=betas), t)}
     net.close()
     g.close()
     return out

@@ -218,7 +218,9 @@ wd_status wd_dslash_slab(const wd_gauge *U, const void *in_slab, const void *fac
 
 /* --------------------------------------------------------------- solve -- */
 
-/* WD_SOLVER_CG        : FP64 even-odd CGLS (CG on the normal equations).
+/* WD_SOLVER_CG        : FP64 even-odd CGLS (CG on the normal equations of
+ *                       the Schur operator; the paper leaves the solver that
+ *                       applies Eq. 3 repeatedly unspecified, Sec. 5).
  * WD_SOLVER_DEFECT_CG : FP64 defect correction, inner even-odd CGLS in FP32
  *                       arithmetic with inner_prec storage.
  * WD_SOLVER_FGCR      : FP64 flexible GCR(fgcr_m) on the full D_W with
@@ -232,10 +234,14 @@ wd_status wd_dslash_slab(const wd_gauge *U, const void *in_slab, const void *fac
  *                       reductions; inner_prec WD_F32 or WD_BF16 stores the
  *                       residual and the directions (z_j, w_j) in that
  *                       precision, the inner solution stays FP32 (with
- *                       WD_BF16 and a BF16-activation network, the network
- *                       runs as wd_ptc_apply_even with WD_PTC_FP16_PRODUCTS);
- *                       falls back to FP64 CG when stalled or non-finite. */
-enum { WD_SOLVER_CG = 0, WD_SOLVER_DEFECT_CG = 1, WD_SOLVER_FGCR = 2, WD_SOLVER_DEFECT_FGCR = 3 };
+ *                       a BF16-activation network, the network runs as
+ *                       wd_ptc_apply_even with WD_PTC_BF16_MFMA);
+ *                       falls back to FP64 CG when stalled or non-finite.
+ * WD_SOLVER_CGLS_FULL : FP64 CGLS on the full-lattice D_W (D^dag D x =
+ *                       D^dag b on full fields, no even-odd reduction): the
+ *                       plain method, for comparison. */
+enum { WD_SOLVER_CG = 0, WD_SOLVER_DEFECT_CG = 1, WD_SOLVER_FGCR = 2, WD_SOLVER_DEFECT_FGCR = 3,
+       WD_SOLVER_CGLS_FULL = 4 };
 
 typedef struct wd_ptc wd_ptc;
 

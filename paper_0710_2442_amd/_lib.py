@@ -35,7 +35,7 @@ WD_TUNE_PRELOAD_LINKS = 512
 WD_TUNE_SPL_SHIFT = 10
 WD_PTC_FP16_PRODUCTS = 1
 WD_PTC_BF16_MFMA = 2
-WD_SOLVER_CG, WD_SOLVER_DEFECT_CG, WD_SOLVER_FGCR, WD_SOLVER_DEFECT_FGCR = 0, 1, 2, 3
+WD_SOLVER_CG, WD_SOLVER_DEFECT_CG, WD_SOLVER_FGCR, WD_SOLVER_DEFECT_FGCR, WD_SOLVER_CGLS_FULL = 0, 1, 2, 3, 4
 
 _vp = C.c_void_p
 _int4 = C.c_int * 4

@@ -67,7 +67,7 @@ wd_status solve_args(const wd_gauge *U, const void *b, void *x, double kappa, do
     memcpy(&prm, p, p->struct_size);
     prm.struct_size = sizeof(prm);
   }
-  if (prm.solver < WD_SOLVER_CG || prm.solver > WD_SOLVER_DEFECT_FGCR)
+  if (prm.solver < WD_SOLVER_CG || prm.solver > WD_SOLVER_CGLS_FULL)
     return set_error(WD_ERR_ARG, "solve: solver = %d", prm.solver);
   if (prm.inner_prec == WD_F64 && prm.solver == WD_SOLVER_DEFECT_CG)
     return set_error(WD_ERR_PREC, "solve: defect correction needs a reduced inner precision");

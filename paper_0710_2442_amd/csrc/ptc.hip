@@ -22,8 +22,8 @@
 // adjoint weights W'^{(hbar)}_{c c'} = (W^{(h)}_{c'c})^dag, hbar the adjoint hop
 // (T_{+mu}^dag = T_{-mu}), so it is a gather with no atomics.  The weight
 // gradient G^{(h)}_{c'c}[s',s] = sum_x sum_a g_{c'}(x)[s',a] conj((T_h psi_c)(x)[s,a])
-// is reduced wave -> block (fixed order) -> FP64 block partials -> one
-// final fixed-order pass.
+// is summed over a wave's sites in FP64 (through LDS), then over the block's
+// waves and the blocks in FP64, each in a fixed order.
 #include <math.h>
 #include <string.h>
 
@@ -91,6 +91,14 @@ __device__ __forceinline__ PtcSite ptc_site(const Geom &g, int i, int p) {
   return s;
 }
 
+// a[d] without dynamic register indexing (a rolled loop would spill it)
+__device__ __forceinline__ int pick8(const int (&a)[8], int d) {
+  int r = a[0];
+#pragma unroll
+  for (int j = 1; j < 8; ++j) r = (d == j) ? a[j] : r;
+  return r;
+}
+
 // v = T_h psi_c at site (p, i); psi channel base `chan` (full field).
 template <int PIN>
 __device__ __forceinline__ void transport(const KPtc &k, const PtcSite &s, int p, int i, int h, const char *chan,
@@ -104,7 +112,7 @@ __device__ __forceinline__ void transport(const KPtc &k, const PtcSite &s, int p
   }
   const int d = h - 1;
   cplx<RealOf<PIN>> t[12];
-  Spinor<PIN>::load(chan + (size_t)(1 - p) * k.in_half, s.nb[d], t);
+  Spinor<PIN>::load(chan + (size_t)(1 - p) * k.in_half, pick8(s.nb, d), t);
   cplx<float> u[6], r2[3];
   Link<float>::load(k.links32 + (size_t)p * k.link_par, d, i, u);
   rebuild_row2(u, r2);
@@ -129,7 +137,7 @@ __device__ __forceinline__ void load_source(const KPtc &k, const PtcSite &s, int
                                             cplx<float> (&v)[12]) {
   cplx<RealOf<PIN>> t[12];
   if (h == 0) Spinor<PIN>::load(chan + (size_t)p * k.in_half, i, t);
-  else Spinor<PIN>::load(chan + (size_t)(1 - p) * k.in_half, s.nb[h - 1], t);
+  else Spinor<PIN>::load(chan + (size_t)(1 - p) * k.in_half, pick8(s.nb, h - 1), t);
 #pragma unroll
   for (int c = 0; c < 12; ++c) v[c] = {(float)t[c].re, (float)t[c].im};
 }
@@ -232,10 +240,15 @@ __global__ __launch_bounds__(PTC_BS) void k_ptc_layer(KPtc k) {
 
 // Weight gradient of one layer: partials[block][f] (+)= block sum of the
 // per-site products; f indexes the layer's floats [h][c'][c][s'][s](re,im).
+// The products of one (h, c', c) chunk (32 floats per site) go through LDS:
+// each wave writes its 64 sites' rows, then lane f < 32 adds column f over
+// the 64 sites in FP64 (site order), and the block adds its 4 waves in FP64.
 template <int PIN, int CIN, int COUT>
 __global__ __launch_bounds__(PTC_BS) void k_ptc_wgrad(KPtc k) {
   constexpr int NF = 9 * COUT * CIN * 32;
-  __shared__ float red[PTC_BS / 64][NF];
+  constexpr int NW = PTC_BS / 64;
+  __shared__ float tile[NW][64][33];  // one chunk's products per wave (row padded: no bank conflicts)
+  __shared__ double wsum[NW][NF];     // the waves' site sums
   const int p = blockIdx.y;
   const int i = blockIdx.x * PTC_BS + threadIdx.x;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -248,6 +261,7 @@ __global__ __launch_bounds__(PTC_BS) void k_ptc_wgrad(KPtc k) {
     for (int co = 0; co < COUT; ++co)
       Spinor<WD_F32>::load(k.gy + co * k.gy_chan + (size_t)p * k.gy_half, i, gy[co]);
   }
+#pragma unroll
   for (int h = 0; h < 9; ++h) {
 #pragma unroll
     for (int ci = 0; ci < CIN; ++ci) {
@@ -260,6 +274,7 @@ __global__ __launch_bounds__(PTC_BS) void k_ptc_wgrad(KPtc k) {
       }
 #pragma unroll
       for (int co = 0; co < COUT; ++co) {
+        float row[32];
 #pragma unroll
         for (int sp = 0; sp < 4; ++sp) {
 #pragma unroll
@@ -274,19 +289,20 @@ __global__ __launch_bounds__(PTC_BS) void k_ptc_wgrad(KPtc k) {
                 acc.im += g.im * x.re - g.re * x.im;
               }
             }
-            float re = acc.re, im = acc.im;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-              re += __shfl_xor(re, off, 64);
-              im += __shfl_xor(im, off, 64);
-            }
-            if (lane == 0) {
-              const int f = (((h * COUT + co) * CIN + ci) * 16 + 4 * sp + t) * 2;
-              red[w][f] = re;
-              red[w][f + 1] = im;
-            }
+            row[2 * (4 * sp + t)] = acc.re;
+            row[2 * (4 * sp + t) + 1] = acc.im;
           }
         }
+#pragma unroll
+        for (int f = 0; f < 32; ++f) tile[w][lane][f] = row[f];
+        __builtin_amdgcn_wave_barrier();  // a wave's LDS accesses complete in order
+        if (lane < 32) {
+          double t = 0.0;
+#pragma unroll 4
+          for (int q = 0; q < 64; ++q) t += (double)tile[w][q][lane];
+          wsum[w][((h * COUT + co) * CIN + ci) * 32 + lane] = t;
+        }
+        __builtin_amdgcn_wave_barrier();
       }
     }
   }
@@ -295,7 +311,7 @@ __global__ __launch_bounds__(PTC_BS) void k_ptc_wgrad(KPtc k) {
   for (int f = threadIdx.x; f < NF; f += PTC_BS) {
     double t = 0.0;
 #pragma unroll
-    for (int q = 0; q < PTC_BS / 64; ++q) t += (double)red[q][f];
+    for (int q = 0; q < NW; ++q) t += wsum[q][f];
     double *dst = k.partials + blk * NF + f;
     *dst = k.accumulate ? (*dst + t) : t;
   }
@@ -568,14 +584,6 @@ __global__ __launch_bounds__(PTC_BS) void k_ptc_h_l1(KPtcH k) {
   }
 #pragma unroll
   for (int co = 0; co < 2; ++co) Spinor<WD_BF16>::store(k.out + co * k.out_chan + (size_t)p * k.out_half, i, acc[co]);
-}
-
-// a[d] without dynamic register indexing (a rolled loop would spill it)
-__device__ __forceinline__ int pick8(const int (&a)[8], int d) {
-  int r = a[0];
-#pragma unroll
-  for (int j = 1; j < 8; ++j) r = (d == j) ? a[j] : r;
-  return r;
 }
 
 // Layer 2 (2 -> 1 channels, even sites only; spins mixed before the
@@ -984,21 +992,28 @@ __global__ __launch_bounds__(256) void k_ptc_b_l2(KPtcB k) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) acc[t][a] = {X[a][2 * t], X[a][2 * t + 1]};
     }
-    // two steps in flight: step j + 2 is loaded once step j's operands are used
+    // two steps in flight: step j + 2 is loaded once step j's operands are
+    // used; the products of step j + 1 are started before step j's transports
+    // (the matrix cores and the vector units work side by side)
     RawB cur[2];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       load_spinor_b(k.y, y_off, nb[j], cur[j].q);
       load_link_b(lb, j + 4 * slot, i, cur[j].l);
     }
+    f4v M[3];  // the hidden channels are colour-major: packet a holds colour a's 4 spins
+#pragma unroll
+    for (int a = 0; a < 3; ++a) M[a] = mfma_bf16(A[0], __builtin_bit_cast(bf8v, cur[0].q[a]), (f4v){0.f, 0.f, 0.f, 0.f});
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      f4v M[3];  // the hidden channels are colour-major: packet a holds colour a's 4 spins
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-        M[a] = mfma_bf16(A[j], __builtin_bit_cast(bf8v, cur[j & 1].q[a]), (f4v){0.f, 0.f, 0.f, 0.f});
       LinkB L;
       link_forms(cur[j & 1].l, 0u, L);
+      f4v Mn[3];
+      if (j < 3) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+          Mn[a] = mfma_bf16(A[j + 1], __builtin_bit_cast(bf8v, cur[(j + 1) & 1].q[a]), (f4v){0.f, 0.f, 0.f, 0.f});
+      }
       if (j < 2) {
         load_spinor_b(k.y, y_off, nb[j + 2], cur[j].q);
         load_link_b(lb, j + 2 + 4 * slot, i, cur[j].l);
@@ -1009,9 +1024,10 @@ __global__ __launch_bounds__(256) void k_ptc_b_l2(KPtcB k) {
       for (int t = 0; t < 2; ++t)
         su3_b_acc(L, pk_bf(M[0][2 * t], M[0][2 * t + 1]) ^ ng, pk_bf(M[1][2 * t], M[1][2 * t + 1]) ^ ng,
                   pk_bf(M[2][2 * t], M[2][2 * t + 1]) ^ ng, acc[t]);
-      // one step at a time: the scheduler would otherwise start every step's
-      // products first and hold all their results (occupancy 3 instead of 4)
-      __builtin_amdgcn_sched_barrier(0);
+      if (j < 3) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) M[a] = Mn[a];
+      }
     }
     // the two slots: lanes l (slot 0) and l + 32 (slot 1) hold the same spins
 #pragma unroll

@@ -1,5 +1,7 @@
 // Solvers for D_W x = b built on the single-parity hop kernels.
 //
+// * FP64 full-lattice CGLS: CG on D^dag D x = D^dag b on full fields, each
+//   operator application one hop launch per parity (no even-odd reduction).
 // * FP64 even-odd CGLS: CG on the normal equations of the Schur operator
 //   M = 1 - k^2 H_eo H_oe (M^dag = 1 - k^2 H^dag_eo H^dag_oe), right-hand
 //   side b_e + k H_eo b_o, odd sites x_o = b_o + k H_oe x_e.  The paper
@@ -119,24 +121,50 @@ static wd_status hop(const wd_gauge *g, wd_prec prec, int nsys, const HopCall &c
 struct CglsVecs {
   wd_prec px, pv;
   int nsys;
-  void *x;            // parity-0 solution (px)
-  void *p, *s, *r, *q;  // parity-0 vectors (pv)
-  void *t;            // parity-1 temporary (pv)
+  void *x;            // parity-0 solution (px); the full solution when full
+  void *p, *s, *r, *q;  // parity-0 vectors (pv); full fields when full
+  void *t;            // parity-1 temporary (pv); unused when full
   size_t sx, sv;      // per-system strides of x and of the pv vectors
+  int full = 0;       // 1: the operator is D_W itself on full fields, not the Schur operator
 };
 
-// q = M p -> qq;  cg_update;  r = M^dag s -> rr[1-j];  p = r + beta p
+// out = A in (dagger: A^dag in), |out|^2 -> norm: A = M = 1 - k^2 H_eo H_oe on
+// even halves (two hops, the first into t), or A = D_W = 1 - k H on full
+// fields (one hop per parity, the norm summed over both).
+static wd_status apply_op(const wd_gauge *g, const CglsVecs &v, double kappa, const void *in, void *out, int dagger,
+                          double *norm, const int *skip, RedBuf red, hipStream_t st) {
+  if (!v.full) {
+    WD_TRY(hop(g, v.pv, v.nsys, HopCall{in, v.t, nullptr, 1.0, 1, dagger, nullptr, skip}, red, st));
+    return hop(g, v.pv, v.nsys, HopCall{v.t, out, in, -kappa * kappa, 0, dagger, norm, skip}, red, st);
+  }
+  const size_t hb = half_bytes(g->geom, v.pv);
+  for (int par = 0; par < 2; ++par) {
+    DslashArgs a;
+    a.in = (const char *)in + (1 - par) * hb;
+    a.out = (char *)out + par * hb;
+    a.X = (const char *)in + par * hb;
+    a.a = -kappa;
+    a.parity = par;
+    a.dagger = dagger;
+    a.norm_out = norm;
+    a.norm_accumulate = par;
+    a.skip = skip;
+    a.red = red;
+    WD_TRY(launch_dslash(g, v.pv, a, st));
+  }
+  return WD_OK;
+}
+
+// q = A p -> qq;  cg_update;  r = A^dag s -> rr[1-j];  p = r + beta p
 static wd_status cgls_iteration(const wd_gauge *g, const CglsVecs &v, double kappa, CgScalars *sc, int j,
                                 RedBuf red, hipStream_t st) {
-  const double mk2 = -kappa * kappa;
   const int *skip = &sc->done;
-  WD_TRY(hop(g, v.pv, v.nsys, HopCall{v.p, v.t, nullptr, 1.0, 1, 0, nullptr, skip}, red, st));
-  WD_TRY(hop(g, v.pv, v.nsys, HopCall{v.t, v.q, v.p, mk2, 0, 0, &sc->qq, skip}, red, st));
-  WD_TRY(blas_cg_update(g->geom, v.px, vref(v.x, 1, v.sx), v.pv, vref(v.p, 1, v.sv), vref(v.s, 1, v.sv),
-                        vref(v.q, 1, v.sv), sc, j, v.nsys, red, st));
-  WD_TRY(hop(g, v.pv, v.nsys, HopCall{v.s, v.t, nullptr, 1.0, 1, 1, nullptr, skip}, red, st));
-  WD_TRY(hop(g, v.pv, v.nsys, HopCall{v.t, v.r, v.s, mk2, 0, 1, &sc->rr[1 - j], skip}, red, st));
-  WD_TRY(blas_cg_pupdate(g->geom, v.pv, vref(v.r, 1, v.sv), vref(v.p, 1, v.sv), sc, j, v.nsys, st));
+  const int nh = v.full ? 2 : 1;
+  WD_TRY(apply_op(g, v, kappa, v.p, v.q, 0, &sc->qq, skip, red, st));
+  WD_TRY(blas_cg_update(g->geom, v.px, vref(v.x, nh, v.sx), v.pv, vref(v.p, nh, v.sv), vref(v.s, nh, v.sv),
+                        vref(v.q, nh, v.sv), sc, j, v.nsys, red, st));
+  WD_TRY(apply_op(g, v, kappa, v.s, v.r, 1, &sc->rr[1 - j], skip, red, st));
+  WD_TRY(blas_cg_pupdate(g->geom, v.pv, vref(v.r, nh, v.sv), vref(v.p, nh, v.sv), sc, j, v.nsys, st));
   return WD_OK;
 }
 
@@ -149,13 +177,12 @@ static wd_status cgls_run(const wd_gauge *g, Workspace *w, const CglsVecs &v, do
   CgScalars *sc = w->sc;
   for (int y = 0; y < v.nsys; ++y) w->sc_host[y] = sc_init[y];
   WD_HIP(hipMemcpyAsync(sc, w->sc_host, sizeof(CgScalars) * v.nsys, hipMemcpyHostToDevice, st));
+  const int nh = v.full ? 2 : 1;
   // x = 0
-  WD_TRY(blas_convert(g->geom, v.pv, vref(v.s, 1, v.sv), v.px, vref(v.x, 1, v.sx), 0.0, nullptr, v.nsys, st));
-  // r = M^dag s, rr[0] = |r|^2;  p = r
-  const double mk2 = -kappa * kappa;
-  WD_TRY(hop(g, v.pv, v.nsys, HopCall{v.s, v.t, nullptr, 1.0, 1, 1, nullptr, nullptr}, red, st));
-  WD_TRY(hop(g, v.pv, v.nsys, HopCall{v.t, v.r, v.s, mk2, 0, 1, &sc->rr[0], nullptr}, red, st));
-  WD_TRY(blas_convert(g->geom, v.pv, vref(v.r, 1, v.sv), v.pv, vref(v.p, 1, v.sv), 1.0, nullptr, v.nsys, st));
+  WD_TRY(blas_convert(g->geom, v.pv, vref(v.s, nh, v.sv), v.px, vref(v.x, nh, v.sx), 0.0, nullptr, v.nsys, st));
+  // r = A^dag s, rr[0] = |r|^2;  p = r
+  WD_TRY(apply_op(g, v, kappa, v.s, v.r, 1, &sc->rr[0], nullptr, red, st));
+  WD_TRY(blas_convert(g->geom, v.pv, vref(v.r, nh, v.sv), v.pv, vref(v.p, nh, v.sv), 1.0, nullptr, v.nsys, st));
   dslash_calls += 2;
 
   int max_iter = 0;
@@ -311,6 +338,58 @@ wd_status solve_cg64_on(wd_gauge *g, Workspace &ws, const void *b, void *x, doub
     WD_TRY(launch_dslash(g, WD_F64, a, st));
     info.dslash_calls += 1;
   }
+  WD_TRY(true_residual64(g, b, x, res, 1, 0, kappa, w->sc, red, st));
+  info.dslash_calls += 2;
+  WD_HIP(hipMemcpyAsync(w->sc_host, w->sc, sizeof(CgScalars), hipMemcpyDeviceToHost, st));
+  WD_HIP(hipStreamSynchronize(st));
+  info.true_rel_resid = sqrt(w->sc_host[0].rnorm2 / bb);
+  info.outer_iters = 1;
+  if (done == 2) return set_error(WD_NOT_CONVERGED, "CG breakdown after %d iterations", info.iters);
+  return info.true_rel_resid <= tol ? WD_OK : WD_NOT_CONVERGED;
+}
+
+// ------------------------------------------------------------ FP64 full CGLS
+// CG on the normal equations of D_W itself, D^dag D x = D^dag b, on full
+// fields: no even-odd reduction (the plain method the even-odd solver is
+// measured against).  Vectors: p s r q (full) + the true residual (full).
+wd_status solve_cgls_full64(wd_gauge *g, const void *b, void *x, double kappa, double tol,
+                            const wd_solve_params &prm, wd_solve_info &info, hipStream_t st) {
+  const Geom &G = g->geom;
+  const size_t fb = 2 * half_bytes(G, WD_F64);
+  WD_TRY(ws_reserve(g, 5 * fb, 1));
+  Workspace *w = g->ws;
+  RedBuf red = red_of(w);
+  char *v0 = (char *)w->base;
+  CglsVecs V;
+  V.px = V.pv = WD_F64;
+  V.nsys = 1;
+  V.full = 1;
+  V.x = x;
+  V.p = v0; V.s = v0 + fb; V.r = v0 + 2 * fb; V.q = v0 + 3 * fb; V.t = nullptr;
+  V.sx = V.sv = 0;
+  void *res = v0 + 4 * fb;
+  WD_TRY(blas_norm2(G, WD_F64, vref(b, 2), 1, red, w->dscal, st));
+  WD_HIP(hipMemcpyAsync(w->dscal_host, w->dscal, sizeof(double), hipMemcpyDeviceToHost, st));
+  WD_HIP(hipStreamSynchronize(st));
+  const double bb = w->dscal_host[0];
+  if (!(bb < 1e300)) return set_error(WD_ERR_NONFINITE, "wd_solve: |b|^2 is not finite");
+  if (bb == 0.0) {
+    WD_TRY(blas_convert(G, WD_F64, vref(b, 2), WD_F64, vref(x, 2), 0.0, nullptr, 1, st));
+    WD_HIP(hipStreamSynchronize(st));
+    info.true_rel_resid = 0.0;
+    return WD_OK;
+  }
+  // s = b (the residual of x = 0)
+  WD_TRY(blas_convert(G, WD_F64, vref(b, 2), WD_F64, vref(V.s, 2), 1.0, nullptr, 1, st));
+  CgScalars init{};
+  init.stop2 = tol * tol * bb;
+  init.max_iters = prm.max_iter;
+  init.bb = bb;
+  int calls = 0;
+  WD_TRY(cgls_run(g, w, V, kappa, &init, prm, st, calls));
+  info.dslash_calls += calls;  // hop launches (one per parity per operator application)
+  info.iters = w->sc_host[0].iters;
+  const int done = w->sc_host[0].done;
   WD_TRY(true_residual64(g, b, x, res, 1, 0, kappa, w->sc, red, st));
   info.dslash_calls += 2;
   WD_HIP(hipMemcpyAsync(w->sc_host, w->sc, sizeof(CgScalars), hipMemcpyDeviceToHost, st));
@@ -486,6 +565,8 @@ wd_status solve(wd_gauge *g, const void *b, void *x, double kappa, double tol, c
     rc = solve_fgcr(g, b, x, kappa, tol, prm, info, st);
   } else if (prm.solver == WD_SOLVER_DEFECT_FGCR) {
     rc = solve_fgcr_mixed(g, b, x, kappa, tol, prm, info, st);
+  } else if (prm.solver == WD_SOLVER_CGLS_FULL) {
+    rc = solve_cgls_full64(g, b, x, kappa, tol, prm, info, st);
   } else {
     return set_error(WD_ERR_ARG, "wd_solve: unknown solver %d", prm.solver);
   }

@@ -53,6 +53,9 @@ wd_status solve_args(const wd_gauge *U, const void *b, void *x, double kappa, do
 wd_status true_residual64(const wd_gauge *g, const void *b, const void *x, void *r, int nsys, size_t sys_stride,
                           double kappa, CgScalars *sc, RedBuf red, hipStream_t st);
 // FP64 even-odd CGLS on stream st (synchronises st)
+// FP64 CGLS on the full-lattice D_W (no even-odd reduction)
+wd_status solve_cgls_full64(wd_gauge *g, const void *b, void *x, double kappa, double tol,
+                            const wd_solve_params &prm, wd_solve_info &info, hipStream_t st);
 wd_status solve_cg64(wd_gauge *g, const void *b, void *x, double kappa, double tol, const wd_solve_params &prm,
                      wd_solve_info &info, hipStream_t st);
 

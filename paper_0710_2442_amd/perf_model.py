@@ -15,6 +15,8 @@ T_exe = max_i T_i (Eq. 2).  For MI355X the tasks are:
   T_VALU  vector ALU work, in lane fused multiply-adds (the fewest
           instructions the flops need; FP32 without packed math and FP64
           both issue 16 lanes per SIMD per clock on gfx950)
+  T_MFMA  matrix-core work, in flops at the dense BF16 peak (the network's
+          spin mixing)
 
 beta_HBM, beta_MALL and beta_L2 are measured by the library's probes:
 wd_micro_stream (HBM read/write mixes) and wd_micro_resident (reads served by
@@ -35,6 +37,7 @@ UNITS = {
     "l2_per_xcd": 4 * 2 ** 20,
     "mall": 256 * 2 ** 20,
     "hbm_peak": 8.0e12,
+    "mfma_bf16_peak": 2.5e15,  # dense BF16 matrix-core flops per second
 }
 
 # Throughputs measured on MI355X with the probes above (the benchmark measures
@@ -129,6 +132,26 @@ def ptc_even_counts():
     return {k: c1[k] + c2[k] for k in c1}
 
 
+def ptc_even_mfma_counts():
+    """The even-parity application on the matrix cores (WD_PTC_BF16_MFMA), per
+    site pair (one odd site of launch 1, one even site of launch 2), BF16
+    fields and links.  HBM: launch 1 reads the input once and the odd links
+    (8 x 24 B) and writes two hidden channels; launch 2 reads the hidden
+    channels and the input once, the even links, and writes the output (BF16).
+    L2: every neighbour spinor read (8 per site and channel).  VALU: the 16
+    transports (each 4 spins x 9 complex MACs = 72 two-product dot
+    instructions) and the third link rows (12 dot instructions each, 8 in
+    launch 1 and 16 in launch 2, where two lane groups rebuild each link).
+    MFMA: the spin mixing, 6 (launch 1) and 15 (launch 2) 16x16x32 products
+    per 16 sites, including the zero blocks of the A operands."""
+    sp = SPINOR_BYTES["bf16"]
+    lk = 8 * 24
+    hbm = (sp + lk + 2 * sp) + (2 * sp + sp + lk + sp)
+    l2 = (8 * sp + lk + 2 * sp) + (8 * 2 * sp + sp + lk + sp)
+    dots = 16 * 72 + (8 + 16) * 12
+    return {"hbm": hbm, "l2": l2, "lds": 0.0, "fma": dots, "mfma": (6 + 15) * 16 * 16 * 32 * 2 / 16}
+
+
 def batch_iteration_counts(prec):
     """One inner CG iteration of the batched solver, per even site: four hops
     in the storage precision and the BLAS (the CG update reads the FP32
@@ -156,6 +179,8 @@ def kernel_model(kernel, prec, units, traffic_ratio=1.0, betas=None):
         return predict(units, ptc_network_counts(), betas)
     if kernel == "ptc_even_fp16_products":
         return predict(units, ptc_even_counts(), betas)
+    if kernel == "ptc_even_bf16_mfma":
+        return predict(units, ptc_even_mfma_counts(), betas)
     if kernel == "batch8_inner_iteration":
         return predict(units, batch_iteration_counts(prec), betas, resident=True)
     if kernel == "cg_iteration":
@@ -185,9 +210,11 @@ def predict(units, counts, betas=None, hbm_beta="hbm_read", mall_bytes=0.0, resi
     t["T_L2"] = units * counts["l2"] / b["l2"]
     t["T_LDS"] = units * counts["lds"] / beta_lds()
     t["T_VALU"] = units * counts["fma"] / beta_valu()
-    t["T_exe"] = max(t[k] for k in ("T_HBM", "T_MALL", "T_L2", "T_LDS", "T_VALU"))
-    t["T_sum"] = sum(t[k] for k in ("T_HBM", "T_MALL", "T_L2", "T_LDS", "T_VALU"))
-    t["bound"] = max(("T_HBM", "T_MALL", "T_L2", "T_LDS", "T_VALU"), key=lambda k: t[k])
+    t["T_MFMA"] = units * counts.get("mfma", 0.0) / UNITS["mfma_bf16_peak"]
+    tasks = ("T_HBM", "T_MALL", "T_L2", "T_LDS", "T_VALU", "T_MFMA")
+    t["T_exe"] = max(t[k] for k in tasks)
+    t["T_sum"] = sum(t[k] for k in tasks)
+    t["bound"] = max(tasks, key=lambda k: t[k])
     return t
 
 

@@ -64,6 +64,7 @@ def trained_weights():
 
 C3_CASES = {
     "fp64_cg": dict(solver=wd.WD_SOLVER_CG),
+    "fp64_cgls_full_lattice": dict(solver=wd.WD_SOLVER_CGLS_FULL),
     "defect_f32": dict(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec="f32", inner_tol=1e-4),
     "defect_f16": dict(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec="f16", inner_tol=1e-2),
     "defect_bf16": dict(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec="bf16", inner_tol=1e-2),

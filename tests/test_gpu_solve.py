@@ -48,6 +48,29 @@ def test_fp64_cg_8x4_matches_oracle():
     assert abs(info["iters"] - it_o10) <= 3, (info["iters"], it_o10)
 
 
+@pytest.mark.parametrize("dims,use_graph", [((6, 4, 6, 10), 0), ((8, 8, 8, 8), 1)])
+def test_full_lattice_cgls_matches_oracle(dims, use_graph):
+    """CGLS on the full-lattice D_W (no even-odd reduction): the oracle's own
+    D_W judges the residual, the solution agrees with the oracle's full CGLS
+    (and with its even-odd solve), and the iteration count with the oracle's
+    full CGLS to within a few (the same recurrence in another summation order)."""
+    kappa = 0.12
+    U, b, x, rc, info = _solve(dims, kappa, 0.3, 11, solver=wd.WD_SOLVER_CGLS_FULL, use_graph=use_graph,
+                               check_every=4)
+    print("info", info, flush=True)
+    assert rc == 0
+    r_oracle = solvers.true_residual(U, b, x, kappa)
+    assert r_oracle <= TOL
+    assert abs(r_oracle - info["true_rel_resid"]) <= 1e-3 * TOL
+    xo, it_o, _ = solvers.solve_cgls_full(U, b, kappa, TOL)
+    assert abs(info["iters"] - it_o) <= 3, (info["iters"], it_o)
+    xe, _, _ = solvers.solve_eo_cgls(U, b, kappa, 1e-12)
+    assert rel_err(x, xe) <= 1e-7
+    # the full operator needs more iterations than the even-odd Schur system
+    _, _, x2, rc2, info2 = _solve(dims, kappa, 0.3, 11, solver=wd.WD_SOLVER_CG)
+    assert rc2 == 0 and info["iters"] > info2["iters"]
+
+
 @pytest.mark.parametrize("use_graph", [0, 1])
 def test_fp64_cg_graph_and_eager_agree(use_graph):
     dims, kappa = (6, 4, 6, 10), 0.124
