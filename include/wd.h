@@ -378,7 +378,8 @@ wd_status wd_ptc_train_step(wd_ptc *n, const void *r, const void *e, int B,
  * the register budget (occ 0: compiler's
  * choice; occ 4: at least 4 waves per SIMD), the output store policy
  * (WD_TUNE_CACHED_STORE set in occ: cached stores), link preloading
- * (WD_TUNE_PRELOAD_LINKS, not FP64), sites per lane along x4
+ * (WD_TUNE_PRELOAD_LINKS, not FP64), LDS staging of the block's input tile
+ * (WD_TUNE_STAGE_LDS, FP64 and FP32), sites per lane along x4
  * (WD_TUNE_SPL_SHIFT) and a cap on resident
  * blocks per CU (dynamic LDS in KiB << WD_TUNE_LDS_SHIFT).  Every candidate's output is
  * first compared byte for byte with the reference variant (256 threads,
@@ -430,10 +431,19 @@ enum { WD_TUNE_SPL_SHIFT = 10 };
 /* The dynamic LDS (KiB, 0..64) reserved per block, shifted into occ: it caps
  * the blocks resident on a CU and so the sites in flight per XCD. */
 enum { WD_TUNE_LDS_SHIFT = 16 };
+/* Bit of the occ value: LDS staging of neighbour spinors.  Each block first
+ * loads the input spinors of its own tile of sites into LDS with coalesced
+ * loads; its lanes then read their x1 and x2 neighbours from there when these
+ * lie in the tile (a tile of consecutive sites holds whole x1 rows), the rest
+ * from memory (Sec. 5's on-chip reuse of neighbour operands).  FP64 and FP32
+ * storage; one site per lane, no link preloading, no LDS cap.  Same bytes as
+ * every other variant. */
+enum { WD_TUNE_STAGE_LDS = 4096 };
 
 /* Set / read the hop variant used for precision prec.  occ: 0 or 4, or'ed
- * with WD_TUNE_CACHED_STORE, WD_TUNE_PRELOAD_LINKS (not FP64), (0, 1, 2) <<
- * WD_TUNE_SPL_SHIFT and (KiB of LDS << WD_TUNE_LDS_SHIFT).  WD_ERR_ARG if the variant does not fit the
+ * with WD_TUNE_CACHED_STORE, WD_TUNE_PRELOAD_LINKS (not FP64),
+ * WD_TUNE_STAGE_LDS (FP64, FP32), (0, 1, 2) << WD_TUNE_SPL_SHIFT and (KiB of
+ * LDS << WD_TUNE_LDS_SHIFT).  WD_ERR_ARG if the variant does not fit the
  * lattice (see wd_tune_dslash). */
 wd_status wd_set_dslash_variant(wd_gauge *g, wd_prec prec, int block, int groups,
                                 int occ);

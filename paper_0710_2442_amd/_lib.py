@@ -33,6 +33,7 @@ WD_ONE_PASS = 2
 WD_TUNE_CACHED_STORE = 256
 WD_TUNE_PRELOAD_LINKS = 512
 WD_TUNE_SPL_SHIFT = 10
+WD_TUNE_STAGE_LDS = 4096
 WD_PTC_FP16_PRODUCTS = 1
 WD_PTC_BF16_MFMA = 2
 WD_SOLVER_CG, WD_SOLVER_DEFECT_CG, WD_SOLVER_FGCR, WD_SOLVER_DEFECT_FGCR, WD_SOLVER_CGLS_FULL = 0, 1, 2, 3, 4

@@ -140,6 +140,7 @@ wd_status wd_gauge_create(const double *U_host, const int dims[4], int t_bc, wd_
     g->hop_lds[p] = 0;
     g->hop_pre[p] = 0;
     g->hop_spl[p] = 1;
+    g->hop_stage[p] = 0;
     g->mrhs_block[p] = (p == WD_F64) ? 16 : 128;
     g->mrhs_rpl[p] = 4;
     g->mrhs_groups[p] = dslash_variant_ok(g->geom, g->mrhs_block[p], 4) ? 4 : 0;
@@ -150,6 +151,9 @@ wd_status wd_gauge_create(const double *U_host, const int dims[4], int t_bc, wd_
   const size_t ubytes = V * 4 * 18 * sizeof(double);
   do {
     if ((rc = hip_check(hipGetDevice(&g->device), "hipGetDevice")) != WD_OK) break;
+    if ((rc = hip_check(hipDeviceGetAttribute(&g->lds_per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, g->device),
+                        "hipDeviceGetAttribute")) != WD_OK)
+      break;
     if ((rc = hip_check(hipStreamCreateWithFlags(&g->own_stream, hipStreamNonBlocking), "stream")) != WD_OK) break;
     if ((rc = hip_check(hipMalloc(&g->links64, link_bytes(g->geom, true)), "links64")) != WD_OK) break;
     if ((rc = hip_check(hipMalloc(&g->links32, link_bytes(g->geom, false)), "links32")) != WD_OK) break;

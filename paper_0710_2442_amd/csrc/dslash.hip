@@ -7,8 +7,9 @@
 // reconstructed 4-spinor.  Hop links are stored per output site (the
 // backward link U^dag_{x-mu,mu} is kept at x), so all 8 link loads are
 // aligned, coalesced, read-once streams; neighbour spinors are the only
-// gathered, reused data.  The epilogue fuses out = a*H in + X - Y and an
-// FP64 |out|^2 reduction.
+// gathered, reused data.  A tuning variant stages each block's input tile in
+// LDS for the x1 and x2 neighbours.  The epilogue fuses out = a*H in + X - Y
+// and an FP64 |out|^2 reduction.
 //
 // Flop count per output site: 1320 (Sec. 5), plus 8 x 42 for rebuilding the
 // third link rows.  Algorithmic bytes per output site: 8 x 12 link reals +
@@ -56,6 +57,59 @@ __device__ __forceinline__ void dslash_body(const KDslash &k) {
 WD_OCC_KERNEL(0, )
 WD_OCC_KERNEL(4, __attribute__((amdgpu_waves_per_eu(4))))
 
+// LDS staging of neighbour half-spinors (FP64, FP32 storage; one site per
+// lane): the block first loads the input spinors of its tile's own slots and
+// of the x1 rows just before and after the tile (coalesced), projects each
+// for the x1+-, x2+- hops and stores the four half-spinors in LDS; then each
+// lane takes its x1 and x2 neighbours' projections from there and the x3 and
+// x4 neighbours from memory.  The tile is k = blockDim.x / L1h whole rows of
+// one x3 plane (k | L2, k >= 2) or whole planes (see dslash_stage_ok).
+// Dynamic LDS: (blockDim.x + 2 L1h) * STAGE_STRIDE complex.
+template <int P, bool DAG, int EPI, bool NORM>
+__global__ __launch_bounds__(512) void k_dslash_stage(KDslash k) {
+  using T = RealOf<P>;
+  extern __shared__ __align__(16) char stage_lds[];
+  cplx<T> *lds = (cplx<T> *)stage_lds;
+  if (k.skip && *k.skip) return;
+  const int n = (int)blockDim.x, t = (int)threadIdx.x, l1h = k.g.L1h;
+  const int t0 = tile_of(k) * n;
+  // the rows around the tile, wrapping in its plane
+  const int r0 = t0 / l1h, r1 = r0 + n / l1h - 1;  // first and last row (row = x2 + L2 (x3 + L3 x4))
+  const int L2 = k.g.L[1];
+  const int lo = ((r0 % L2 == 0) ? r0 + L2 - 1 : r0 - 1) * l1h;
+  const int hi = ((r1 % L2 == L2 - 1) ? r1 - (L2 - 1) : r1 + 1) * l1h;
+  {
+    cplx<T> psi[12];
+    Spinor<P>::load(k.in, t0 + t, psi);
+    stage_store<T>(lds, t, psi);
+    if (t < 2 * l1h) {
+      Spinor<P>::load(k.in, (t < l1h) ? lo + t : hi + t - l1h, psi);
+      stage_store<T>(lds, n + t, psi);
+    }
+  }
+  __syncthreads();
+  const double nrm =
+      dslash_site<P, DAG, EPI, NORM, false, true>(k, t0 + t, Stage<T>{lds, t0, n, lo, hi, l1h});
+  if constexpr (NORM) {
+    double v[1] = {nrm};
+    block_sum_store<1>(v, k.partials, gridDim.x, blockIdx.x);
+  }
+}
+
+// A block size fits LDS staging when its tile is k >= 2 whole x1 rows of one
+// x3 plane (k | L2) or whole planes (L2 | k; then every x2 neighbour is in
+// the tile), and the tiles cover the slots exactly.
+size_t dslash_stage_lds_bytes(const Geom &G, int bs, wd_prec prec) {
+  return (size_t)(bs + 2 * G.L1h) * STAGE_STRIDE * (prec == WD_F64 ? 16 : 8);
+}
+
+bool dslash_stage_ok(const Geom &G, int bs) {
+  if (bs % G.L1h) return false;
+  const int rows = bs / G.L1h;
+  return rows >= 2 && (G.L[1] % rows == 0 || rows % G.L[1] == 0) && G.vpad == G.vh && G.vh % bs == 0 &&
+         2 * G.L1h <= bs;
+}
+
 // ------------------------------------------------------------ launchers
 static KDslash make_k(const wd_gauge *g, wd_prec prec, int parity) {
   KDslash k{};
@@ -73,6 +127,13 @@ static KDslash make_k(const wd_gauge *g, wd_prec prec, int parity) {
 // smaller set of neighbour spinors the L2 must hold for reuse.
 template <int P, bool DAG, int EPI, bool NORM>
 static void launch_t(const KDslash &k, unsigned nblk, unsigned bs, unsigned lds, hipStream_t st) {
+  if constexpr (P == WD_F64 || P == WD_F32) {
+    if (k.stage) {
+      const unsigned sb = (bs + 2 * (unsigned)k.g.L1h) * STAGE_STRIDE * (unsigned)sizeof(cplx<RealOf<P>>);
+      hipLaunchKernelGGL((k_dslash_stage<P, DAG, EPI, NORM>), dim3(nblk), dim3(bs), sb + lds, st, k);
+      return;
+    }
+  }
   if constexpr (P != WD_F64) {
     if (k.preload) {
       if (k.occ == 4) hipLaunchKernelGGL((k_dslash_o4<P, DAG, EPI, NORM, true>), dim3(nblk), dim3(bs), lds, st, k);
@@ -159,6 +220,10 @@ wd_status launch_dslash(const wd_gauge *g, wd_prec prec, const DslashArgs &a, hi
   k.occ = g->hop_occ[pi];
   k.nt_store = g->hop_ntst[pi];
   k.preload = (prec != WD_F64) ? g->hop_pre[pi] : 0;
+  k.stage = (prec == WD_F64 || prec == WD_F32) && spl == 1 && !k.preload && dslash_stage_ok(g->geom, bs) &&
+                    dslash_stage_lds_bytes(g->geom, bs, prec) + (size_t)g->hop_lds[pi] <= (size_t)g->lds_per_block
+                ? g->hop_stage[pi]
+                : 0;
   k.tiles_per_slice = (groups || spl > 1) ? (int)((long)g->geom.vh / g->geom.L[3] / bs) : 0;
   const unsigned nblk = (unsigned)((g->geom.vpad + bs - 1) / bs) / (unsigned)spl;
   const unsigned lds = (unsigned)g->hop_lds[pi];

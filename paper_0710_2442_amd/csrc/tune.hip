@@ -73,20 +73,23 @@ static void cache_append(const char *path, const std::string &key, int bs, int g
 // occ value: bits 0..7 register budget (0 or 4), WD_TUNE_CACHED_STORE,
 // WD_TUNE_PRELOAD_LINKS, log2 of the sites per lane at WD_TUNE_SPL_SHIFT and
 // the dynamic LDS per block in KiB at WD_TUNE_LDS_SHIFT (0..64)
-static wd_status decode_occ(int occ, int &o, int &nts, int &lkb, int &pre, int &spl) {
+static wd_status decode_occ(int occ, int &o, int &nts, int &lkb, int &pre, int &spl, int &stage) {
   o = occ & 0xff;
   nts = (occ & WD_TUNE_CACHED_STORE) ? 0 : 1;
   pre = (occ & WD_TUNE_PRELOAD_LINKS) ? 1 : 0;
+  stage = (occ & WD_TUNE_STAGE_LDS) ? 1 : 0;
   lkb = (occ >> WD_TUNE_LDS_SHIFT) & 0xff;
   const int sp = (occ >> WD_TUNE_SPL_SHIFT) & 3;
   spl = 1 << sp;
-  const int rest = occ & ~(0xff | WD_TUNE_CACHED_STORE | WD_TUNE_PRELOAD_LINKS | (3 << WD_TUNE_SPL_SHIFT) |
-                           (0xff << WD_TUNE_LDS_SHIFT));
+  const int rest = occ & ~(0xff | WD_TUNE_CACHED_STORE | WD_TUNE_PRELOAD_LINKS | WD_TUNE_STAGE_LDS |
+                           (3 << WD_TUNE_SPL_SHIFT) | (0xff << WD_TUNE_LDS_SHIFT));
   if ((o != 0 && o != 4) || rest || lkb > 64 || sp == 3)
     return set_error(WD_ERR_ARG,
                      "occ = 0x%x: register budget 0 or 4, | WD_TUNE_CACHED_STORE, | WD_TUNE_PRELOAD_LINKS, "
-                     "| (0, 1, 2) << WD_TUNE_SPL_SHIFT, | KiB << %d (<= 64)",
+                     "| WD_TUNE_STAGE_LDS, | (0, 1, 2) << WD_TUNE_SPL_SHIFT, | KiB << %d (<= 64)",
                      occ, WD_TUNE_LDS_SHIFT);
+  if (stage && (pre || spl != 1))
+    return set_error(WD_ERR_ARG, "occ = 0x%x: LDS staging takes one site per lane and no link preloading", occ);
   return WD_OK;
 }
 
@@ -98,8 +101,8 @@ static int log2i(int v) {
 
 static int encode_occ(const wd_gauge *g, wd_prec prec) {
   return g->hop_occ[prec] | (g->hop_ntst[prec] ? 0 : WD_TUNE_CACHED_STORE) |
-         (g->hop_pre[prec] ? WD_TUNE_PRELOAD_LINKS : 0) | (log2i(g->hop_spl[prec]) << WD_TUNE_SPL_SHIFT) |
-         ((g->hop_lds[prec] / 1024) << WD_TUNE_LDS_SHIFT);
+         (g->hop_pre[prec] ? WD_TUNE_PRELOAD_LINKS : 0) | (g->hop_stage[prec] ? WD_TUNE_STAGE_LDS : 0) |
+         (log2i(g->hop_spl[prec]) << WD_TUNE_SPL_SHIFT) | ((g->hop_lds[prec] / 1024) << WD_TUNE_LDS_SHIFT);
 }
 
 // *differ = 1 if the n 16-byte words of a and b are not all equal (vector
@@ -136,12 +139,20 @@ wd_status wd_set_dslash_variant(wd_gauge *g, wd_prec prec, int block, int groups
   if ((int)prec < 0 || (int)prec > 3) return set_error(WD_ERR_PREC, "prec = %d", (int)prec);
   if (block < 64 || !dslash_variant_ok(g->geom, block, groups))
     return set_error(WD_ERR_ARG, "variant (block %d, groups %d) does not fit this lattice", block, groups);
-  int o, nts, lkb, pre, spl;
-  WD_TRY(decode_occ(occ, o, nts, lkb, pre, spl));
+  int o, nts, lkb, pre, spl, stage;
+  WD_TRY(decode_occ(occ, o, nts, lkb, pre, spl, stage));
   if (!dslash_variant_ok(g->geom, block, groups, spl))
     return set_error(WD_ERR_ARG, "variant (block %d, groups %d, %d sites per lane) does not fit this lattice", block,
                      groups, spl);
   if (pre && prec == WD_F64) return set_error(WD_ERR_ARG, "link preloading is for FP32-arithmetic hops");
+  if (stage && prec != WD_F64 && prec != WD_F32)
+    return set_error(WD_ERR_ARG, "LDS staging is for FP64 and FP32 storage");
+  if (stage && !dslash_stage_ok(g->geom, block))
+    return set_error(WD_ERR_ARG, "LDS staging needs tiles of whole x1 rows of one plane, or whole planes (block %d)",
+                     block);
+  if (stage && dslash_stage_lds_bytes(g->geom, block, prec) + (size_t)lkb * 1024 > (size_t)g->lds_per_block)
+    return set_error(WD_ERR_ARG, "LDS staging of %d-site tiles needs %zu bytes of LDS, the device allows %d", block,
+                     dslash_stage_lds_bytes(g->geom, block, prec) + (size_t)lkb * 1024, g->lds_per_block);
   g->hop_block[prec] = block;
   g->hop_groups[prec] = groups;
   g->hop_occ[prec] = o;
@@ -149,6 +160,7 @@ wd_status wd_set_dslash_variant(wd_gauge *g, wd_prec prec, int block, int groups
   g->hop_lds[prec] = lkb * 1024;
   g->hop_pre[prec] = pre;
   g->hop_spl[prec] = spl;
+  g->hop_stage[prec] = stage;
   return WD_OK;
 }
 
@@ -235,18 +247,18 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
       if ((rc = hip_check(hipEventCreate(&e1), "event")) != WD_OK) break;
       const int save_b = g->hop_block[prec], save_g = g->hop_groups[prec], save_o = g->hop_occ[prec];
       const int save_n = g->hop_ntst[prec], save_l = g->hop_lds[prec], save_p = g->hop_pre[prec];
-      const int save_s = g->hop_spl[prec];
+      const int save_s = g->hop_spl[prec], save_t = g->hop_stage[prec];
       DslashArgs a;
       a.in = in; a.a = 1.0; a.parity = WD_EVEN;
       // reference variant
       g->hop_block[prec] = 256; g->hop_groups[prec] = 0; g->hop_occ[prec] = 0; g->hop_ntst[prec] = 1;
-      g->hop_lds[prec] = 0; g->hop_pre[prec] = 0; g->hop_spl[prec] = 1;
+      g->hop_lds[prec] = 0; g->hop_pre[prec] = 0; g->hop_spl[prec] = 1; g->hop_stage[prec] = 0;
       a.out = ref;
       if ((rc = launch_dslash(g, prec, a, st)) != WD_OK) break;
       const int blocks[] = {64, 128, 256, 512};
       const int grps[] = {0, 2, 4, 8, 16, -8, -16, -101, -102, -104, -108};
       best_us = 1e30;
-      int nbest_b = 256, nbest_g = 0, nbest_o = 0, nbest_n = 1, nbest_l = 0, nbest_p = 0, nbest_s = 1;
+      int nbest_b = 256, nbest_g = 0, nbest_o = 0, nbest_n = 1, nbest_l = 0, nbest_p = 0, nbest_s = 1, nbest_t = 0;
       size_t lds_max = 65536;
       {
         hipDeviceProp_t prop;
@@ -254,27 +266,32 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
       }
       // the candidates, listed first so that one loop runs them and a failure
       // ends the whole search
-      struct Cand { int spl, pre, lkb, nts, oc, b, gr; };
+      struct Cand { int spl, pre, lkb, nts, oc, b, gr, stg; };
       std::vector<Cand> cands;
-      for (int spl : {1, 2, 4})
-        for (int pre : {0, 1})
-          for (int lkb : {0, 24, 40, 60})
-            for (int nts : {1, 0})
-              for (int oc : {0, 4})
-                for (int b : blocks)
-                  for (int gr : grps) {
-                    if (!dslash_variant_ok(G, b, gr, spl)) continue;
-                    if (pre && prec == WD_F64) continue;
-                    if (oc == 4 && lkb != 0) continue;  // both only lower occupancy; keep the grid small
-                    if ((size_t)lkb * 1024 + 1024 > lds_max) continue;
-                    cands.push_back({spl, pre, lkb, nts, oc, b, gr});
-                  }
+      for (int stg : {0, 1})
+        for (int spl : {1, 2, 4})
+          for (int pre : {0, 1})
+            for (int lkb : {0, 24, 40, 60})
+              for (int nts : {1, 0})
+                for (int oc : {0, 4})
+                  for (int b : blocks)
+                    for (int gr : grps) {
+                      if (!dslash_variant_ok(G, b, gr, spl)) continue;
+                      if (pre && prec == WD_F64) continue;
+                      if (oc == 4 && lkb != 0) continue;  // both only lower occupancy; keep the grid small
+                      if ((size_t)lkb * 1024 + 1024 > lds_max) continue;
+                      if (stg && (spl != 1 || pre || lkb || (prec != WD_F64 && prec != WD_F32))) continue;
+                      if (stg && (!dslash_stage_ok(G, b) || dslash_stage_lds_bytes(G, b, prec) > (size_t)g->lds_per_block))
+                        continue;
+                      cands.push_back({spl, pre, lkb, nts, oc, b, gr, stg});
+                    }
       for (const Cand &c : cands) {
         const int spl = c.spl, pre = c.pre, lkb = c.lkb, nts = c.nts, oc = c.oc, b = c.b, gr = c.gr;
         g->hop_block[prec] = b; g->hop_groups[prec] = gr; g->hop_occ[prec] = oc; g->hop_ntst[prec] = nts;
         g->hop_lds[prec] = lkb * 1024;
         g->hop_pre[prec] = pre;
         g->hop_spl[prec] = spl;
+        g->hop_stage[prec] = c.stg;
         if ((rc = launch_pack_spinor(g, canon, in, WD_ODD, prec, st)) != WD_OK) break;
         a.out = cand;
         if ((rc = hip_check(hipMemsetAsync(cand, 0xff, hb, st), "memset")) != WD_OK) break;
@@ -297,11 +314,11 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
         (void)hipEventElapsedTime(&ms, e0, e1);
         const double us = 1e3 * ms / (2 * reps);
         if (getenv("WD_TUNE_VERBOSE"))
-          fprintf(stderr, "tune %s: block %d groups %d occ %d ntstore %d lds %dK preload %d spl %d: %.2f us\n",
-                  key.c_str(), b, gr, oc, nts, lkb, pre, spl, us);
+          fprintf(stderr, "tune %s: block %d groups %d occ %d ntstore %d lds %dK preload %d spl %d stage %d: %.2f us\n",
+                  key.c_str(), b, gr, oc, nts, lkb, pre, spl, c.stg, us);
         if (us < best_us) {
           best_us = us; nbest_b = b; nbest_g = gr; nbest_o = oc; nbest_n = nts; nbest_l = lkb; nbest_p = pre;
-          nbest_s = spl;
+          nbest_s = spl; nbest_t = c.stg;
         }
       }
       if (rc != WD_OK) {
@@ -310,6 +327,7 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
         g->hop_lds[prec] = save_l;
         g->hop_pre[prec] = save_p;
         g->hop_spl[prec] = save_s;
+        g->hop_stage[prec] = save_t;
         break;
       }
       g->hop_block[prec] = nbest_b;
@@ -319,6 +337,7 @@ wd_status wd_tune_dslash(wd_gauge *g, wd_prec prec, const char *cache_path, int 
       g->hop_lds[prec] = nbest_l * 1024;
       g->hop_pre[prec] = nbest_p;
       g->hop_spl[prec] = nbest_s;
+      g->hop_stage[prec] = nbest_t;
       bs = nbest_b; groups = nbest_g;
       occ = encode_occ(g, prec);
       if (cache_path) cache_append(cache_path, key, bs, groups, occ, best_us);

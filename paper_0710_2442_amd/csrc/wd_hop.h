@@ -28,6 +28,7 @@ struct KDslash {
   int occ;              // register-budget variant (0 or 4), host side only
   int nt_store;         // 1: streaming output stores; 0: cached stores
   int preload;          // 1: load all 8 links before the first hop (FP32 arithmetic only), host side
+  int stage;            // 1: stage the tile's input spinors in LDS (FP64, FP32), host side
   int spl;              // sites per lane along x4 (1, 2, 4): lane covers tiles t, t + T, ... of consecutive slices
 };
 
@@ -111,6 +112,10 @@ __device__ __forceinline__ void neighbours(const Geom &g, const Coords &c, int i
 // LDAG: multiply by u^dag instead of u (u holds the rows of the link that
 // the neighbour stores as its forward link).
 template <int P, int MU, int S, bool LDAG = false>
+__device__ __forceinline__ void hop_term_h(cplx<RealOf<P>> (&acc)[12], const cplx<RealOf<P>> (&h)[6],
+                                           const cplx<RealOf<P>> (&u)[6]);
+
+template <int P, int MU, int S, bool LDAG = false>
 __device__ __forceinline__ void hop_term_u(cplx<RealOf<P>> (&acc)[12], const char *in, int nb,
                                            const cplx<RealOf<P>> (&u)[6], RealOf<P> sign) {
   using T = RealOf<P>;
@@ -125,6 +130,25 @@ __device__ __forceinline__ void hop_term_u(cplx<RealOf<P>> (&acc)[12], const cha
     Spinor<P>::load(in, nb, psi);
     project<MU, S>(psi, h);
   }
+  hop_term_h<P, MU, S, LDAG>(acc, h, u);
+}
+
+// The same for a spatial hop (MU < 3) whose neighbour spinor is already in
+// registers (read from LDS by the staged kernel).
+template <int P, int MU, int S>
+__device__ __forceinline__ void hop_term_psi(cplx<RealOf<P>> (&acc)[12], const cplx<RealOf<P>> (&psi)[12],
+                                             const cplx<RealOf<P>> (&u)[6]) {
+  static_assert(MU < 3, "time hops read half spinors");
+  cplx<RealOf<P>> h[6];
+  project<MU, S>(psi, h);
+  hop_term_h<P, MU, S>(acc, h, u);
+}
+
+// acc += reconstruct(M h): the projected half spinor h times the link.
+template <int P, int MU, int S, bool LDAG>
+__device__ __forceinline__ void hop_term_h(cplx<RealOf<P>> (&acc)[12], const cplx<RealOf<P>> (&h)[6],
+                                           const cplx<RealOf<P>> (&u)[6]) {
+  using T = RealOf<P>;
   cplx<T> r2[3];
   rebuild_row2(u, r2);
   cplx<T> g[6];
@@ -216,17 +240,160 @@ __device__ __forceinline__ void hop_all_preload(const KDslash &k, int i, cplx<Re
   hop_all_u<P, DAG>(k.in, nb, u, sf, sb, acc);
 }
 
+// Neighbour half-spinors staged in LDS by a block whose tile is k whole x1
+// rows of one x3 plane (k | L2, k >= 2) or whole planes.  Slots 0 .. n-1 are
+// the tile's own input sites t0 .. t0+n-1, slots n .. n+L1h-1 the x1 row
+// before the tile's first row (its x2 - 1 neighbour row, wrapping in the
+// plane) starting at site lo, and slots n+L1h .. n+2 L1h-1 the row after its
+// last row starting at site hi: every x1 and x2 neighbour of the tile's
+// output sites is one of these.  Each slot holds the four projections
+// (1 + S gamma_mu) psi the x1 and x2 hops take (q = 2 mu + (S < 0)), six
+// complex numbers each; component c of projection q of slot s is at
+// lds[s * STAGE_STRIDE + 6 q + c] (one slot's 24 numbers together, so that a
+// lane's reads are one address plus constant offsets; the stride of 25
+// spreads consecutive slots over the LDS banks).
+constexpr int STAGE_STRIDE = 13;
+template <class T>
+struct Stage {
+  const cplx<T> *lds;
+  int t0, n, lo, hi, l1h;
+};
+
+// (every candidate computed, then selected: no branches, which would cut the
+// hop into basic blocks the scheduler cannot interleave)
+template <class T>
+__device__ __forceinline__ int stage_slot(const Stage<T> &sv, int nb) {
+  const int s = nb - sv.t0;
+  const int l = nb - sv.lo;
+  const int in_lo = sv.n + l;
+  const int in_hi = sv.n + sv.l1h + (nb - sv.hi);
+  int r = ((unsigned)l < (unsigned)sv.l1h) ? in_lo : in_hi;
+  r = ((unsigned)s < (unsigned)sv.n) ? s : r;
+  return r;
+}
+
+// psi into slot s.
+template <class T>
+__device__ __forceinline__ void stage_store(cplx<T> *lds, int s, const cplx<T> (&psi)[12]) {
+  cplx<T> *p = lds + (size_t)s * STAGE_STRIDE;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) p[c] = psi[c];
+}
+
+// A spatial hop (x1 or x2) with the neighbour's projection from the staged
+// tile: the same values as projected from memory, so the result is bitwise
+// that of hop_term.
+template <int P, int MU, int S>
+__device__ __forceinline__ void staged_term(cplx<RealOf<P>> (&acc)[12], const KDslash &k, const Stage<RealOf<P>> &sv,
+                                            int nb, int d, size_t i) {
+  using T = RealOf<P>;
+  static_assert(MU < 2, "x1 and x2 hops only");
+  cplx<T> u[6];
+  Link<T>::load(k.links, d, i, u);
+  cplx<T> psi[12];
+  const int slot = stage_slot(sv, nb);
+  const cplx<T> *p = sv.lds + (size_t)slot * STAGE_STRIDE;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) psi[c] = p[c];
+  hop_term_psi<P, MU, S>(acc, psi, u);
+  // FP64: one hop at a time (started all at once, the hops' operands exceed
+  // the registers); FP32 keeps the early loads, which hide more latency
+  if constexpr (P == WD_F64) __builtin_amdgcn_sched_barrier(0);
+}
+
+// The same with the link already in registers.
+template <int P, int MU, int S>
+__device__ __forceinline__ void staged_term_u(cplx<RealOf<P>> (&acc)[12], const Stage<RealOf<P>> &sv, int nb,
+                                              const cplx<RealOf<P>> (&u)[6]) {
+  using T = RealOf<P>;
+  cplx<T> psi[12];
+  const cplx<T> *p = sv.lds + (size_t)stage_slot(sv, nb) * STAGE_STRIDE;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) psi[c] = p[c];
+  hop_term_psi<P, MU, S>(acc, psi, u);
+}
+
+// A time hop on a half spinor h already loaded (load_half of the hop's
+// projector), the same arithmetic as hop_term_u's time path.
+template <int P, int S>
+__device__ __forceinline__ void hop_term_x4(cplx<RealOf<P>> (&acc)[12], const cplx<RealOf<P>> (&hraw)[6],
+                                            const cplx<RealOf<P>> (&u)[6], RealOf<P> sign) {
+  using T = RealOf<P>;
+  const T f = (T)2 * sign;
+  cplx<T> h[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) h[c] = f * hraw[c];
+  hop_term_h<P, 3, S>(acc, h, u);
+}
+
+// The 8 hops with the x1 and x2 neighbours read from the staged tile, the x3
+// and x4 neighbours from memory.  Same hop order and arithmetic as hop_all.
+// FP32: every link and every neighbour in memory is loaded before the first
+// hop (the loads in flight hide more latency); FP64 takes one hop at a time
+// (its operands would not fit the registers all at once).
+template <int P, bool DAG>
+__device__ __forceinline__ void hop_all_staged(const KDslash &k, int i, const Stage<RealOf<P>> &sv,
+                                               cplx<RealOf<P>> (&acc)[12]) {
+  using T = RealOf<P>;
+  const Coords c = coords_of(k.g, i, k.parity);
+  int nb[8];
+  neighbours(k.g, c, i, nb);
+  const T one = (T)1;
+  const T sf = (c.x4 == k.g.L[3] - 1) ? (T)k.g.tbc : one;
+  const T sb = (c.x4 == 0) ? (T)k.g.tbc : one;
+  constexpr int F = DAG ? -1 : 1;
+  constexpr int B = -F;
+  const char *L = k.links;
+  if constexpr (P == WD_F32) {
+    cplx<T> u[8][6];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) Link<T>::load(L, d, i, u[d]);
+    cplx<T> p2f[12], p2b[12], h3f[6], h3b[6];
+    Spinor<P>::load(k.in, nb[2], p2f);
+    Spinor<P>::load(k.in, nb[6], p2b);
+    Spinor<P>::template load_half<(F < 0)>(k.in, nb[3], h3f);
+    Spinor<P>::template load_half<(B < 0)>(k.in, nb[7], h3b);
+#pragma unroll
+    for (int c2 = 0; c2 < 12; ++c2) acc[c2] = {(T)0, (T)0};
+    staged_term_u<P, 0, F>(acc, sv, nb[0], u[0]);
+    staged_term_u<P, 1, F>(acc, sv, nb[1], u[1]);
+    hop_term_psi<P, 2, F>(acc, p2f, u[2]);
+    hop_term_x4<P, F>(acc, h3f, u[3], sf);
+    staged_term_u<P, 0, B>(acc, sv, nb[4], u[4]);
+    staged_term_u<P, 1, B>(acc, sv, nb[5], u[5]);
+    hop_term_psi<P, 2, B>(acc, p2b, u[6]);
+    hop_term_x4<P, B>(acc, h3b, u[7], sb);
+    return;
+  }
+#pragma unroll
+  for (int c2 = 0; c2 < 12; ++c2) acc[c2] = {(T)0, (T)0};
+  constexpr bool one_at_a_time = (P == WD_F64);
+  staged_term<P, 0, F>(acc, k, sv, nb[0], 0, i);
+  staged_term<P, 1, F>(acc, k, sv, nb[1], 1, i);
+  hop_term<P, 2, F>(acc, k.in, nb[2], L, 2, i, one);
+  if constexpr (one_at_a_time) __builtin_amdgcn_sched_barrier(0);
+  hop_term<P, 3, F>(acc, k.in, nb[3], L, 3, i, sf);
+  if constexpr (one_at_a_time) __builtin_amdgcn_sched_barrier(0);
+  staged_term<P, 0, B>(acc, k, sv, nb[4], 4, i);
+  staged_term<P, 1, B>(acc, k, sv, nb[5], 5, i);
+  hop_term<P, 2, B>(acc, k.in, nb[6], L, 6, i, one);
+  if constexpr (one_at_a_time) __builtin_amdgcn_sched_barrier(0);
+  hop_term<P, 3, B>(acc, k.in, nb[7], L, 7, i, sb);
+}
+
 // One output site i of the hop with the fused epilogue
 //   EPI 0: out = a H in;  1: out = X + a H in;  2: out = X - Y + a H in.
 // Padding slots (vh <= i < vpad) get zeros.  Returns |stored out|^2 (FP64)
-// when NORM, else 0.  PRE: links loaded up front (same arithmetic).
-template <int P, bool DAG, int EPI, bool NORM, bool PRE = false>
-__device__ __forceinline__ double dslash_site(const KDslash &k, int i) {
+// when NORM, else 0.  PRE: links loaded up front (same arithmetic).  STG:
+// x1, x2 neighbours from the block's staged input tile sv.
+template <int P, bool DAG, int EPI, bool NORM, bool PRE = false, bool STG = false>
+__device__ __forceinline__ double dslash_site(const KDslash &k, int i, Stage<RealOf<P>> sv = {}) {
   using T = RealOf<P>;
   double nrm = 0.0;
   if (i < k.g.vh) {
     cplx<T> acc[12];
     if constexpr (PRE) hop_all_preload<P, DAG>(k, i, acc);
+    else if constexpr (STG) hop_all_staged<P, DAG>(k, i, sv, acc);
     else hop_all<P, DAG>(k, i, acc);
     const T a = (T)k.a;
 #pragma unroll

@@ -66,6 +66,7 @@ struct wd_gauge {
   int tbc;
   wd_prec prec;
   int device;
+  int lds_per_block;       // the device's LDS limit per block (bytes)
   hipStream_t stream;      // caller's stream for dslash / pack
   hipStream_t own_stream;  // library stream for synchronous solves (default priority)
   void *links64;
@@ -80,6 +81,7 @@ struct wd_gauge {
   int hop_lds[4];          // per precision: dynamic LDS bytes per block (caps blocks per CU)
   int hop_pre[4];          // per precision: 1 = links loaded before the first hop (not FP64)
   int hop_spl[4];          // per precision: output sites per lane along x4 (1, 2, 4)
+  int hop_stage[4];        // per precision: 1 = x1/x2 neighbours from an LDS-staged tile (FP64, FP32)
   double *scratch_red;     // reduction partials / scalars for the BLAS entry points
   wd::Workspace *ws;
   void *fg_mem;            // mixed FGCR: vectors + scalars + partials, kept between solves
@@ -161,6 +163,10 @@ wd_status launch_dslash_slab(const wd_gauge *g, const void *in_slab, const void 
                              hipStream_t st);
 unsigned dslash_grid_blocks(const wd_gauge *g);
 bool dslash_variant_ok(const Geom &G, int bs, int groups, int spl = 1);
+// LDS staging of the input tile fits block size bs (whole x1 rows of one plane)
+bool dslash_stage_ok(const Geom &G, int bs);
+// its dynamic LDS per block (FP64 or FP32 storage)
+size_t dslash_stage_lds_bytes(const Geom &G, int bs, wd_prec prec);
 // box order (groups -(100 + n)) of the FP32-arithmetic multi-RHS hop fits the lattice
 bool mrhs_box_ok(const Geom &G, int bs, int groups);
 // grid.x of the multi-RHS hop (16 sites per block)

@@ -470,16 +470,19 @@ def test_full_size_plane_wave():
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_every_hop_variant_is_bitwise_identical(dims, prec):
     """Block size, block -> tile order (box orders -101 .. -108 included) and
-    the other schedule knobs (store policy, link preloading, sites per lane)
-    change only the schedule, never a result bit."""
+    the other schedule knobs (store policy, link preloading, sites per lane,
+    LDS staging of the input tile) change only the schedule, never a result
+    bit."""
     U, psi, _, _ = _inputs(dims, prec, seed=15)
     g = wd.Gauge(U, dims, -1, prec)
     src = to_field(g, psi, prec, wd.WD_ODD)
     ref = wd.wd_new_field(dims, prec, 1, wd.WD_EVEN)
     wd.wd_set_dslash_variant(g, prec, 256, 0, 0)
     wd.wd_dslash_ex(g, src, ref, 0.9, wd.WD_EVEN, prec)
+    ref_dag = wd.wd_new_field(dims, prec, 1, wd.WD_EVEN)
+    wd.wd_dslash_ex(g, src, ref_dag, 0.9, wd.WD_EVEN, prec, wd.WD_DAGGER)
     n = 0
-    for bs, groups, occ in [(b, gr, o) for b in (64, 128, 256, 512) for gr in (0, 2, 4, 8, 16, -2, -4, -8, -16, -101, -102, -104, -108) for o in (0, 4, 256, 512, 516, 1024, 2048, 1536, 2308)]:
+    for bs, groups, occ in [(b, gr, o) for b in (64, 128, 256, 512) for gr in (0, 2, 4, 8, 16, -2, -4, -8, -16, -101, -102, -104, -108) for o in (0, 4, 256, 512, 516, 1024, 2048, 1536, 2308, 4096, 4100, 4352)]:
             try:
                 wd.wd_set_dslash_variant(g, prec, bs, groups, occ)
             except wd.WdError:
@@ -489,8 +492,38 @@ def test_every_hop_variant_is_bitwise_identical(dims, prec):
             wd.wd_dslash_ex(g, src, out, 0.9, wd.WD_EVEN, prec)
             torch.cuda.synchronize()
             assert torch.equal(out, ref), (bs, groups, occ)
+            out.fill_(0xAB)
+            wd.wd_dslash_ex(g, src, out, 0.9, wd.WD_EVEN, prec, wd.WD_DAGGER)
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref_dag), ("dagger", bs, groups, occ)
             n += 1
     assert n >= 4
     b, gr, oc, us = wd.wd_tune_dslash(g, prec)
     assert wd.wd_get_dslash_variant(g, prec) == (b, gr, oc) and us > 0
+    g.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_lds_staged_hop_in_a_solve_is_bitwise_the_default(prec):
+    """The LDS-staged variant in every form a solver launches it (dagger,
+    xpay and xmy epilogues, fused norms, FP64 true residual): an FP64 CG solve
+    (prec f64) or an FP32 defect-correction solve (prec f32) gives the same
+    bytes and iteration counts with the staged hop as with the default one."""
+    dims, kappa = (8, 8, 8, 8), 0.124
+    U = syn.gauge_field(dims, 0.3, 1701)
+    b = syn.gaussian_spinor(dims, 1702)
+    g = wd.Gauge(U, dims, -1, "f64")
+    fb = to_field(g, b)
+    kw = dict(solver=wd.WD_SOLVER_CG) if prec == "f64" else dict(solver=wd.WD_SOLVER_DEFECT_CG, inner_prec="f32",
+                                                                   inner_tol=1e-4)
+    outs = []
+    for occ in (0, wd.WD_TUNE_STAGE_LDS):
+        for p in ("f64", "f32"):
+            wd.wd_set_dslash_variant(g, p, 128, 0, occ)
+        fx = wd.wd_new_field(dims, "f64")
+        rc, info = wd.wd_solve(g, fb, fx, kappa, 1e-10, wd.wd_solve_params_default(**kw))
+        assert rc == 0
+        outs.append((fx.clone(), info["iters"], info["outer_iters"]))
+    assert outs[0][1:] == outs[1][1:]
+    assert torch.equal(outs[0][0], outs[1][0])
     g.close()
