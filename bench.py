@@ -181,6 +181,9 @@ def use_tuned(wd, g, table, retune, precs=("f64", "f32", "f16", "bf16")):
     for prec in precs:
         b, gr, oc, us = wd.wd_tune_dslash(g, prec, table, force=retune)
         log(f"hop {prec} {g.dims}: block {b}, groups {gr}, occ {oc} ({us:.1f} us)")
+        if prec in ("f64", "f32"):
+            sl, ti, us = wd.wd_tune_dirac(g, prec, table, force=retune)
+            log(f"one-launch D_W {prec} {g.dims}: slices {sl}, tile {ti} ({us:.1f} us)")
 
 
 def solve_leg(wd, torch, syn, log_every=True, table=None, retune=False):
@@ -497,6 +500,18 @@ def kernels_leg(wd, torch, syn, U, psi, betas=None):
     t2 = ev_time(lambda: wd.wd_dslash(g, x, z, 0.124, DIMS, wd.WD_FULL))
     out["dirac_full_f64_two_pass"] = {"us": round(t2 * 1e6, 2), "GBps": round(V * 1344 / t2 / 1e9, 1),
                                       "bytes_per_site": 1344, "one_launch_speedup": round(t2 / t, 3)}
+    out["dirac_full_f64_one_launch"]["variant_slices_tile"] = list(wd.wd_get_dirac_variant(g, "f64"))
+    # the same in FP32 (FP32 links and spinors: 384 B per site in one launch, 672 B in two)
+    x32 = canon_to_field(g, psi, "f32")
+    z32 = wd.wd_new_field(DIMS, "f32")
+    t = ev_time(lambda: wd.wd_dslash_ex(g, x32, z32, 0.124, wd.WD_FULL, "f32", wd.WD_ONE_PASS))
+    t2 = ev_time(lambda: wd.wd_dslash_ex(g, x32, z32, 0.124, wd.WD_FULL, "f32", 0))
+    out["dirac_full_f32_one_launch"] = {"us": round(t * 1e6, 2), "GBps": round(V * 384 / t / 1e9, 1),
+                                        "frac_hbm": round(V * 384 / t / 1e9 / HBM_PEAK_GBS, 4),
+                                        "bytes_per_site": 384,
+                                        "variant_slices_tile": list(wd.wd_get_dirac_variant(g, "f32")),
+                                        "two_pass_us": round(t2 * 1e6, 2), "one_launch_speedup": round(t2 / t, 3)}
+    del x32, z32
     # one rank's share of an 8-way time decomposition (32^3 x 8 slab): the slab hop, with its two
     # time faces read from packed face buffers, and the face packing (what a GPU would send)
     R, nt = 8, DIMS[3] // 8

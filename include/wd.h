@@ -85,7 +85,14 @@ enum { WD_EVEN = 0, WD_ODD = 1, WD_FULL = 2 };
 /* flags of wd_dslash_ex.  WD_DAGGER: apply H^dag (D_W^dag).  WD_ONE_PASS
  * (parity WD_FULL only): compute D_W in one full-lattice launch that takes
  * each site's backward links from its neighbours' forward links (each link
- * is needed once per application) instead of two single-parity launches. */
+ * is needed once per application) instead of two single-parity launches.
+ * That launch marches along x4 through ranges of time slices, one spatial
+ * site per lane, the way Sec. 5 streams a lattice held in main memory a
+ * slice at a time: the time link, the backward time hop and the partial
+ * output pass from one slice to the next in registers, so each link and
+ * spinor is fetched once (768 B per site in FP64).  The full-lattice
+ * solvers (WD_SOLVER_CGLS_FULL, WD_SOLVER_FGCR) apply D_W this way when its
+ * work items fill the device. */
 enum { WD_DAGGER = 1, WD_ONE_PASS = 2 };
 
 typedef struct wd_gauge wd_gauge;
@@ -449,6 +456,28 @@ wd_status wd_set_dslash_variant(wd_gauge *g, wd_prec prec, int block, int groups
                                 int occ);
 wd_status wd_get_dslash_variant(const wd_gauge *g, wd_prec prec, int *block,
                                 int *groups, int *occ);
+
+/* Tune the one-launch D_W (WD_ONE_PASS; Eq. 3 on both checkerboards, the
+ * slice-marching scheme of Sec. 5) for precision prec: slices = time slices
+ * per range that one block marches through (8, 16, 32, ... up to L4) and
+ * tile = the shape of a block's 256 spatial sites (2: bricks of L1 x n2 x 2
+ * sites, where n2 = 128 / L1 divides L2 and L3 is even; 0: 256 consecutive
+ * sites, x1 fastest).  Every candidate is checked byte for byte against the
+ * current variant, then timed on a random field; the fastest is kept in the
+ * handle.  cache_path and force as for wd_tune_dslash (key
+ * "<arch>/dirac/p<prec>/<L1>x<L2>x<L3>x<L4>"; the cache line's "block" is
+ * 256, "groups" the tile and the third field "slices").  Outputs may be
+ * NULL.  Synchronous. */
+wd_status wd_tune_dirac(wd_gauge *g, wd_prec prec, const char *cache_path, int force,
+                        int *slices, int *tile, double *us);
+
+/* Set / read the one-launch D_W variant of precision prec: slices 0 (the
+ * default: the shortest range of 8, 16, ... for which every work item is
+ * resident on the device at once) or 1..L4, tile 0 or 2 as above.
+ * WD_ERR_ARG for a value outside these or a brick that does not fit the
+ * lattice.  The variants compute the same bytes; only the time differs. */
+wd_status wd_set_dirac_variant(wd_gauge *g, wd_prec prec, int slices, int tile);
+wd_status wd_get_dirac_variant(const wd_gauge *g, wd_prec prec, int *slices, int *tile);
 
 /* Solve one system on each of n lattices (uneven sizes allowed) together:
  * every kernel of the solve is one persistent launch over a work list of

@@ -111,6 +111,10 @@ _decl("wd_tune_dslash", C.c_int, [_vp, C.c_int, C.c_char_p, C.c_int, C.POINTER(C
 _decl("wd_tune_dslash_mrhs", C.c_int, [_vp, C.c_int, C.c_int, C.c_char_p, C.c_int, C.POINTER(C.c_int),
                                        C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double)])
 _decl("wd_set_dslash_variant", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int])
+_decl("wd_tune_dirac", C.c_int, [_vp, C.c_int, C.c_char_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                 C.POINTER(C.c_double)])
+_decl("wd_set_dirac_variant", C.c_int, [_vp, C.c_int, C.c_int, C.c_int])
+_decl("wd_get_dirac_variant", C.c_int, [_vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)])
 _decl("wd_get_dslash_variant", C.c_int, [_vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)])
 _decl("wd_set_dslash_mrhs_variant", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int])
 _decl("wd_get_dslash_mrhs_variant", C.c_int,
@@ -464,6 +468,28 @@ def wd_tune_dslash(g, prec, cache_path=None, force=False):
     _check(lib.wd_tune_dslash(g.handle, _prec(prec), cp, int(force), C.byref(b), C.byref(gr), C.byref(oc),
                               C.byref(us)), "wd_tune_dslash")
     return b.value, gr.value, oc.value, us.value
+
+
+def wd_tune_dirac(g, prec, cache_path=None, force=False):
+    """Tune the one-launch D_W (time slices per range, tile shape) or take the
+    variant from the JSON-lines cache; returns (slices, tile, microseconds per
+    launch)."""
+    g.sync_stream()
+    sl, ti, us = C.c_int(), C.c_int(), C.c_double()
+    cp = cache_path.encode() if cache_path else None
+    _check(lib.wd_tune_dirac(g.handle, _prec(prec), cp, int(force), C.byref(sl), C.byref(ti), C.byref(us)),
+           "wd_tune_dirac")
+    return sl.value, ti.value, us.value
+
+
+def wd_set_dirac_variant(g, prec, slices, tile):
+    _check(lib.wd_set_dirac_variant(g.handle, _prec(prec), int(slices), int(tile)), "wd_set_dirac_variant")
+
+
+def wd_get_dirac_variant(g, prec):
+    sl, ti = C.c_int(), C.c_int()
+    _check(lib.wd_get_dirac_variant(g.handle, _prec(prec), C.byref(sl), C.byref(ti)), "wd_get_dirac_variant")
+    return sl.value, ti.value
 
 
 def wd_set_dslash_variant(g, prec, block, groups, occ=0):

@@ -154,6 +154,9 @@ wd_status wd_gauge_create(const double *U_host, const int dims[4], int t_bc, wd_
     if ((rc = hip_check(hipDeviceGetAttribute(&g->lds_per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, g->device),
                         "hipDeviceGetAttribute")) != WD_OK)
       break;
+    if ((rc = hip_check(hipDeviceGetAttribute(&g->n_cu, hipDeviceAttributeMultiprocessorCount, g->device),
+                        "hipDeviceGetAttribute")) != WD_OK)
+      break;
     if ((rc = hip_check(hipStreamCreateWithFlags(&g->own_stream, hipStreamNonBlocking), "stream")) != WD_OK) break;
     if ((rc = hip_check(hipMalloc(&g->links64, link_bytes(g->geom, true)), "links64")) != WD_OK) break;
     if ((rc = hip_check(hipMalloc(&g->links32, link_bytes(g->geom, false)), "links32")) != WD_OK) break;
@@ -163,6 +166,7 @@ wd_status wd_gauge_create(const double *U_host, const int dims[4], int t_bc, wd_
     if ((rc = hip_check(hipMemcpyAsync(canon, U_host, ubytes, hipMemcpyHostToDevice, g->own_stream), "upload")) !=
         WD_OK)
       break;
+    if ((rc = dirac_init(g)) != WD_OK) break;
     if ((rc = launch_pack_gauge(g, canon, g->own_stream)) != WD_OK) break;
     rc = hip_check(hipStreamSynchronize(g->own_stream), "pack gauge");
   } while (0);

@@ -1,32 +1,58 @@
 // Full-lattice Wilson-Dirac operator (Eq. 3 on both checkerboards) in one
-// launch, so that each link is fetched from HBM once per application.
+// launch, marching along x4 the way the paper streams a lattice that lives
+// in main memory through on-chip storage a time slice at a time (Sec. 5).
 //
-// A site x of parity p takes its forward links U_{x,mu} from the hop-link
-// array of parity p (directions 0..3) and its backward links from the
-// forward links of its neighbours x - mu, i.e. the hop-link array of parity
-// 1 - p at the neighbour's index, applied as U^dag.  Those are the same bytes
-// that the neighbour, processed in the same launch, reads as its own forward
-// links; the block order pairs the even and odd tiles of a region on the
-// same XCD so the second read is an L2 hit.  Per site the method then moves
-// 4 x 12 link reals + 24 input reals + 24 output reals (96 reals: 768 B in
-// FP64), against 2 x 144 reals for two single-parity launches.
+// Every site's forward links serve two hops: U_{x,mu} for the forward hop of
+// x and U^dag_{x,mu} for the backward hop of x + mu.  So do the spinors: a
+// spinor psi_y is read by y's eight neighbours and, as X = psi for D_W, by
+// y itself.  A lane owns one spatial site (x1, x2, x3) and walks a range of
+// time slices; a block owns a tile of 256 spatial sites (a brick of whole x1
+// rows, n2 rows deep in x2 and 2 planes in x3, where that fits the lattice,
+// else 256 consecutive sites) and the same range.  At step k the lane
+//   1. loads its own spinor psi(x, k), whose half kept by the forward time
+//      projector finishes out(x, k-1) with the link U_{(x,k-1),4} carried from
+//      the step before (then out(x, k-1) is stored);
+//   2. loads its own time link U_{(x,k),4} and forms, from the other half of
+//      psi(x, k), the backward time hop that out(x, k+1) receives (carried);
+//   3. adds to that carried term the six spatial hops of (x, k): its own
+//      spatial links, the neighbours' forward links as U^dag, and the
+//      neighbours' spinors of slice k, all read in the same step by the
+//      lanes that own them, so every byte of slice k is fetched from HBM
+//      once and re-read from L1 or L2 within the step;
+//   the partial output starts from the epilogue terms X - Y (taken before
+//   the hops, so the own spinor is dead early) and every hop adds a times
+//   its term.
+// Across steps only three small objects move, in registers: the partial
+// output (12 complex), the time link (6 complex) and the backward time term
+// (6 complex).  The time neighbours, a whole slice of traffic apart in
+// memory order, are therefore never fetched twice.  A range boundary costs
+// one extra time link and half spinor on each side (per lane and range).
 //
-// Epilogue as in the single-parity hop: EPI 1 out = X + a H in,
-// EPI 2 out = X - Y + a H in (full fields), with an optional FP64 |out|^2.
+// Per site the launch moves 4 x 12 link reals + 24 input reals + 24 output
+// reals (96 reals: 768 B in FP64), against 2 x 144 reals for two
+// single-parity launches.
 //
-// Measured on MI355X at 32^3x64 in FP64: the launch fetches ~3.5 GB, not
-// 1.2 GB, because a neighbour's forward link does not stay in L2 until the
-// backward hop needs it (time neighbours are a whole slice, ~19 MB of
-// traffic, apart, and cached link loads also push out the spinors), so it
-// runs about as fast as two tuned single-parity launches.  It is available
-// through WD_ONE_PASS; the solvers keep the single-parity launches.
+// Blocks go round robin to the 8 XCDs.  Work items (range, tile) are
+// numbered range-major and XCD x takes the x-th contiguous eighth of them,
+// so the tiles that march a range side by side share one L2 and their
+// x2 / x3 halo reads hit there.  The range length and the tile shape are a
+// tuned variant (wd_tune_dirac); by default the ranges are as short as lets
+// every work item be resident at once.
+//
+// Epilogue as in the single-parity hop: EPI 1 out = X + a H in, EPI 2
+// out = X - Y + a H in (full fields), with an optional FP64 |out|^2.  XIN:
+// X is the input field itself (D_W = 1 - kappa H), taken from the spinor
+// already in registers.
+#include <algorithm>
+
+#include "wd_blas.h"
 #include "wd_hop.h"
 
 namespace wd {
 
 namespace {
 
-constexpr int DR_BS = 64;
+constexpr int DM_BS = 256;
 
 struct KDirac {
   Geom g;
@@ -37,89 +63,252 @@ struct KDirac {
   const char *links[2];  // hop-link arrays of output parity 0 and 1
   size_t half;           // bytes per half field
   double a;
-  double *norm_out;
-  int norm_accumulate;
   double *partials;
-  int ntiles;            // tiles of DR_BS sites per parity
+  const int *skip;  // device flag: nothing to do when set
+  int nsp;    // sites per time slice (L1 L2 L3)
+  int nt;     // tiles of DM_BS spatial sites per slice
+  int S;      // time slices per range
+  int items;  // nt * number of ranges
+  int per;    // work items per XCD
+  int npad;   // padding slots per half field (zeroed)
+  int n2;     // brick tiles: x2 rows per tile (0: tiles of consecutive sites)
+  int n3;     // brick tiles: x3 planes per tile
 };
 
-// Block b: parity (b / 8) % 2, tile (b / 16) * 8 + b % 8.  Blocks go round
-// robin to the 8 XCDs, so the even and the odd tile t of a region both run
-// on XCD t % 8, as do their x3 (+-8 tiles) and x4 neighbours.
-template <int P, bool DAG, int EPI, bool NORM>
-__global__ __launch_bounds__(DR_BS) void k_dirac(KDirac k) {
+// What a lane carries from one step to the next.
+template <int P>
+struct MarchCarry {
+  cplx<RealOf<P>> acc[12];  // X + a (spatial + backward time hops) - Y of out(x, k)
+  cplx<RealOf<P>> u4[6];    // U_{(x,k),4}: rows 0, 1
+  cplx<RealOf<P>> gb[6];    // a U^dag_{(x,k),4} (projected psi(x,k)): the backward time hop of out(x, k+1)
+};
+
+// Lane constants: spatial neighbour offsets (checkerboard index deltas, the
+// same on every slice), index and parity of the lane's site at x4 = 0.
+struct MarchLane {
+  int dn[6];  // x1+, x2+, x3+, x1-, x2-, x3-
+  int i0;
+  int par0;
+};
+
+__device__ __forceinline__ MarchLane march_lane(const Geom &g, int s) {
+  MarchLane m;
+  const int L1 = g.L[0], L2 = g.L[1], L3 = g.L[2];
+  const int x1 = s % L1, r3 = s / L1, x2 = r3 % L2, x3 = r3 / L2;
+  const int xp1 = (x1 + 1 == L1) ? 0 : x1 + 1, xm1 = (x1 == 0) ? L1 - 1 : x1 - 1;
+  m.dn[0] = (xp1 >> 1) - (x1 >> 1);
+  m.dn[3] = (xm1 >> 1) - (x1 >> 1);
+  m.dn[1] = (x2 == L2 - 1) ? -(L2 - 1) * g.s2 : g.s2;
+  m.dn[4] = (x2 == 0) ? (L2 - 1) * g.s2 : -g.s2;
+  m.dn[2] = (x3 == L3 - 1) ? -(L3 - 1) * g.s3 : g.s3;
+  m.dn[5] = (x3 == 0) ? (L3 - 1) * g.s3 : -g.s3;
+  m.i0 = (x1 >> 1) + g.s2 * x2 + g.s3 * x3;
+  m.par0 = (x1 + x2 + x3) & 1;
+  return m;
+}
+
+// gb = U^dag (f h) for the backward time hop (projector sign B): h is the
+// half of psi that (1 + B gamma_4) keeps, f = 2 a times the boundary factor.
+template <int P, int B>
+__device__ __forceinline__ void time_back(const cplx<RealOf<P>> (&u)[6], const cplx<RealOf<P>> (&half)[6],
+                                          RealOf<P> f, cplx<RealOf<P>> (&gb)[6]) {
   using T = RealOf<P>;
-  const int b = (int)blockIdx.x;
-  const int p = (b >> 3) & 1;
-  const int tile = ((b >> 4) << 3) | (b & 7);
-  const int i = tile * DR_BS + (int)threadIdx.x;
+  cplx<T> r2[3];
+  rebuild_row2(u, r2);
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    cplx<T> v[3] = {f * half[3 * a], f * half[3 * a + 1], f * half[3 * a + 2]};
+    cplx<T> y[3];
+    su3_mul_dag(u, r2, v, y);
+    gb[3 * a] = y[0];
+    gb[3 * a + 1] = y[1];
+    gb[3 * a + 2] = y[2];
+  }
+}
+
+// Finishes out(x, k-1) = acc + U (f h) (forward time hop, sign F; h the half
+// of psi(x, k) that the projector keeps, f = 2 a times the boundary factor)
+// and stores it; returns its |out|^2 when NORM.
+template <int P, int F, bool NORM>
+__device__ __forceinline__ double time_fwd_store(const KDirac &k, cplx<RealOf<P>> (&acc)[12],
+                                                 const cplx<RealOf<P>> (&u)[6], const cplx<RealOf<P>> (&half)[6],
+                                                 RealOf<P> f, int p, size_t i) {
+  using T = RealOf<P>;
+  cplx<T> r2[3];
+  rebuild_row2(u, r2);
+  constexpr int o = F > 0 ? 0 : 6;  // the projector (1 + F gamma_4) keeps the upper (F > 0) or lower rows
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    cplx<T> v[3] = {f * half[3 * h], f * half[3 * h + 1], f * half[3 * h + 2]};
+    cplx<T> y[3];
+    su3_mul(u, r2, v, y);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[o + 3 * h + c] = acc[o + 3 * h + c] + y[c];
+  }
+  char *out = k.out + (size_t)p * k.half;
+  Spinor<P>::store(out, i, acc);
   double nrm = 0.0;
-  if (tile < k.ntiles && i < k.g.vpad) {
-    const size_t own = (size_t)p * k.half;
-    char *out = k.out + own;
-    if (i < k.g.vh) {
-      const Coords c = coords_of(k.g, i, p);
-      int nb[8];
-      neighbours(k.g, c, i, nb);
-      const T one = (T)1;
-      const T sf = (c.x4 == k.g.L[3] - 1) ? (T)k.g.tbc : one;
-      const T sb = (c.x4 == 0) ? (T)k.g.tbc : one;
-      constexpr int F = DAG ? -1 : 1;
-      constexpr int B = -F;
-      const char *in = k.in + (size_t)(1 - p) * k.half;
-      const char *Lo = k.links[p], *Ln = k.links[1 - p];
-      cplx<T> acc[12];
+  if constexpr (NORM) {
+    cplx<T> st[12];
+    if constexpr (P == WD_F64 || P == WD_F32) {
 #pragma unroll
-      for (int q = 0; q < 12; ++q) acc[q] = {(T)0, (T)0};
-      cplx<T> u[6];
-      Link<T>::template load<false>(Lo, 0, i, u);
-      hop_term_u<P, 0, F>(acc, in, nb[0], u, one);
-      Link<T>::template load<false>(Lo, 1, i, u);
-      hop_term_u<P, 1, F>(acc, in, nb[1], u, one);
-      Link<T>::template load<false>(Lo, 2, i, u);
-      hop_term_u<P, 2, F>(acc, in, nb[2], u, one);
-      Link<T>::template load<false>(Lo, 3, i, u);
-      hop_term_u<P, 3, F>(acc, in, nb[3], u, sf);
-      Link<T>::template load<false>(Ln, 0, nb[4], u);
-      hop_term_u<P, 0, B, true>(acc, in, nb[4], u, one);
-      Link<T>::template load<false>(Ln, 1, nb[5], u);
-      hop_term_u<P, 1, B, true>(acc, in, nb[5], u, one);
-      Link<T>::template load<false>(Ln, 2, nb[6], u);
-      hop_term_u<P, 2, B, true>(acc, in, nb[6], u, one);
-      Link<T>::template load<false>(Ln, 3, nb[7], u);
-      hop_term_u<P, 3, B, true>(acc, in, nb[7], u, sb);
-      const T a = (T)k.a;
-#pragma unroll
-      for (int q = 0; q < 12; ++q) acc[q] = a * acc[q];
-      if constexpr (EPI >= 1) {
-        cplx<T> x[12];
-        Spinor<P>::load(k.X + own, i, x);
-#pragma unroll
-        for (int q = 0; q < 12; ++q) acc[q] = acc[q] + x[q];
-      }
-      if constexpr (EPI == 2) {
-        cplx<T> y[12];
-        Spinor<P>::load(k.Y + own, i, y);
-#pragma unroll
-        for (int q = 0; q < 12; ++q) acc[q] = acc[q] - y[q];
-      }
-      Spinor<P>::store(out, i, acc);
-      if constexpr (NORM) {
-        cplx<T> st[12];
-        if constexpr (P == WD_F64 || P == WD_F32) {
-#pragma unroll
-          for (int q = 0; q < 12; ++q) st[q] = acc[q];
-        } else {
-          Spinor<P>::load(out, i, st);
-        }
-#pragma unroll
-        for (int q = 0; q < 12; ++q) nrm += (double)st[q].re * st[q].re + (double)st[q].im * st[q].im;
-      }
+      for (int q = 0; q < 12; ++q) st[q] = acc[q];
     } else {
+      Spinor<P>::load(out, i, st);
+    }
+#pragma unroll
+    for (int q = 0; q < 12; ++q) nrm += (double)st[q].re * st[q].re + (double)st[q].im * st[q].im;
+  }
+  return nrm;
+}
+
+// acc += a M (1 + S gamma_MU) psi_nb for a spatial hop: the projected half
+// spinor is scaled by a before the link multiply (LDAG: M = u^dag).
+template <int P, int MU, int S, bool LDAG>
+__device__ __forceinline__ void hop_scaled(cplx<RealOf<P>> (&acc)[12], const char *in, int nb,
+                                           const cplx<RealOf<P>> (&u)[6], RealOf<P> a) {
+  using T = RealOf<P>;
+  cplx<T> psi[12], h[6];
+  Spinor<P>::load(in, nb, psi);
+  project<MU, S>(psi, h);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) h[c] = a * h[c];
+  hop_term_h<P, MU, S, LDAG>(acc, h, u);
+}
+
+// One step on slice t: finish out(x, t-1) (FIN), then build the carry for
+// out(x, t) and the backward time hop of out(x, t+1).
+template <int P, bool DAG, int EPI, bool XIN, bool NORM, bool FIN>
+__device__ __forceinline__ double march_step(const KDirac &k, const MarchLane &m, int t, MarchCarry<P> &c) {
+  using T = RealOf<P>;
+  constexpr int F = DAG ? -1 : 1;
+  constexpr int B = -F;
+  const Geom &g = k.g;
+  const int L4 = g.L[3];
+  const int p = (m.par0 + t) & 1;
+  const size_t i = (size_t)m.i0 + (size_t)t * g.s4;
+  cplx<T> psi[12];
+  Spinor<P>::load(k.in + (size_t)p * k.half, i, psi);
+  double nrm = 0.0;
+  const T one = (T)1;
+  if constexpr (FIN) {
+    cplx<T> h[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) h[q] = psi[(F > 0 ? 0 : 6) + q];
+    const T f = (T)2 * ((t - 1 == L4 - 1) ? (T)g.tbc : one) * (T)k.a;
+    nrm = time_fwd_store<P, F, NORM>(k, c.acc, c.u4, h, f, 1 - p, i - g.s4);
+  }
+  // backward time hop received by out(x, t+1), from U_{(x,t),4}
+  cplx<T> gb_next[6];
+  Link<T>::template load<true>(k.links[p], 3, i, c.u4);
+  {
+    cplx<T> h[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) h[q] = psi[(B > 0 ? 0 : 6) + q];
+    const T f = (T)2 * ((t == L4 - 1) ? (T)g.tbc : one) * (T)k.a;
+    time_back<P, B>(c.u4, h, f, gb_next);
+  }
+  // out(x, t) starts from the epilogue terms X - Y, so that the own spinor
+  // is dead before the spatial hops; each hop then adds a times its term
+  // (the projected half spinor is scaled by a before the link multiply)
+  cplx<T> acc[12];
+  if constexpr (XIN) {
+#pragma unroll
+    for (int q = 0; q < 12; ++q) acc[q] = psi[q];
+  } else if constexpr (EPI >= 1) {
+    Spinor<P>::load(k.X + (size_t)p * k.half, i, acc);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 12; ++q) acc[q] = {(T)0, (T)0};
+  }
+  if constexpr (EPI == 2) {
+    cplx<T> y[12];
+    Spinor<P>::load(k.Y + (size_t)p * k.half, i, y);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) acc[q] = acc[q] - y[q];
+  }
+  reconstruct_add<3, B>(acc, c.gb);  // the backward time hop, formed one step earlier
+  const T a = (T)k.a;
+  const char *inn = k.in + (size_t)(1 - p) * k.half;
+  const char *Lo = k.links[p], *Ln = k.links[1 - p];
+  cplx<T> u[6];
+  Link<T>::template load<false>(Lo, 0, i, u);
+  hop_scaled<P, 0, F, false>(acc, inn, (int)i + m.dn[0], u, a);
+  Link<T>::template load<false>(Lo, 1, i, u);
+  hop_scaled<P, 1, F, false>(acc, inn, (int)i + m.dn[1], u, a);
+  Link<T>::template load<false>(Lo, 2, i, u);
+  hop_scaled<P, 2, F, false>(acc, inn, (int)i + m.dn[2], u, a);
+  Link<T>::template load<false>(Ln, 0, i + m.dn[3], u);
+  hop_scaled<P, 0, B, true>(acc, inn, (int)i + m.dn[3], u, a);
+  Link<T>::template load<false>(Ln, 1, i + m.dn[4], u);
+  hop_scaled<P, 1, B, true>(acc, inn, (int)i + m.dn[4], u, a);
+  Link<T>::template load<false>(Ln, 2, i + m.dn[5], u);
+  hop_scaled<P, 2, B, true>(acc, inn, (int)i + m.dn[5], u, a);
+#pragma unroll
+  for (int q = 0; q < 12; ++q) c.acc[q] = acc[q];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) c.gb[q] = gb_next[q];
+  return nrm;
+}
+
+template <int P, bool DAG, int EPI, bool XIN, bool NORM>
+__global__ __launch_bounds__(DM_BS) void k_dirac_march(KDirac k) {
+  using T = RealOf<P>;
+  constexpr int F = DAG ? -1 : 1;
+  constexpr int B = -F;
+  if (k.skip && *k.skip) return;
+  const int b = (int)blockIdx.x, q = b >> 3;
+  const int item = (b & 7) * k.per + q;
+  double nrm = 0.0;
+  if (q < k.per && item < k.items) {
+    const int tile = item % k.nt, r = item / k.nt;
+    int s = tile * DM_BS + (int)threadIdx.x;
+    if (k.n2 > 0) {
+      // brick tile of L1 x n2 x n3 sites: half of its x3 neighbours and all
+      // but 2 / n2 of its x2 neighbours are its own
+      const int L1 = k.g.L[0], nb2 = k.g.L[1] / k.n2;
+      const int tid = (int)threadIdx.x, rr = tid / L1;
+      const int x2 = (tile % nb2) * k.n2 + rr % k.n2, x3 = (tile / nb2) * k.n3 + rr / k.n2;
+      s = tid % L1 + L1 * (x2 + k.g.L[1] * x3);
+    }
+    if (r == 0) {
+      // padding slots of both halves stay zero
       cplx<T> z[12];
 #pragma unroll
-      for (int q = 0; q < 12; ++q) z[q] = {(T)0, (T)0};
-      Spinor<P>::store(out, i, z);
+      for (int j = 0; j < 12; ++j) z[j] = {(T)0, (T)0};
+      for (int j = s; j < k.npad; j += k.nt * DM_BS) {
+        Spinor<P>::store(k.out, (size_t)k.g.vh + j, z);
+        Spinor<P>::store(k.out + k.half, (size_t)k.g.vh + j, z);
+      }
+    }
+    if (s < k.nsp) {
+      const Geom &g = k.g;
+      const int L4 = g.L[3];
+      const MarchLane m = march_lane(g, s);
+      const int t0 = r * k.S, t1 = min(t0 + k.S, L4);
+      MarchCarry<P> c;
+      {
+        // the backward time hop that out(x, t0) receives from slice t0 - 1
+        const int tp = (t0 == 0) ? L4 - 1 : t0 - 1;
+        const int p = (m.par0 + tp) & 1;
+        const size_t i = (size_t)m.i0 + (size_t)tp * g.s4;
+        cplx<T> h[6], u[6];
+        Spinor<P>::template load_half<(B < 0)>(k.in + (size_t)p * k.half, i, h);
+        Link<T>::template load<true>(k.links[p], 3, i, u);
+        time_back<P, B>(u, h, (T)2 * ((tp == L4 - 1) ? (T)g.tbc : (T)1) * (T)k.a, c.gb);
+      }
+      nrm += march_step<P, DAG, EPI, XIN, NORM, false>(k, m, t0, c);
+#pragma unroll 1
+      for (int t = t0 + 1; t < t1; ++t) nrm += march_step<P, DAG, EPI, XIN, NORM, true>(k, m, t, c);
+      {
+        // the forward time hop of out(x, t1 - 1) from slice t1
+        const int te = (t1 == L4) ? 0 : t1;
+        const int p = (m.par0 + te) & 1;
+        cplx<T> h[6];
+        Spinor<P>::template load_half<(F < 0)>(k.in + (size_t)p * k.half, (size_t)m.i0 + (size_t)te * g.s4, h);
+        const T f = (T)2 * ((t1 - 1 == L4 - 1) ? (T)g.tbc : (T)1) * (T)k.a;
+        nrm += time_fwd_store<P, F, NORM>(k, c.acc, c.u4, h, f, 1 - p, (size_t)m.i0 + (size_t)(t1 - 1) * g.s4);
+      }
     }
   }
   if constexpr (NORM) {
@@ -129,18 +318,91 @@ __global__ __launch_bounds__(DR_BS) void k_dirac(KDirac k) {
 }
 
 template <int P, bool DAG>
-void launch_p(const KDirac &k, int epi, bool norm, unsigned nblk, hipStream_t st) {
-#define WD_DR(E, N) \
-  if (epi == E && norm == N) hipLaunchKernelGGL((k_dirac<P, DAG, E, N>), dim3(nblk), dim3(DR_BS), 0, st, k);
-  WD_DR(0, false) WD_DR(1, false) WD_DR(2, false) WD_DR(0, true) WD_DR(1, true) WD_DR(2, true)
+void launch_p(const KDirac &k, int epi, bool xin, bool norm, unsigned nblk, hipStream_t st) {
+#define WD_DR(E, XI, N)                    \
+  if (epi == E && xin == XI && norm == N) \
+    hipLaunchKernelGGL((k_dirac_march<P, DAG, E, XI, N>), dim3(nblk), dim3(DM_BS), 0, st, k);
+  WD_DR(0, false, false) WD_DR(1, false, false) WD_DR(2, false, false)
+  WD_DR(1, true, false) WD_DR(2, true, false)
+  WD_DR(0, false, true) WD_DR(1, false, true) WD_DR(2, false, true)
+  WD_DR(1, true, true) WD_DR(2, true, true)
 #undef WD_DR
+}
+
+struct MarchGrid {
+  int nsp, nt, S, items, per, n2, n3;
+};
+
+// Brick tiles of L1 x n2 x 2 sites (L1 n2 2 = 256) fit when n2 divides L2
+// and L3 is even; n2 = 0 if not.
+int march_brick_n2(const Geom &g) {
+  if (DM_BS % (2 * g.L[0]) != 0) return 0;
+  const int n2 = DM_BS / (2 * g.L[0]);
+  return (g.L[1] % n2 == 0 && g.L[2] % 2 == 0) ? n2 : 0;
+}
+
+// tile: 2 = brick tiles (where they fit), 0 = 256 consecutive spatial sites.
+// S > 0: time slices per range (at most L4); S = 0: the smallest of 8, 16,
+// 32, ... for which every work item is resident at once (capacity =
+// resident blocks per CU x CUs), so that the tiles marching a range side by
+// side run together.
+MarchGrid march_grid(const Geom &g, int S, int tile, int capacity) {
+  MarchGrid m;
+  m.nsp = g.L[0] * g.L[1] * g.L[2];
+  m.n2 = tile == 2 ? march_brick_n2(g) : 0;
+  m.n3 = m.n2 ? 2 : 0;
+  m.nt = m.n2 ? (g.L[1] / m.n2) * (g.L[2] / m.n3) : (m.nsp + DM_BS - 1) / DM_BS;
+  if (S > 0) {
+    m.S = std::min(S, g.L[3]);
+  } else {
+    m.S = std::min(8, g.L[3]);
+    while (m.S < g.L[3] && (long)m.nt * ((g.L[3] + m.S - 1) / m.S) > capacity) m.S *= 2;
+    m.S = std::min(m.S, g.L[3]);
+  }
+  m.items = m.nt * ((g.L[3] + m.S - 1) / m.S);
+  m.per = (m.items + 7) / 8;
+  return m;
+}
+
+template <int P>
+int march_blocks_per_cu() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_dirac_march<P, false, 1, true, false>, DM_BS, 0) !=
+          hipSuccess ||
+      n < 1)
+    n = 1;
+  return n;
+}
+
+int march_capacity(const wd_gauge *g, wd_prec prec) {
+  return std::max(g->dirac_bpc[prec], 1) * std::max(g->n_cu, 1);
+}
+
+MarchGrid march_grid_of(const wd_gauge *g, wd_prec prec) {
+  return march_grid(g->geom, g->dirac_slices[prec], g->dirac_tile[prec], march_capacity(g, prec));
 }
 
 }  // namespace
 
-unsigned dirac_grid_blocks(const wd_gauge *g) {
-  const unsigned nt = (unsigned)((g->geom.vpad + DR_BS - 1) / DR_BS);
-  return (nt + 7) / 8 * 16;  // both parities, tiles rounded up to groups of 8
+bool dirac_variant_ok(const Geom &g, int slices, int tile) {
+  return slices >= 0 && slices <= g.L[3] && (tile == 0 || (tile == 2 && march_brick_n2(g) > 0));
+}
+
+wd_status dirac_init(wd_gauge *g) {
+  for (int p = 0; p < 4; ++p) {
+    g->dirac_slices[p] = 0;
+    g->dirac_tile[p] = march_brick_n2(g->geom) ? 2 : 0;
+  }
+  g->dirac_bpc[WD_F64] = march_blocks_per_cu<WD_F64>();
+  g->dirac_bpc[WD_F32] = march_blocks_per_cu<WD_F32>();
+  g->dirac_bpc[WD_F16] = march_blocks_per_cu<WD_F16>();
+  g->dirac_bpc[WD_BF16] = march_blocks_per_cu<WD_BF16>();
+  return WD_OK;
+}
+
+bool dirac_fills_device(const wd_gauge *g, wd_prec prec) {
+  const int cap = march_capacity(g, prec);
+  return 2 * march_grid_of(g, prec).items >= cap;
 }
 
 wd_status launch_dirac(const wd_gauge *g, wd_prec prec, const DiracArgs &a, hipStream_t st) {
@@ -160,15 +422,27 @@ wd_status launch_dirac(const wd_gauge *g, wd_prec prec, const DiracArgs &a, hipS
   k.links[1] = lk + lp;
   k.half = half_bytes(g->geom, prec);
   k.a = a.a;
-  k.norm_out = a.norm_out;
-  k.norm_accumulate = a.norm_accumulate;
   k.partials = a.red.partials;
-  k.ntiles = (int)((g->geom.vpad + DR_BS - 1) / DR_BS);
+  k.skip = a.skip;
+  if ((int)prec < 0 || (int)prec > 3) return set_error(WD_ERR_PREC, "dirac: unknown precision %d", (int)prec);
+  const MarchGrid mg = march_grid_of(g, prec);
+  k.nsp = mg.nsp;
+  k.nt = mg.nt;
+  k.S = mg.S;
+  k.items = mg.items;
+  k.per = mg.per;
+  k.npad = g->geom.vpad - g->geom.vh;
+  k.n2 = mg.n2;
+  k.n3 = mg.n3;
   const int epi = a.Y ? 2 : (a.X ? 1 : 0);
-  const unsigned nblk = dirac_grid_blocks(g);
-#define WD_DP(PR)                                          \
-  if (a.dagger) launch_p<PR, true>(k, epi, norm, nblk, st); \
-  else launch_p<PR, false>(k, epi, norm, nblk, st);
+  const bool xin = a.X && a.X == a.in;
+  const unsigned nblk = 8u * (unsigned)mg.per;
+  // the reduction buffers hold at least this many partials (sized for the hop and level-1 grids)
+  if (norm && nblk > std::max(dslash_grid_blocks(g), BLAS_MAX_BLOCKS))
+    return set_error(WD_ERR_ARG, "dirac norm: %u blocks exceed the reduction buffer", nblk);
+#define WD_DP(PR)                                                \
+  if (a.dagger) launch_p<PR, true>(k, epi, xin, norm, nblk, st); \
+  else launch_p<PR, false>(k, epi, xin, norm, nblk, st);
   switch (prec) {
     case WD_F64: WD_DP(WD_F64) break;
     case WD_F32: WD_DP(WD_F32) break;
@@ -178,7 +452,7 @@ wd_status launch_dirac(const wd_gauge *g, wd_prec prec, const DiracArgs &a, hipS
   }
 #undef WD_DP
   WD_TRY(hip_check(hipGetLastError(), "dirac launch"));
-  if (norm) return launch_finish_sums(k.partials, nblk, 1, k.norm_out, 1, k.norm_accumulate, nullptr, 1, st);
+  if (norm) return launch_finish_sums(k.partials, nblk, 1, a.norm_out, 1, a.norm_accumulate, a.skip, 1, st);
   return WD_OK;
 }
 

@@ -72,8 +72,18 @@ wd_status scale(FgcrCtx &c, void *x, double s) {
   return blas_convert(c.g->geom, WD_F64, vref(x, 2), WD_F64, vref(x, 2), s, nullptr, 1, c.st);
 }
 
-// out = D_W in (FP64 full fields)
+// out = D_W in (FP64 full fields): the one-launch marching kernel where it
+// fills the device, else one hop per parity
 wd_status apply_D(FgcrCtx &c, const void *in, void *out, double kappa) {
+  c.dslash_calls += 2;
+  if (dirac_fills_device(c.g, WD_F64)) {
+    DiracArgs a;
+    a.in = in;
+    a.out = out;
+    a.X = in;
+    a.a = -kappa;
+    return launch_dirac(c.g, WD_F64, a, c.st);
+  }
   const size_t hb = half_bytes(c.g->geom, WD_F64);
   for (int p = 0; p < 2; ++p) {
     DslashArgs a;
@@ -84,7 +94,6 @@ wd_status apply_D(FgcrCtx &c, const void *in, void *out, double kappa) {
     a.parity = p;
     WD_TRY(launch_dslash(c.g, WD_F64, a, c.st));
   }
-  c.dslash_calls += 2;
   return WD_OK;
 }
 

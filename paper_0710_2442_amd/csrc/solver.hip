@@ -130,12 +130,25 @@ struct CglsVecs {
 
 // out = A in (dagger: A^dag in), |out|^2 -> norm: A = M = 1 - k^2 H_eo H_oe on
 // even halves (two hops, the first into t), or A = D_W = 1 - k H on full
-// fields (one hop per parity, the norm summed over both).
+// fields (the one-launch marching kernel where it fills the device, else one
+// hop per parity with the norm summed over both).
 static wd_status apply_op(const wd_gauge *g, const CglsVecs &v, double kappa, const void *in, void *out, int dagger,
                           double *norm, const int *skip, RedBuf red, hipStream_t st) {
   if (!v.full) {
     WD_TRY(hop(g, v.pv, v.nsys, HopCall{in, v.t, nullptr, 1.0, 1, dagger, nullptr, skip}, red, st));
     return hop(g, v.pv, v.nsys, HopCall{v.t, out, in, -kappa * kappa, 0, dagger, norm, skip}, red, st);
+  }
+  if (dirac_fills_device(g, v.pv)) {
+    DiracArgs a;
+    a.in = in;
+    a.out = out;
+    a.X = in;
+    a.a = -kappa;
+    a.dagger = dagger;
+    a.norm_out = norm;
+    a.skip = skip;
+    a.red = red;
+    return launch_dirac(g, v.pv, a, st);
   }
   const size_t hb = half_bytes(g->geom, v.pv);
   for (int par = 0; par < 2; ++par) {

@@ -14,6 +14,7 @@
 #include <string.h>
 
 #include <string>
+#include <algorithm>
 #include <array>
 #include <vector>
 
@@ -22,6 +23,7 @@
 
 namespace wd {
 
+// nrhs > 0: the multi-RHS hop; nrhs < 0: the one-launch D_W
 static std::string tune_key(const wd_gauge *g, wd_prec prec, int nrhs = 0) {
   hipDeviceProp_t prop;
   char arch[64] = "unknown";
@@ -32,6 +34,7 @@ static std::string tune_key(const wd_gauge *g, wd_prec prec, int nrhs = 0) {
   }
   char kern[32] = "hop";
   if (nrhs > 0) snprintf(kern, sizeof kern, "hop_mrhs%d", nrhs);
+  if (nrhs < 0) snprintf(kern, sizeof kern, "dirac");
   char buf[160];
   snprintf(buf, sizeof buf, "%s/%s/p%d/%dx%dx%dx%d", arch, kern, (int)prec, g->dims[0], g->dims[1], g->dims[2],
            g->dims[3]);
@@ -477,6 +480,123 @@ wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, const char *c
   if (out_block) *out_block = best_b;
   if (out_rpl) *out_rpl = best_r;
   if (out_groups) *out_groups = best_g;
+  if (out_us) *out_us = best_us;
+  return WD_OK;
+}
+
+wd_status wd_set_dirac_variant(wd_gauge *g, wd_prec prec, int slices, int tile) {
+  if (!g) return set_error(WD_ERR_ARG, "gauge handle is NULL");
+  if ((int)prec < 0 || (int)prec > 3) return set_error(WD_ERR_PREC, "prec = %d", (int)prec);
+  if (!dirac_variant_ok(g->geom, slices, tile))
+    return set_error(WD_ERR_ARG, "one-launch D_W variant: slices %d, tile %d does not fit %dx%dx%dx%d", slices,
+                     tile, g->dims[0], g->dims[1], g->dims[2], g->dims[3]);
+  g->dirac_slices[prec] = slices;
+  g->dirac_tile[prec] = tile;
+  return WD_OK;
+}
+
+wd_status wd_get_dirac_variant(const wd_gauge *g, wd_prec prec, int *slices, int *tile) {
+  if (!g) return set_error(WD_ERR_ARG, "gauge handle is NULL");
+  if ((int)prec < 0 || (int)prec > 3) return set_error(WD_ERR_PREC, "prec = %d", (int)prec);
+  if (slices) *slices = g->dirac_slices[prec];
+  if (tile) *tile = g->dirac_tile[prec];
+  return WD_OK;
+}
+
+wd_status wd_tune_dirac(wd_gauge *g, wd_prec prec, const char *cache_path, int force, int *out_slices,
+                        int *out_tile, double *out_us) {
+  if (!g) return set_error(WD_ERR_ARG, "gauge handle is NULL");
+  if ((int)prec < 0 || (int)prec > 3) return set_error(WD_ERR_PREC, "prec = %d", (int)prec);
+  WD_HIP(hipSetDevice(g->device));
+  const std::string key = tune_key(g, prec, -1);
+  {
+    int cb, ct, cs;
+    double cus;
+    if (cache_path && !force && cache_lookup(cache_path, key, cb, ct, cs, cus, "slices") &&
+        wd_set_dirac_variant(g, prec, cs, ct) == WD_OK) {
+      if (out_slices) *out_slices = cs;
+      if (out_tile) *out_tile = ct;
+      if (out_us) *out_us = cus;
+      return WD_OK;
+    }
+  }
+  const Geom &G = g->geom;
+  const size_t fb = 2 * half_bytes(G, prec);
+  hipStream_t st = g->own_stream;
+  void *in = nullptr, *ref = nullptr, *cand = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  wd_status rc = WD_OK;
+  int *flag = nullptr;
+  const int save_s = g->dirac_slices[prec], save_t = g->dirac_tile[prec];
+  int best_s = save_s, best_t = save_t;
+  double best_us = 1e30;
+  DiracArgs a;
+  a.a = -0.124;
+  do {
+    if ((rc = hip_check(hipMalloc(&in, fb), "tune alloc")) != WD_OK) break;
+    if ((rc = hip_check(hipMalloc(&ref, fb), "tune alloc")) != WD_OK) break;
+    if ((rc = hip_check(hipMalloc(&cand, fb), "tune alloc")) != WD_OK) break;
+    if ((rc = hip_check(hipMalloc(&flag, 256), "tune alloc")) != WD_OK) break;
+    {
+      std::vector<unsigned char> h(fb);
+      uint64_t s = 0x13198A2E03707344ull;
+      for (size_t n = 0; n < fb; ++n) {
+        s ^= s << 13; s ^= s >> 7; s ^= s << 17;
+        h[n] = (unsigned char)(s >> 56);
+      }
+      // keep every value a finite number in every precision: clear the exponent MSBs
+      if (prec == WD_F64) for (size_t n = 7; n < fb; n += 8) h[n] &= 0x3f;
+      else for (size_t n = 1; n < fb; n += 2) h[n] &= 0x3f;
+      if ((rc = hip_check(hipMemcpy(in, h.data(), fb, hipMemcpyHostToDevice), "upload")) != WD_OK) break;
+    }
+    if ((rc = hip_check(hipEventCreate(&e0), "event")) != WD_OK) break;
+    if ((rc = hip_check(hipEventCreate(&e1), "event")) != WD_OK) break;
+    a.in = in;
+    a.X = in;
+    a.out = ref;
+    if ((rc = launch_dirac(g, prec, a, st)) != WD_OK) break;
+    std::vector<std::array<int, 2>> cands;
+    for (int tile : {2, 0})
+      for (int sl = 8;; sl *= 2) {
+        const int S = std::min(sl, G.L[3]);
+        if (dirac_variant_ok(G, S, tile)) cands.push_back({S, tile});
+        if (S == G.L[3]) break;
+      }
+    a.out = cand;
+    for (const auto &c : cands) {
+      g->dirac_slices[prec] = c[0];
+      g->dirac_tile[prec] = c[1];
+      if ((rc = hip_check(hipMemsetAsync(cand, 0xff, fb, st), "memset")) != WD_OK) break;
+      if ((rc = launch_dirac(g, prec, a, st)) != WD_OK) break;
+      bool same = false;
+      if ((rc = same_bytes(ref, cand, fb, flag, same, st)) != WD_OK) break;
+      if (!same) continue;
+      const int reps = 6;
+      for (int w = 0; w < 2; ++w) (void)launch_dirac(g, prec, a, st);
+      (void)hipEventRecord(e0, st);
+      for (int r = 0; r < reps; ++r) (void)launch_dirac(g, prec, a, st);
+      (void)hipEventRecord(e1, st);
+      if ((rc = hip_check(hipEventSynchronize(e1), "tune timing")) != WD_OK) break;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      const double us = 1e3 * ms / reps;
+      if (getenv("WD_TUNE_VERBOSE"))
+        fprintf(stderr, "tune dirac p%d: slices %d tile %d: %.2f us\n", (int)prec, c[0], c[1], us);
+      if (us < best_us) { best_us = us; best_s = c[0]; best_t = c[1]; }
+    }
+  } while (0);
+  g->dirac_slices[prec] = (rc == WD_OK) ? best_s : save_s;
+  g->dirac_tile[prec] = (rc == WD_OK) ? best_t : save_t;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (in) (void)hipFree(in);
+  if (ref) (void)hipFree(ref);
+  if (cand) (void)hipFree(cand);
+  if (flag) (void)hipFree(flag);
+  if (rc != WD_OK) return rc;
+  if (cache_path) cache_append(cache_path, key, 256, best_t, best_s, best_us, "slices");
+  if (out_slices) *out_slices = best_s;
+  if (out_tile) *out_tile = best_t;
   if (out_us) *out_us = best_us;
   return WD_OK;
 }

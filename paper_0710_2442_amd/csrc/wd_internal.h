@@ -67,6 +67,10 @@ struct wd_gauge {
   wd_prec prec;
   int device;
   int lds_per_block;       // the device's LDS limit per block (bytes)
+  int n_cu;                // compute units of the device
+  int dirac_bpc[4];        // per precision: resident blocks per CU of the one-launch D_W
+  int dirac_slices[4];     // per precision: time slices per range of the one-launch D_W (0: from occupancy)
+  int dirac_tile[4];       // per precision: its tiles, 2 = bricks of L1 x n2 x 2 sites, 0 = consecutive sites
   hipStream_t stream;      // caller's stream for dslash / pack
   hipStream_t own_stream;  // library stream for synchronous solves (default priority)
   void *links64;
@@ -145,10 +149,16 @@ struct DiracArgs {
   int dagger = 0;
   double *norm_out = nullptr;
   int norm_accumulate = 0;
+  const int *skip = nullptr;  // device flag: when set, the launch does nothing
   RedBuf red{nullptr};
 };
-unsigned dirac_grid_blocks(const wd_gauge *g);
 wd_status launch_dirac(const wd_gauge *g, wd_prec prec, const DiracArgs &args, hipStream_t st);
+// one-launch D_W: occupancy of its kernels, queried once per handle (dirac.hip)
+wd_status dirac_init(wd_gauge *g);
+// whether the one-launch D_W has work items for at least half of the device's resident blocks
+bool dirac_fills_device(const wd_gauge *g, wd_prec prec);
+// whether (time slices per range, tile shape) is a valid one-launch D_W variant for the lattice
+bool dirac_variant_ok(const Geom &g, int slices, int tile);
 // out[j * ostride] = (accumulate ? out[j * ostride] : 0) + sum over b of
 // partials[j * nblocks + b], for j < n, in block order (one workgroup per j);
 // entries whose skip[j * sstride] is set are left alone (blas.hip).

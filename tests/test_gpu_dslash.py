@@ -96,6 +96,48 @@ def test_one_launch_dirac_matches_oracle_and_two_pass(dims, prec):
     g.close()
 
 
+@pytest.mark.parametrize("dims", [(6, 6, 10, 32), (4, 4, 4, 48), (8, 8, 8, 64), (16, 8, 4, 16), (8, 16, 6, 32)])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16", "bf16"])
+def test_marching_dirac_over_ranges_and_tiles(dims, prec):
+    """The one-launch D_W marches each spatial tile (256 sites) through
+    ranges of at least 8 time slices: several ranges here, so every range
+    boundary (time link and half spinor fetched across it) and the
+    antiperiodic wrap are crossed.  Tiles of consecutive sites, the last one
+    ragged (6x6x10), and brick tiles of L1 x n2 x 2 sites (16x8x4: one brick
+    per x3 pair; 8x16x6: three bricks along x3).  Against the oracle, D_W
+    and D_W^dag; the output's padding slots must come back zero.
+
+    FP16 per-site bar 2^-10: the output's own rounding is bounded by 2^-11 of
+    the site's largest component (half an FP16 ulp of each storage-basis real,
+    two of which mix in each chiral-basis real), and the X term carries the
+    input spinor at weight one, so a one-ulp difference between the oracle's
+    emulated input rounding and the device packing adds up to another 2^-11."""
+    print(f"case: marching D_W dims={dims} prec={prec}", flush=True)
+    kappa = 0.124
+    U, psi, Ur, pr = _inputs(dims, prec, seed=23)
+    g = wd.Gauge(U, dims, -1, prec)
+    src = to_field(g, psi, prec)
+    for flags, dag in ((0, False), (wd.WD_DAGGER, True)):
+        out = wd.wd_new_field(dims, prec)
+        out.fill_(0xFF)  # NaN in every float format
+        wd.wd_dslash_ex(g, src, out, kappa, wd.WD_FULL, prec, flags | wd.WD_ONE_PASS)
+        want = wilson.dirac(Ur, pr, kappa) if not dag else wilson.gamma5(wilson.dirac(Ur, wilson.gamma5(pr), kappa))
+        site = 2.0 ** -10 + 4e-6 if prec == "f16" else None
+        assert_close(from_field(g, out, prec), want, prec, site=site, what=f"marching D_W {dims} {prec} dag={dag}")
+        if prec in ("f64", "f32"):
+            vh, vpad = int(np.prod(dims)) // 2, wd.wd_vh_pad(dims)
+            nc = vpad // 64
+            lanes = np.arange(vh, vpad)
+            if prec == "f64":  # [parity][chunk][component][lane]
+                dev = out.cpu().numpy().view(np.complex128).reshape(2, nc, 12, 64)
+                pads = dev[:, lanes // 64, :, lanes % 64]
+            else:  # [parity][chunk][packet][lane][2 components]
+                dev = out.cpu().numpy().view(np.complex64).reshape(2, nc, 6, 64, 2)
+                pads = dev[:, lanes // 64, :, lanes % 64, :]
+            assert np.all(pads == 0), "padding slots not cleared"
+    g.close()
+
+
 def test_periodic_time_boundary():
     dims = (4, 4, 2, 6)
     U, psi, _, _ = _inputs(dims, "f64", seed=11)
@@ -316,6 +358,51 @@ def test_tuning_cache_round_trip(tmp_path):
     g.close()
 
 
+def test_one_launch_dirac_variants_and_tuning(tmp_path):
+    """Every one-launch D_W variant (time slices per range, brick or
+    consecutive tiles) computes the same bytes, D_W and D_W^dag; the tuner
+    keeps its choice in the JSON-lines cache and takes it back from there;
+    variants that do not fit the lattice are refused."""
+    dims = (16, 8, 4, 16)  # bricks of 16 x 8 x 2 sites fit
+    U = syn.gauge_field(dims, 0.3, 31)
+    psi = syn.gaussian_spinor(dims, 32)
+    for prec in ("f64", "bf16"):
+        g = wd.Gauge(U, dims, -1, prec)
+        src = to_field(g, psi, prec)
+        assert wd.wd_get_dirac_variant(g, prec) == (0, 2)
+        for flags in (0, wd.WD_DAGGER):
+            ref = wd.wd_new_field(dims, prec)
+            wd.wd_dslash_ex(g, src, ref, 0.124, wd.WD_FULL, prec, flags | wd.WD_ONE_PASS)
+            for sl, tile in ((1, 0), (3, 2), (8, 0), (16, 2), (16, 0), (0, 0)):
+                wd.wd_set_dirac_variant(g, prec, sl, tile)
+                assert wd.wd_get_dirac_variant(g, prec) == (sl, tile)
+                out = wd.wd_new_field(dims, prec)
+                out.fill_(0xFF)
+                wd.wd_dslash_ex(g, src, out, 0.124, wd.WD_FULL, prec, flags | wd.WD_ONE_PASS)
+                assert torch.equal(out, ref), (prec, flags, sl, tile)
+            wd.wd_set_dirac_variant(g, prec, 0, 2)
+        with pytest.raises(wd.WdError):
+            wd.wd_set_dirac_variant(g, prec, 17, 2)
+        with pytest.raises(wd.WdError):
+            wd.wd_set_dirac_variant(g, prec, 8, 1)
+        g.close()
+    g = wd.Gauge(U, dims, -1, "f64")
+    path = str(tmp_path / "tune.jsonl")
+    a = wd.wd_tune_dirac(g, "f64", path)
+    lines = open(path).read().splitlines()
+    assert len(lines) == 1 and '"slices"' in lines[0] and "/dirac/p0/16x8x4x16" in lines[0]
+    wd.wd_set_dirac_variant(g, "f64", 1, 0)
+    b = wd.wd_tune_dirac(g, "f64", path)
+    assert b[:2] == a[:2] and abs(b[2] - a[2]) < 1e-3 and wd.wd_get_dirac_variant(g, "f64") == a[:2]
+    assert len(open(path).read().splitlines()) == 1
+    g.close()
+    g = wd.Gauge(syn.gauge_field((6, 4, 6, 10), 0.3, 33), (6, 4, 6, 10), -1, "f32")
+    assert wd.wd_get_dirac_variant(g, "f32") == (0, 0)  # 256 is not a multiple of 2 x 6: no bricks
+    with pytest.raises(wd.WdError):
+        wd.wd_set_dirac_variant(g, "f32", 4, 2)
+    g.close()
+
+
 def test_blas_against_numpy():
     dims = (6, 4, 6, 10)
     g = wd.Gauge(syn.gauge_field(dims, 0.3, 31), dims, -1, "f64")
@@ -405,6 +492,39 @@ def test_full_size_sampled_sites(big, prec):
         assert_close(g_s, want, prec, what=f"32^3x64 {prec} p{parity} ({len(sites)} sites)")
         # sites of the other parity were not written
         assert np.all(got[wilson.parity_field(dims) != parity] == 0)
+    g.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_full_size_marching_dirac(big, prec):
+    """The one-launch D_W at 32^3x64 in the benchmark's launch configuration
+    (the committed tuned variant: range length and tile shape): the whole
+    field against the two single-parity launches, and sampled sites of both
+    parities against the oracle's D_W = 1 - kappa H, element by element."""
+    dims, U, psi = big
+    print(f"case: 32^3x64 one-launch D_W prec={prec}", flush=True)
+    kappa = 0.124
+    g = wd.Gauge(U, dims, -1, prec)
+    table = os.path.join(os.path.dirname(wd.__file__), "tuned", "mi355x_hop.jsonl")
+    key = "gfx950/dirac/p%d/32x32x32x64" % wd.PRECS[prec]
+    entry = [json.loads(line) for line in open(table) if line.strip() and key in line][-1]
+    sl, tile, _ = wd.wd_tune_dirac(g, prec, table)
+    assert (sl, tile) == (entry["slices"], entry["groups"]) == wd.wd_get_dirac_variant(g, prec)
+    src = to_field(g, psi, prec)
+    one = wd.wd_new_field(dims, prec)
+    two = wd.wd_new_field(dims, prec)
+    wd.wd_dslash_ex(g, src, one, kappa, wd.WD_FULL, prec, wd.WD_ONE_PASS)
+    wd.wd_dslash_ex(g, src, two, kappa, wd.WD_FULL, prec, 0)
+    got = from_field(g, one, prec)
+    assert rel_err(got, from_field(g, two, prec)) <= {"f64": 1e-14, "f32": 1e-6}[prec]
+    Ur = U if prec == "f64" else round_c64(U)
+    pr = storage_round(psi, prec)
+    rng = np.random.default_rng(5)
+    sites = [(0, 0, 0, 0), (31, 31, 31, 63), (0, 0, 0, 31), (0, 0, 0, 32), (31, 3, 1, 63), (5, 7, 15, 16)]
+    sites += [tuple(int(rng.integers(0, L)) for L in dims) for _ in range(200)]
+    want = np.stack([pr[x4, x3, x2, x1] for (x1, x2, x3, x4) in sites]) - kappa * wilson.hop_sites(Ur, pr, sites)
+    g_s = np.stack([got[x4, x3, x2, x1] for (x1, x2, x3, x4) in sites])
+    assert_close(g_s, want, prec, what=f"32^3x64 one-launch D_W {prec} ({len(sites)} sites)")
     g.close()
 
 

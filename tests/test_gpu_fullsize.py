@@ -31,6 +31,8 @@ TABLE = os.path.join(os.path.dirname(wd.__file__), "tuned", "mi355x_hop.jsonl")
 def _use_table(g):
     for prec in ("f64", "f32", "f16", "bf16"):
         wd.wd_tune_dslash(g, prec, TABLE)
+    for prec in ("f64", "f32"):
+        wd.wd_tune_dirac(g, prec, TABLE)
 
 
 @pytest.fixture(scope="module")

@@ -71,6 +71,26 @@ def test_full_lattice_cgls_matches_oracle(dims, use_graph):
     assert rc2 == 0 and info["iters"] > info2["iters"]
 
 
+@pytest.mark.parametrize("solver", ["cgls_full", "fgcr"])
+def test_full_lattice_solvers_on_the_one_launch_operator(solver):
+    """32^3x8 is large enough that the full-lattice solvers apply D_W (and
+    CGLS also D_W^dag, with its norm and convergence flag) through the
+    one-launch marching kernel, whose work items then fill the device.  The
+    oracle's D_W judges the residual; the solution agrees with the even-odd
+    CG's."""
+    dims, kappa = (32, 32, 32, 8), 0.12
+    print(f"case: {solver} on the one-launch D_W, {dims}", flush=True)
+    kw = dict(solver=wd.WD_SOLVER_CGLS_FULL, use_graph=1, check_every=4) if solver == "cgls_full" else \
+        dict(solver=wd.WD_SOLVER_FGCR, fgcr_m=8)
+    U, b, x, rc, info = _solve(dims, kappa, 0.3, 13, **kw)
+    print("info", info, flush=True)
+    assert rc == 0 and info["fallback_used"] == 0
+    r = solvers.true_residual(U, b, x, kappa)
+    assert r <= TOL and abs(r - info["true_rel_resid"]) <= 1e-3 * TOL
+    _, _, x2, rc2, _ = _solve(dims, kappa, 0.3, 13, solver=wd.WD_SOLVER_CG)
+    assert rc2 == 0 and rel_err(x, x2) <= 1e-7
+
+
 @pytest.mark.parametrize("use_graph", [0, 1])
 def test_fp64_cg_graph_and_eager_agree(use_graph):
     dims, kappa = (6, 4, 6, 10), 0.124
