@@ -461,8 +461,11 @@ wd_status wd_get_dslash_variant(const wd_gauge *g, wd_prec prec, int *block,
  * slice-marching scheme of Sec. 5) for precision prec: slices = time slices
  * per range that one block marches through (8, 16, 32, ... up to L4) and
  * tile = the shape of a block's 256 spatial sites (2: bricks of L1 x n2 x 2
- * sites, where n2 = 128 / L1 divides L2 and L3 is even; 0: 256 consecutive
- * sites, x1 fastest).  Every candidate is checked byte for byte against the
+ * sites, where n2 = 128 / L1 divides L2 and L3 is even; 3: the same bricks,
+ * with the spinors of each slice of the brick and of its four side faces
+ * staged in LDS at every step, so the spatial neighbours are read from LDS
+ * (FP64 and FP32 storage; (256 + 2 L1 (n2 + 2)) x 192 or 96 bytes of LDS
+ * per block); 0: 256 consecutive sites, x1 fastest).  Every candidate is checked byte for byte against the
  * current variant, then timed on a random field; the fastest is kept in the
  * handle.  cache_path and force as for wd_tune_dslash (key
  * "<arch>/dirac/p<prec>/<L1>x<L2>x<L3>x<L4>"; the cache line's "block" is
@@ -473,7 +476,8 @@ wd_status wd_tune_dirac(wd_gauge *g, wd_prec prec, const char *cache_path, int f
 
 /* Set / read the one-launch D_W variant of precision prec: slices 0 (the
  * default: the shortest range of 8, 16, ... for which every work item is
- * resident on the device at once) or 1..L4, tile 0 or 2 as above.
+ * resident on the device at once) or 1..L4, tile 0, 2 or 3 as above (the
+ * default: 3 where it fits, else 2 where bricks fit, else 0).
  * WD_ERR_ARG for a value outside these or a brick that does not fit the
  * lattice.  The variants compute the same bytes; only the time differs. */
 wd_status wd_set_dirac_variant(wd_gauge *g, wd_prec prec, int slices, int tile);

@@ -37,7 +37,16 @@
 // so the tiles that march a range side by side share one L2 and their
 // x2 / x3 halo reads hit there.  The range length and the tile shape are a
 // tuned variant (wd_tune_dirac); by default the ranges are as short as lets
-// every work item be resident at once.
+// every work item be resident at once, and the tiles are LDS-staged bricks
+// where they fit.
+//
+// LDS-staged form (brick tiles, FP64 and FP32 storage): at the start of each
+// step the block copies the spinors of its brick's slice and of the brick's
+// four side faces into LDS (each lane its own site and up to three face
+// sites) and reads all six spatial neighbours from there, so a spinor's
+// seven reads within a step no longer depend on it staying in L2; only the
+// face sites, which the neighbouring bricks load in the same step, go
+// through L2.
 //
 // Epilogue as in the single-parity hop: EPI 1 out = X + a H in, EPI 2
 // out = X - Y + a H in (full fields), with an optional FP64 |out|^2.  XIN:
@@ -73,6 +82,7 @@ struct KDirac {
   int npad;   // padding slots per half field (zeroed)
   int n2;     // brick tiles: x2 rows per tile (0: tiles of consecutive sites)
   int n3;     // brick tiles: x3 planes per tile
+  int nslot;  // LDS-staged form: staged sites per block (the brick and its four side faces)
 };
 
 // What a lane carries from one step to the next.
@@ -176,10 +186,121 @@ __device__ __forceinline__ void hop_scaled(cplx<RealOf<P>> (&acc)[12], const cha
   hop_term_h<P, MU, S, LDAG>(acc, h, u);
 }
 
+// Raw 16-byte packets of a stored spinor (FP64: 12, FP32: 6), in the
+// order of the field layout; unpacked exactly as Spinor<P>::load does.
+template <int P>
+struct Raw;
+template <>
+struct Raw<WD_F64> {
+  using V = v2d;
+  static constexpr int N = 12;
+  __device__ static void unpack(const V (&r)[N], cplx<double> (&s)[12]) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) s[c] = {r[c].x, r[c].y};
+  }
+};
+template <>
+struct Raw<WD_F32> {
+  using V = v4f;
+  static constexpr int N = 6;
+  __device__ static void unpack(const V (&r)[N], cplx<float> (&s)[12]) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      s[2 * q] = {r[q].x, r[q].y};
+      s[2 * q + 1] = {r[q].z, r[q].w};
+    }
+  }
+};
+
+template <int P>
+__device__ __forceinline__ void raw_load(const char *base, int i, typename Raw<P>::V (&r)[Raw<P>::N]) {
+  using V = typename Raw<P>::V;
+  const V *q = (const V *)base + chunk_base<Raw<P>::N * 64>((size_t)i);
+#pragma unroll
+  for (int c = 0; c < Raw<P>::N; ++c) r[c] = q[64 * c];
+}
+
+// LDS: packet c of staged site `slot` at lds[c * nslot + slot] (consecutive
+// lanes touch consecutive 16-byte words).
+template <int P>
+__device__ __forceinline__ void raw_to_lds(typename Raw<P>::V *lds, int nslot, int slot,
+                                           const typename Raw<P>::V (&r)[Raw<P>::N]) {
+#pragma unroll
+  for (int c = 0; c < Raw<P>::N; ++c) lds[c * nslot + slot] = r[c];
+}
+
+// The staging plan of a lane in the LDS-staged form: its own slot is its
+// thread index; the six spatial neighbours' slots; up to 3 face sites it
+// stages (slot, checkerboard index and parity at x4 = 0).
+struct MarchLds {
+  int nsl[6];  // x1+, x2+, x3+, x1-, x2-, x3-
+  int nh;
+  int hslot[3], hi0[3], hpar0[3];
+};
+
+// Staged sites of a brick tile (L1 x n2 x n3 sites at x2 = b2 n2 + a2, x3 =
+// b3 n3 + a3): slots 0..255 the brick, lane t = x1 + L1 (a2 + n2 a3); then
+// the two x2 faces (a2 = -1, n2; 2 L1 n3 sites), then the two x3 faces
+// (a3 = -1, n3; 2 L1 n2 sites).
+__device__ __forceinline__ MarchLds march_lds_plan(const Geom &g, int n2, int n3, int b2, int b3, int tid) {
+  MarchLds m;
+  const int L1 = g.L[0], L2 = g.L[1], L3 = g.L[2];
+  const int x1 = tid % L1, r = tid / L1, a2 = r % n2, a3 = r / n2;
+  const int F2 = DM_BS, F3 = DM_BS + 2 * L1 * n3;
+  auto own = [&](int y1, int c2, int c3) { return y1 + L1 * (c2 + n2 * c3); };
+  m.nsl[0] = own(x1 + 1 == L1 ? 0 : x1 + 1, a2, a3);
+  m.nsl[3] = own(x1 == 0 ? L1 - 1 : x1 - 1, a2, a3);
+  m.nsl[1] = (a2 + 1 < n2) ? own(x1, a2 + 1, a3) : F2 + x1 + L1 * (a3 + n3);
+  m.nsl[4] = (a2 > 0) ? own(x1, a2 - 1, a3) : F2 + x1 + L1 * a3;
+  m.nsl[2] = (a3 + 1 < n3) ? own(x1, a2, a3 + 1) : F3 + x1 + L1 * (a2 + n2);
+  m.nsl[5] = (a3 > 0) ? own(x1, a2, a3 - 1) : F3 + x1 + L1 * a2;
+  const int nface = 2 * L1 * (n2 + n3);
+  m.nh = 0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int h = tid + j * DM_BS;
+    int y1 = 0, y2 = 0, y3 = 0;
+    if (h < 2 * L1 * n3) {
+      const int q = h / L1, c3 = q % n3, f = q / n3;
+      y1 = h % L1;
+      y2 = (b2 * n2 + (f ? n2 : -1) + L2) % L2;
+      y3 = b3 * n3 + c3;
+    } else {
+      const int e = h - 2 * L1 * n3, q = e / L1, c2 = q % n2, f = q / n2;
+      y1 = e % L1;
+      y2 = b2 * n2 + c2;
+      y3 = (b3 * n3 + (f ? n3 : -1) + L3) % L3;
+    }
+    m.hslot[j] = DM_BS + h;
+    m.hi0[j] = (y1 >> 1) + g.s2 * y2 + g.s3 * y3;
+    m.hpar0[j] = (y1 + y2 + y3) & 1;
+    if (h < nface) m.nh = j + 1;
+  }
+  return m;
+}
+
+// acc += a M (1 + S gamma_MU) psi for a spatial hop whose neighbour spinor
+// is staged in LDS.
+template <int P, int MU, int S, bool LDAG>
+__device__ __forceinline__ void hop_lds(cplx<RealOf<P>> (&acc)[12], const typename Raw<P>::V *lds, int nslot,
+                                        int slot, const cplx<RealOf<P>> (&u)[6], RealOf<P> a) {
+  using T = RealOf<P>;
+  typename Raw<P>::V r[Raw<P>::N];
+#pragma unroll
+  for (int c = 0; c < Raw<P>::N; ++c) r[c] = lds[c * nslot + slot];
+  cplx<T> psi[12], h[6];
+  Raw<P>::unpack(r, psi);
+  project<MU, S>(psi, h);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) h[c] = a * h[c];
+  hop_term_h<P, MU, S, LDAG>(acc, h, u);
+}
+
 // One step on slice t: finish out(x, t-1) (FIN), then build the carry for
 // out(x, t) and the backward time hop of out(x, t+1).
-template <int P, bool DAG, int EPI, bool XIN, bool NORM, bool FIN>
-__device__ __forceinline__ double march_step(const KDirac &k, const MarchLane &m, int t, MarchCarry<P> &c) {
+template <int P, bool DAG, int EPI, bool XIN, bool NORM, bool FIN, bool LDS>
+__device__ __forceinline__ double march_step(const KDirac &k, const MarchLane &m, int t, MarchCarry<P> &c,
+                                             void *lds_raw, const MarchLds &pl) {
   using T = RealOf<P>;
   constexpr int F = DAG ? -1 : 1;
   constexpr int B = -F;
@@ -188,7 +309,26 @@ __device__ __forceinline__ double march_step(const KDirac &k, const MarchLane &m
   const int p = (m.par0 + t) & 1;
   const size_t i = (size_t)m.i0 + (size_t)t * g.s4;
   cplx<T> psi[12];
-  Spinor<P>::load(k.in + (size_t)p * k.half, i, psi);
+  if constexpr (LDS) {
+    // stage slice t: the lane's own spinor and its share of the face sites
+    using V = typename Raw<P>::V;
+    V *lds = (V *)lds_raw;
+    if constexpr (FIN) __syncthreads();  // the previous step has read the staged slice
+    V r[Raw<P>::N];
+    raw_load<P>(k.in + (size_t)p * k.half, (int)i, r);
+    raw_to_lds<P>(lds, k.nslot, (int)threadIdx.x, r);
+    Raw<P>::unpack(r, psi);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      if (j < pl.nh) {
+        V hr[Raw<P>::N];
+        raw_load<P>(k.in + (size_t)((pl.hpar0[j] + t) & 1) * k.half, pl.hi0[j] + t * g.s4, hr);
+        raw_to_lds<P>(lds, k.nslot, pl.hslot[j], hr);
+      }
+    }
+  } else {
+    Spinor<P>::load(k.in + (size_t)p * k.half, i, psi);
+  }
   double nrm = 0.0;
   const T one = (T)1;
   if constexpr (FIN) {
@@ -231,19 +371,39 @@ __device__ __forceinline__ double march_step(const KDirac &k, const MarchLane &m
   const T a = (T)k.a;
   const char *inn = k.in + (size_t)(1 - p) * k.half;
   const char *Lo = k.links[p], *Ln = k.links[1 - p];
+  // forward and backward hop of each direction back to back: a spatial link
+  // is read by its owner and by the neighbour it points to close together
   cplx<T> u[6];
-  Link<T>::template load<false>(Lo, 0, i, u);
-  hop_scaled<P, 0, F, false>(acc, inn, (int)i + m.dn[0], u, a);
-  Link<T>::template load<false>(Lo, 1, i, u);
-  hop_scaled<P, 1, F, false>(acc, inn, (int)i + m.dn[1], u, a);
-  Link<T>::template load<false>(Lo, 2, i, u);
-  hop_scaled<P, 2, F, false>(acc, inn, (int)i + m.dn[2], u, a);
-  Link<T>::template load<false>(Ln, 0, i + m.dn[3], u);
-  hop_scaled<P, 0, B, true>(acc, inn, (int)i + m.dn[3], u, a);
-  Link<T>::template load<false>(Ln, 1, i + m.dn[4], u);
-  hop_scaled<P, 1, B, true>(acc, inn, (int)i + m.dn[4], u, a);
-  Link<T>::template load<false>(Ln, 2, i + m.dn[5], u);
-  hop_scaled<P, 2, B, true>(acc, inn, (int)i + m.dn[5], u, a);
+  if constexpr (LDS) {
+    using V = typename Raw<P>::V;
+    const V *lds = (const V *)lds_raw;
+    __syncthreads();  // slice t is staged
+    Link<T>::template load<false>(Lo, 0, i, u);
+    hop_lds<P, 0, F, false>(acc, lds, k.nslot, pl.nsl[0], u, a);
+    Link<T>::template load<false>(Ln, 0, i + m.dn[3], u);
+    hop_lds<P, 0, B, true>(acc, lds, k.nslot, pl.nsl[3], u, a);
+    Link<T>::template load<false>(Lo, 1, i, u);
+    hop_lds<P, 1, F, false>(acc, lds, k.nslot, pl.nsl[1], u, a);
+    Link<T>::template load<false>(Ln, 1, i + m.dn[4], u);
+    hop_lds<P, 1, B, true>(acc, lds, k.nslot, pl.nsl[4], u, a);
+    Link<T>::template load<false>(Lo, 2, i, u);
+    hop_lds<P, 2, F, false>(acc, lds, k.nslot, pl.nsl[2], u, a);
+    Link<T>::template load<false>(Ln, 2, i + m.dn[5], u);
+    hop_lds<P, 2, B, true>(acc, lds, k.nslot, pl.nsl[5], u, a);
+  } else {
+    Link<T>::template load<false>(Lo, 0, i, u);
+    hop_scaled<P, 0, F, false>(acc, inn, (int)i + m.dn[0], u, a);
+    Link<T>::template load<false>(Ln, 0, i + m.dn[3], u);
+    hop_scaled<P, 0, B, true>(acc, inn, (int)i + m.dn[3], u, a);
+    Link<T>::template load<false>(Lo, 1, i, u);
+    hop_scaled<P, 1, F, false>(acc, inn, (int)i + m.dn[1], u, a);
+    Link<T>::template load<false>(Ln, 1, i + m.dn[4], u);
+    hop_scaled<P, 1, B, true>(acc, inn, (int)i + m.dn[4], u, a);
+    Link<T>::template load<false>(Lo, 2, i, u);
+    hop_scaled<P, 2, F, false>(acc, inn, (int)i + m.dn[2], u, a);
+    Link<T>::template load<false>(Ln, 2, i + m.dn[5], u);
+    hop_scaled<P, 2, B, true>(acc, inn, (int)i + m.dn[5], u, a);
+  }
 #pragma unroll
   for (int q = 0; q < 12; ++q) c.acc[q] = acc[q];
 #pragma unroll
@@ -251,8 +411,9 @@ __device__ __forceinline__ double march_step(const KDirac &k, const MarchLane &m
   return nrm;
 }
 
-template <int P, bool DAG, int EPI, bool XIN, bool NORM>
+template <int P, bool DAG, int EPI, bool XIN, bool NORM, bool LDS>
 __global__ __launch_bounds__(DM_BS) void k_dirac_march(KDirac k) {
+  extern __shared__ __align__(16) unsigned char dm_lds[];
   using T = RealOf<P>;
   constexpr int F = DAG ? -1 : 1;
   constexpr int B = -F;
@@ -263,6 +424,7 @@ __global__ __launch_bounds__(DM_BS) void k_dirac_march(KDirac k) {
   if (q < k.per && item < k.items) {
     const int tile = item % k.nt, r = item / k.nt;
     int s = tile * DM_BS + (int)threadIdx.x;
+    MarchLds pl{};
     if (k.n2 > 0) {
       // brick tile of L1 x n2 x n3 sites: half of its x3 neighbours and all
       // but 2 / n2 of its x2 neighbours are its own
@@ -270,6 +432,7 @@ __global__ __launch_bounds__(DM_BS) void k_dirac_march(KDirac k) {
       const int tid = (int)threadIdx.x, rr = tid / L1;
       const int x2 = (tile % nb2) * k.n2 + rr % k.n2, x3 = (tile / nb2) * k.n3 + rr / k.n2;
       s = tid % L1 + L1 * (x2 + k.g.L[1] * x3);
+      if constexpr (LDS) pl = march_lds_plan(k.g, k.n2, k.n3, tile % nb2, tile / nb2, tid);
     }
     if (r == 0) {
       // padding slots of both halves stay zero
@@ -297,9 +460,9 @@ __global__ __launch_bounds__(DM_BS) void k_dirac_march(KDirac k) {
         Link<T>::template load<true>(k.links[p], 3, i, u);
         time_back<P, B>(u, h, (T)2 * ((tp == L4 - 1) ? (T)g.tbc : (T)1) * (T)k.a, c.gb);
       }
-      nrm += march_step<P, DAG, EPI, XIN, NORM, false>(k, m, t0, c);
+      nrm += march_step<P, DAG, EPI, XIN, NORM, false, LDS>(k, m, t0, c, dm_lds, pl);
 #pragma unroll 1
-      for (int t = t0 + 1; t < t1; ++t) nrm += march_step<P, DAG, EPI, XIN, NORM, true>(k, m, t, c);
+      for (int t = t0 + 1; t < t1; ++t) nrm += march_step<P, DAG, EPI, XIN, NORM, true, LDS>(k, m, t, c, dm_lds, pl);
       {
         // the forward time hop of out(x, t1 - 1) from slice t1
         const int te = (t1 == L4) ? 0 : t1;
@@ -317,11 +480,11 @@ __global__ __launch_bounds__(DM_BS) void k_dirac_march(KDirac k) {
   }
 }
 
-template <int P, bool DAG>
-void launch_p(const KDirac &k, int epi, bool xin, bool norm, unsigned nblk, hipStream_t st) {
+template <int P, bool DAG, bool LDS>
+void launch_p(const KDirac &k, int epi, bool xin, bool norm, unsigned nblk, size_t lds, hipStream_t st) {
 #define WD_DR(E, XI, N)                    \
   if (epi == E && xin == XI && norm == N) \
-    hipLaunchKernelGGL((k_dirac_march<P, DAG, E, XI, N>), dim3(nblk), dim3(DM_BS), 0, st, k);
+    hipLaunchKernelGGL((k_dirac_march<P, DAG, E, XI, N, LDS>), dim3(nblk), dim3(DM_BS), lds, st, k);
   WD_DR(0, false, false) WD_DR(1, false, false) WD_DR(2, false, false)
   WD_DR(1, true, false) WD_DR(2, true, false)
   WD_DR(0, false, true) WD_DR(1, false, true) WD_DR(2, false, true)
@@ -341,7 +504,16 @@ int march_brick_n2(const Geom &g) {
   return (g.L[1] % n2 == 0 && g.L[2] % 2 == 0) ? n2 : 0;
 }
 
-// tile: 2 = brick tiles (where they fit), 0 = 256 consecutive spatial sites.
+// Staged sites and LDS bytes per block of the LDS-staged form (the brick
+// and its four side faces; FP64 12, FP32 6 packets of 16 bytes per site).
+int march_nslot(const Geom &g, int n2) { return DM_BS + 2 * g.L[0] * (n2 + 2); }
+size_t march_lds_bytes(const Geom &g, wd_prec prec) {
+  const int n2 = march_brick_n2(g);
+  return n2 ? (size_t)march_nslot(g, n2) * (prec == WD_F64 ? 12 : 6) * 16 : 0;
+}
+
+// tile: 2 = brick tiles, 3 = brick tiles staged in LDS (where bricks fit),
+// 0 = 256 consecutive spatial sites.
 // S > 0: time slices per range (at most L4); S = 0: the smallest of 8, 16,
 // 32, ... for which every work item is resident at once (capacity =
 // resident blocks per CU x CUs), so that the tiles marching a range side by
@@ -349,7 +521,7 @@ int march_brick_n2(const Geom &g) {
 MarchGrid march_grid(const Geom &g, int S, int tile, int capacity) {
   MarchGrid m;
   m.nsp = g.L[0] * g.L[1] * g.L[2];
-  m.n2 = tile == 2 ? march_brick_n2(g) : 0;
+  m.n2 = tile >= 2 ? march_brick_n2(g) : 0;
   m.n3 = m.n2 ? 2 : 0;
   m.nt = m.n2 ? (g.L[1] / m.n2) * (g.L[2] / m.n3) : (m.nsp + DM_BS - 1) / DM_BS;
   if (S > 0) {
@@ -364,10 +536,10 @@ MarchGrid march_grid(const Geom &g, int S, int tile, int capacity) {
   return m;
 }
 
-template <int P>
-int march_blocks_per_cu() {
+template <int P, bool LDS>
+int march_blocks_per_cu(size_t lds) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_dirac_march<P, false, 1, true, false>, DM_BS, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_dirac_march<P, false, 1, true, false, LDS>, DM_BS, lds) !=
           hipSuccess ||
       n < 1)
     n = 1;
@@ -375,7 +547,8 @@ int march_blocks_per_cu() {
 }
 
 int march_capacity(const wd_gauge *g, wd_prec prec) {
-  return std::max(g->dirac_bpc[prec], 1) * std::max(g->n_cu, 1);
+  const int bpc = (g->dirac_tile[prec] == 3 && prec <= WD_F32) ? g->dirac_bpc_lds[prec] : g->dirac_bpc[prec];
+  return std::max(bpc, 1) * std::max(g->n_cu, 1);
 }
 
 MarchGrid march_grid_of(const wd_gauge *g, wd_prec prec) {
@@ -384,19 +557,34 @@ MarchGrid march_grid_of(const wd_gauge *g, wd_prec prec) {
 
 }  // namespace
 
-bool dirac_variant_ok(const Geom &g, int slices, int tile) {
-  return slices >= 0 && slices <= g.L[3] && (tile == 0 || (tile == 2 && march_brick_n2(g) > 0));
+bool dirac_variant_ok(const wd_gauge *g, wd_prec prec, int slices, int tile) {
+  const Geom &G = g->geom;
+  if (slices < 0 || slices > G.L[3]) return false;
+  if (tile == 0) return true;
+  if (tile == 2) return march_brick_n2(G) > 0;
+  if (tile == 3)
+    return march_brick_n2(G) > 0 && (prec == WD_F64 || prec == WD_F32) &&
+           march_lds_bytes(G, prec) <= (size_t)g->lds_per_block;
+  return false;
 }
 
 wd_status dirac_init(wd_gauge *g) {
+  // default tiles: bricks staged in LDS where they fit (FP64, FP32), else bricks, else consecutive sites
   for (int p = 0; p < 4; ++p) {
     g->dirac_slices[p] = 0;
     g->dirac_tile[p] = march_brick_n2(g->geom) ? 2 : 0;
   }
-  g->dirac_bpc[WD_F64] = march_blocks_per_cu<WD_F64>();
-  g->dirac_bpc[WD_F32] = march_blocks_per_cu<WD_F32>();
-  g->dirac_bpc[WD_F16] = march_blocks_per_cu<WD_F16>();
-  g->dirac_bpc[WD_BF16] = march_blocks_per_cu<WD_BF16>();
+  g->dirac_bpc[WD_F64] = march_blocks_per_cu<WD_F64, false>(0);
+  g->dirac_bpc[WD_F32] = march_blocks_per_cu<WD_F32, false>(0);
+  g->dirac_bpc[WD_F16] = march_blocks_per_cu<WD_F16, false>(0);
+  g->dirac_bpc[WD_BF16] = march_blocks_per_cu<WD_BF16, false>(0);
+  g->dirac_bpc_lds[WD_F64] = g->dirac_bpc_lds[WD_F32] = 0;
+  if (dirac_variant_ok(g, WD_F64, 0, 3))
+    g->dirac_bpc_lds[WD_F64] = march_blocks_per_cu<WD_F64, true>(march_lds_bytes(g->geom, WD_F64));
+  if (dirac_variant_ok(g, WD_F32, 0, 3))
+    g->dirac_bpc_lds[WD_F32] = march_blocks_per_cu<WD_F32, true>(march_lds_bytes(g->geom, WD_F32));
+  for (int p = 0; p < 2; ++p)
+    if (g->dirac_bpc_lds[p] > 0) g->dirac_tile[p] = 3;
   return WD_OK;
 }
 
@@ -434,20 +622,29 @@ wd_status launch_dirac(const wd_gauge *g, wd_prec prec, const DiracArgs &a, hipS
   k.npad = g->geom.vpad - g->geom.vh;
   k.n2 = mg.n2;
   k.n3 = mg.n3;
+  const bool staged = g->dirac_tile[prec] == 3;
+  if (staged && !dirac_variant_ok(g, prec, g->dirac_slices[prec], 3))
+    return set_error(WD_ERR_ARG, "dirac: the LDS-staged variant does not fit this lattice / precision");
+  k.nslot = staged ? march_nslot(g->geom, mg.n2) : 0;
+  const size_t lds = staged ? march_lds_bytes(g->geom, prec) : 0;
   const int epi = a.Y ? 2 : (a.X ? 1 : 0);
   const bool xin = a.X && a.X == a.in;
   const unsigned nblk = 8u * (unsigned)mg.per;
   // the reduction buffers hold at least this many partials (sized for the hop and level-1 grids)
   if (norm && nblk > std::max(dslash_grid_blocks(g), BLAS_MAX_BLOCKS))
     return set_error(WD_ERR_ARG, "dirac norm: %u blocks exceed the reduction buffer", nblk);
-#define WD_DP(PR)                                                \
-  if (a.dagger) launch_p<PR, true>(k, epi, xin, norm, nblk, st); \
-  else launch_p<PR, false>(k, epi, xin, norm, nblk, st);
+#define WD_DP(PR, L)                                                           \
+  if (a.dagger) launch_p<PR, true, L>(k, epi, xin, norm, nblk, lds, st);        \
+  else launch_p<PR, false, L>(k, epi, xin, norm, nblk, lds, st);
   switch (prec) {
-    case WD_F64: WD_DP(WD_F64) break;
-    case WD_F32: WD_DP(WD_F32) break;
-    case WD_F16: WD_DP(WD_F16) break;
-    case WD_BF16: WD_DP(WD_BF16) break;
+    case WD_F64:
+      if (staged) { WD_DP(WD_F64, true) } else { WD_DP(WD_F64, false) }
+      break;
+    case WD_F32:
+      if (staged) { WD_DP(WD_F32, true) } else { WD_DP(WD_F32, false) }
+      break;
+    case WD_F16: WD_DP(WD_F16, false) break;
+    case WD_BF16: WD_DP(WD_BF16, false) break;
     default: return set_error(WD_ERR_PREC, "dirac: unknown precision %d", (int)prec);
   }
 #undef WD_DP

@@ -487,7 +487,7 @@ wd_status wd_tune_dslash_mrhs(wd_gauge *g, wd_prec prec, int nrhs, const char *c
 wd_status wd_set_dirac_variant(wd_gauge *g, wd_prec prec, int slices, int tile) {
   if (!g) return set_error(WD_ERR_ARG, "gauge handle is NULL");
   if ((int)prec < 0 || (int)prec > 3) return set_error(WD_ERR_PREC, "prec = %d", (int)prec);
-  if (!dirac_variant_ok(g->geom, slices, tile))
+  if (!dirac_variant_ok(g, prec, slices, tile))
     return set_error(WD_ERR_ARG, "one-launch D_W variant: slices %d, tile %d does not fit %dx%dx%dx%d", slices,
                      tile, g->dims[0], g->dims[1], g->dims[2], g->dims[3]);
   g->dirac_slices[prec] = slices;
@@ -556,10 +556,10 @@ wd_status wd_tune_dirac(wd_gauge *g, wd_prec prec, const char *cache_path, int f
     a.out = ref;
     if ((rc = launch_dirac(g, prec, a, st)) != WD_OK) break;
     std::vector<std::array<int, 2>> cands;
-    for (int tile : {2, 0})
+    for (int tile : {3, 2, 0})
       for (int sl = 8;; sl *= 2) {
         const int S = std::min(sl, G.L[3]);
-        if (dirac_variant_ok(G, S, tile)) cands.push_back({S, tile});
+        if (dirac_variant_ok(g, prec, S, tile)) cands.push_back({S, tile});
         if (S == G.L[3]) break;
       }
     a.out = cand;

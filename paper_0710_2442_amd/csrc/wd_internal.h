@@ -69,6 +69,7 @@ struct wd_gauge {
   int lds_per_block;       // the device's LDS limit per block (bytes)
   int n_cu;                // compute units of the device
   int dirac_bpc[4];        // per precision: resident blocks per CU of the one-launch D_W
+  int dirac_bpc_lds[2];    // FP64, FP32: the same for its LDS-staged form (0: does not fit)
   int dirac_slices[4];     // per precision: time slices per range of the one-launch D_W (0: from occupancy)
   int dirac_tile[4];       // per precision: its tiles, 2 = bricks of L1 x n2 x 2 sites, 0 = consecutive sites
   hipStream_t stream;      // caller's stream for dslash / pack
@@ -158,7 +159,7 @@ wd_status dirac_init(wd_gauge *g);
 // whether the one-launch D_W has work items for at least half of the device's resident blocks
 bool dirac_fills_device(const wd_gauge *g, wd_prec prec);
 // whether (time slices per range, tile shape) is a valid one-launch D_W variant for the lattice
-bool dirac_variant_ok(const Geom &g, int slices, int tile);
+bool dirac_variant_ok(const wd_gauge *g, wd_prec prec, int slices, int tile);
 // out[j * ostride] = (accumulate ? out[j * ostride] : 0) + sum over b of
 // partials[j * nblocks + b], for j < n, in block order (one workgroup per j);
 // entries whose skip[j * sstride] is set are left alone (blas.hip).

@@ -104,8 +104,10 @@ def test_marching_dirac_over_ranges_and_tiles(dims, prec):
     boundary (time link and half spinor fetched across it) and the
     antiperiodic wrap are crossed.  Tiles of consecutive sites, the last one
     ragged (6x6x10), and brick tiles of L1 x n2 x 2 sites (16x8x4: one brick
-    per x3 pair; 8x16x6: three bricks along x3).  Against the oracle, D_W
-    and D_W^dag; the output's padding slots must come back zero.
+    per x3 pair; 8x16x6: three bricks along x3; FP64 and FP32 stage them in
+    LDS with their side faces, FP16 and BF16 keep them in registers).
+    Against the oracle, D_W and D_W^dag; the output's padding slots must
+    come back zero.
 
     FP16 per-site bar 2^-10: the output's own rounding is bounded by 2^-11 of
     the site's largest component (half an FP16 ulp of each storage-basis real,
@@ -359,28 +361,33 @@ def test_tuning_cache_round_trip(tmp_path):
 
 
 def test_one_launch_dirac_variants_and_tuning(tmp_path):
-    """Every one-launch D_W variant (time slices per range, brick or
+    """Every one-launch D_W variant (time slices per range; brick tiles,
+    brick tiles staged in LDS with their side faces (FP64, FP32), or
     consecutive tiles) computes the same bytes, D_W and D_W^dag; the tuner
     keeps its choice in the JSON-lines cache and takes it back from there;
-    variants that do not fit the lattice are refused."""
+    variants that do not fit the lattice or precision are refused."""
     dims = (16, 8, 4, 16)  # bricks of 16 x 8 x 2 sites fit
     U = syn.gauge_field(dims, 0.3, 31)
     psi = syn.gaussian_spinor(dims, 32)
-    for prec in ("f64", "bf16"):
+    for prec in ("f64", "f32", "bf16"):
         g = wd.Gauge(U, dims, -1, prec)
         src = to_field(g, psi, prec)
-        assert wd.wd_get_dirac_variant(g, prec) == (0, 2)
+        assert wd.wd_get_dirac_variant(g, prec) == (0, 3 if prec != "bf16" else 2)
+        staged = ((1, 3), (3, 3), (8, 3), (0, 3)) if prec != "bf16" else ()
         for flags in (0, wd.WD_DAGGER):
             ref = wd.wd_new_field(dims, prec)
             wd.wd_dslash_ex(g, src, ref, 0.124, wd.WD_FULL, prec, flags | wd.WD_ONE_PASS)
-            for sl, tile in ((1, 0), (3, 2), (8, 0), (16, 2), (16, 0), (0, 0)):
+            for sl, tile in ((1, 0), (3, 2), (8, 0), (16, 2), (16, 0), (0, 0)) + staged:
                 wd.wd_set_dirac_variant(g, prec, sl, tile)
                 assert wd.wd_get_dirac_variant(g, prec) == (sl, tile)
                 out = wd.wd_new_field(dims, prec)
                 out.fill_(0xFF)
                 wd.wd_dslash_ex(g, src, out, 0.124, wd.WD_FULL, prec, flags | wd.WD_ONE_PASS)
                 assert torch.equal(out, ref), (prec, flags, sl, tile)
-            wd.wd_set_dirac_variant(g, prec, 0, 2)
+            wd.wd_set_dirac_variant(g, prec, 0, 3 if prec != "bf16" else 2)
+        if prec == "bf16":
+            with pytest.raises(wd.WdError):
+                wd.wd_set_dirac_variant(g, prec, 8, 3)  # LDS staging: FP64 and FP32 storage only
         with pytest.raises(wd.WdError):
             wd.wd_set_dirac_variant(g, prec, 17, 2)
         with pytest.raises(wd.WdError):
@@ -398,8 +405,9 @@ def test_one_launch_dirac_variants_and_tuning(tmp_path):
     g.close()
     g = wd.Gauge(syn.gauge_field((6, 4, 6, 10), 0.3, 33), (6, 4, 6, 10), -1, "f32")
     assert wd.wd_get_dirac_variant(g, "f32") == (0, 0)  # 256 is not a multiple of 2 x 6: no bricks
-    with pytest.raises(wd.WdError):
-        wd.wd_set_dirac_variant(g, "f32", 4, 2)
+    for tile in (2, 3):
+        with pytest.raises(wd.WdError):
+            wd.wd_set_dirac_variant(g, "f32", 4, tile)
     g.close()
 
 
