@@ -49,6 +49,9 @@ KERNEL_SOURCES = ["paper_0710_2442_amd/csrc/dslash.hip", "paper_0710_2442_amd/cs
 MRHS_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "mrhs_24x24x24x48_traffic.txt")
 MRHS_SOURCES = ["paper_0710_2442_amd/csrc/mrhs.hip", "paper_0710_2442_amd/csrc/wd_hop.h",
                 "paper_0710_2442_amd/csrc/wd_device.h"]
+DIRAC_SOURCES = ["paper_0710_2442_amd/csrc/dirac.hip", "paper_0710_2442_amd/csrc/wd_hop.h",
+                 "paper_0710_2442_amd/csrc/wd_device.h"]
+DIRAC_TRAFFIC = os.path.join(ROOT, "profiles", "dirac_one_launch_32x32x32x64_traffic.txt")
 
 
 def log(*a):
@@ -500,17 +503,28 @@ def kernels_leg(wd, torch, syn, U, psi, betas=None):
     t2 = ev_time(lambda: wd.wd_dslash(g, x, z, 0.124, DIMS, wd.WD_FULL))
     out["dirac_full_f64_two_pass"] = {"us": round(t2 * 1e6, 2), "GBps": round(V * 1344 / t2 / 1e9, 1),
                                       "bytes_per_site": 1344, "one_launch_speedup": round(t2 / t, 3)}
-    out["dirac_full_f64_one_launch"]["variant_slices_tile"] = list(wd.wd_get_dirac_variant(g, "f64"))
+    dvar = list(wd.wd_get_dirac_variant(g, "f64"))
+    out["dirac_full_f64_one_launch"]["variant_slices_tile"] = dvar
+    tb, why = read_traffic("f64", dvar, DIRAC_TRAFFIC, DIRAC_SOURCES)
+    ratio = tb / (V * 768) if tb else 1.0
+    out["dirac_full_f64_one_launch"]["traffic_ratio_counters"] = round(ratio, 3) if tb else None
+    out["dirac_full_f64_one_launch"]["model_eq1_eq2"] = perf_model.report(
+        perf_model.kernel_model("dirac_one_launch", "f64", V, ratio, betas), t)
     # the same in FP32 (FP32 links and spinors: 384 B per site in one launch, 672 B in two)
     x32 = canon_to_field(g, psi, "f32")
     z32 = wd.wd_new_field(DIMS, "f32")
     t = ev_time(lambda: wd.wd_dslash_ex(g, x32, z32, 0.124, wd.WD_FULL, "f32", wd.WD_ONE_PASS))
     t2 = ev_time(lambda: wd.wd_dslash_ex(g, x32, z32, 0.124, wd.WD_FULL, "f32", 0))
+    dvar = list(wd.wd_get_dirac_variant(g, "f32"))
+    tb, why = read_traffic("f32", dvar, DIRAC_TRAFFIC, DIRAC_SOURCES)
+    ratio = tb / (V * 384) if tb else 1.0
     out["dirac_full_f32_one_launch"] = {"us": round(t * 1e6, 2), "GBps": round(V * 384 / t / 1e9, 1),
                                         "frac_hbm": round(V * 384 / t / 1e9 / HBM_PEAK_GBS, 4),
-                                        "bytes_per_site": 384,
-                                        "variant_slices_tile": list(wd.wd_get_dirac_variant(g, "f32")),
-                                        "two_pass_us": round(t2 * 1e6, 2), "one_launch_speedup": round(t2 / t, 3)}
+                                        "bytes_per_site": 384, "variant_slices_tile": dvar,
+                                        "two_pass_us": round(t2 * 1e6, 2), "one_launch_speedup": round(t2 / t, 3),
+                                        "traffic_ratio_counters": round(ratio, 3) if tb else None,
+                                        "model_eq1_eq2": perf_model.report(
+                                            perf_model.kernel_model("dirac_one_launch", "f32", V, ratio, betas), t)}
     del x32, z32
     # one rank's share of an 8-way time decomposition (32^3 x 8 slab): the slab hop, with its two
     # time faces read from packed face buffers, and the face packing (what a GPU would send)

@@ -77,6 +77,21 @@ def hop_counts(prec):
     return {"hbm": lk + 2 * sp, "l2": lk + 6 * sp + sp + sp, "lds": 0.0, "fma": HOP_FLOPS / 2}
 
 
+def dirac_counts(prec, staged=True):
+    """Per site (both parities) of the one-launch D_W marching along x4:
+    algorithmic HBM bytes 4 x 12 link reals + the input spinor once + the
+    output.  Through L2: the own spinor, the own 4 links, the three
+    neighbours' forward links read as U^dag, the output and, staged, the
+    side-face spinors of the brick (384 of 640 staged sites per 256 sites),
+    else the six spatial neighbour spinors.  Through LDS (staged): the staged
+    sites written once, six neighbour spinors read.  Lane FMAs: the hopping
+    term, the third link rows, the a-scaled half spinors and the X term."""
+    sp, lr = SPINOR_BYTES[prec], LINK_REAL_BYTES[prec]
+    nb = 1.5 * sp if staged else 6 * sp
+    return {"hbm": 48 * lr + 2 * sp, "l2": sp + 48 * lr + 36 * lr + nb + sp,
+            "lds": (2.5 * sp + 6 * sp) if staged else 0.0, "fma": (HOP_FLOPS + 8 * 12 + 24) / 2}
+
+
 def mrhs_counts(prec, nrhs):
     """Per site (all nrhs right-hand sides) of the multi-RHS hop: each link
     loaded once for the nrhs spinor sets (FP64 links for FP64, FP32 otherwise)."""
@@ -169,6 +184,10 @@ def kernel_model(kernel, prec, units, traffic_ratio=1.0, betas=None):
     T_exe (Eq. 2, full overlap), T_sum (no overlap) and the bound."""
     if kernel == "hop":
         c = hop_counts(prec)
+        refetch = (traffic_ratio - 1.0) * c["hbm"] if traffic_ratio > 1.0 else 0.0
+        return predict(units, c, betas, hbm_beta="hbm_hop_mix", mall_bytes=refetch)
+    if kernel == "dirac_one_launch":
+        c = dirac_counts(prec)
         refetch = (traffic_ratio - 1.0) * c["hbm"] if traffic_ratio > 1.0 else 0.0
         return predict(units, c, betas, hbm_beta="hbm_hop_mix", mall_bytes=refetch)
     if kernel == "mrhs12":

@@ -41,7 +41,8 @@ STREAMING = {"hop", "cg_iteration", "caxpy"}
 def test_summary_has_every_kernel_and_task_throughput():
     assert set(BETAS) == {"l2", "mall", "hbm_read", "hbm_copy", "hbm_hop_mix"}
     assert {r[0] for r in ROWS} >= {"hop", "cg_iteration", "caxpy", "mrhs12", "ptc_network",
-                                    "ptc_even_fp16_products", "ptc_even_bf16_mfma", "batch8_inner_iteration"}
+                                    "ptc_even_fp16_products", "ptc_even_bf16_mfma", "batch8_inner_iteration",
+                                    "dirac_one_launch"}
 
 
 @pytest.mark.parametrize("row", ROWS, ids=[f"{r[0]}-{r[1]}" for r in ROWS])
