@@ -254,9 +254,20 @@ wd_status true_residual64(const wd_gauge *g, const void *b, const void *x, void 
                           double kappa, CgScalars *sc, RedBuf red, hipStream_t st) {
   const size_t hb = half_bytes(g->geom, WD_F64);
   if (nsys == 1) {
-    // two single-parity launches with the xpay and norm epilogues (the tuned
-    // hop; the one-launch kernel moves fewer bytes but re-reads its shared
-    // links from HBM at this size, see the full-lattice kernel)
+    // r = b - x + kappa H x with |r|^2: the one-launch marching D_W where its
+    // work items fill the device (each link and spinor fetched once), else
+    // two single-parity launches with the xpay and norm epilogues
+    if (dirac_fills_device(g, WD_F64)) {
+      DiracArgs a;
+      a.in = x;
+      a.out = r;
+      a.X = b;
+      a.Y = x;
+      a.a = kappa;
+      a.norm_out = &sc->rnorm2;
+      a.red = red;
+      return launch_dirac(g, WD_F64, a, st);
+    }
     for (int par = 0; par < 2; ++par) {
       DslashArgs a;
       a.in = (const char *)x + (1 - par) * hb;
