@@ -18,7 +18,9 @@
 //      spatial links, the neighbours' forward links as U^dag, and the
 //      neighbours' spinors of slice k, all read in the same step by the
 //      lanes that own them, so every byte of slice k is fetched from HBM
-//      once and re-read from L1 or L2 within the step;
+//      once and re-read within the step (from LDS in the staged form below,
+//      else from L1 or L2); each direction's forward and backward hop run
+//      back to back, so a spatial link's two reads are close together;
 //   the partial output starts from the epilogue terms X - Y (taken before
 //   the hops, so the own spinor is dead early) and every hop adds a times
 //   its term.
