@@ -106,6 +106,30 @@ __global__ __launch_bounds__(FIN_BS) void k_finish_sums(const double *partials, 
 }
 
 // ------------------------------------------------------------ elementwise
+// A spinor read with streaming (non-temporal) loads, for operands read once
+// that no later kernel needs in the caches; FP16 and BF16 as Spinor<P>::load.
+template <int P>
+__device__ __forceinline__ void load_stream(const char *base, int i, cplx<RealOf<P>> (&s)[12]) {
+  if constexpr (P == WD_F64) {
+    const v2d *p = (const v2d *)base + chunk_base<Spinor<WD_F64>::CHUNK>((size_t)i);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const v2d v = ld_stream(p + 64 * c);
+      s[c] = {v.x, v.y};
+    }
+  } else if constexpr (P == WD_F32) {
+    const v4f *p = (const v4f *)base + chunk_base<Spinor<WD_F32>::CHUNK>((size_t)i);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const v4f v = ld_stream(p + 64 * q);
+      s[2 * q] = {v.x, v.y};
+      s[2 * q + 1] = {v.z, v.w};
+    }
+  } else {
+    Spinor<P>::load(base, (size_t)i, s);
+  }
+}
+
 // out = c * x + y  (out may alias y)
 template <int P>
 __global__ __launch_bounds__(BLAS_BS) void k_caxpy(KBlas k) {
@@ -117,8 +141,9 @@ __global__ __launch_bounds__(BLAS_BS) void k_caxpy(KBlas k) {
     int h, i;
     site_of(k.v, f, h, i);
     cplx<T> a[12], b[12];
-    Spinor<P>::load(k.x + sys * k.sx + h * k.hx, i, a);
-    Spinor<P>::load(k.y + sys * k.sy + h * k.hy, i, b);
+    // both operands are read once: streaming loads
+    load_stream<P>(k.x + sys * k.sx + h * k.hx, i, a);
+    load_stream<P>(k.y + sys * k.sy + h * k.hy, i, b);
 #pragma unroll
     for (int q = 0; q < 12; ++q) cfma(b[q], c, a[q]);
     Spinor<P>::store(k.out + sys * k.so + h * k.ho, i, b);
