@@ -47,6 +47,33 @@ __device__ __forceinline__ bool site_of(const VecGeom &v, long f, int &h, int &i
 }
 
 // ------------------------------------------------------------ reductions
+// A spinor read with streaming (non-temporal) loads, for operands read once
+// per kernel (caxpy and the reductions |x|^2, <x, y>): full fields of the
+// solvers are larger than the caches, so keeping them buys nothing and
+// streaming them frees the caches for the hop's gathers.  FP16 and BF16 as
+// Spinor<P>::load.
+template <int P>
+__device__ __forceinline__ void load_stream(const char *base, int i, cplx<RealOf<P>> (&s)[12]) {
+  if constexpr (P == WD_F64) {
+    const v2d *p = (const v2d *)base + chunk_base<Spinor<WD_F64>::CHUNK>((size_t)i);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const v2d v = ld_stream(p + 64 * c);
+      s[c] = {v.x, v.y};
+    }
+  } else if constexpr (P == WD_F32) {
+    const v4f *p = (const v4f *)base + chunk_base<Spinor<WD_F32>::CHUNK>((size_t)i);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const v4f v = ld_stream(p + 64 * q);
+      s[2 * q] = {v.x, v.y};
+      s[2 * q + 1] = {v.z, v.w};
+    }
+  } else {
+    Spinor<P>::load(base, (size_t)i, s);
+  }
+}
+
 template <int P>
 __global__ __launch_bounds__(BLAS_BS) void k_norm2(KBlas k) {
   using T = RealOf<P>;
@@ -58,7 +85,7 @@ __global__ __launch_bounds__(BLAS_BS) void k_norm2(KBlas k) {
     int h, i;
     site_of(k.v, f, h, i);
     cplx<T> a[12];
-    Spinor<P>::load(x + h * k.hx, i, a);
+    load_stream<P>(x + h * k.hx, i, a);
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc += (double)a[c].re * a[c].re + (double)a[c].im * a[c].im;
   }
@@ -78,8 +105,8 @@ __global__ __launch_bounds__(BLAS_BS) void k_cdot(KBlas k) {
     int h, i;
     site_of(k.v, f, h, i);
     cplx<T> a[12], b[12];
-    Spinor<P>::load(x + h * k.hx, i, a);
-    Spinor<P>::load(y + h * k.hy, i, b);
+    load_stream<P>(x + h * k.hx, i, a);
+    load_stream<P>(y + h * k.hy, i, b);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
       re += (double)a[c].re * b[c].re + (double)a[c].im * b[c].im;
@@ -106,30 +133,6 @@ __global__ __launch_bounds__(FIN_BS) void k_finish_sums(const double *partials, 
 }
 
 // ------------------------------------------------------------ elementwise
-// A spinor read with streaming (non-temporal) loads, for operands read once
-// that no later kernel needs in the caches; FP16 and BF16 as Spinor<P>::load.
-template <int P>
-__device__ __forceinline__ void load_stream(const char *base, int i, cplx<RealOf<P>> (&s)[12]) {
-  if constexpr (P == WD_F64) {
-    const v2d *p = (const v2d *)base + chunk_base<Spinor<WD_F64>::CHUNK>((size_t)i);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      const v2d v = ld_stream(p + 64 * c);
-      s[c] = {v.x, v.y};
-    }
-  } else if constexpr (P == WD_F32) {
-    const v4f *p = (const v4f *)base + chunk_base<Spinor<WD_F32>::CHUNK>((size_t)i);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      const v4f v = ld_stream(p + 64 * q);
-      s[2 * q] = {v.x, v.y};
-      s[2 * q + 1] = {v.z, v.w};
-    }
-  } else {
-    Spinor<P>::load(base, (size_t)i, s);
-  }
-}
-
 // out = c * x + y  (out may alias y)
 template <int P>
 __global__ __launch_bounds__(BLAS_BS) void k_caxpy(KBlas k) {
