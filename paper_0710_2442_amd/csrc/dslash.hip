@@ -57,14 +57,14 @@ __device__ __forceinline__ void dslash_body(const KDslash &k) {
 WD_OCC_KERNEL(0, )
 WD_OCC_KERNEL(4, __attribute__((amdgpu_waves_per_eu(4))))
 
-// LDS staging of neighbour half-spinors (FP64, FP32 storage; one site per
-// lane): the block first loads the input spinors of its tile's own slots and
-// of the x1 rows just before and after the tile (coalesced), projects each
-// for the x1+-, x2+- hops and stores the four half-spinors in LDS; then each
-// lane takes its x1 and x2 neighbours' projections from there and the x3 and
+// LDS staging of neighbour spinors (FP64, FP32 storage; one site per lane):
+// the block first loads the input spinors of its tile's own slots and of the
+// x1 rows just before and after the tile (coalesced) and stores them in LDS
+// (packet-major, see Stage); then each lane takes its x1 and x2 neighbours
+// from there, projecting them as it would after a memory load, and the x3 and
 // x4 neighbours from memory.  The tile is k = blockDim.x / L1h whole rows of
 // one x3 plane (k | L2, k >= 2) or whole planes (see dslash_stage_ok).
-// Dynamic LDS: (blockDim.x + 2 L1h) * STAGE_STRIDE complex.
+// Dynamic LDS: (blockDim.x + 2 L1h) spinors.
 template <int P, bool DAG, int EPI, bool NORM>
 __global__ __launch_bounds__(512) void k_dslash_stage(KDslash k) {
   using T = RealOf<P>;
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(512) void k_dslash_stage(KDslash k) {
   cplx<T> *lds = (cplx<T> *)stage_lds;
   if (k.skip && *k.skip) return;
   const int n = (int)blockDim.x, t = (int)threadIdx.x, l1h = k.g.L1h;
-  const int t0 = tile_of(k) * n;
+  const int t0 = tile_of(k) * n, ns = n + 2 * l1h;
   // the rows around the tile, wrapping in its plane
   const int r0 = t0 / l1h, r1 = r0 + n / l1h - 1;  // first and last row (row = x2 + L2 (x3 + L3 x4))
   const int L2 = k.g.L[1];
@@ -81,15 +81,15 @@ __global__ __launch_bounds__(512) void k_dslash_stage(KDslash k) {
   {
     cplx<T> psi[12];
     Spinor<P>::load(k.in, t0 + t, psi);
-    stage_store<T>(lds, t, psi);
+    stage_store<T>(lds, t, ns, psi);
     if (t < 2 * l1h) {
       Spinor<P>::load(k.in, (t < l1h) ? lo + t : hi + t - l1h, psi);
-      stage_store<T>(lds, n + t, psi);
+      stage_store<T>(lds, n + t, ns, psi);
     }
   }
   __syncthreads();
   const double nrm =
-      dslash_site<P, DAG, EPI, NORM, false, true>(k, t0 + t, Stage<T>{lds, t0, n, lo, hi, l1h});
+      dslash_site<P, DAG, EPI, NORM, false, true>(k, t0 + t, Stage<T>{lds, t0, n, lo, hi, l1h, ns});
   if constexpr (NORM) {
     double v[1] = {nrm};
     block_sum_store<1>(v, k.partials, gridDim.x, blockIdx.x);
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(512) void k_dslash_stage(KDslash k) {
 // x3 plane (k | L2) or whole planes (L2 | k; then every x2 neighbour is in
 // the tile), and the tiles cover the slots exactly.
 size_t dslash_stage_lds_bytes(const Geom &G, int bs, wd_prec prec) {
-  return (size_t)(bs + 2 * G.L1h) * STAGE_STRIDE * (prec == WD_F64 ? 16 : 8);
+  return (size_t)(bs + 2 * G.L1h) * 12 * (prec == WD_F64 ? 16 : 8);
 }
 
 bool dslash_stage_ok(const Geom &G, int bs) {
@@ -129,7 +129,7 @@ template <int P, bool DAG, int EPI, bool NORM>
 static void launch_t(const KDslash &k, unsigned nblk, unsigned bs, unsigned lds, hipStream_t st) {
   if constexpr (P == WD_F64 || P == WD_F32) {
     if (k.stage) {
-      const unsigned sb = (bs + 2 * (unsigned)k.g.L1h) * STAGE_STRIDE * (unsigned)sizeof(cplx<RealOf<P>>);
+      const unsigned sb = (bs + 2 * (unsigned)k.g.L1h) * 12 * (unsigned)sizeof(cplx<RealOf<P>>);
       hipLaunchKernelGGL((k_dslash_stage<P, DAG, EPI, NORM>), dim3(nblk), dim3(bs), sb + lds, st, k);
       return;
     }
