@@ -600,6 +600,65 @@ def test_full_size_plane_wave():
     g.close()
 
 
+# ------------------------------------------------------------ largest fields
+@pytest.fixture(scope="module")
+def largest():
+    """32^3 x 384 (12,582,912 sites): one parity's FP64 hop links take 4.8 GB
+    and FP32 2.4 GB, a full FP64 field 2.4 GB, so device offsets run past 2^31
+    and 2^32 bytes.  The links are a random 32^3 x 8 block repeated along x4,
+    each copy multiplied on the right by its own Haar SU(3) matrix (still
+    SU(3), no two time blocks alike); the spinors are Gaussian everywhere."""
+    dims = (32, 32, 32, 384)
+    small = syn.gauge_field((32, 32, 32, 8), 0.3, 1004)
+    R = syn.random_su3(48, 1005)
+    U = np.empty((384,) + small.shape[1:], dtype=np.complex128)
+    for b in range(48):
+        U[8 * b:8 * b + 8] = small @ R[b]
+    psi = syn.gaussian_spinor(dims, 2004)
+    return dims, U, psi
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_largest_fields_sampled_sites(largest, prec):
+    """The single-parity hop (both parities) and the one-launch D_W on the
+    32^3 x 384 lattice, in their default launch configurations, against the
+    oracle at sampled sites (the last time slice included, where the offsets
+    are largest), element by element."""
+    dims, U, psi = largest
+    print(f"case: 32^3x384 largest fields prec={prec}", flush=True)
+    kappa = 0.124
+    g = wd.Gauge(U, dims, -1, prec)
+    Ur = U if prec == "f64" else round_c64(U)
+    pr = storage_round(psi, prec)
+    rng = np.random.default_rng(7)
+    edge = [(0, 0, 0, 0), (31, 31, 31, 383), (0, 0, 0, 383), (31, 31, 31, 382), (1, 0, 0, 383), (30, 31, 31, 191)]
+    last = (wilson.parity_field(dims[:3] + (1,))[0] + dims[3] - 1) % 2  # parity of the last slice's sites
+    for parity in (0, 1):
+        src = to_field(g, psi, prec, 1 - parity)
+        out = wd.wd_new_field(dims, prec, 1, parity)
+        wd.wd_dslash(g, src, out, 1.0, dims, parity)
+        got = from_field(g, out, prec, parity)
+        del src, out
+        sites = edge + [tuple(int(rng.integers(0, L)) for L in dims) for _ in range(200)]
+        sites = [s for s in sites if sum(s) % 2 == parity]
+        want = wilson.hop_sites(Ur, pr, sites)
+        g_s = np.stack([got[x4, x3, x2, x1] for (x1, x2, x3, x4) in sites])
+        assert_close(g_s, want, prec, what=f"32^3x384 hop {prec} p{parity} ({len(sites)} sites)")
+        # the other parity's sites of the last slice were not written
+        assert np.all(got[-1][last != parity] == 0)
+        del got
+    src = to_field(g, psi, prec)
+    one = wd.wd_new_field(dims, prec)
+    wd.wd_dslash_ex(g, src, one, kappa, wd.WD_FULL, prec, wd.WD_ONE_PASS)
+    got = from_field(g, one, prec)
+    del src, one
+    sites = edge + [tuple(int(rng.integers(0, L)) for L in dims) for _ in range(200)]
+    want = np.stack([pr[x4, x3, x2, x1] for (x1, x2, x3, x4) in sites]) - kappa * wilson.hop_sites(Ur, pr, sites)
+    g_s = np.stack([got[x4, x3, x2, x1] for (x1, x2, x3, x4) in sites])
+    assert_close(g_s, want, prec, what=f"32^3x384 one-launch D_W {prec} ({len(sites)} sites)")
+    g.close()
+
+
 @pytest.mark.parametrize("dims", [(8, 8, 8, 8), (16, 16, 16, 16), (6, 4, 6, 10)])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_every_hop_variant_is_bitwise_identical(dims, prec):
