@@ -247,12 +247,16 @@ def report(t, measured_s):
 
 
 def cg_iteration_model(vh, prec="f64", hop_traffic_ratio=1.0, betas=None):
-    """Eqs. 1-2 for one eo-CGLS iteration on vh even sites: the hops' bytes
-    (times the measured traffic ratio) at the hop-mix ceiling, the BLAS bytes
-    at the copy ceiling; the tasks run one after another (T = sum)."""
+    """Eqs. 1-2 for one eo-CGLS iteration on vh even sites.  The hop launches
+    are modelled as the hop kernel is: their algorithmic bytes at the hop-mix
+    ceiling, the bytes fetched again beyond them (the measured traffic ratio)
+    as an Infinity-Cache task overlapping it (Eq. 2 within a launch).  The
+    BLAS bytes run at the copy ceiling, and the launches follow one another
+    (T = sum over the launches)."""
     b = dict(BETAS, **(betas or {}))
     c = cg_iteration_bytes(prec)
-    t_hops = vh * c["hops"] * hop_traffic_ratio / b["hbm_hop_mix"]
+    refetch = max(hop_traffic_ratio - 1.0, 0.0)
+    t_hops = max(vh * c["hops"] / b["hbm_hop_mix"], vh * c["hops"] * refetch / b["mall"])
     t_blas = vh * c["blas"] / b["hbm_copy"]
     return {"T_hops": t_hops, "T_blas": t_blas, "T_iter": t_hops + t_blas}
 
